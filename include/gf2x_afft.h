@@ -1,0 +1,143 @@
+/*
+ * gf2x_afft.h -- multiplication of long binary polynomials on AMD MI355X
+ * (gfx950) with the additive FFT over a tower field.
+ *
+ * Method: Chen, Cheng, Kuo, Li, Yang, "Faster Multiplication for Long Binary
+ * Polynomials" (arXiv:1708.09746), Alg. 5 with w = 64 over TGF(2^128):
+ * Split -> BasisCvt (Alg. 3) -> changeRepr -> FFT_LCH (Alg. 1) -> pointmul ->
+ * iFFT_LCH -> iBasisCvt -> changeRepr back -> InterleavedCombine.
+ *
+ * Problem (Sec. 2.1): given a(x), b(x) in GF(2)[x] as bit sequences, return
+ * c(x) = a(x) b(x).  Results are exact (bit for bit).
+ *
+ * Conventions shared by every entry point
+ *   - Bit i of a polynomial is bit (i mod 64) of word floor(i / 64)
+ *     (little-endian words).  An n-bit operand occupies ceil(n/64) words; bits
+ *     at and above n in its last word are ignored.
+ *   - The product of an na-bit and an nb-bit operand has na+nb-1 coefficients
+ *     and is written as gf2x_out_words(na, nb) = ceil((na+nb-1)/64) words; bits
+ *     at and above na+nb-1 in the last word are written as zero.
+ *   - An operand of 0 bits is the zero polynomial: the product has 0 words,
+ *     nothing is written and the call returns GF2X_OK.
+ *   - Spectra are arrays of TGF(2^128) elements, 16 bytes each: bit j of an
+ *     element is the coefficient of the tower basis element v_j (Sec. 3.2,
+ *     definition of (v_k)).  Spectrum entry j holds f(j̄), the value at the
+ *     element whose tower representation is the integer j, of
+ *     f(x) = sum_k Phi(a_k) x^k, where a_k is the k-th 64-bit word and
+ *     Phi(u) = u(theta) is the polynomial u(z) evaluated at theta = x7, the
+ *     tower element with only bit 64 set (Sec. 2.1 Kronecker segmentation;
+ *     any generator of TGF(2^128) over GF(2) gives the same product).
+ *   - Device pointers must be 8-byte aligned (words) or 16-byte aligned
+ *     (spectra) and come from hipMalloc (or torch on ROCm).
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *     *_dev calls only enqueue work and return; completion is observed on the
+ *     stream.  A context's scratch is reused by its next call, so calls on one
+ *     context must be issued from one host thread and on one stream (or the
+ *     caller serializes them).
+ *
+ * Status codes: every function returns GF2X_OK or a negative code and never
+ * aborts.  gf2x_strerror() names a code; gf2x_last_error() gives the message
+ * of the last failure on a context (HIP error text included).
+ */
+#ifndef GF2X_AFFT_H
+#define GF2X_AFFT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    GF2X_OK = 0,
+    GF2X_EINVAL = -1, /* NULL pointer with a nonzero size, bad length, overlap */
+    GF2X_ERANGE = -2, /* transform length above 2^32 points (multiplier width) */
+    GF2X_ENOMEM = -3, /* device workspace could not be allocated */
+    GF2X_EDEVICE = -4 /* a HIP runtime error; see gf2x_last_error */
+};
+
+typedef struct gf2x_ctx gf2x_ctx;
+
+/* Create a context on HIP device `device`: builds the constant tables (GF(256)
+ * product table, butterfly multiplier basis lambda[i][t] = s_i(v_t) of
+ * Sec. 4.4, the changeRepr tables of Sec. 4.3) on the host and uploads them.
+ * The context owns them and a growable device workspace. */
+int gf2x_ctx_create(gf2x_ctx **ctx, int device);
+
+/* Release a context (synchronizes its device first). NULL is ignored. */
+void gf2x_ctx_destroy(gf2x_ctx *ctx);
+
+/* Words of the product of an na-bit and an nb-bit operand (0 if either is 0). */
+size_t gf2x_out_words(uint64_t na_bits, uint64_t nb_bits);
+
+/* log2 of the number of evaluation points N used for that product:
+ * N = max(2, 2^ceil(log2(ceil(na/64) + ceil(nb/64) - 1))); -1 if either is 0. */
+int gf2x_fft_log2(uint64_t na_bits, uint64_t nb_bits);
+
+/* Device workspace bytes one product of these sizes needs (two N-point spectra
+ * plus the converted operand words). */
+size_t gf2x_workspace_bytes(uint64_t na_bits, uint64_t nb_bits);
+
+/* c = a * b with HOST pointers; blocking.  Uses a process-wide context on the
+ * current HIP device (created on first use, guarded by a mutex); copies the
+ * operands to the device and the product back.  c receives
+ * gf2x_out_words(na_bits, nb_bits) words and must not overlap a or b. */
+int gf2x_mul(const uint64_t *a, uint64_t na_bits, const uint64_t *b, uint64_t nb_bits, uint64_t *c);
+
+/* c = a * b with DEVICE pointers, enqueued on `stream` (Alg. 5).  a and b may
+ * alias each other (squaring); c must not overlap either. */
+int gf2x_mul_dev(gf2x_ctx *ctx, const uint64_t *a, uint64_t na_bits, const uint64_t *b, uint64_t nb_bits,
+                 uint64_t *c, void *stream);
+
+/* Forward transform of one operand (Split, BasisCvt of Alg. 3 on 64-bit words,
+ * changeRepr, FFT_LCH of Alg. 1 at alpha = 0): spec[j] = f(j̄) for
+ * j < 2^log2n (see the spectrum convention above).  Requires
+ * 2^log2n >= 2^ceil(log2(ceil(na/64))) and log2n <= 32.  spec is DEVICE memory of
+ * 16 * 2^log2n bytes, written entirely. */
+int gf2x_forward_dev(gf2x_ctx *ctx, const uint64_t *a, uint64_t na_bits, int log2n, void *spec, void *stream);
+
+/* Pointwise product of two spectra in TGF(2^128) (pointmul of Alg. 5):
+ * sc[j] = sa[j] * sb[j] for j < n.  sc may equal sa or sb. */
+int gf2x_pointmul_dev(gf2x_ctx *ctx, const void *sa, const void *sb, void *sc, uint64_t n, void *stream);
+
+/* Inverse transform (iFFT_LCH, iBasisCvt, changeRepr back, InterleavedCombine):
+ * spec holds the values at all 2^log2n points of a polynomial
+ * F(x) = sum_k F_k x^k of degree < 2^log2n with coefficients in TGF(2^128); the
+ * call writes ceil(nc_bits/64) words of sum_k Psi(F_k) x^(64k), truncated to
+ * nc_bits bits, where Psi is the inverse of the changeRepr map above (defined
+ * on all of TGF(2^128), giving polynomials of degree < 128).  spec is
+ * overwritten (used as scratch). */
+int gf2x_inverse_dev(gf2x_ctx *ctx, void *spec, int log2n, uint64_t *c, uint64_t nc_bits, void *stream);
+
+/* BasisCvt (Alg. 3) of 2^log2n 64-bit words in place: the words become the
+ * coefficients g_k of the same polynomial in the novel basis X_k (Sec. 2.3.1,
+ * Def. of X_k); inverse != 0 applies iBasisCvt.  The conversion only XORs
+ * whole words, so it acts on each of the 64 bit positions independently. */
+int gf2x_basiscvt_dev(gf2x_ctx *ctx, uint64_t *words, int log2n, int inverse, void *stream);
+
+/* One job of a batch: DEVICE pointers, same conventions as gf2x_mul_dev. */
+typedef struct {
+    const uint64_t *a;
+    uint64_t na_bits;
+    const uint64_t *b;
+    uint64_t nb_bits;
+    uint64_t *c;
+} gf2x_job;
+
+/* Independent products of uneven sizes, enqueued on `stream`.  `jobs` is HOST
+ * memory and may be reused as soon as the call returns.  Each job's result is
+ * bit-identical to gf2x_mul_dev on the same operands. */
+int gf2x_mul_batch(gf2x_ctx *ctx, const gf2x_job *jobs, size_t njobs, void *stream);
+
+/* Name of a status code. */
+const char *gf2x_strerror(int status);
+
+/* Message of the last failure on ctx ("" if none); valid until the next call. */
+const char *gf2x_last_error(gf2x_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GF2X_AFFT_H */

@@ -1,2 +1,205 @@
-"""MI355X additive-FFT multiplier for long binary polynomials (placeholder; the
-binding is added with the HIP library)."""
+"""MI355X (gfx950) multiplier for long binary polynomials: the additive FFT over
+a tower field (Chen, Cheng, Kuo, Li, Yang, arXiv:1708.09746, Alg. 5).
+
+This module only marshals arguments to the C ABI of ``libgf2x_afft.so``
+(declared in ``include/gf2x_afft.h``); every step of the product runs in the
+library's HIP kernels.  PyTorch supplies device memory and streams.  Polynomials
+are 1-D int64/uint64 tensors of little-endian 64-bit words; spectra are int64
+tensors of shape (N, 2) (16-byte TGF(2^128) elements).
+
+If the library is missing, every call raises: there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libgf2x_afft.so")
+HEADER_PATH = os.path.join(os.path.dirname(_HERE), "include", "gf2x_afft.h")
+
+GF2X_OK, GF2X_EINVAL, GF2X_ERANGE, GF2X_ENOMEM, GF2X_EDEVICE = 0, -1, -2, -3, -4
+
+_lib = None
+
+
+class Gf2xError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{msg} (status {code})")
+        self.code = code
+
+
+class Job(ctypes.Structure):
+    _fields_ = [("a", ctypes.c_void_p), ("na_bits", ctypes.c_uint64), ("b", ctypes.c_void_p),
+                ("nb_bits", ctypes.c_uint64), ("c", ctypes.c_void_p)]
+
+
+def lib():
+    """The loaded C library (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, u64, i32, sz = ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int, ctypes.c_size_t
+        sig = {
+            "gf2x_ctx_create": (i32, [ctypes.POINTER(vp), i32]),
+            "gf2x_ctx_destroy": (None, [vp]),
+            "gf2x_out_words": (sz, [u64, u64]),
+            "gf2x_fft_log2": (i32, [u64, u64]),
+            "gf2x_workspace_bytes": (sz, [u64, u64]),
+            "gf2x_mul": (i32, [vp, u64, vp, u64, vp]),
+            "gf2x_mul_dev": (i32, [vp, vp, u64, vp, u64, vp, vp]),
+            "gf2x_forward_dev": (i32, [vp, vp, u64, i32, vp, vp]),
+            "gf2x_pointmul_dev": (i32, [vp, vp, vp, vp, u64, vp]),
+            "gf2x_inverse_dev": (i32, [vp, vp, i32, vp, u64, vp]),
+            "gf2x_basiscvt_dev": (i32, [vp, vp, i32, i32, vp]),
+            "gf2x_mul_batch": (i32, [vp, ctypes.POINTER(Job), sz, vp]),
+            "gf2x_strerror": (ctypes.c_char_p, [i32]),
+            "gf2x_last_error": (ctypes.c_char_p, [vp]),
+        }
+        for name, (res, args) in sig.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def header_functions() -> list[str]:
+    """Names of the functions declared in include/gf2x_afft.h."""
+    with open(HEADER_PATH) as f:
+        text = f.read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(gf2x_[a-z0-9_]+)\s*\(", text)))
+
+
+def out_words(na_bits: int, nb_bits: int) -> int:
+    return int(lib().gf2x_out_words(na_bits, nb_bits))
+
+
+def fft_log2(na_bits: int, nb_bits: int) -> int:
+    return int(lib().gf2x_fft_log2(na_bits, nb_bits))
+
+
+def workspace_bytes(na_bits: int, nb_bits: int) -> int:
+    return int(lib().gf2x_workspace_bytes(na_bits, nb_bits))
+
+
+def strerror(code: int) -> str:
+    return lib().gf2x_strerror(code).decode()
+
+
+def _stream_handle(stream):
+    import torch
+
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(int(stream.cuda_stream))
+
+
+def _ptr(t):
+    return ctypes.c_void_p(int(t.data_ptr())) if t is not None else ctypes.c_void_p(0)
+
+
+class Context:
+    """A library context on one HIP device (tables and workspace)."""
+
+    def __init__(self, device: int = 0):
+        h = ctypes.c_void_p()
+        rc = lib().gf2x_ctx_create(ctypes.byref(h), int(device))
+        if rc != GF2X_OK:
+            raise Gf2xError(rc, f"gf2x_ctx_create({device}): {strerror(rc)}")
+        self._h = h
+        self.device = device
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().gf2x_ctx_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, rc: int, what: str):
+        if rc != GF2X_OK:
+            msg = lib().gf2x_last_error(self._h).decode()
+            raise Gf2xError(rc, f"{what}: {strerror(rc)}: {msg}")
+
+    @property
+    def handle(self):
+        return self._h
+
+    # ---- products
+    def mul_into(self, a, na_bits: int, b, nb_bits: int, c, stream=None):
+        rc = lib().gf2x_mul_dev(self._h, _ptr(a), na_bits, _ptr(b), nb_bits, _ptr(c), _stream_handle(stream))
+        self._check(rc, "gf2x_mul_dev")
+        return c
+
+    def mul(self, a, na_bits: int, b, nb_bits: int, stream=None):
+        import torch
+
+        ow = out_words(na_bits, nb_bits)
+        c = torch.empty(max(ow, 1), dtype=torch.int64, device=a.device)[:ow]
+        return self.mul_into(a, na_bits, b, nb_bits, c, stream)
+
+    def mul_batch(self, jobs, stream=None):
+        """jobs: list of (a, na_bits, b, nb_bits, c) with device tensors."""
+        arr = (Job * max(len(jobs), 1))()
+        for i, (a, na, b, nb, c) in enumerate(jobs):
+            arr[i] = Job(int(a.data_ptr()), na, int(b.data_ptr()), nb, int(c.data_ptr()))
+        rc = lib().gf2x_mul_batch(self._h, arr, len(jobs), _stream_handle(stream))
+        self._check(rc, "gf2x_mul_batch")
+
+    # ---- stages
+    def forward(self, a, na_bits: int, log2n: int, spec=None, stream=None):
+        import torch
+
+        if spec is None:
+            spec = torch.empty((1 << log2n, 2), dtype=torch.int64, device=a.device)
+        rc = lib().gf2x_forward_dev(self._h, _ptr(a), na_bits, log2n, _ptr(spec), _stream_handle(stream))
+        self._check(rc, "gf2x_forward_dev")
+        return spec
+
+    def pointmul(self, sa, sb, sc=None, stream=None):
+        import torch
+
+        if sc is None:
+            sc = torch.empty_like(sa)
+        rc = lib().gf2x_pointmul_dev(self._h, _ptr(sa), _ptr(sb), _ptr(sc), sa.shape[0], _stream_handle(stream))
+        self._check(rc, "gf2x_pointmul_dev")
+        return sc
+
+    def inverse(self, spec, log2n: int, nc_bits: int, c=None, stream=None):
+        import torch
+
+        if c is None:
+            nw = (nc_bits + 63) // 64
+            c = torch.empty(max(nw, 1), dtype=torch.int64, device=spec.device)[:nw]
+        rc = lib().gf2x_inverse_dev(self._h, _ptr(spec), log2n, _ptr(c), nc_bits, _stream_handle(stream))
+        self._check(rc, "gf2x_inverse_dev")
+        return c
+
+    def basiscvt(self, words, log2n: int, inverse: bool = False, stream=None):
+        rc = lib().gf2x_basiscvt_dev(self._h, _ptr(words), log2n, 1 if inverse else 0, _stream_handle(stream))
+        self._check(rc, "gf2x_basiscvt_dev")
+        return words
+
+
+def mul_host(a, na_bits: int, b, nb_bits: int):
+    """c = a * b for numpy uint64 word arrays through the blocking host-pointer call."""
+    import numpy as np
+
+    a = np.ascontiguousarray(a, dtype=np.uint64)
+    b = np.ascontiguousarray(b, dtype=np.uint64)
+    ow = out_words(na_bits, nb_bits)
+    c = np.zeros(max(ow, 1), dtype=np.uint64)
+    rc = lib().gf2x_mul(a.ctypes.data_as(ctypes.c_void_p), na_bits, b.ctypes.data_as(ctypes.c_void_p), nb_bits,
+                        c.ctypes.data_as(ctypes.c_void_p))
+    if rc != GF2X_OK:
+        raise Gf2xError(rc, f"gf2x_mul: {strerror(rc)}")
+    return c[:ow]

@@ -1,0 +1,195 @@
+// Device arithmetic and per-tile kernel bodies of the additive-FFT multiplier.
+//
+// Every kernel body is written as phases separated by AFFT_SYNC(); inside a
+// phase, work items are visited by a strided loop (tid, tid + nt, ...).  On the
+// GPU tid/nt are the thread index and block size; the same body also runs on
+// the host with tid = 0, nt = 1 (a sequential emulation used for debugging).
+//
+// Field elements: TGF(2^128) elements are uint4 (x = bits 0..31, ..., w = bits
+// 96..127).  Word c of an element is its component in TGF(2^32) along the basis
+// element {1, x6, x7, x6 x7}[c]; multiplying by a subfield element acts on each
+// word independently (Prop. 2).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#if defined(__HIP_DEVICE_COMPILE__)
+#define AFFT_SYNC() __syncthreads()
+#else
+#define AFFT_SYNC() \
+    do {            \
+    } while (0)
+#endif
+#define AFFT_HD __host__ __device__ __forceinline__
+
+namespace gf2x {
+
+constexpr int kMaxBcLayers = 96;
+
+struct BcLayer {
+    uint32_t log_d;  // D = 2^log_d units
+    uint32_t log_k;  // k = 2^log_k units
+    uint32_t log_u;  // unit = 2^log_u elements
+    uint32_t pad;
+};
+
+struct BcLayerList {
+    int n;
+    BcLayer l[kMaxBcLayers];
+};
+
+// ------------------------------------------------------------ GF(256) table
+// mt[(x << 8) | y] = x * y in GF(256) = TGF(2^8), tower basis.
+
+AFFT_HD uint32_t m8(const uint8_t* mt, uint32_t x, uint32_t y) { return mt[(x << 8) | y]; }
+
+// ----------------------------------------- multiplication by a subfield scalar
+// For lambda in TGF(2^32) let w_k = lambda * v_{8k} (k = 0..3; v_8 = x4,
+// v_16 = x5, v_24 = x4 x5).  A word a = sum_k a_k v_{8k} with bytes a_k in
+// GF(256) gives a * lambda = sum_k a_k w_k, and a_k w_k is the GF(256) scalar a_k
+// times each byte of w_k.  So byte r of the product is XOR_k a_k * byte_r(w_k).
+// (w_0, w_1, w_2, w_3) is stored as a uint4 "mu-set".
+
+// e * x4 for e in TGF(2^16) = GF(256)[x4]: e0 + e1 x4 -> e1 c16 + (e0 + e1) x4,
+// with c16 = x1 x2 x3 = 0x80.
+AFFT_HD uint32_t mulx4_16(const uint8_t* mt, uint32_t e) {
+    uint32_t e0 = e & 255u, e1 = (e >> 8) & 255u;
+    return m8(mt, 0x80u, e1) | ((e0 ^ e1) << 8);
+}
+AFFT_HD uint32_t mulx4_32(const uint8_t* mt, uint32_t w) {
+    return mulx4_16(mt, w & 0xffffu) | (mulx4_16(mt, w >> 16) << 16);
+}
+// e * c32 for e in TGF(2^16), c32 = x1 x2 x3 x4 = 0x8000 = c16 * x4
+AFFT_HD uint32_t mulc32(const uint8_t* mt, uint32_t e) {
+    uint32_t t = mulx4_16(mt, e);
+    return m8(mt, 0x80u, t & 255u) | (m8(mt, 0x80u, t >> 8) << 8);
+}
+// w * x5 for w in TGF(2^32) = TGF(2^16)[x5]: l0 + l1 x5 -> l1 c32 + (l0 + l1) x5
+AFFT_HD uint32_t mulx5(const uint8_t* mt, uint32_t w) {
+    uint32_t l0 = w & 0xffffu, l1 = w >> 16;
+    return mulc32(mt, l1) | ((l0 ^ l1) << 16);
+}
+
+AFFT_HD uint4 make_mu(const uint8_t* mt, uint32_t lam) {
+    uint4 m;
+    m.x = lam;
+    m.y = mulx4_32(mt, lam);
+    m.z = mulx5(mt, lam);
+    m.w = mulx5(mt, m.y);
+    return m;
+}
+
+// a * lambda, lambda arbitrary in TGF(2^32): 16 table lookups
+AFFT_HD uint32_t mul_mu32(const uint8_t* mt, const uint4& m, uint32_t a) {
+    uint32_t a0 = a & 255u, a1 = (a >> 8) & 255u, a2 = (a >> 16) & 255u, a3 = a >> 24;
+    uint32_t out = 0;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        uint32_t sh = 8u * r;
+        uint32_t b = m8(mt, (m.x >> sh) & 255u, a0) ^ m8(mt, (m.y >> sh) & 255u, a1) ^
+                     m8(mt, (m.z >> sh) & 255u, a2) ^ m8(mt, (m.w >> sh) & 255u, a3);
+        out |= b << sh;
+    }
+    return out;
+}
+// lambda in TGF(2^16): the two 16-bit halves of a are multiplied separately
+// by the 2x2 GF(256) matrix (w_0, w_1): 8 lookups
+AFFT_HD uint32_t mul_mu16(const uint8_t* mt, const uint4& m, uint32_t a) {
+    uint32_t p0 = m.x & 255u, p1 = (m.x >> 8) & 255u, q0 = m.y & 255u, q1 = (m.y >> 8) & 255u;
+    uint32_t a0 = a & 255u, a1 = (a >> 8) & 255u, a2 = (a >> 16) & 255u, a3 = a >> 24;
+    uint32_t r0 = m8(mt, p0, a0) ^ m8(mt, q0, a1);
+    uint32_t r1 = m8(mt, p1, a0) ^ m8(mt, q1, a1);
+    uint32_t r2 = m8(mt, p0, a2) ^ m8(mt, q0, a3);
+    uint32_t r3 = m8(mt, p1, a2) ^ m8(mt, q1, a3);
+    return r0 | (r1 << 8) | (r2 << 16) | (r3 << 24);
+}
+// lambda in GF(256): bytewise, 4 lookups
+AFFT_HD uint32_t mul_mu8(const uint8_t* mt, uint32_t lam, uint32_t a) {
+    return m8(mt, lam, a & 255u) | (m8(mt, lam, (a >> 8) & 255u) << 8) |
+           (m8(mt, lam, (a >> 16) & 255u) << 16) | (m8(mt, lam, a >> 24) << 24);
+}
+
+// v * lambda for v in TGF(2^128): each word separately (Prop. 2).
+// mode 0: lambda in GF(256), 1: TGF(2^16), 2: TGF(2^32)
+AFFT_HD uint4 mul_sub(const uint8_t* mt, const uint4& m, const uint4& v, int mode) {
+    uint4 r;
+    if (mode == 0) {
+        r.x = mul_mu8(mt, m.x, v.x);
+        r.y = mul_mu8(mt, m.x, v.y);
+        r.z = mul_mu8(mt, m.x, v.z);
+        r.w = mul_mu8(mt, m.x, v.w);
+    } else if (mode == 1) {
+        r.x = mul_mu16(mt, m, v.x);
+        r.y = mul_mu16(mt, m, v.y);
+        r.z = mul_mu16(mt, m, v.z);
+        r.w = mul_mu16(mt, m, v.w);
+    } else {
+        r.x = mul_mu32(mt, m, v.x);
+        r.y = mul_mu32(mt, m, v.y);
+        r.z = mul_mu32(mt, m, v.z);
+        r.w = mul_mu32(mt, m, v.w);
+    }
+    return r;
+}
+
+AFFT_HD uint4 xor4(const uint4& a, const uint4& b) {
+    uint4 r;
+    r.x = a.x ^ b.x;
+    r.y = a.y ^ b.y;
+    r.z = a.z ^ b.z;
+    r.w = a.w ^ b.w;
+    return r;
+}
+
+// ------------------------------------------------- generic tower product
+// Karatsuba form of the defining relation, down to GF(256):
+//   t = a1 b1, lo = a0 b0 + c_W t, hi = (a0 + a1)(b0 + b1) + a0 b0.
+// c_W (the product of the generators below the top one) satisfies
+// c_{2W} = x_{log2 W} c_W, so e * c_{2W} = (e * x) * c_W with
+// (e0 + e1 x) x = e1 c_W + (e0 + e1) x:  mulc_{2W}(e) = (c_W c_W e1, c_W (e0 + e1)).
+
+AFFT_HD uint32_t mulc64(const uint8_t* mt, uint32_t e) {  // e in TGF(2^32), times c64 = 0x80000000
+    uint32_t e0 = e & 0xffffu, e1 = e >> 16;
+    return mulc32(mt, mulc32(mt, e1)) | (mulc32(mt, e0 ^ e1) << 16);
+}
+AFFT_HD uint64_t mulc128(const uint8_t* mt, uint64_t e) {  // e in TGF(2^64), times c128 = 1 << 63
+    uint32_t e0 = (uint32_t)e, e1 = (uint32_t)(e >> 32);
+    return (uint64_t)mulc64(mt, mulc64(mt, e1)) | ((uint64_t)mulc64(mt, e0 ^ e1) << 32);
+}
+
+AFFT_HD uint32_t gm16(const uint8_t* mt, uint32_t a, uint32_t b) {
+    uint32_t a0 = a & 255u, a1 = a >> 8, b0 = b & 255u, b1 = b >> 8;
+    uint32_t t = m8(mt, a1, b1), p0 = m8(mt, a0, b0), p1 = m8(mt, a0 ^ a1, b0 ^ b1);
+    return (p0 ^ m8(mt, 0x80u, t)) | ((p1 ^ p0) << 8);
+}
+AFFT_HD uint32_t gm32(const uint8_t* mt, uint32_t a, uint32_t b) {
+    uint32_t a0 = a & 0xffffu, a1 = a >> 16, b0 = b & 0xffffu, b1 = b >> 16;
+    uint32_t t = gm16(mt, a1, b1), p0 = gm16(mt, a0, b0), p1 = gm16(mt, a0 ^ a1, b0 ^ b1);
+    return (p0 ^ mulc32(mt, t)) | ((p1 ^ p0) << 16);
+}
+AFFT_HD uint64_t gm64(const uint8_t* mt, uint64_t a, uint64_t b) {
+    uint32_t a0 = (uint32_t)a, a1 = (uint32_t)(a >> 32), b0 = (uint32_t)b, b1 = (uint32_t)(b >> 32);
+    uint32_t t = gm32(mt, a1, b1), p0 = gm32(mt, a0, b0), p1 = gm32(mt, a0 ^ a1, b0 ^ b1);
+    return (uint64_t)(p0 ^ mulc64(mt, t)) | ((uint64_t)(p1 ^ p0) << 32);
+}
+AFFT_HD uint4 gm128(const uint8_t* mt, const uint4& a, const uint4& b) {
+    uint64_t a0 = a.x | ((uint64_t)a.y << 32), a1 = a.z | ((uint64_t)a.w << 32);
+    uint64_t b0 = b.x | ((uint64_t)b.y << 32), b1 = b.z | ((uint64_t)b.w << 32);
+    uint64_t t = gm64(mt, a1, b1), p0 = gm64(mt, a0, b0), p1 = gm64(mt, a0 ^ a1, b0 ^ b1);
+    uint64_t lo = p0 ^ mulc128(mt, t), hi = p1 ^ p0;
+    uint4 r;
+    r.x = (uint32_t)lo;
+    r.y = (uint32_t)(lo >> 32);
+    r.z = (uint32_t)hi;
+    r.w = (uint32_t)(hi >> 32);
+    return r;
+}
+
+// ------------------------------------------------------- table loaders
+
+template <typename W>
+AFFT_HD void copy_words(int tid, int nt, W* dst, const W* src, int n) {
+    for (int i = tid; i < n; i += nt) dst[i] = src[i];
+}
+
+}  // namespace gf2x

@@ -1,0 +1,265 @@
+// Planning: sizes of a product and the op list that computes it (Alg. 5).
+#pragma once
+#include <cstdint>
+#include <vector>
+
+#include "afft_ops.hpp"
+
+namespace gf2x {
+
+enum class OpKind : int { Pack, BcTile, BcLayer, Fft, Pmul, Psi };
+
+struct Op {
+    OpKind kind;
+    PackOp pack;
+    BcTileOp bct;
+    BcLayerOp bcl;
+    FftPass fft;
+    PmulOp pmul;
+    PsiOp psi;
+};
+
+inline int ceil_log2(uint64_t n) {
+    int l = 0;
+    while ((1ull << l) < n) ++l;
+    return l;
+}
+
+// Sizes of one product (readings: operands converted at their own power-of-two
+// length; N = max(2, 2^ceil(log2(n_a + n_b - 1))) evaluation points).
+struct Sizes {
+    uint64_t na_bits = 0, nb_bits = 0;
+    uint64_t n_a = 0, n_b = 0;    // words
+    int m_a = 0, m_b = 0, m = 0;  // log2 of n'_a, n'_b, N
+    uint64_t out_words = 0;       // ceil((na + nb - 1) / 64)
+    uint64_t nc_bits = 0;         // na + nb - 1
+};
+
+inline Sizes make_sizes(uint64_t na_bits, uint64_t nb_bits) {
+    Sizes s;
+    s.na_bits = na_bits;
+    s.nb_bits = nb_bits;
+    if (!na_bits || !nb_bits) return s;
+    s.n_a = (na_bits + 63) / 64;
+    s.n_b = (nb_bits + 63) / 64;
+    s.m_a = ceil_log2(s.n_a);
+    s.m_b = ceil_log2(s.n_b);
+    s.m = ceil_log2(s.n_a + s.n_b - 1);
+    if (s.m < 1) s.m = 1;
+    s.nc_bits = na_bits + nb_bits - 1;
+    s.out_words = (s.nc_bits + 63) / 64;
+    return s;
+}
+
+// Flat layer list of BasisCvt on 2^m units of 2^log_u elements (Alg. 3 with
+// Alg. 2 unrolled into in-place divisions by x^D + x^k): with K the largest
+// power of two below m, VarSubs divides by y^(2^j) = x^(2^(K+j)) + x^(2^j) for
+// j = m-K-1 .. 0 on every aligned block; then the series in y is converted
+// with units of 2^K elements, and finally every block of 2^K.
+inline void bc_layer_list(int m, int log_u, std::vector<BcLayer>& out) {
+    if (m <= 1) return;
+    int K = 1;
+    while (2 * K < m) K *= 2;
+    for (int j = m - K - 1; j >= 0; --j) out.push_back(BcLayer{(uint32_t)(K + j), (uint32_t)j, (uint32_t)log_u, 0});
+    bc_layer_list(m - K, log_u + K, out);
+    bc_layer_list(K, log_u, out);
+}
+
+inline uint64_t bc_span_log(const BcLayer& L) { return L.log_d + 1 + L.log_u; }
+
+// Emit BasisCvt (or its inverse) of 2^m elements at `data`.
+inline void emit_bc(std::vector<Op>& ops, void* data, int wide, int m, int inverse) {
+    std::vector<BcLayer> L;
+    bc_layer_list(m, 0, L);
+    if (L.empty()) return;
+    const int tile_log = std::min(m, wide ? kBcTileLog128 : kBcTileLog64);
+    const uint64_t n = 1ull << m;
+    // group maximal runs of layers whose blocks fit a tile
+    std::vector<std::pair<int, int>> runs;  // [begin, end) of tile runs; begin == end marks a global layer
+    std::vector<int> kind;                  // 1 = tile run, 0 = single global layer
+    size_t i = 0;
+    while (i < L.size()) {
+        if ((int)bc_span_log(L[i]) <= tile_log) {
+            size_t j = i;
+            while (j < L.size() && (int)bc_span_log(L[j]) <= tile_log && j - i < (size_t)kMaxBcLayers) ++j;
+            runs.push_back({(int)i, (int)j});
+            kind.push_back(1);
+            i = j;
+        } else {
+            runs.push_back({(int)i, (int)i + 1});
+            kind.push_back(0);
+            ++i;
+        }
+    }
+    auto emit_run = [&](size_t r) {
+        Op op{};
+        if (kind[r]) {
+            op.kind = OpKind::BcTile;
+            op.bct.data = data;
+            op.bct.nelem = n;
+            op.bct.log_tile = (uint32_t)tile_log;
+            op.bct.wide = (uint32_t)wide;
+            op.bct.inverse = (uint32_t)inverse;
+            op.bct.layers.n = runs[r].second - runs[r].first;
+            for (int t = runs[r].first; t < runs[r].second; ++t) op.bct.layers.l[t - runs[r].first] = L[t];
+            ops.push_back(op);
+        } else {
+            for (int part = 0; part < 2; ++part) {
+                Op g{};
+                g.kind = OpKind::BcLayer;
+                g.bcl.data = data;
+                g.bcl.nelem = n;
+                g.bcl.wide = (uint32_t)wide;
+                g.bcl.which = (uint32_t)(inverse ? 1 - part : part);
+                g.bcl.layer = L[runs[r].first];
+                ops.push_back(g);
+            }
+        }
+    };
+    if (!inverse)
+        for (size_t r = 0; r < runs.size(); ++r) emit_run(r);
+    else
+        for (size_t r = runs.size(); r-- > 0;) emit_run(r);
+}
+
+// Layer ranges of the FFT passes: a contiguous bottom pass of up to 2^11
+// elements, and strided passes of up to 2^8 rows above it.
+inline std::vector<std::pair<int, int>> fft_pass_ranges(int M) {
+    std::vector<std::pair<int, int>> col;
+    int bottom = std::min(M, kFftTileLog);
+    int rem = M - bottom;
+    int ncol = (rem + kFftColRowsLog - 1) / kFftColRowsLog;
+    int lo = bottom;
+    for (int c = 0; c < ncol; ++c) {
+        int sz = rem / ncol + (c < rem % ncol ? 1 : 0);
+        col.push_back({lo, lo + sz});
+        lo += sz;
+    }
+    std::vector<std::pair<int, int>> r;
+    r.push_back({0, bottom});
+    for (auto& p : col) r.push_back(p);
+    return r;  // bottom first (inverse order); the forward FFT runs it reversed
+}
+
+inline uint32_t fft_log_tc(int lo, int hi) {
+    if (lo == 0) return 0;
+    return (uint32_t)std::min(lo, kFftTileLog - (hi - lo));
+}
+
+// Forward transform of one operand: `words` holds 2^M converted words; the
+// spectrum has 2^(M + log_cosets) elements.
+inline void emit_fft_forward(std::vector<Op>& ops, const uint64_t* words, uint4* spec, int M, int log_cosets) {
+    auto ranges = fft_pass_ranges(M);
+    for (size_t r = ranges.size(); r-- > 0;) {
+        Op op{};
+        op.kind = OpKind::Fft;
+        FftPass& A = op.fft;
+        A.phi_in = (r == ranges.size() - 1) ? 1u : 0u;
+        A.src = A.phi_in ? (const void*)words : (const void*)spec;
+        A.dst = spec;
+        A.log_m = (uint32_t)M;
+        A.lo = (uint32_t)ranges[r].first;
+        A.hi = (uint32_t)ranges[r].second;
+        A.log_tc = fft_log_tc(ranges[r].first, ranges[r].second);
+        A.log_cosets = (uint32_t)log_cosets;
+        A.inverse = 0;
+        A.log_total = (uint32_t)(M + log_cosets);
+        ops.push_back(op);
+    }
+}
+
+inline void emit_fft_inverse(std::vector<Op>& ops, uint4* spec, int m) {
+    auto ranges = fft_pass_ranges(m);
+    for (size_t r = 0; r < ranges.size(); ++r) {
+        if (ranges[r].first == ranges[r].second) continue;
+        Op op{};
+        op.kind = OpKind::Fft;
+        FftPass& A = op.fft;
+        A.src = spec;
+        A.dst = spec;
+        A.log_m = (uint32_t)m;
+        A.lo = (uint32_t)ranges[r].first;
+        A.hi = (uint32_t)ranges[r].second;
+        A.log_tc = fft_log_tc(ranges[r].first, ranges[r].second);
+        A.log_cosets = 0;
+        A.inverse = 1;
+        A.phi_in = 0;
+        A.log_total = (uint32_t)m;
+        ops.push_back(op);
+    }
+}
+
+inline void emit_pack(std::vector<Op>& ops, const uint64_t* src, uint64_t nbits, uint64_t* dst, uint64_t ndst) {
+    Op op{};
+    op.kind = OpKind::Pack;
+    op.pack = PackOp{src, nbits, dst, ndst};
+    ops.push_back(op);
+}
+
+inline void emit_pmul(std::vector<Op>& ops, const uint4* a, const uint4* b, uint4* c, uint64_t n) {
+    Op op{};
+    op.kind = OpKind::Pmul;
+    op.pmul = PmulOp{a, b, c, n};
+    ops.push_back(op);
+}
+
+inline void emit_psi(std::vector<Op>& ops, const uint4* spec, uint64_t nspec, uint64_t* out, uint64_t nbits) {
+    Op op{};
+    op.kind = OpKind::Psi;
+    op.psi = PsiOp{spec, nspec, out, (nbits + 63) / 64, nbits};
+    ops.push_back(op);
+}
+
+// Workspace of one product: converted words of a and b, then the two spectra.
+struct Workspace {
+    size_t off_wa, off_wb, off_sa, off_sb, bytes;
+};
+
+inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+inline Workspace workspace_for(const Sizes& s) {
+    Workspace w{};
+    size_t o = 0;
+    w.off_wa = o;
+    o = align256(o + (8ull << s.m_a));
+    w.off_wb = o;
+    o = align256(o + (8ull << s.m_b));
+    w.off_sa = o;
+    o = align256(o + (16ull << s.m));
+    w.off_sb = o;
+    o = align256(o + (16ull << s.m));
+    w.bytes = o;
+    return w;
+}
+
+// Forward transform of one operand into an N-point spectrum (Split, BasisCvt
+// on 64-bit words, changeRepr, FFT_LCH at 0).  `words` is scratch of 2^m_op words.
+inline void emit_forward(std::vector<Op>& ops, const uint64_t* src, uint64_t nbits, uint64_t* words, int m_op, uint4* spec,
+                         int m) {
+    emit_pack(ops, src, nbits, words, 1ull << m_op);
+    emit_bc(ops, words, 0, m_op, 0);
+    emit_fft_forward(ops, words, spec, m_op, m - m_op);
+}
+
+// Inverse transform of an N-point spectrum into nc_bits product bits
+// (iFFT_LCH, iBasisCvt, changeRepr back, InterleavedCombine).
+inline void emit_inverse(std::vector<Op>& ops, uint4* spec, int m, uint64_t* out, uint64_t nc_bits) {
+    emit_fft_inverse(ops, spec, m);
+    emit_bc(ops, spec, 1, m, 1);
+    emit_psi(ops, spec, 1ull << m, out, nc_bits);
+}
+
+// The whole product c = a * b with the workspace at `ws`.
+inline void plan_mul(std::vector<Op>& ops, const Sizes& s, const uint64_t* a, const uint64_t* b, uint64_t* c, char* ws) {
+    Workspace w = workspace_for(s);
+    uint64_t* wa = (uint64_t*)(ws + w.off_wa);
+    uint64_t* wb = (uint64_t*)(ws + w.off_wb);
+    uint4* sa = (uint4*)(ws + w.off_sa);
+    uint4* sb = (uint4*)(ws + w.off_sb);
+    emit_forward(ops, a, s.na_bits, wa, s.m_a, sa, s.m);
+    emit_forward(ops, b, s.nb_bits, wb, s.m_b, sb, s.m);
+    emit_pmul(ops, sa, sb, sb, 1ull << s.m);
+    emit_inverse(ops, sb, s.m, c, s.nc_bits);
+}
+
+}  // namespace gf2x

@@ -1,0 +1,49 @@
+"""The C-ABI library loads on the CPU and exports every function declared in
+include/gf2x_afft.h; the size helpers follow the documented conventions.  No
+GPU work is launched here."""
+import ctypes
+
+import pytest
+
+import paper_1708_09746_amd as P
+
+
+def test_library_exports_every_declared_function():
+    L = ctypes.CDLL(P.LIB_PATH)
+    names = P.header_functions()
+    assert len(names) >= 14
+    for n in names:
+        assert hasattr(L, n), n
+
+
+def test_binding_names_match_header():
+    P.lib()  # binds signatures for all of them
+    for n in P.header_functions():
+        assert getattr(P.lib(), n).argtypes is not None, n
+
+
+@pytest.mark.parametrize("na,nb,ow", [(0, 5, 0), (5, 0, 0), (1, 1, 1), (64, 1, 1), (64, 2, 2), (65, 64, 2),
+                                      (64, 64, 2), (1 << 16, 1 << 16, 2048), (1 << 28, 1 << 28, 1 << 23)])
+def test_out_words(na, nb, ow):
+    assert P.out_words(na, nb) == ow
+
+
+@pytest.mark.parametrize("na,nb,m", [(1, 1, 1), (64, 64, 1), (65, 64, 1), (65, 65, 2), (64 * 3, 64 * 2, 2), (64 * 3, 64 * 3, 3),
+                                     (1 << 16, 1 << 16, 11), (1 << 20, 1 << 20, 15), (1 << 28, 1 << 28, 23),
+                                     (1 << 29, 1 << 29, 24), (0, 7, -1)])
+def test_fft_size(na, nb, m):
+    assert P.fft_log2(na, nb) == m
+
+
+def test_workspace_grows_with_size():
+    small = P.workspace_bytes(1 << 16, 1 << 16)
+    big = P.workspace_bytes(1 << 28, 1 << 28)
+    # two spectra of N = 2^23 elements (16 B) plus two 2^22-word operands
+    assert big >= 2 * 16 * (1 << 23) + 2 * 8 * (1 << 22)
+    assert 0 < small < big
+
+
+def test_status_names():
+    for code in (0, -1, -2, -3, -4):
+        assert P.strerror(code)
+    assert P.strerror(-99) == "unknown status"
