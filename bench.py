@@ -1,0 +1,217 @@
+"""Benchmark: one 2^28 x 2^28-bit GF(2)[x] product per step on one MI355X.
+
+python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c3a|c3b|c2|c1]
+
+Prints ONE JSON line.  `value` is milliseconds per product (lower is better)
+with both operands already resident in HBM; the whole hot path (Split,
+BasisCvt, changeRepr, FFT, pointmul, iFFT, iBasisCvt, changeRepr back,
+InterleavedCombine) runs inside every step.  The `roofline` object covers the
+kernel with the largest share of the product's time, timed with HIP events on
+the library's launch stream during the timed region; `cpu_baseline` times the
+oracle (plain CPU Karatsuba) on a bounded sample of the same workload.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "ms per 2^28-bit GF(2)[x] product (bit-exact); batched products/s; p99 ms"
+HBM_PEAK_GBS = 8000.0  # MI355X published HBM3E bandwidth
+PAPER_MS = {"c3a": 2302.0, "c3b": 4812.0}  # Tab. 2, TGF(2^128) row, Haswell (context)
+WORKLOADS = {
+    "c1": (1 << 16, "2^16 x 2^16-bit product"),
+    "c2": (1 << 20, "2^20 x 2^20-bit product"),
+    "c3a": (1 << 28, "2^28 x 2^28-bit product"),
+    "c3b": (1 << 29, "2^29 x 2^29-bit product"),
+}
+COUNTERS = os.path.join(ROOT, "profiles", "k_fft_c3a_counters.txt")
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def source_digest():
+    import hashlib
+
+    h = hashlib.sha256()
+    cs = os.path.join(ROOT, "paper_1708_09746_amd", "csrc")
+    for f in sorted(os.listdir(cs)):
+        with open(os.path.join(cs, f), "rb") as fh:
+            h.update(f.encode() + fh.read())
+    return h.hexdigest()[:16]
+
+
+def counter_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary, if it was taken on the current kernel sources; else None."""
+    if not os.path.exists(COUNTERS):
+        return None
+    kv = {}
+    with open(COUNTERS) as f:
+        for line in f:
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                kv[k.strip()] = v.strip()
+    if kv.get("kernel") != kernel or kv.get("source_digest") != source_digest():
+        return None
+    try:
+        return float(kv["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def cpu_baseline(na, seeds, sample_log2=25):
+    """The oracle on the low 2^sample_log2 bits of each operand, scaled by
+    3^(log2(na) - sample_log2) (Karatsuba's cost ratio) to one full product."""
+    import oracle
+    from paper_1708_09746_amd import inputs
+
+    threads = max(1, min(16, os.cpu_count() or 1))
+    n = min(na, 1 << sample_log2)
+    a = inputs.random_poly(seeds[0], na)[: n // 64]
+    b = inputs.random_poly(seeds[1], na)[: n // 64]
+    t0 = time.perf_counter()
+    oracle.mul(a, n, b, n, threads=threads)
+    dt = time.perf_counter() - t0
+    levels = (na.bit_length() - 1) - (n.bit_length() - 1)
+    est_ms = dt * 1e3 * (3 ** levels)
+    return {
+        "value": round(est_ms, 1),
+        "unit": "ms",
+        "cores": threads,
+        "kind": "oracle",
+        "sample": f"oracle Karatsuba product of the low 2^{n.bit_length() - 1} bits of each operand "
+                  f"({dt:.2f} s wall on {threads} threads), scaled by 3^{levels} to one "
+                  f"2^{na.bit_length() - 1}-bit product",
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="c3a", choices=sorted(WORKLOADS))
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-mib", type=int, default=0,
+                    help="first run a plain device copy of this many MiB (counter calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build measures one GPU; --gpus {args.gpus} is not supported "
+              "(independent products shard across GPUs without communication)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_1708_09746_amd as P
+    from paper_1708_09746_amd import inputs
+
+    n, desc = WORKLOADS[args.workload]
+    seeds = inputs.SEEDS[args.workload]
+    log(f"bench: workload {args.workload} ({desc}), steps {args.steps}, warmup {args.warmup}")
+    if args.copy_mib:
+        src = torch.ones(args.copy_mib << 17, dtype=torch.int64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"bench: calibration copy of {args.copy_mib} MiB done (3 dispatches)")
+        del src, dst
+    ctx = P.Context(0)
+    a = torch.from_numpy(inputs.random_poly(seeds[0], n).view(np.int64).copy()).cuda()
+    b = torch.from_numpy(inputs.random_poly(seeds[1], n).view(np.int64).copy()).cuda()
+    c = torch.empty(P.out_words(n, n), dtype=torch.int64, device="cuda")
+    stream = torch.cuda.current_stream()
+
+    # warmup, traced for every kernel kind: per-stage times and the dominant kernel
+    ctx.trace_begin(0x3F)
+    for _ in range(args.warmup):
+        ctx.mul_into(a, n, b, n, c, stream)
+    torch.cuda.synchronize()
+    recs = ctx.trace_end()
+    per_kernel = {}
+    for r in recs:
+        per_kernel[r["kernel"]] = per_kernel.get(r["kernel"], 0.0) + r["ms"]
+    w = max(args.warmup, 1)
+    stages = {k: round(v / w, 4) for k, v in sorted(per_kernel.items(), key=lambda kv: -kv[1])}
+    dominant = max(per_kernel, key=per_kernel.get) if per_kernel else "k_fft"
+    kind_bit = 1 << P.KERNEL_OF_KIND.index(dominant)
+    log(f"bench: per-kernel ms per product (warmup, traced): {stages}")
+
+    # timed region: only the dominant kernel is bracketed by events
+    ctx.trace_begin(kind_bit)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        ctx.mul_into(a, n, b, n, c, stream)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    recs = ctx.trace_end()
+    ms = (t1 - t0) * 1e3 / args.steps
+
+    tot_ms = sum(r["ms"] for r in recs)
+    tot_bytes = sum(r["bytes_read"] + r["bytes_written"] for r in recs)
+    nl = max(len(recs), 1)
+    achieved = (tot_bytes / nl) / ((tot_ms / nl) * 1e-3) / 1e9 if tot_ms > 0 else 0.0
+    traffic = counter_traffic(dominant)
+    roofline = {
+        "bound": "hbm",
+        "achieved": round(achieved, 1),
+        "peak": HBM_PEAK_GBS,
+        "unit": "GB/s",
+        "frac": round(achieved / HBM_PEAK_GBS, 4),
+        "traffic": traffic,
+        "kernel": dominant,
+        "launches": len(recs),
+        "avg_launch_ms": round(tot_ms / nl, 5),
+        "alg_bytes_per_launch": int(tot_bytes / nl),
+    }
+
+    # bit-exactness spot check of the timed product (two words from the oracle)
+    import oracle
+
+    got = c.cpu().numpy().view(np.uint64)
+    an = a.cpu().numpy().view(np.uint64)
+    bn = b.cpu().numpy().view(np.uint64)
+    for k in (0, got.size // 3):
+        assert int(got[k]) == oracle.word(an, n, bn, n, k), f"word {k} differs from the oracle"
+
+    out = {
+        "metric": METRIC,
+        "value": round(ms, 4),
+        "unit": "ms",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms, 4),
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": round(ms / PAPER_MS[args.workload], 6) if args.workload in PAPER_MS else None,
+        "dtype": "u64",
+        "data": "synthetic",
+        "config": {
+            "workload": desc,
+            "na_bits": n,
+            "nb_bits": n,
+            "fft_points": 1 << P.fft_log2(n, n),
+            "field": "TGF(2^128), w = 64",
+            "seeds": [hex(s) for s in seeds],
+        },
+        "roofline": roofline,
+        "stages_ms": stages,
+    }
+    if not args.no_cpu_baseline:
+        log("bench: timing the oracle on a bounded sample")
+        out["cpu_baseline"] = cpu_baseline(n, seeds)
+    ctx.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

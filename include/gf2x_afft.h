@@ -130,6 +130,28 @@ typedef struct {
  * bit-identical to gf2x_mul_dev on the same operands. */
 int gf2x_mul_batch(gf2x_ctx *ctx, const gf2x_job *jobs, size_t njobs, void *stream);
 
+/* ---- tracing: per-kernel timing with HIP events (Sec. "Results" profiles the
+ * same stages per component).  While a mask is set, every launch of a kernel
+ * kind whose bit is in the mask is bracketed by two hipEvents recorded on the
+ * launch stream; gf2x_trace_read() waits for them and returns one record per
+ * launch.  Kinds (bit = 1 << kind): 0 pack, 1 BasisCvt tile, 2 BasisCvt global
+ * layer, 3 FFT pass, 4 pointmul, 5 changeRepr back + combine. */
+typedef struct {
+    int kind;            /* one of the kinds above */
+    uint64_t elements;   /* elements (words or 16-byte field elements) the launch covers */
+    uint64_t bytes_read; /* bytes the launch must read from memory (algorithmic) */
+    uint64_t bytes_written;
+    float ms;            /* hipEventElapsedTime between the two events */
+} gf2x_trace_rec;
+
+/* Start recording launches of the kinds in `kind_mask` (0 stops; records kept). */
+int gf2x_trace_begin(gf2x_ctx *ctx, uint32_t kind_mask);
+
+/* Wait for the recorded events and copy up to `max` records into `out` (host
+ * memory); returns the number of records available (may exceed max), or a
+ * negative status.  The records are cleared afterwards. */
+int64_t gf2x_trace_read(gf2x_ctx *ctx, gf2x_trace_rec *out, size_t max);
+
 /* Name of a status code. */
 const char *gf2x_strerror(int status);
 

@@ -30,6 +30,15 @@ class Gf2xError(RuntimeError):
         self.code = code
 
 
+class TraceRec(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int), ("elements", ctypes.c_uint64), ("bytes_read", ctypes.c_uint64),
+                ("bytes_written", ctypes.c_uint64), ("ms", ctypes.c_float)]
+
+
+KIND_NAMES = ["pack", "basiscvt_tile", "basiscvt_layer", "fft_pass", "pointmul", "psi_combine"]
+KERNEL_OF_KIND = ["k_pack", "k_bc_tile", "k_bc_layer", "k_fft", "k_pmul", "k_psi"]
+
+
 class Job(ctypes.Structure):
     _fields_ = [("a", ctypes.c_void_p), ("na_bits", ctypes.c_uint64), ("b", ctypes.c_void_p),
                 ("nb_bits", ctypes.c_uint64), ("c", ctypes.c_void_p)]
@@ -56,6 +65,8 @@ def lib():
             "gf2x_inverse_dev": (i32, [vp, vp, i32, vp, u64, vp]),
             "gf2x_basiscvt_dev": (i32, [vp, vp, i32, i32, vp]),
             "gf2x_mul_batch": (i32, [vp, ctypes.POINTER(Job), sz, vp]),
+            "gf2x_trace_begin": (i32, [vp, ctypes.c_uint32]),
+            "gf2x_trace_read": (ctypes.c_int64, [vp, ctypes.POINTER(TraceRec), sz]),
             "gf2x_strerror": (ctypes.c_char_p, [i32]),
             "gf2x_last_error": (ctypes.c_char_p, [vp]),
         }
@@ -154,6 +165,27 @@ class Context:
             arr[i] = Job(int(a.data_ptr()), na, int(b.data_ptr()), nb, int(c.data_ptr()))
         rc = lib().gf2x_mul_batch(self._h, arr, len(jobs), _stream_handle(stream))
         self._check(rc, "gf2x_mul_batch")
+
+    # ---- tracing
+    def trace_begin(self, kind_mask: int = 0x3F):
+        self._check(lib().gf2x_trace_begin(self._h, kind_mask), "gf2x_trace_begin")
+
+    def trace_end(self):
+        """Stop tracing and return the traced launches (see trace_collect)."""
+        recs = self.trace_collect()
+        lib().gf2x_trace_begin(self._h, 0)
+        return recs
+
+    def trace_collect(self):
+        """Wait for and return the traced launches so far (tracing continues)."""
+        n = 1 << 16
+        buf = (TraceRec * n)()
+        got = lib().gf2x_trace_read(self._h, buf, n)
+        if got < 0:
+            self._check(int(got), "gf2x_trace_read")
+        return [dict(kind=KIND_NAMES[r.kind], kernel=KERNEL_OF_KIND[r.kind], elements=r.elements,
+                     bytes_read=r.bytes_read, bytes_written=r.bytes_written, ms=r.ms)
+                for r in buf[:min(got, n)]]
 
     # ---- stages
     def forward(self, a, na_bits: int, log2n: int, spec=None, stream=None):

@@ -87,6 +87,13 @@ struct gf2x_ctx {
     size_t io_bytes = 0;
     hipStream_t own_stream = nullptr;
     std::string err;
+    // tracing
+    uint32_t trace_mask = 0;
+    struct Pending {
+        gf2x_trace_rec rec;
+        hipEvent_t start, stop;
+    };
+    std::vector<Pending> trace;
 };
 
 namespace {
@@ -150,9 +157,61 @@ unsigned grid_for(uint64_t tiles, uint64_t cap) {
     return (unsigned)std::max<uint64_t>(g, 1);
 }
 
+// Bytes a launch must move through memory, by its definition (each element it
+// covers is read once and written once), and the elements it covers.
+void op_traffic(const Op& op, gf2x_trace_rec& r) {
+    r.kind = (int)op.kind;
+    switch (op.kind) {
+        case OpKind::Pack:
+            r.elements = op.pack.ndst;
+            r.bytes_read = 8 * std::min<uint64_t>(op.pack.ndst, (op.pack.nbits + 63) / 64);
+            r.bytes_written = 8 * op.pack.ndst;
+            break;
+        case OpKind::BcTile:
+            r.elements = op.bct.nelem;
+            r.bytes_read = r.bytes_written = op.bct.nelem * (op.bct.wide ? 16 : 8);
+            break;
+        case OpKind::BcLayer: {
+            uint64_t half = op.bcl.nelem / 2, es = op.bcl.wide ? 16 : 8;
+            uint64_t D = 1ull << op.bcl.layer.log_d, k = 1ull << op.bcl.layer.log_k;
+            uint64_t part = op.bcl.which == 0 ? half / D * k : half / D * (D - k);
+            r.elements = part;
+            r.bytes_read = 2 * part * es;  // source and target
+            r.bytes_written = part * es;
+            break;
+        }
+        case OpKind::Fft: {
+            uint64_t n = 1ull << (op.fft.log_m + op.fft.log_cosets);
+            r.elements = n;
+            r.bytes_read = op.fft.phi_in ? 8 * n : 16 * n;
+            r.bytes_written = 16 * n;
+            break;
+        }
+        case OpKind::Pmul:
+            r.elements = op.pmul.n;
+            r.bytes_read = 32 * op.pmul.n;
+            r.bytes_written = 16 * op.pmul.n;
+            break;
+        case OpKind::Psi:
+            r.elements = op.psi.nwords;
+            r.bytes_read = 16 * std::min(op.psi.nwords, op.psi.nspec);
+            r.bytes_written = 8 * op.psi.nwords;
+            break;
+    }
+}
+
 int run_ops(gf2x_ctx* ctx, const std::vector<Op>& ops, hipStream_t st) {
     const uint64_t ncu = (uint64_t)ctx->ncu;
     for (const Op& op : ops) {
+        gf2x_ctx::Pending pend{};
+        const bool traced = (ctx->trace_mask >> (int)op.kind) & 1u;
+        if (traced) {
+            op_traffic(op, pend.rec);
+            hipError_t e = hipEventCreate(&pend.start);
+            if (e == hipSuccess) e = hipEventCreate(&pend.stop);
+            if (e == hipSuccess) e = hipEventRecord(pend.start, st);
+            if (e != hipSuccess) return hip_fail(ctx, e, "trace event");
+        }
         switch (op.kind) {
             case OpKind::Pack:
                 hipLaunchKernelGGL(k_pack, dim3(grid_for(pack_tiles(op.pack), 8 * ncu)), dim3(kThreads), 0, st, op.pack);
@@ -187,6 +246,11 @@ int run_ops(gf2x_ctx* ctx, const std::vector<Op>& ops, hipStream_t st) {
         }
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return hip_fail(ctx, e, "kernel launch");
+        if (traced) {
+            e = hipEventRecord(pend.stop, st);
+            if (e != hipSuccess) return hip_fail(ctx, e, "trace event");
+            ctx->trace.push_back(pend);
+        }
     }
     return GF2X_OK;
 }
@@ -290,6 +354,33 @@ void gf2x_ctx_destroy(gf2x_ctx* ctx) {
     if (ctx->io) (void)hipFree(ctx->io);
     if (ctx->own_stream) (void)hipStreamDestroy(ctx->own_stream);
     delete ctx;
+}
+
+int gf2x_trace_begin(gf2x_ctx* ctx, uint32_t kind_mask) {
+    if (check_ctx(ctx)) return GF2X_EINVAL;
+    ctx->trace_mask = kind_mask;
+    return GF2X_OK;
+}
+
+int64_t gf2x_trace_read(gf2x_ctx* ctx, gf2x_trace_rec* out, size_t max) {
+    if (check_ctx(ctx)) return GF2X_EINVAL;
+    if (max && !out) return GF2X_EINVAL;
+    DeviceGuard g(ctx->device);
+    int64_t n = (int64_t)ctx->trace.size();
+    int rc = GF2X_OK;
+    for (size_t i = 0; i < ctx->trace.size(); ++i) {
+        auto& p = ctx->trace[i];
+        hipError_t e = hipEventSynchronize(p.stop);
+        float ms = 0.f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, p.start, p.stop);
+        if (e != hipSuccess && rc == GF2X_OK) rc = hip_fail(ctx, e, "trace read");
+        p.rec.ms = ms;
+        if (i < max) out[i] = p.rec;
+        (void)hipEventDestroy(p.start);
+        (void)hipEventDestroy(p.stop);
+    }
+    ctx->trace.clear();
+    return rc ? rc : n;
 }
 
 int gf2x_mul_dev(gf2x_ctx* ctx, const uint64_t* a, uint64_t na_bits, const uint64_t* b, uint64_t nb_bits,
