@@ -135,7 +135,8 @@ int gf2x_mul_batch(gf2x_ctx *ctx, const gf2x_job *jobs, size_t njobs, void *stre
  * kind whose bit is in the mask is bracketed by two hipEvents recorded on the
  * launch stream; gf2x_trace_read() waits for them and returns one record per
  * launch.  Kinds (bit = 1 << kind): 0 pack, 1 BasisCvt tile, 2 BasisCvt global
- * layer, 3 FFT pass, 4 pointmul, 5 changeRepr back + combine. */
+ * layer, 3 FFT pass, 4 pointmul, 5 changeRepr back + combine, 6 BasisCvt
+ * VarSubs class pass. */
 typedef struct {
     int kind;            /* one of the kinds above */
     uint64_t elements;   /* elements (words or 16-byte field elements) the launch covers */

@@ -35,8 +35,8 @@ class TraceRec(ctypes.Structure):
                 ("bytes_written", ctypes.c_uint64), ("ms", ctypes.c_float)]
 
 
-KIND_NAMES = ["pack", "basiscvt_tile", "basiscvt_layer", "fft_pass", "pointmul", "psi_combine"]
-KERNEL_OF_KIND = ["k_pack", "k_bc_tile", "k_bc_layer", "k_fft", "k_pmul", "k_psi"]
+KIND_NAMES = ["pack", "basiscvt_tile", "basiscvt_layer", "fft_pass", "pointmul", "psi_combine", "basiscvt_class"]
+KERNEL_OF_KIND = ["k_pack", "k_bc_tile", "k_bc_layer", "k_fft", "k_pmul", "k_psi", "k_bc_class"]
 
 
 class Job(ctypes.Structure):
@@ -167,7 +167,7 @@ class Context:
         self._check(rc, "gf2x_mul_batch")
 
     # ---- tracing
-    def trace_begin(self, kind_mask: int = 0x3F):
+    def trace_begin(self, kind_mask: int = 0x7F):
         self._check(lib().gf2x_trace_begin(self._h, kind_mask), "gf2x_trace_begin")
 
     def trace_end(self):

@@ -34,6 +34,18 @@ __global__ __launch_bounds__(kThreads) void k_bc_tile(BcTileOp B) {
 }
 
 template <int WIDE>
+__global__ __launch_bounds__(kThreads) void k_bc_class(BcClassOp C) {
+    __shared__ uint4 lds[1 << kBcTileLog128];  // 64 KiB
+    const uint64_t nt = bc_class_tiles(C);
+    for (uint64_t t = blockIdx.x; t < nt; t += gridDim.x) {
+        if (WIDE)
+            bc_class_tile<uint4>(threadIdx.x, blockDim.x, t, C, lds);
+        else
+            bc_class_tile<uint64_t>(threadIdx.x, blockDim.x, t, C, (uint64_t*)lds);
+    }
+}
+
+template <int WIDE>
 __global__ __launch_bounds__(kThreads) void k_bc_layer(BcLayerOp L) {
     const int tid = blockIdx.x * blockDim.x + threadIdx.x;
     const int nt = gridDim.x * blockDim.x;
@@ -53,7 +65,7 @@ __global__ __launch_bounds__(kThreads) void k_fft(FftPass A, const uint8_t* g_mt
     copy_words(threadIdx.x, blockDim.x, lam, g_lam, 1024);
     __syncthreads();
     const uint64_t nt = fft_tiles(A);
-    for (uint64_t t = blockIdx.x; t < nt; t += gridDim.x) fft_tile(threadIdx.x, blockDim.x, t, A, mt, lam, g_phi, tl, mu);
+    for (uint64_t t = blockIdx.x; t < nt; t += gridDim.x) fft_tile<1>(threadIdx.x, blockDim.x, t, A, mt, lam, g_phi, tl, mu);
 }
 
 __global__ __launch_bounds__(kThreads) void k_pmul(PmulOp P, const uint8_t* g_mt) {
@@ -192,6 +204,10 @@ void op_traffic(const Op& op, gf2x_trace_rec& r) {
             r.bytes_read = 32 * op.pmul.n;
             r.bytes_written = 16 * op.pmul.n;
             break;
+        case OpKind::BcClass:
+            r.elements = op.bcc.nelem;
+            r.bytes_read = r.bytes_written = op.bcc.nelem * (op.bcc.wide ? 16 : 8);
+            break;
         case OpKind::Psi:
             r.elements = op.psi.nwords;
             r.bytes_read = 16 * std::min(op.psi.nwords, op.psi.nspec);
@@ -238,6 +254,12 @@ int run_ops(gf2x_ctx* ctx, const std::vector<Op>& ops, hipStream_t st) {
             case OpKind::Pmul:
                 hipLaunchKernelGGL(k_pmul, dim3(grid_for(pmul_tiles(op.pmul), 2 * ncu)), dim3(kThreads), 0, st, op.pmul,
                                    (const uint8_t*)ctx->d_mt);
+                break;
+            case OpKind::BcClass:
+                if (op.bcc.wide)
+                    hipLaunchKernelGGL(k_bc_class<1>, dim3(grid_for(bc_class_tiles(op.bcc), 2 * ncu)), dim3(kThreads), 0, st, op.bcc);
+                else
+                    hipLaunchKernelGGL(k_bc_class<0>, dim3(grid_for(bc_class_tiles(op.bcc), 2 * ncu)), dim3(kThreads), 0, st, op.bcc);
                 break;
             case OpKind::Psi:
                 hipLaunchKernelGGL(k_psi, dim3(grid_for(psi_tiles(op.psi), 2 * ncu)), dim3(kThreads), 0, st, op.psi,

@@ -9,7 +9,7 @@
 
 namespace gf2x {
 
-constexpr int kThreads = 512;     // threads per block in every kernel
+constexpr int kThreads = 1024;    // threads per block in every kernel
 constexpr int kFftTileLog = 11;   // FFT tile: up to 2^11 elements (32 KiB)
 constexpr int kFftColRowsLog = 8; // strided passes: up to 2^8 rows per tile
 constexpr int kBcTileLog64 = 13;  // BasisCvt tile on 64-bit words: 64 KiB
@@ -46,9 +46,18 @@ AFFT_HD void pack_tile(int tid, int nt, uint64_t tile, const PackOp& P) {
 }
 
 // --------------------------------------------------------------- BasisCvt
-// Layers whose blocks fit in a tile run together in LDS (BcTileOp); a layer
-// with larger blocks runs as two global passes (BcLayerOp, which = 0 then 1;
-// reversed for the inverse).
+// BasisCvt runs as tile passes: layers whose blocks fit a tile run together
+// in LDS (BcTileOp, contiguous or strided "column" tiles), the VarSubs layers
+// of a large block run as one class pass (BcClassOp).  A layer that fits
+// neither runs as two global passes (BcLayerOp, which = 0 then 1; reversed for
+// the inverse).
+
+template <typename T>
+AFFT_HD T zero_elem();
+template <>
+AFFT_HD uint64_t zero_elem<uint64_t>() { return 0; }
+template <>
+AFFT_HD uint4 zero_elem<uint4>() { return make_uint4(0, 0, 0, 0); }
 
 template <typename T>
 AFFT_HD void bc_part(int tid, int nt, T* a, uint64_t nelem, const BcLayer& L, int which) {
@@ -72,10 +81,35 @@ AFFT_HD void bc_part(int tid, int nt, T* a, uint64_t nelem, const BcLayer& L, in
     }
 }
 
+// The same layer part on an LDS tile (32-bit indices).
+template <typename T>
+AFFT_HD void bc_part_lds(int tid, int nt, T* a, uint32_t nelem, const BcLayer& L, int which) {
+    const uint32_t ld = L.log_d, lk = L.log_k, lu = L.log_u;
+    const uint32_t D = 1u << ld, k = 1u << lk;
+    const uint32_t log_cnt = which == 0 ? lk : ld;
+    const uint32_t t0 = which == 0 ? 2 * D - k : D;
+    const uint32_t tend = which == 0 ? 2 * D : 2 * D - k;
+    const uint32_t shift = (D - k) << lu;
+    const uint32_t items = (nelem >> (ld + 1 + lu)) << (log_cnt + lu);
+    const uint32_t cm = (1u << lu) - 1, tm = (1u << log_cnt) - 1;
+    for (uint32_t w = tid; w < items; w += nt) {
+        uint32_t rest = w >> lu;
+        uint32_t t = t0 + (rest & tm);
+        if (t >= tend) continue;
+        uint32_t e = ((((rest >> log_cnt) << (ld + 1)) + t) << lu) + (w & cm);
+        a[e - shift] = a[e - shift] ^ a[e];
+    }
+}
+
+// A tile of 2^log_rows rows, 2^log_stride elements apart, each holding
+// 2^log_tc consecutive elements; LDS keeps it row-major ([row][col]).  The
+// layer list is in LDS-element units, so a layer on whole rows of a strided
+// view ("columns") has its unit scaled by 2^log_tc.  A contiguous tile is
+// log_stride = log_tc = 0.
 struct BcTileOp {
     void* data;
     uint64_t nelem;
-    uint32_t log_tile;
+    uint32_t log_rows, log_stride, log_tc;
     uint32_t wide;     // 0: 64-bit words, 1: 128-bit elements
     uint32_t inverse;  // run the layers (and their two parts) in reverse
     uint32_t pad;
@@ -90,23 +124,117 @@ struct BcLayerOp {
     BcLayer layer;
 };
 
-AFFT_HD uint64_t bc_tiles(const BcTileOp& B) { return B.nelem >> B.log_tile; }
+AFFT_HD uint64_t bc_tiles(const BcTileOp& B) { return B.nelem >> (B.log_rows + B.log_tc); }
 
 template <typename T>
 AFFT_HD void bc_tile(int tid, int nt, uint64_t tile, const BcTileOp& B, T* lds) {
-    T* g = (T*)B.data + (tile << B.log_tile);
-    uint32_t ne = 1u << B.log_tile;
-    for (uint32_t e = tid; e < ne; e += nt) lds[e] = g[e];
+    const uint32_t ncb_log = B.log_stride - B.log_tc;
+    const uint64_t cb = tile & ((1ull << ncb_log) - 1);
+    const uint64_t o = tile >> ncb_log;
+    T* g = (T*)B.data + (o << (B.log_rows + B.log_stride)) + (cb << B.log_tc);
+    const uint32_t ne = 1u << (B.log_rows + B.log_tc);
+    const uint32_t cmask = (1u << B.log_tc) - 1;
+    for (uint32_t e = tid; e < ne; e += nt) lds[e] = g[((uint64_t)(e >> B.log_tc) << B.log_stride) + (e & cmask)];
     AFFT_SYNC();
     int n = B.layers.n;
     for (int li = 0; li < n; ++li) {
         const BcLayer& L = B.layers.l[B.inverse ? n - 1 - li : li];
         for (int part = 0; part < 2; ++part) {
-            bc_part<T>(tid, nt, lds, ne, L, B.inverse ? 1 - part : part);
+            bc_part_lds<T>(tid, nt, lds, ne, L, B.inverse ? 1 - part : part);
             AFFT_SYNC();
         }
     }
-    for (uint32_t e = tid; e < ne; e += nt) g[e] = lds[e];
+    for (uint32_t e = tid; e < ne; e += nt) g[((uint64_t)(e >> B.log_tc) << B.log_stride) + (e & cmask)] = lds[e];
+    AFFT_SYNC();
+}
+
+// VarSubs (Alg. 2) with y = x^(2^K) + x on blocks of 2^m units of 2^log_u
+// elements, all m-K division layers in one pass.  Layer j moves unit t to
+// t - 2^j (2^K - 1), so it only combines units in the same residue class
+// mod P = 2^K - 1.  Writing t = q P + r, a tile holds the positions
+// x = r 2^log_u + c in [x0, x0 + W) of every row q (Q rows cover the block);
+// the layer becomes  row[q - 2^j] ^= row[q]  for the rows whose t has
+// t mod 2D in the layer's source range.
+struct BcClassOp {
+    void* data;
+    uint64_t nelem;
+    uint32_t m, K, log_u;
+    uint32_t log_w;   // W = 2^log_w positions per tile
+    uint32_t q_rows;  // Q = ceil(2^m / P)
+    uint32_t wide, inverse, pad;
+};
+
+AFFT_HD uint64_t bc_class_tiles_per_block(const BcClassOp& C) {
+    uint64_t X = ((1ull << C.K) - 1) << C.log_u;
+    return (X + (1ull << C.log_w) - 1) >> C.log_w;
+}
+AFFT_HD uint64_t bc_class_tiles(const BcClassOp& C) {
+    return (C.nelem >> (C.m + C.log_u)) * bc_class_tiles_per_block(C);
+}
+
+template <typename T>
+AFFT_HD void bc_class_tile(int tid, int nt, uint64_t tile, const BcClassOp& C, T* lds) {
+    const uint64_t P = (1ull << C.K) - 1;
+    const uint64_t X = P << C.log_u;
+    const uint64_t tpb = bc_class_tiles_per_block(C);
+    const uint64_t blk = tile / tpb;
+    const uint64_t x0 = (tile - blk * tpb) << C.log_w;
+    const uint32_t lw = C.log_w, wm = (1u << lw) - 1;
+    const uint64_t nunits = 1ull << C.m;
+    T* g = (T*)C.data + (blk << (C.m + C.log_u));
+    const uint32_t ne = C.q_rows << lw;
+    // position (q, xw) holds unit t = q P + ((x0 + xw) >> log_u); absent if
+    // x0 + xw >= X or t >= 2^m
+    for (uint32_t e = tid; e < ne; e += nt) {
+        uint64_t q = e >> lw, x = x0 + (e & wm);
+        T v = zero_elem<T>();
+        if (x < X && q * P + (x >> C.log_u) < nunits) v = g[q * X + x];
+        lds[e] = v;
+    }
+    AFFT_SYNC();
+    const int nl = (int)(C.m - C.K);
+    const uint64_t xend = x0 + (1ull << lw) < X ? x0 + (1ull << lw) : X;
+    for (int li = 0; li < nl; ++li) {
+        int j = C.inverse ? li : nl - 1 - li;
+        const uint64_t D = 1ull << (C.K + j), k = 1ull << j;
+        for (int part = 0; part < 2; ++part) {
+            int which = C.inverse ? 1 - part : part;
+            if (which == 0) {
+                // sources: the top k units of every 2D block, 2^(m-K-1) of them
+                // per block; only those whose class lies in this tile act here
+                const uint64_t nsrc = nunits >> (C.K + 1);
+                for (uint64_t w = tid; w < nsrc; w += nt) {
+                    uint64_t t = ((w >> j) << (C.K + j + 1)) + 2 * D - k + (w & (k - 1));
+                    uint64_t q = t / P, r = t - q * P;
+                    uint64_t xa = r << C.log_u, xb = xa + (1ull << C.log_u);
+                    if (xa < x0) xa = x0;
+                    if (xb > xend) xb = xend;
+                    for (uint64_t x = xa; x < xb; ++x) {
+                        uint32_t e = ((uint32_t)q << lw) + (uint32_t)(x - x0);
+                        uint32_t tgt = e - ((uint32_t)k << lw);
+                        lds[tgt] = lds[tgt] ^ lds[e];
+                    }
+                }
+            } else {
+                const uint64_t hi = 2 * D - k;
+                for (uint32_t e = tid; e < ne; e += nt) {
+                    uint64_t x = x0 + (e & wm);
+                    if (x >= X) continue;
+                    uint64_t t = (uint64_t)(e >> lw) * P + (x >> C.log_u);
+                    if (t >= nunits) continue;
+                    uint64_t pos = t & (2 * D - 1);
+                    if (pos < D || pos >= hi) continue;
+                    uint32_t tgt = e - ((uint32_t)k << lw);
+                    lds[tgt] = lds[tgt] ^ lds[e];
+                }
+            }
+            AFFT_SYNC();
+        }
+    }
+    for (uint32_t e = tid; e < ne; e += nt) {
+        uint64_t q = e >> lw, x = x0 + (e & wm);
+        if (x < X && q * P + (x >> C.log_u) < nunits) g[q * X + x] = lds[e];
+    }
     AFFT_SYNC();
 }
 
@@ -142,6 +270,52 @@ AFFT_HD uint4 phi_word(const uint4* phi_tab, uint64_t w) {
     return r;
 }
 
+// One step of RL consecutive layers [i0, i0 + RL) held in registers: a thread
+// owns the 2^RL elements whose rows differ only in the bits (i0 - lo) ..
+// (i0 - lo + RL - 1) (same column) and runs all their butterflies.
+template <int RL, bool INV>
+AFFT_HD void fft_step(int tid, int nt, const FftPass& A, int i0, const uint8_t* mt, uint4* tl, const uint4* mu) {
+    const uint32_t nel = 1u << (A.hi - A.lo + A.log_tc);
+    const uint32_t groups = nel >> RL;
+    const uint32_t tcm = (1u << A.log_tc) - 1;
+    const int h0 = i0 - (int)A.lo;
+    for (uint32_t g = tid; g < groups; g += nt) {
+        uint32_t c = g & tcm;
+        uint32_t rr = g >> A.log_tc;
+        uint32_t base_r = ((rr >> h0) << (h0 + RL)) | (rr & ((1u << h0) - 1));
+        uint4 x[1 << RL];
+#pragma unroll
+        for (int j = 0; j < (1 << RL); ++j) x[j] = tl[((base_r | ((uint32_t)j << h0)) << A.log_tc) | c];
+#pragma unroll
+        for (int s = 0; s < RL; ++s) {
+            const int l = INV ? s : RL - 1 - s;  // layer i0 + l
+            const int i = i0 + l;
+            const int mode = width_mode((int)A.log_total - i);
+            const uint32_t off = (1u << (A.hi - 1 - i)) - 1;
+#pragma unroll
+            for (int j = 0; j < (1 << RL); ++j) {
+                if (j & (1 << l)) continue;
+                uint32_t r0 = base_r | ((uint32_t)j << h0);
+                uint4 m = mu[off + (r0 >> (i - (int)A.lo + 1))];
+                uint4 u = x[j], v = x[j | (1 << l)];
+                if (!INV) {
+                    u = u ^ mul_sub_k(mt, m, v, mode);
+                    v = v ^ u;
+                } else {
+                    v = v ^ u;
+                    u = u ^ mul_sub_k(mt, m, v, mode);
+                }
+                x[j] = u;
+                x[j | (1 << l)] = v;
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < (1 << RL); ++j) tl[((base_r | ((uint32_t)j << h0)) << A.log_tc) | c] = x[j];
+    }
+}
+
+// RL: most layers kept in registers per LDS round trip (1..3).
+template <int RL>
 AFFT_HD void fft_tile(int tid, int nt, uint64_t tile, const FftPass& A, const uint8_t* mt, const uint32_t* lam,
                       const uint4* phi_tab, uint4* tl, uint4* mu) {
     const uint32_t rlog = A.hi - A.lo, tc = 1u << A.log_tc;
@@ -164,45 +338,44 @@ AFFT_HD void fft_tile(int tid, int nt, uint64_t tile, const FftPass& A, const ui
         tl[e] = v;
     }
     // multipliers of every (layer, block) of the tile: entry E <-> layer
-    // i = hi - 1 - floor(log2(E + 1)), block b = E + 1 - 2^floor(log2(E + 1))
+    // i = hi - 1 - floor(log2(E + 1)), block b = E + 1 - 2^floor(log2(E + 1));
+    // lambda = s_i of the block start: the tile-wide high bits plus the
+    // block's row bits above i (s_i is GF(2)-linear)
     const uint32_t nmu = (1u << rlog) - 1;
     const uint64_t s_hi = gbase | (outer << A.hi);
     for (uint32_t E = tid; E < nmu; E += nt) {
         uint32_t q = E + 1;
         int lg = 31 - __builtin_clz(q);
         int i = (int)A.hi - 1 - lg;
-        uint64_t s = s_hi | ((uint64_t)(q - (1u << lg)) << (i + 1));
         uint32_t lv = 0;
-        for (int t = i + 1; t < 32; ++t)
-            if ((s >> t) & 1) lv ^= lam[i * 32 + t];
-        mu[E] = make_mu(mt, lv);
+        for (uint64_t sb = s_hi >> A.hi; sb; sb &= sb - 1) lv ^= lam[i * 32 + (int)A.hi + __builtin_ctzll(sb)];
+        for (uint32_t b = q - (1u << lg); b; b &= b - 1) lv ^= lam[i * 32 + i + 1 + __builtin_ctz(b)];
+        mu[E] = make_mu_k(mt, lv);
     }
     AFFT_SYNC();
-    for (uint32_t li = 0; li < rlog; ++li) {
-        int i = A.inverse ? (int)(A.lo + li) : (int)(A.hi - 1 - li);
-        int h = i - (int)A.lo;
-        int mode = width_mode((int)A.log_total - i);
-        uint32_t off = (1u << (A.hi - 1 - i)) - 1;
-        for (uint32_t w = tid; w < nel / 2; w += nt) {
-            uint32_t c = w & (tc - 1);
-            uint32_t q = w >> A.log_tc;
-            uint32_t blk = q >> h;
-            uint32_t r0 = (blk << (h + 1)) | (q & ((1u << h) - 1));
-            uint32_t r1 = r0 | (1u << h);
-            uint32_t i0 = (r0 << A.log_tc) | c, i1 = (r1 << A.log_tc) | c;
-            uint4 u = tl[i0], v = tl[i1];
-            uint4 m = mu[off + blk];
-            if (!A.inverse) {
-                u = u ^ mul_sub(mt, m, v, mode);
-                v = v ^ u;
-            } else {
-                v = v ^ u;
-                u = u ^ mul_sub(mt, m, v, mode);
-            }
-            tl[i0] = u;
-            tl[i1] = v;
+    // layers in steps of up to RL: forward from the top, inverse from the bottom
+    int done = 0;
+    while (done < (int)rlog) {
+        int r = (int)rlog - done;
+        int R = r >= RL ? RL : r;
+        int i0 = A.inverse ? (int)A.lo + done : (int)A.hi - done - R;
+        if (A.inverse) {
+            if (R == 3)
+                fft_step<3, true>(tid, nt, A, i0, mt, tl, mu);
+            else if (R == 2)
+                fft_step<2, true>(tid, nt, A, i0, mt, tl, mu);
+            else
+                fft_step<1, true>(tid, nt, A, i0, mt, tl, mu);
+        } else {
+            if (R == 3)
+                fft_step<3, false>(tid, nt, A, i0, mt, tl, mu);
+            else if (R == 2)
+                fft_step<2, false>(tid, nt, A, i0, mt, tl, mu);
+            else
+                fft_step<1, false>(tid, nt, A, i0, mt, tl, mu);
         }
         AFFT_SYNC();
+        done += R;
     }
     for (uint32_t e = tid; e < nel; e += nt) {
         uint64_t p = base_p | ((uint64_t)(e >> A.log_tc) << A.lo) | (e & (tc - 1));

@@ -7,7 +7,7 @@
 
 namespace gf2x {
 
-enum class OpKind : int { Pack, BcTile, BcLayer, Fft, Pmul, Psi };
+enum class OpKind : int { Pack, BcTile, BcLayer, Fft, Pmul, Psi, BcClass };
 
 struct Op {
     OpKind kind;
@@ -17,6 +17,7 @@ struct Op {
     FftPass fft;
     PmulOp pmul;
     PsiOp psi;
+    BcClassOp bcc;
 };
 
 inline int ceil_log2(uint64_t n) {
@@ -67,59 +68,105 @@ inline void bc_layer_list(int m, int log_u, std::vector<BcLayer>& out) {
 
 inline uint64_t bc_span_log(const BcLayer& L) { return L.log_d + 1 + L.log_u; }
 
-// Emit BasisCvt (or its inverse) of 2^m elements at `data`.
-inline void emit_bc(std::vector<Op>& ops, void* data, int wide, int m, int inverse) {
-    std::vector<BcLayer> L;
-    bc_layer_list(m, 0, L);
-    if (L.empty()) return;
-    const int tile_log = std::min(m, wide ? kBcTileLog128 : kBcTileLog64);
-    const uint64_t n = 1ull << m;
-    // group maximal runs of layers whose blocks fit a tile
-    std::vector<std::pair<int, int>> runs;  // [begin, end) of tile runs; begin == end marks a global layer
-    std::vector<int> kind;                  // 1 = tile run, 0 = single global layer
-    size_t i = 0;
-    while (i < L.size()) {
-        if ((int)bc_span_log(L[i]) <= tile_log) {
-            size_t j = i;
-            while (j < L.size() && (int)bc_span_log(L[j]) <= tile_log && j - i < (size_t)kMaxBcLayers) ++j;
-            runs.push_back({(int)i, (int)j});
-            kind.push_back(1);
-            i = j;
-        } else {
-            runs.push_back({(int)i, (int)i + 1});
-            kind.push_back(0);
-            ++i;
-        }
-    }
-    auto emit_run = [&](size_t r) {
-        Op op{};
-        if (kind[r]) {
+struct BcPlanner {
+    void* data;
+    int wide;
+    uint64_t n;         // elements
+    int cap_log;        // LDS capacity of a tile, log2 elements
+    std::vector<Op> ops;
+
+    void tile_pass(int log_rows, int log_stride, int log_tc, const std::vector<BcLayer>& L) {
+        for (size_t i = 0; i < L.size(); i += kMaxBcLayers) {
+            Op op{};
             op.kind = OpKind::BcTile;
             op.bct.data = data;
             op.bct.nelem = n;
-            op.bct.log_tile = (uint32_t)tile_log;
+            op.bct.log_rows = (uint32_t)log_rows;
+            op.bct.log_stride = (uint32_t)log_stride;
+            op.bct.log_tc = (uint32_t)log_tc;
             op.bct.wide = (uint32_t)wide;
-            op.bct.inverse = (uint32_t)inverse;
-            op.bct.layers.n = runs[r].second - runs[r].first;
-            for (int t = runs[r].first; t < runs[r].second; ++t) op.bct.layers.l[t - runs[r].first] = L[t];
+            size_t e = std::min(L.size(), i + (size_t)kMaxBcLayers);
+            op.bct.layers.n = (int)(e - i);
+            for (size_t t = i; t < e; ++t) op.bct.layers.l[t - i] = L[t];
+            ops.push_back(op);
+        }
+    }
+
+    void global_layer(const BcLayer& L) {
+        for (int part = 0; part < 2; ++part) {
+            Op g{};
+            g.kind = OpKind::BcLayer;
+            g.bcl.data = data;
+            g.bcl.nelem = n;
+            g.bcl.wide = (uint32_t)wide;
+            g.bcl.which = (uint32_t)part;
+            g.bcl.layer = L;
+            ops.push_back(g);
+        }
+    }
+
+    // BasisCvt on every aligned block of 2^m units of 2^log_u elements.
+    void cvt(int m, int log_u) {
+        if (m <= 1) return;
+        const int blk_log = m + log_u;
+        if (blk_log <= cap_log) {
+            // whole blocks fit: a contiguous tile holds 2^(T - blk_log) of them
+            std::vector<BcLayer> L;
+            bc_layer_list(m, log_u, L);
+            int T = std::min<int>(cap_log, ceil_log2(n));
+            tile_pass(T, 0, 0, L);
+            return;
+        }
+        if (log_u > 0 && m + std::min(log_u, 3) <= cap_log) {
+            // strided "column" tiles: all 2^m rows of up to 2^log_tc columns
+            int log_tc = std::min(log_u, cap_log - m);
+            std::vector<BcLayer> L;
+            bc_layer_list(m, log_tc, L);  // row units scaled to LDS elements
+            tile_pass(m, log_u, log_tc, L);
+            return;
+        }
+        int K = 1;
+        while (2 * K < m) K *= 2;
+        uint64_t P = (1ull << K) - 1;
+        uint64_t Q = ((1ull << m) + P - 1) / P;
+        if (Q <= (1ull << cap_log)) {
+            int log_w = 0;
+            while ((Q << (log_w + 1)) <= (1ull << cap_log) && (1ull << (log_w + 1)) <= (P << log_u)) ++log_w;
+            Op op{};
+            op.kind = OpKind::BcClass;
+            op.bcc.data = data;
+            op.bcc.nelem = n;
+            op.bcc.m = (uint32_t)m;
+            op.bcc.K = (uint32_t)K;
+            op.bcc.log_u = (uint32_t)log_u;
+            op.bcc.log_w = (uint32_t)log_w;
+            op.bcc.q_rows = (uint32_t)Q;
+            op.bcc.wide = (uint32_t)wide;
             ops.push_back(op);
         } else {
-            for (int part = 0; part < 2; ++part) {
-                Op g{};
-                g.kind = OpKind::BcLayer;
-                g.bcl.data = data;
-                g.bcl.nelem = n;
-                g.bcl.wide = (uint32_t)wide;
-                g.bcl.which = (uint32_t)(inverse ? 1 - part : part);
-                g.bcl.layer = L[runs[r].first];
-                ops.push_back(g);
-            }
+            for (int j = m - K - 1; j >= 0; --j) global_layer(BcLayer{(uint32_t)(K + j), (uint32_t)j, (uint32_t)log_u, 0});
         }
-    };
-    if (!inverse)
-        for (size_t r = 0; r < runs.size(); ++r) emit_run(r);
-    else
-        for (size_t r = runs.size(); r-- > 0;) emit_run(r);
+        cvt(m - K, log_u + K);
+        cvt(K, log_u);
+    }
+};
+
+// Emit BasisCvt (or its inverse) of 2^m elements at `data`: the forward op
+// list, reversed (each op running its layers backwards) for the inverse.
+inline void emit_bc(std::vector<Op>& ops, void* data, int wide, int m, int inverse) {
+    BcPlanner P{data, wide, 1ull << m, wide ? kBcTileLog128 : kBcTileLog64, {}};
+    P.cvt(m, 0);
+    if (!inverse) {
+        for (auto& op : P.ops) ops.push_back(op);
+        return;
+    }
+    for (size_t i = P.ops.size(); i-- > 0;) {
+        Op op = P.ops[i];
+        if (op.kind == OpKind::BcTile) op.bct.inverse = 1;
+        if (op.kind == OpKind::BcClass) op.bcc.inverse = 1;
+        if (op.kind == OpKind::BcLayer) op.bcl.which = 1 - op.bcl.which;
+        ops.push_back(op);
+    }
 }
 
 // Layer ranges of the FFT passes: a contiguous bottom pass of up to 2^11
