@@ -55,17 +55,57 @@ __global__ __launch_bounds__(kThreads) void k_bc_layer(BcLayerOp L) {
         bc_part<uint64_t>(tid, nt, (uint64_t*)L.data, L.nelem, L.layer, (int)L.which);
 }
 
+// Tiles of one FFT pass, block-strided; each block loads the tables and the
+// pass's local mu-sets once, and prefetches the next tile's elements into
+// registers while the current tile's layers run.
+constexpr int kFftPrefetch = (1 << kFftTileLog) / kThreads;
+
 __global__ __launch_bounds__(kThreads) void k_fft(FftPass A, const uint8_t* g_mt, const uint32_t* g_lam,
                                                   const uint4* g_phi) {
     __shared__ __align__(16) uint8_t mt[65536];
     __shared__ uint32_t lam[1024];
     __shared__ uint4 tl[1 << kFftTileLog];
     __shared__ uint4 mu[1 << kFftTileLog];
-    copy_words(threadIdx.x, blockDim.x, (uint32_t*)mt, (const uint32_t*)g_mt, 16384);
-    copy_words(threadIdx.x, blockDim.x, lam, g_lam, 1024);
+    __shared__ uint4 mu_tile[32];
+    const int tid = threadIdx.x, nt = blockDim.x;
+    copy_words(tid, nt, (uint32_t*)mt, (const uint32_t*)g_mt, 16384);
+    copy_words(tid, nt, lam, g_lam, 1024);
     __syncthreads();
-    const uint64_t nt = fft_tiles(A);
-    for (uint64_t t = blockIdx.x; t < nt; t += gridDim.x) fft_tile<1>(threadIdx.x, blockDim.x, t, A, mt, lam, g_phi, tl, mu);
+    fft_local_mu(tid, nt, A, mt, lam, mu);
+    const uint64_t ntiles = fft_tiles(A);
+    uint64_t t = blockIdx.x;
+    if (t >= ntiles) return;
+    FftTileGeom G = fft_geom(A, t);
+    uint4 pre[kFftPrefetch];
+#pragma unroll
+    for (int j = 0; j < kFftPrefetch; ++j) {
+        uint32_t e = tid + j * nt;
+        if (e < G.nel) pre[j] = fft_load(A, g_phi, G, e);
+    }
+    while (true) {
+#pragma unroll
+        for (int j = 0; j < kFftPrefetch; ++j) {
+            uint32_t e = tid + j * nt;
+            if (e < G.nel) tl[e] = pre[j];
+        }
+        __syncthreads();
+        const uint64_t tn = t + gridDim.x;
+        FftTileGeom Gn = G;
+        if (tn < ntiles) {
+            Gn = fft_geom(A, tn);
+#pragma unroll
+            for (int j = 0; j < kFftPrefetch; ++j) {
+                uint32_t e = tid + j * nt;
+                if (e < Gn.nel) pre[j] = fft_load(A, g_phi, Gn, e);
+            }
+        }
+        fft_tile_layers<1>(tid, nt, A, G, mt, lam, tl, mu, mu_tile);
+        for (uint32_t e = tid; e < G.nel; e += nt) A.dst[G.gbase | fft_elem_index(A, G, e)] = tl[e];
+        if (tn >= ntiles) break;
+        __syncthreads();
+        t = tn;
+        G = Gn;
+    }
 }
 
 __global__ __launch_bounds__(kThreads) void k_pmul(PmulOp P, const uint8_t* g_mt) {

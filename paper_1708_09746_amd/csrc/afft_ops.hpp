@@ -17,6 +17,7 @@ constexpr int kBcTileLog128 = 12; // BasisCvt tile on 128-bit elements: 64 KiB
 constexpr int kPmulTile = 1024;
 constexpr int kPsiTile = 1024;
 constexpr int kPackTile = 4096;
+constexpr int kGatherUnroll = 1;  // global loads kept in flight per thread (more was slower)
 
 // ------------------------------------------------------------------ pack
 // Split (Alg. 5 first step, w = 64): the operand's words, bits at and above
@@ -134,7 +135,19 @@ AFFT_HD void bc_tile(int tid, int nt, uint64_t tile, const BcTileOp& B, T* lds) 
     T* g = (T*)B.data + (o << (B.log_rows + B.log_stride)) + (cb << B.log_tc);
     const uint32_t ne = 1u << (B.log_rows + B.log_tc);
     const uint32_t cmask = (1u << B.log_tc) - 1;
-    for (uint32_t e = tid; e < ne; e += nt) lds[e] = g[((uint64_t)(e >> B.log_tc) << B.log_stride) + (e & cmask)];
+    for (uint32_t e0 = tid; e0 < ne; e0 += nt * kGatherUnroll) {
+        T v[kGatherUnroll];
+#pragma unroll
+        for (int u = 0; u < kGatherUnroll; ++u) {
+            uint32_t e = e0 + u * nt;
+            v[u] = e < ne ? g[((uint64_t)(e >> B.log_tc) << B.log_stride) + (e & cmask)] : zero_elem<T>();
+        }
+#pragma unroll
+        for (int u = 0; u < kGatherUnroll; ++u) {
+            uint32_t e = e0 + u * nt;
+            if (e < ne) lds[e] = v[u];
+        }
+    }
     AFFT_SYNC();
     int n = B.layers.n;
     for (int li = 0; li < n; ++li) {
@@ -144,7 +157,19 @@ AFFT_HD void bc_tile(int tid, int nt, uint64_t tile, const BcTileOp& B, T* lds) 
             AFFT_SYNC();
         }
     }
-    for (uint32_t e = tid; e < ne; e += nt) g[((uint64_t)(e >> B.log_tc) << B.log_stride) + (e & cmask)] = lds[e];
+    for (uint32_t e0 = tid; e0 < ne; e0 += nt * kGatherUnroll) {
+        T v[kGatherUnroll];
+#pragma unroll
+        for (int u = 0; u < kGatherUnroll; ++u) {
+            uint32_t e = e0 + u * nt;
+            v[u] = e < ne ? lds[e] : zero_elem<T>();
+        }
+#pragma unroll
+        for (int u = 0; u < kGatherUnroll; ++u) {
+            uint32_t e = e0 + u * nt;
+            if (e < ne) g[((uint64_t)(e >> B.log_tc) << B.log_stride) + (e & cmask)] = v[u];
+        }
+    }
     AFFT_SYNC();
 }
 
@@ -185,11 +210,20 @@ AFFT_HD void bc_class_tile(int tid, int nt, uint64_t tile, const BcClassOp& C, T
     const uint32_t ne = C.q_rows << lw;
     // position (q, xw) holds unit t = q P + ((x0 + xw) >> log_u); absent if
     // x0 + xw >= X or t >= 2^m
-    for (uint32_t e = tid; e < ne; e += nt) {
-        uint64_t q = e >> lw, x = x0 + (e & wm);
-        T v = zero_elem<T>();
-        if (x < X && q * P + (x >> C.log_u) < nunits) v = g[q * X + x];
-        lds[e] = v;
+    for (uint32_t e0 = tid; e0 < ne; e0 += nt * kGatherUnroll) {
+        T v[kGatherUnroll];
+#pragma unroll
+        for (int u = 0; u < kGatherUnroll; ++u) {
+            uint32_t e = e0 + u * nt;
+            uint64_t q = e >> lw, x = x0 + (e & wm);
+            v[u] = zero_elem<T>();
+            if (e < ne && x < X && q * P + (x >> C.log_u) < nunits) v[u] = g[q * X + x];
+        }
+#pragma unroll
+        for (int u = 0; u < kGatherUnroll; ++u) {
+            uint32_t e = e0 + u * nt;
+            if (e < ne) lds[e] = v[u];
+        }
     }
     AFFT_SYNC();
     const int nl = (int)(C.m - C.K);
@@ -231,9 +265,19 @@ AFFT_HD void bc_class_tile(int tid, int nt, uint64_t tile, const BcClassOp& C, T
             AFFT_SYNC();
         }
     }
-    for (uint32_t e = tid; e < ne; e += nt) {
-        uint64_t q = e >> lw, x = x0 + (e & wm);
-        if (x < X && q * P + (x >> C.log_u) < nunits) g[q * X + x] = lds[e];
+    for (uint32_t e0 = tid; e0 < ne; e0 += nt * kGatherUnroll) {
+        T v[kGatherUnroll];
+#pragma unroll
+        for (int u = 0; u < kGatherUnroll; ++u) {
+            uint32_t e = e0 + u * nt;
+            v[u] = e < ne ? lds[e] : zero_elem<T>();
+        }
+#pragma unroll
+        for (int u = 0; u < kGatherUnroll; ++u) {
+            uint32_t e = e0 + u * nt;
+            uint64_t q = e >> lw, x = x0 + (e & wm);
+            if (e < ne && x < X && q * P + (x >> C.log_u) < nunits) g[q * X + x] = v[u];
+        }
     }
     AFFT_SYNC();
 }
@@ -314,73 +358,111 @@ AFFT_HD void fft_step(int tid, int nt, const FftPass& A, int i0, const uint8_t* 
     }
 }
 
-// RL: most layers kept in registers per LDS round trip (1..3).
-template <int RL>
-AFFT_HD void fft_tile(int tid, int nt, uint64_t tile, const FftPass& A, const uint8_t* mt, const uint32_t* lam,
-                      const uint4* phi_tab, uint4* tl, uint4* mu) {
-    const uint32_t rlog = A.hi - A.lo, tc = 1u << A.log_tc;
-    const uint64_t ncb = 1ull << (A.lo - A.log_tc), nouter = 1ull << (A.log_m - A.hi);
-    const uint64_t cb = tile & (ncb - 1);
-    const uint64_t rest = tile >> (A.lo - A.log_tc);
-    const uint64_t outer = rest & (nouter - 1);
-    const uint64_t coset = rest >> (A.log_m - A.hi);
-    const uint64_t base_p = (outer << A.hi) | (cb << A.log_tc);
-    const uint64_t gbase = coset << A.log_m;
-    const uint32_t nel = 1u << (rlog + A.log_tc);
-
-    for (uint32_t e = tid; e < nel; e += nt) {
-        uint64_t p = base_p | ((uint64_t)(e >> A.log_tc) << A.lo) | (e & (tc - 1));
-        uint4 v;
-        if (A.phi_in)
-            v = phi_word(phi_tab, ((const uint64_t*)A.src)[p]);
-        else
-            v = A.dst[gbase | p];
-        tl[e] = v;
-    }
-    // multipliers of every (layer, block) of the tile: entry E <-> layer
-    // i = hi - 1 - floor(log2(E + 1)), block b = E + 1 - 2^floor(log2(E + 1));
-    // lambda = s_i of the block start: the tile-wide high bits plus the
-    // block's row bits above i (s_i is GF(2)-linear)
-    const uint32_t nmu = (1u << rlog) - 1;
-    const uint64_t s_hi = gbase | (outer << A.hi);
+// The multiplier of layer i for the block starting at global index s is
+// lambda = s_i(s̄) = XOR of lam[i][t] over the set bits t of s.  Inside a tile,
+// s = S | (b << (i + 1)) with S the tile's bits at and above `hi` and b the
+// block's row bits, and the mu-set of lambda is GF(2)-linear in lambda, so
+//   mu(lambda) = mu(s_i(S̄)) + mu(s_i(b << (i + 1)))
+// with the second term the same for every tile of the pass.  Entry E of the
+// local table <-> layer i = hi - 1 - floor(log2(E + 1)), block
+// b = E + 1 - 2^floor(log2(E + 1)).
+AFFT_HD void fft_local_mu(int tid, int nt, const FftPass& A, const uint8_t* mt, const uint32_t* lam, uint4* mu) {
+    const uint32_t nmu = (1u << (A.hi - A.lo)) - 1;
     for (uint32_t E = tid; E < nmu; E += nt) {
         uint32_t q = E + 1;
         int lg = 31 - __builtin_clz(q);
         int i = (int)A.hi - 1 - lg;
         uint32_t lv = 0;
-        for (uint64_t sb = s_hi >> A.hi; sb; sb &= sb - 1) lv ^= lam[i * 32 + (int)A.hi + __builtin_ctzll(sb)];
         for (uint32_t b = q - (1u << lg); b; b &= b - 1) lv ^= lam[i * 32 + i + 1 + __builtin_ctz(b)];
         mu[E] = make_mu_k(mt, lv);
     }
+}
+
+struct FftTileGeom {
+    uint64_t base_p, gbase, s_hi;
+    uint32_t nel;
+};
+
+AFFT_HD FftTileGeom fft_geom(const FftPass& A, uint64_t tile) {
+    const uint64_t ncb = 1ull << (A.lo - A.log_tc), nouter = 1ull << (A.log_m - A.hi);
+    const uint64_t cb = tile & (ncb - 1);
+    const uint64_t rest = tile >> (A.lo - A.log_tc);
+    const uint64_t outer = rest & (nouter - 1);
+    const uint64_t coset = rest >> (A.log_m - A.hi);
+    FftTileGeom G;
+    G.base_p = (outer << A.hi) | (cb << A.log_tc);
+    G.gbase = coset << A.log_m;
+    G.s_hi = G.gbase | (outer << A.hi);
+    G.nel = 1u << (A.hi - A.lo + A.log_tc);
+    return G;
+}
+
+AFFT_HD uint64_t fft_elem_index(const FftPass& A, const FftTileGeom& G, uint32_t e) {
+    return G.base_p | ((uint64_t)(e >> A.log_tc) << A.lo) | (e & ((1u << A.log_tc) - 1));
+}
+
+AFFT_HD uint4 fft_load(const FftPass& A, const uint4* phi_tab, const FftTileGeom& G, uint32_t e) {
+    uint64_t p = fft_elem_index(A, G, e);
+    if (A.phi_in) return phi_word(phi_tab, ((const uint64_t*)A.src)[p]);
+    return A.dst[G.gbase | p];
+}
+
+// Layers [lo, hi) of one tile already in LDS (tl); mu holds the local
+// mu-sets (fft_local_mu), which hold the tile's full mu-sets while its layers
+// run and are restored afterwards; mu_tile (32 entries) takes the tile parts.
+// RL: layers kept in registers per LDS round trip.
+template <int RL>
+AFFT_HD void fft_tile_layers(int tid, int nt, const FftPass& A, const FftTileGeom& G, const uint8_t* mt,
+                             const uint32_t* lam, uint4* tl, uint4* mu, uint4* mu_tile) {
+    const int rlog = (int)(A.hi - A.lo);
+    for (int li = tid; li < rlog; li += nt) {
+        int i = (int)A.lo + li;
+        uint32_t lv = 0;
+        for (uint64_t sb = G.s_hi >> A.hi; sb; sb &= sb - 1) lv ^= lam[i * 32 + (int)A.hi + __builtin_ctzll(sb)];
+        mu_tile[li] = make_mu_k(mt, lv);
+    }
     AFFT_SYNC();
-    // layers in steps of up to RL: forward from the top, inverse from the bottom
+    // full mu-sets of this tile: add the tile part of each layer into the
+    // shared local table in place (undone below: XOR is an involution)
+    const uint32_t nmu = (1u << rlog) - 1;
+    for (uint32_t E = tid; E < nmu; E += nt) mu[E] = mu[E] ^ mu_tile[rlog - 1 - (31 - __builtin_clz(E + 1))];
+    AFFT_SYNC();
+    uint4* muf = mu;
     int done = 0;
-    while (done < (int)rlog) {
-        int r = (int)rlog - done;
+    while (done < rlog) {
+        int r = rlog - done;
         int R = r >= RL ? RL : r;
         int i0 = A.inverse ? (int)A.lo + done : (int)A.hi - done - R;
         if (A.inverse) {
             if (R == 3)
-                fft_step<3, true>(tid, nt, A, i0, mt, tl, mu);
+                fft_step<3, true>(tid, nt, A, i0, mt, tl, muf);
             else if (R == 2)
-                fft_step<2, true>(tid, nt, A, i0, mt, tl, mu);
+                fft_step<2, true>(tid, nt, A, i0, mt, tl, muf);
             else
-                fft_step<1, true>(tid, nt, A, i0, mt, tl, mu);
+                fft_step<1, true>(tid, nt, A, i0, mt, tl, muf);
         } else {
             if (R == 3)
-                fft_step<3, false>(tid, nt, A, i0, mt, tl, mu);
+                fft_step<3, false>(tid, nt, A, i0, mt, tl, muf);
             else if (R == 2)
-                fft_step<2, false>(tid, nt, A, i0, mt, tl, mu);
+                fft_step<2, false>(tid, nt, A, i0, mt, tl, muf);
             else
-                fft_step<1, false>(tid, nt, A, i0, mt, tl, mu);
+                fft_step<1, false>(tid, nt, A, i0, mt, tl, muf);
         }
         AFFT_SYNC();
         done += R;
     }
-    for (uint32_t e = tid; e < nel; e += nt) {
-        uint64_t p = base_p | ((uint64_t)(e >> A.log_tc) << A.lo) | (e & (tc - 1));
-        A.dst[gbase | p] = tl[e];
-    }
+    for (uint32_t E = tid; E < nmu; E += nt) mu[E] = mu[E] ^ mu_tile[rlog - 1 - (31 - __builtin_clz(E + 1))];
+}
+
+// One whole tile: load, layers, store (the sequential form; the GPU kernel
+// overlaps the next tile's loads with these layers).
+template <int RL>
+AFFT_HD void fft_tile(int tid, int nt, uint64_t tile, const FftPass& A, const uint8_t* mt, const uint32_t* lam,
+                      const uint4* phi_tab, uint4* tl, uint4* mu, uint4* mu_tile) {
+    FftTileGeom G = fft_geom(A, tile);
+    for (uint32_t e = tid; e < G.nel; e += nt) tl[e] = fft_load(A, phi_tab, G, e);
+    fft_tile_layers<RL>(tid, nt, A, G, mt, lam, tl, mu, mu_tile);
+    for (uint32_t e = tid; e < G.nel; e += nt) A.dst[G.gbase | fft_elem_index(A, G, e)] = tl[e];
     AFFT_SYNC();
 }
 
