@@ -91,6 +91,66 @@ def cpu_baseline(na, seeds, sample_log2=25):
     }
 
 
+def bench_batched(ctx, njobs=4096, reps=5):
+    """Configured batch: njobs products, operand lengths floor(2^u) with
+    u ~ U[12, 20] bits independently for a and b.  Products/s of (1) a loop of
+    gf2x_mul_dev calls, (2) the staged batch replayed as a hipGraph, (3) the
+    persistent single-launch batch replayed as a hipGraph."""
+    import numpy as np
+    import torch
+
+    import paper_1708_09746_amd as P
+    from paper_1708_09746_amd import inputs
+
+    spec = inputs.batch_workload(njobs, 12, 20)
+    jobs = []
+    for na, nb, sa, sb in spec:
+        a = torch.from_numpy(inputs.random_poly(sa, na).view(np.int64).copy()).cuda()
+        b = torch.from_numpy(inputs.random_poly(sb, nb).view(np.int64).copy()).cuda()
+        c = torch.zeros(P.out_words(na, nb), dtype=torch.int64, device="cuda")
+        jobs.append((a, na, b, nb, c))
+    stream = torch.cuda.current_stream()
+    res = {"jobs": njobs, "lengths": "floor(2^u), u ~ U[12, 20] bits, a and b independent"}
+
+    def timed(run):
+        run()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            run()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / reps
+
+    def loop():
+        for (a, na, b, nb, c) in jobs:
+            ctx.mul_into(a, na, b, nb, c, stream)
+
+    t_loop = timed(loop)
+    res["loop_products_per_s"] = round(njobs / t_loop, 1)
+    out = {}
+    for name, persistent in (("staged_graph", False), ("persistent_graph", True)):
+        B = ctx.batch(jobs, persistent=persistent)
+        t = timed(lambda: B.run(stream))
+        B.check()
+        st = B.stats()
+        out[name] = t
+        res[f"{name}_products_per_s"] = round(njobs / t, 1)
+        res[f"{name}_launches"] = st["launches"]
+        B.close()
+    best = min(out, key=out.get)
+    res["best"] = best
+    res["speedup_vs_loop"] = round(t_loop / out[best], 2)
+    # spot check against the oracle
+    import oracle
+
+    for k in (0, njobs // 2, njobs - 1):
+        a, na, b, nb, c = jobs[k]
+        got = c.cpu().numpy().view(np.uint64)
+        ref = oracle.mul(a.cpu().numpy().view(np.uint64), na, b.cpu().numpy().view(np.uint64), nb)
+        assert np.array_equal(got, ref), f"batched job {k} differs from the oracle"
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -98,6 +158,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="c3a", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched-products measurement")
+    ap.add_argument("--batch-jobs", type=int, default=4096)
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="first run a plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -206,6 +268,9 @@ def main():
         "roofline": roofline,
         "stages_ms": stages,
     }
+    if not args.no_batch:
+        log(f"bench: batched products ({args.batch_jobs} jobs)")
+        out["batched"] = bench_batched(ctx, args.batch_jobs)
     if not args.no_cpu_baseline:
         log("bench: timing the oracle on a bounded sample")
         out["cpu_baseline"] = cpu_baseline(n, seeds)

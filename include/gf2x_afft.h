@@ -125,9 +125,11 @@ typedef struct {
     uint64_t *c;
 } gf2x_job;
 
-/* Independent products of uneven sizes, enqueued on `stream`.  `jobs` is HOST
- * memory and may be reused as soon as the call returns.  Each job's result is
- * bit-identical to gf2x_mul_dev on the same operands. */
+/* Independent products of uneven sizes, enqueued on `stream` (a one-shot
+ * batch: see gf2x_batch_create).  `jobs` is HOST memory and may be reused as
+ * soon as the call returns.  Each job's result is bit-identical to
+ * gf2x_mul_dev on the same operands.  The plan is kept by the context until
+ * its next gf2x_mul_batch call (which first waits for it). */
 int gf2x_mul_batch(gf2x_ctx *ctx, const gf2x_job *jobs, size_t njobs, void *stream);
 
 /* ---- tracing: per-kernel timing with HIP events (Sec. "Results" profiles the
@@ -152,6 +154,43 @@ int gf2x_trace_begin(gf2x_ctx *ctx, uint32_t kind_mask);
  * memory); returns the number of records available (may exceed max), or a
  * negative status.  The records are cleared afterwards. */
 int64_t gf2x_trace_read(gf2x_ctx *ctx, gf2x_trace_rec *out, size_t max);
+
+/* ---- reusable batches.  A batch fixes its jobs (device pointers and sizes)
+ * at creation: the library plans every product, allocates the batch's own
+ * workspace and uploads the op descriptors (synchronously).  Each run then
+ * enqueues all products on `stream`: op r of every job runs in one launch per
+ * kernel kind, rank after rank.  The first run records the launch sequence as
+ * a hipGraph on the context's stream; later runs replay the graph.  The
+ * operand and product buffers must stay valid while the batch exists; runs of
+ * one batch must not overlap (they share its workspace). */
+typedef struct gf2x_batch gf2x_batch;
+
+typedef struct {
+    uint64_t ops;             /* ops of all jobs */
+    uint64_t ranks;           /* longest op list of a job */
+    uint64_t launches;        /* kernel launches per run */
+    uint64_t tiles;           /* work tiles per run */
+    uint64_t workspace_bytes; /* device memory held by the batch */
+} gf2x_batch_stats;
+
+/* Execution modes: STAGED runs rank after rank, one launch per kernel kind;
+ * PERSISTENT runs the whole batch in one launch of a persistent kernel (one
+ * block per CU) whose blocks take (op, tile) items of a rank from a counter
+ * and meet at a grid barrier between ranks (bounded wait: on timeout the run
+ * stops early and gf2x_batch_check reports GF2X_EDEVICE). */
+enum { GF2X_BATCH_STAGED = 0, GF2X_BATCH_PERSISTENT = 1 };
+
+int gf2x_batch_create(gf2x_ctx *ctx, const gf2x_job *jobs, size_t njobs, int mode, gf2x_batch **batch);
+int gf2x_batch_run(gf2x_batch *batch, void *stream);
+/* Waits for the device, then reports whether the last persistent run finished
+ * every item (GF2X_OK) or stopped on a wait timeout (GF2X_EDEVICE). */
+int gf2x_batch_check(gf2x_batch *batch);
+/* Polls a persistent run's barrier wait may make before the run is abandoned
+ * (default 2^26, about 4 s); 0 abandons it at the first wait. */
+int gf2x_batch_set_spin_limit(gf2x_batch *batch, uint32_t polls);
+int gf2x_batch_info(const gf2x_batch *batch, gf2x_batch_stats *stats);
+/* Synchronizes the device, then frees the batch. NULL is ignored. */
+void gf2x_batch_destroy(gf2x_batch *batch);
 
 /* Name of a status code. */
 const char *gf2x_strerror(int status);

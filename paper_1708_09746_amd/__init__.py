@@ -39,6 +39,11 @@ KIND_NAMES = ["pack", "basiscvt_tile", "basiscvt_layer", "fft_pass", "pointmul",
 KERNEL_OF_KIND = ["k_pack", "k_bc_tile", "k_bc_layer", "k_fft", "k_pmul", "k_psi", "k_bc_class"]
 
 
+class BatchStats(ctypes.Structure):
+    _fields_ = [("ops", ctypes.c_uint64), ("ranks", ctypes.c_uint64), ("launches", ctypes.c_uint64),
+                ("tiles", ctypes.c_uint64), ("workspace_bytes", ctypes.c_uint64)]
+
+
 class Job(ctypes.Structure):
     _fields_ = [("a", ctypes.c_void_p), ("na_bits", ctypes.c_uint64), ("b", ctypes.c_void_p),
                 ("nb_bits", ctypes.c_uint64), ("c", ctypes.c_void_p)]
@@ -65,6 +70,12 @@ def lib():
             "gf2x_inverse_dev": (i32, [vp, vp, i32, vp, u64, vp]),
             "gf2x_basiscvt_dev": (i32, [vp, vp, i32, i32, vp]),
             "gf2x_mul_batch": (i32, [vp, ctypes.POINTER(Job), sz, vp]),
+            "gf2x_batch_create": (i32, [vp, ctypes.POINTER(Job), sz, i32, ctypes.POINTER(vp)]),
+            "gf2x_batch_check": (i32, [vp]),
+            "gf2x_batch_set_spin_limit": (i32, [vp, ctypes.c_uint32]),
+            "gf2x_batch_run": (i32, [vp, vp]),
+            "gf2x_batch_info": (i32, [vp, ctypes.POINTER(BatchStats)]),
+            "gf2x_batch_destroy": (None, [vp]),
             "gf2x_trace_begin": (i32, [vp, ctypes.c_uint32]),
             "gf2x_trace_read": (ctypes.c_int64, [vp, ctypes.POINTER(TraceRec), sz]),
             "gf2x_strerror": (ctypes.c_char_p, [i32]),
@@ -160,11 +171,12 @@ class Context:
 
     def mul_batch(self, jobs, stream=None):
         """jobs: list of (a, na_bits, b, nb_bits, c) with device tensors."""
-        arr = (Job * max(len(jobs), 1))()
-        for i, (a, na, b, nb, c) in enumerate(jobs):
-            arr[i] = Job(int(a.data_ptr()), na, int(b.data_ptr()), nb, int(c.data_ptr()))
-        rc = lib().gf2x_mul_batch(self._h, arr, len(jobs), _stream_handle(stream))
+        rc = lib().gf2x_mul_batch(self._h, _job_array(jobs), len(jobs), _stream_handle(stream))
         self._check(rc, "gf2x_mul_batch")
+
+    def batch(self, jobs, persistent: bool = False):
+        """A reusable Batch of (a, na_bits, b, nb_bits, c) device-tensor jobs."""
+        return Batch(self, jobs, persistent)
 
     # ---- tracing
     def trace_begin(self, kind_mask: int = 0x7F):
@@ -220,6 +232,56 @@ class Context:
         rc = lib().gf2x_basiscvt_dev(self._h, _ptr(words), log2n, 1 if inverse else 0, _stream_handle(stream))
         self._check(rc, "gf2x_basiscvt_dev")
         return words
+
+
+def _job_array(jobs):
+    arr = (Job * max(len(jobs), 1))()
+    for i, (a, na, b, nb, c) in enumerate(jobs):
+        arr[i] = Job(int(a.data_ptr()), na, int(b.data_ptr()), nb, int(c.data_ptr()))
+    return arr
+
+
+class Batch:
+    """Products planned once (gf2x_batch_create) and run many times; the first
+    run records a hipGraph that later runs replay."""
+
+    STAGED, PERSISTENT = 0, 1
+
+    def __init__(self, ctx: "Context", jobs, persistent: bool = False):
+        self.ctx = ctx
+        self.jobs = list(jobs)  # keeps the tensors alive
+        self.mode = self.PERSISTENT if persistent else self.STAGED
+        h = ctypes.c_void_p()
+        rc = lib().gf2x_batch_create(ctx.handle, _job_array(self.jobs), len(self.jobs), self.mode, ctypes.byref(h))
+        ctx._check(rc, "gf2x_batch_create")
+        self._h = h
+
+    def run(self, stream=None):
+        rc = lib().gf2x_batch_run(self._h, _stream_handle(stream))
+        self.ctx._check(rc, "gf2x_batch_run")
+
+    def set_spin_limit(self, polls: int):
+        self.ctx._check(lib().gf2x_batch_set_spin_limit(self._h, polls), "gf2x_batch_set_spin_limit")
+
+    def check(self):
+        """Wait for the device; raise if the last persistent run stopped early."""
+        self.ctx._check(lib().gf2x_batch_check(self._h), "gf2x_batch_check")
+
+    def stats(self) -> dict:
+        st = BatchStats()
+        lib().gf2x_batch_info(self._h, ctypes.byref(st))
+        return {k: int(getattr(st, k)) for k, _ in BatchStats._fields_}
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().gf2x_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def mul_host(a, na_bits: int, b, nb_bits: int):

@@ -5,6 +5,7 @@
 #include <cstdio>
 #include <cstring>
 #include <mutex>
+#include <type_traits>
 #include <string>
 #include <vector>
 
@@ -124,6 +125,266 @@ __global__ __launch_bounds__(kThreads) void k_psi(PsiOp P, const uint4* g_psi) {
     for (uint64_t t = blockIdx.x; t < nt; t += gridDim.x) psi_tile(threadIdx.x, blockDim.x, t, P, tab);
 }
 
+// ------------------------------------------------------- multi-op kernels
+// One launch runs the tiles of an array of ops of one kind (a batch group).
+// Block b takes a contiguous chunk of the tiles, so consecutive tiles mostly
+// belong to the same op.
+
+__device__ inline void block_chunk(uint64_t total, uint64_t& g0, uint64_t& g1) {
+    uint64_t per = (total + gridDim.x - 1) / gridDim.x;
+    g0 = (uint64_t)blockIdx.x * per;
+    g1 = g0 + per < total ? g0 + per : total;
+}
+
+__global__ __launch_bounds__(kThreads) void k_pack_multi(const PackOp* ops, const uint64_t* prefix, int nops,
+                                                         uint64_t total) {
+    uint64_t g0, g1;
+    block_chunk(total, g0, g1);
+    int o = -1;
+    for (uint64_t g = g0; g < g1; ++g) {
+        o = op_of_tile(prefix, nops, g, o);
+        pack_tile(threadIdx.x, blockDim.x, g - prefix[o], ops[o]);
+    }
+}
+
+template <int WIDE>
+__global__ __launch_bounds__(kThreads) void k_bc_tile_multi(const BcTileOp* ops, const uint64_t* prefix, int nops,
+                                                            uint64_t total) {
+    __shared__ uint4 lds[1 << kBcTileLog128];
+    uint64_t g0, g1;
+    block_chunk(total, g0, g1);
+    int o = -1;
+    for (uint64_t g = g0; g < g1; ++g) {
+        o = op_of_tile(prefix, nops, g, o);
+        const BcTileOp B = ops[o];
+        if (WIDE)
+            bc_tile<uint4>(threadIdx.x, blockDim.x, g - prefix[o], B, lds);
+        else
+            bc_tile<uint64_t>(threadIdx.x, blockDim.x, g - prefix[o], B, (uint64_t*)lds);
+    }
+}
+
+template <int WIDE>
+__global__ __launch_bounds__(kThreads) void k_bc_class_multi(const BcClassOp* ops, const uint64_t* prefix, int nops,
+                                                             uint64_t total) {
+    __shared__ uint4 lds[1 << kBcTileLog128];
+    uint64_t g0, g1;
+    block_chunk(total, g0, g1);
+    int o = -1;
+    for (uint64_t g = g0; g < g1; ++g) {
+        o = op_of_tile(prefix, nops, g, o);
+        const BcClassOp C = ops[o];
+        if (WIDE)
+            bc_class_tile<uint4>(threadIdx.x, blockDim.x, g - prefix[o], C, lds);
+        else
+            bc_class_tile<uint64_t>(threadIdx.x, blockDim.x, g - prefix[o], C, (uint64_t*)lds);
+    }
+}
+
+__global__ __launch_bounds__(kThreads) void k_fft_multi(const FftPass* ops, const uint64_t* prefix, int nops,
+                                                        uint64_t total, const uint8_t* g_mt, const uint32_t* g_lam,
+                                                        const uint4* g_phi) {
+    __shared__ __align__(16) uint8_t mt[65536];
+    __shared__ uint32_t lam[1024];
+    __shared__ uint4 tl[1 << kFftTileLog];
+    __shared__ uint4 mu[1 << kFftTileLog];
+    __shared__ uint4 mu_tile[32];
+    const int tid = threadIdx.x, nt = blockDim.x;
+    copy_words(tid, nt, (uint32_t*)mt, (const uint32_t*)g_mt, 16384);
+    copy_words(tid, nt, lam, g_lam, 1024);
+    __syncthreads();
+    uint64_t g0, g1;
+    block_chunk(total, g0, g1);
+    int o = -1;
+    uint32_t cur_lo = ~0u, cur_hi = ~0u;
+    for (uint64_t g = g0; g < g1; ++g) {
+        o = op_of_tile(prefix, nops, g, o);
+        const FftPass A = ops[o];
+        if (A.lo != cur_lo || A.hi != cur_hi) {
+            // the local mu-sets depend only on the layer range of the pass
+            fft_local_mu(tid, nt, A, mt, lam, mu);
+            cur_lo = A.lo;
+            cur_hi = A.hi;
+        }
+        fft_tile<1>(tid, nt, g - prefix[o], A, mt, lam, g_phi, tl, mu, mu_tile);
+    }
+}
+
+__global__ __launch_bounds__(kThreads) void k_pmul_multi(const PmulOp* ops, const uint64_t* prefix, int nops,
+                                                         uint64_t total, const uint8_t* g_mt) {
+    __shared__ __align__(16) uint8_t mt[65536];
+    copy_words(threadIdx.x, blockDim.x, (uint32_t*)mt, (const uint32_t*)g_mt, 16384);
+    __syncthreads();
+    uint64_t g0, g1;
+    block_chunk(total, g0, g1);
+    int o = -1;
+    for (uint64_t g = g0; g < g1; ++g) {
+        o = op_of_tile(prefix, nops, g, o);
+        pmul_tile(threadIdx.x, blockDim.x, g - prefix[o], ops[o], mt);
+    }
+}
+
+__global__ __launch_bounds__(kThreads) void k_psi_multi(const PsiOp* ops, const uint64_t* prefix, int nops,
+                                                        uint64_t total, const uint4* g_psi) {
+    __shared__ uint4 tab[16 * 256];
+    copy_words(threadIdx.x, blockDim.x, tab, g_psi, 16 * 256);
+    __syncthreads();
+    uint64_t g0, g1;
+    block_chunk(total, g0, g1);
+    int o = -1;
+    for (uint64_t g = g0; g < g1; ++g) {
+        o = op_of_tile(prefix, nops, g, o);
+        psi_tile(threadIdx.x, blockDim.x, g - prefix[o], ops[o], tab);
+    }
+}
+
+// ------------------------------------------------ persistent batch kernel
+// All tiles of a batch in one launch.  Items (op, tile) are numbered rank by
+// rank; inside a rank, blocks take items from the rank's counter, and the
+// grid meets at a barrier between ranks (op r of a job needs op r - 1 done).
+// Every block is resident (one per CU), and every wait is bounded: a timeout
+// raises the abort flag, after which all blocks leave.
+struct DevOp {
+    int kind;
+    int wide;
+    int pad0;
+    uint32_t tiles;  // tiles of this op
+    union {
+        PackOp pack;
+        BcTileOp bct;
+        BcLayerOp bcl;
+        FftPass fft;
+        PmulOp pmul;
+        PsiOp psi;
+        BcClassOp bcc;
+    };
+};
+
+struct PersistArgs {
+    const DevOp* ops;
+    const uint64_t* prefix;      // first item of each op (ops in item order), prefix[nops] = items
+    const uint64_t* rank_first;  // first item of each rank, rank_first[nranks] = items
+    int nops;
+    int nranks;
+    uint64_t items;
+    unsigned long long* next;    // per rank: item counter
+    uint32_t* arrive;            // per rank: blocks past the rank
+    uint32_t* abort;             // set when a wait times out
+    uint32_t spin_limit;
+};
+
+__global__ __launch_bounds__(kThreads) void k_zero_u32(uint32_t* p, uint64_t n) {
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x) p[i] = 0;
+}
+
+__global__ __launch_bounds__(kThreads) void k_persistent(PersistArgs P, const uint8_t* g_mt, const uint32_t* g_lam,
+                                                         const uint4* g_phi, const uint4* g_psi) {
+    __shared__ __align__(16) uint8_t mt[65536];
+    __shared__ uint32_t lam[1024];
+    __shared__ uint4 work[2 << kFftTileLog];  // FFT tile + local mu-sets, a BasisCvt tile, or the Psi table
+    __shared__ uint4 mu_tile[32];
+    __shared__ uint64_t s_item;
+    __shared__ int s_stop;
+    const int tid = threadIdx.x, nt = blockDim.x;
+    copy_words(tid, nt, (uint32_t*)mt, (const uint32_t*)g_mt, 16384);
+    copy_words(tid, nt, lam, g_lam, 1024);
+    uint4* tl = work;
+    uint4* mu = work + (1 << kFftTileLog);
+    // what `work` holds: 0 nothing reusable, 1 FFT local mu-sets of (cur_lo, cur_hi), 2 the Psi table
+    int held = 0;
+    uint32_t cur_lo = ~0u, cur_hi = ~0u;
+    int o = -1;
+    for (int r = 0; r < P.nranks; ++r) {
+        const uint64_t end = P.rank_first[r + 1];
+        while (true) {
+            __syncthreads();
+            if (tid == 0) {
+                uint64_t it = end;
+                if (!__hip_atomic_load(P.abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+                    it = P.rank_first[r] + __hip_atomic_fetch_add(&P.next[r], 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                s_item = it;
+            }
+            __syncthreads();
+            const uint64_t item = s_item;
+            if (item >= end) break;
+            o = op_of_tile(P.prefix, P.nops, item, -1);
+            const DevOp& D = P.ops[o];
+            const uint64_t t = item - P.prefix[o];
+            switch ((OpKind)D.kind) {
+                case OpKind::Pack: pack_tile(tid, nt, t, D.pack); break;
+                case OpKind::BcTile:
+                    if (D.wide)
+                        bc_tile<uint4>(tid, nt, t, D.bct, work);
+                    else
+                        bc_tile<uint64_t>(tid, nt, t, D.bct, (uint64_t*)work);
+                    held = 0;
+                    break;
+                case OpKind::BcClass:
+                    if (D.wide)
+                        bc_class_tile<uint4>(tid, nt, t, D.bcc, work);
+                    else
+                        bc_class_tile<uint64_t>(tid, nt, t, D.bcc, (uint64_t*)work);
+                    held = 0;
+                    break;
+                case OpKind::BcLayer: {
+                    // one item covers one global layer part (only very long jobs)
+                    const BcLayerOp L = D.bcl;
+                    if (L.wide)
+                        bc_part<uint4>(tid, nt, (uint4*)L.data, L.nelem, L.layer, (int)L.which);
+                    else
+                        bc_part<uint64_t>(tid, nt, (uint64_t*)L.data, L.nelem, L.layer, (int)L.which);
+                    break;
+                }
+                case OpKind::Fft: {
+                    const FftPass A = D.fft;
+                    if (held != 1 || A.lo != cur_lo || A.hi != cur_hi) {
+                        fft_local_mu(tid, nt, A, mt, lam, mu);
+                        held = 1;
+                        cur_lo = A.lo;
+                        cur_hi = A.hi;
+                    }
+                    fft_tile<1>(tid, nt, t, A, mt, lam, g_phi, tl, mu, mu_tile);
+                    break;
+                }
+                case OpKind::Pmul: pmul_tile(tid, nt, t, D.pmul, mt); break;
+                case OpKind::Psi:
+                    if (held != 2) {
+                        copy_words(tid, nt, work, g_psi, 16 * 256);
+                        __syncthreads();
+                        held = 2;
+                    }
+                    psi_tile(tid, nt, t, D.psi, work);
+                    break;
+            }
+        }
+        // grid barrier between ranks: release this block's writes, arrive,
+        // wait for every block, acquire
+        __threadfence();
+        __syncthreads();
+        if (tid == 0) {
+            int stop = 0;
+            __hip_atomic_fetch_add(&P.arrive[r], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            uint32_t spins = 0;
+            while (__hip_atomic_load(&P.arrive[r], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < gridDim.x) {
+                if (__hip_atomic_load(P.abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+                    stop = 1;
+                    break;
+                }
+                if (++spins > P.spin_limit) {
+                    __hip_atomic_store(P.abort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    stop = 1;
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(2);
+            }
+            s_stop = stop;
+        }
+        __syncthreads();
+        if (s_stop) break;
+        __threadfence();
+    }
+}
+
 // ------------------------------------------------------------------ context
 
 struct gf2x_ctx {
@@ -139,6 +400,11 @@ struct gf2x_ctx {
     size_t io_bytes = 0;
     hipStream_t own_stream = nullptr;
     std::string err;
+    gf2x_batch* transient = nullptr;  // the last gf2x_mul_batch call's plan
+    hipStream_t transient_stream = nullptr;
+    LayerPool pool;  // BasisCvt layer lists; pool.base points at d_layers
+    BcLayer* d_layers = nullptr;
+    PlanParams params;
     // tracing
     uint32_t trace_mask = 0;
     struct Pending {
@@ -146,6 +412,32 @@ struct gf2x_ctx {
         hipEvent_t start, stop;
     };
     std::vector<Pending> trace;
+};
+
+struct gf2x_batch {
+    gf2x_ctx* ctx = nullptr;
+    int mode = 0;
+    BatchPlan plan;
+    char* ws = nullptr;
+    char* desc = nullptr;
+    size_t desc_bytes = 0;
+    struct Group {
+        OpKind kind;
+        int wide;
+        size_t ops_off, prefix_off;
+        int nops;
+        uint64_t total;
+    };
+    std::vector<Group> groups;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    bool use_graph = true;
+    // persistent mode: ops in item order, their item prefix, scheduler state
+    char* pdesc = nullptr;
+    size_t p_ops_off = 0, p_prefix_off = 0, p_rank_off = 0, p_state_off = 0, p_state_words = 0;
+    int p_nops = 0, p_nranks = 0;
+    uint64_t p_items = 0;
+    uint32_t spin_limit = 1u << 26;
 };
 
 namespace {
@@ -317,6 +609,259 @@ int run_ops(gf2x_ctx* ctx, const std::vector<Op>& ops, hipStream_t st) {
     return GF2X_OK;
 }
 
+// Upload every group's op array and tile prefix sums in one copy.
+int batch_upload(gf2x_batch* B) {
+    gf2x_ctx* ctx = B->ctx;
+    std::vector<char> host;
+    auto put = [&](const void* p, size_t n) {
+        size_t off = (host.size() + 255) & ~(size_t)255;
+        host.resize(off + n);
+        memcpy(host.data() + off, p, n);
+        return off;
+    };
+    B->groups.clear();
+    for (const BatchGroup& G : B->plan.groups) {
+        gf2x_batch::Group d{};
+        d.kind = G.kind;
+        d.wide = G.wide;
+        d.nops = (int)G.ops.size();
+        std::vector<uint64_t> prefix(G.ops.size() + 1, 0);
+        for (size_t i = 0; i < G.ops.size(); ++i) prefix[i + 1] = prefix[i] + op_tiles(B->plan.ops[G.ops[i]]);
+        d.total = prefix.back();
+        auto gather = [&](auto member) {
+            using T = std::decay_t<decltype(B->plan.ops[0].*member)>;
+            std::vector<T> v;
+            for (uint32_t i : G.ops) v.push_back(B->plan.ops[i].*member);
+            return put(v.data(), v.size() * sizeof(T));
+        };
+        switch (G.kind) {
+            case OpKind::Pack: d.ops_off = gather(&Op::pack); break;
+            case OpKind::BcTile: d.ops_off = gather(&Op::bct); break;
+            case OpKind::BcLayer: d.ops_off = gather(&Op::bcl); break;
+            case OpKind::Fft: d.ops_off = gather(&Op::fft); break;
+            case OpKind::Pmul: d.ops_off = gather(&Op::pmul); break;
+            case OpKind::Psi: d.ops_off = gather(&Op::psi); break;
+            case OpKind::BcClass: d.ops_off = gather(&Op::bcc); break;
+        }
+        d.prefix_off = put(prefix.data(), prefix.size() * sizeof(uint64_t));
+        B->groups.push_back(d);
+    }
+    B->desc_bytes = host.size();
+    hipError_t e = hipMalloc((void**)&B->desc, std::max<size_t>(host.size(), 256));
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(ctx, GF2X_ENOMEM, "batch descriptors");
+    }
+    e = hipMemcpy(B->desc, host.data(), host.size(), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail(ctx, e, "batch descriptor upload");
+    return GF2X_OK;
+}
+
+int batch_launch_groups(gf2x_batch* B, hipStream_t st) {
+    gf2x_ctx* ctx = B->ctx;
+    const uint64_t ncu = (uint64_t)ctx->ncu;
+    for (const auto& G : B->groups) {
+        const uint64_t* prefix = (const uint64_t*)(B->desc + G.prefix_off);
+        const void* ops = B->desc + G.ops_off;
+        switch (G.kind) {
+            case OpKind::Pack:
+                hipLaunchKernelGGL(k_pack_multi, dim3(grid_for(G.total, 8 * ncu)), dim3(kThreads), 0, st,
+                                   (const PackOp*)ops, prefix, G.nops, G.total);
+                break;
+            case OpKind::BcTile:
+                if (G.wide)
+                    hipLaunchKernelGGL(k_bc_tile_multi<1>, dim3(grid_for(G.total, 2 * ncu)), dim3(kThreads), 0, st,
+                                       (const BcTileOp*)ops, prefix, G.nops, G.total);
+                else
+                    hipLaunchKernelGGL(k_bc_tile_multi<0>, dim3(grid_for(G.total, 2 * ncu)), dim3(kThreads), 0, st,
+                                       (const BcTileOp*)ops, prefix, G.nops, G.total);
+                break;
+            case OpKind::BcClass:
+                if (G.wide)
+                    hipLaunchKernelGGL(k_bc_class_multi<1>, dim3(grid_for(G.total, 2 * ncu)), dim3(kThreads), 0, st,
+                                       (const BcClassOp*)ops, prefix, G.nops, G.total);
+                else
+                    hipLaunchKernelGGL(k_bc_class_multi<0>, dim3(grid_for(G.total, 2 * ncu)), dim3(kThreads), 0, st,
+                                       (const BcClassOp*)ops, prefix, G.nops, G.total);
+                break;
+            case OpKind::BcLayer: {
+                // global layers (only for very long jobs): one launch per op
+                for (int i = 0; i < G.nops; ++i) {
+                    const Op& op = B->plan.ops[B->plan.groups[&G - &B->groups[0]].ops[i]];
+                    uint64_t blocks = (op.bcl.nelem / 2 + kThreads - 1) / kThreads;
+                    if (op.bcl.wide)
+                        hipLaunchKernelGGL(k_bc_layer<1>, dim3(grid_for(blocks, 16 * ncu)), dim3(kThreads), 0, st, op.bcl);
+                    else
+                        hipLaunchKernelGGL(k_bc_layer<0>, dim3(grid_for(blocks, 16 * ncu)), dim3(kThreads), 0, st, op.bcl);
+                }
+                break;
+            }
+            case OpKind::Fft:
+                hipLaunchKernelGGL(k_fft_multi, dim3(grid_for(G.total, ncu)), dim3(kThreads), 0, st, (const FftPass*)ops,
+                                   prefix, G.nops, G.total, (const uint8_t*)ctx->d_mt, (const uint32_t*)ctx->d_lam,
+                                   (const uint4*)ctx->d_phi);
+                break;
+            case OpKind::Pmul:
+                hipLaunchKernelGGL(k_pmul_multi, dim3(grid_for(G.total, 2 * ncu)), dim3(kThreads), 0, st,
+                                   (const PmulOp*)ops, prefix, G.nops, G.total, (const uint8_t*)ctx->d_mt);
+                break;
+            case OpKind::Psi:
+                hipLaunchKernelGGL(k_psi_multi, dim3(grid_for(G.total, 2 * ncu)), dim3(kThreads), 0, st,
+                                   (const PsiOp*)ops, prefix, G.nops, G.total, (const uint4*)ctx->d_psi);
+                break;
+        }
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return hip_fail(ctx, e, "batch launch");
+    }
+    return GF2X_OK;
+}
+
+// Persistent mode: one array of DevOp in item order (group after group, so
+// rank by rank), the op and rank item prefixes, then the scheduler words
+// (abort flag, per-rank arrive counters, per-rank 64-bit item counters).
+int batch_upload_persistent(gf2x_batch* B) {
+    gf2x_ctx* ctx = B->ctx;
+    const BatchPlan& P = B->plan;
+    std::vector<DevOp> dops;
+    std::vector<uint64_t> prefix(1, 0);
+    std::vector<uint64_t> rank_first;
+    uint32_t cur_rank = ~0u;
+    for (const BatchGroup& G : P.groups)
+        for (uint32_t i : G.ops) {
+            const Op& op = P.ops[i];
+            if (P.rank_of[i] != cur_rank) {
+                cur_rank = P.rank_of[i];
+                rank_first.push_back(prefix.back());
+            }
+            DevOp d;
+            memset(&d, 0, sizeof(d));
+            d.kind = (int)op.kind;
+            d.wide = op_wide(op);
+            d.tiles = (uint32_t)(op.kind == OpKind::BcLayer ? 1 : op_tiles(op));
+            switch (op.kind) {
+                case OpKind::Pack: d.pack = op.pack; break;
+                case OpKind::BcTile: d.bct = op.bct; break;
+                case OpKind::BcLayer: d.bcl = op.bcl; break;
+                case OpKind::Fft: d.fft = op.fft; break;
+                case OpKind::Pmul: d.pmul = op.pmul; break;
+                case OpKind::Psi: d.psi = op.psi; break;
+                case OpKind::BcClass: d.bcc = op.bcc; break;
+            }
+            dops.push_back(d);
+            prefix.push_back(prefix.back() + d.tiles);
+        }
+    rank_first.push_back(prefix.back());
+    const int nranks = (int)rank_first.size() - 1;
+    size_t off = 0;
+    B->p_ops_off = off;
+    off = align256(off + dops.size() * sizeof(DevOp));
+    B->p_prefix_off = off;
+    off = align256(off + prefix.size() * sizeof(uint64_t));
+    B->p_rank_off = off;
+    off = align256(off + rank_first.size() * sizeof(uint64_t));
+    B->p_state_off = off;
+    B->p_state_words = 2 + (size_t)nranks + 2 * (size_t)nranks;  // abort, pad, arrive[], next[] (64-bit)
+    if (B->p_state_words & 1) ++B->p_state_words;
+    off = align256(off + B->p_state_words * sizeof(uint32_t));
+    hipError_t e = hipMalloc((void**)&B->pdesc, off);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(ctx, GF2X_ENOMEM, "persistent batch descriptors");
+    }
+    std::vector<char> host(off, 0);
+    memcpy(host.data() + B->p_ops_off, dops.data(), dops.size() * sizeof(DevOp));
+    memcpy(host.data() + B->p_prefix_off, prefix.data(), prefix.size() * sizeof(uint64_t));
+    memcpy(host.data() + B->p_rank_off, rank_first.data(), rank_first.size() * sizeof(uint64_t));
+    e = hipMemcpy(B->pdesc, host.data(), off, hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail(ctx, e, "persistent descriptor upload");
+    B->p_nops = (int)dops.size();
+    B->p_nranks = nranks;
+    B->p_items = prefix.back();
+    return GF2X_OK;
+}
+
+PersistArgs persist_args(gf2x_batch* B) {
+    PersistArgs a;
+    a.ops = (const DevOp*)(B->pdesc + B->p_ops_off);
+    a.prefix = (const uint64_t*)(B->pdesc + B->p_prefix_off);
+    a.rank_first = (const uint64_t*)(B->pdesc + B->p_rank_off);
+    a.nops = B->p_nops;
+    a.nranks = B->p_nranks;
+    a.items = B->p_items;
+    uint32_t* st = (uint32_t*)(B->pdesc + B->p_state_off);
+    a.abort = st;
+    a.arrive = st + 2;
+    size_t nxt = 2 + (size_t)B->p_nranks;
+    if (nxt & 1) ++nxt;
+    a.next = (unsigned long long*)(st + nxt);
+    a.spin_limit = B->spin_limit;
+    return a;
+}
+
+int batch_launch_persistent(gf2x_batch* B, hipStream_t st) {
+    gf2x_ctx* ctx = B->ctx;
+    PersistArgs a = persist_args(B);
+    uint64_t nstate = B->p_state_words;
+    // scheduler state is cleared by a kernel (kept inside graphs)
+    hipLaunchKernelGGL(k_zero_u32, dim3(grid_for((nstate + kThreads - 1) / kThreads, 64)), dim3(kThreads), 0, st,
+                       (uint32_t*)(B->pdesc + B->p_state_off), nstate);
+    hipLaunchKernelGGL(k_persistent, dim3((unsigned)std::max(1, ctx->ncu)), dim3(kThreads), 0, st, a,
+                       (const uint8_t*)ctx->d_mt, (const uint32_t*)ctx->d_lam, (const uint4*)ctx->d_phi,
+                       (const uint4*)ctx->d_psi);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(ctx, e, "persistent batch launch");
+    return GF2X_OK;
+}
+
+void batch_free(gf2x_batch* B) {
+    if (!B) return;
+    if (B->pdesc) (void)hipFree(B->pdesc);
+    if (B->exec) (void)hipGraphExecDestroy(B->exec);
+    if (B->graph) (void)hipGraphDestroy(B->graph);
+    if (B->ws) (void)hipFree(B->ws);
+    if (B->desc) (void)hipFree(B->desc);
+    delete B;
+}
+
+int check_jobs(gf2x_ctx* ctx, const gf2x_job* jobs, size_t njobs) {
+    for (size_t j = 0; j < njobs; ++j) {
+        const gf2x_job& J = jobs[j];
+        Sizes s = make_sizes(J.na_bits, J.nb_bits);
+        if (!s.out_words) continue;
+        if (!J.a || !J.b || !J.c) return fail(ctx, GF2X_EINVAL, "NULL pointer in job " + std::to_string(j));
+        if (s.m > 32) return fail(ctx, GF2X_ERANGE, "job " + std::to_string(j) + " too long");
+        if (ranges_overlap(J.c, 8 * s.out_words, J.a, 8 * s.n_a) || ranges_overlap(J.c, 8 * s.out_words, J.b, 8 * s.n_b))
+            return fail(ctx, GF2X_EINVAL, "job " + std::to_string(j) + ": product overlaps an operand");
+    }
+    return GF2X_OK;
+}
+
+int batch_build(gf2x_ctx* ctx, const gf2x_job* jobs, size_t njobs, int mode, gf2x_batch** out) {
+    std::vector<BatchJob> bj(njobs);
+    for (size_t j = 0; j < njobs; ++j) bj[j] = BatchJob{jobs[j].a, jobs[j].na_bits, jobs[j].b, jobs[j].nb_bits, jobs[j].c};
+    gf2x_batch* B = new gf2x_batch();
+    B->ctx = ctx;
+    plan_batch(B->plan, ctx->pool, ctx->params, bj.data(), njobs, nullptr);
+    if (B->plan.ws_bytes) {
+        hipError_t e = hipMalloc((void**)&B->ws, B->plan.ws_bytes);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            batch_free(B);
+            return fail(ctx, GF2X_ENOMEM, "batch workspace of " + std::to_string(B->plan.ws_bytes) + " bytes");
+        }
+    }
+    plan_batch(B->plan, ctx->pool, ctx->params, bj.data(), njobs, B->ws);
+    B->mode = mode;
+    int rc = batch_upload(B);
+    if (!rc && mode == GF2X_BATCH_PERSISTENT) rc = batch_upload_persistent(B);
+    if (rc) {
+        batch_free(B);
+        return rc;
+    }
+    *out = B;
+    return GF2X_OK;
+}
+
 constexpr int kMaxLog2N = 32;  // multipliers s_i(v_t) are tabulated for t < 32
 
 int check_ctx(gf2x_ctx* ctx) { return ctx ? GF2X_OK : GF2X_EINVAL; }
@@ -394,6 +939,10 @@ int gf2x_ctx_create(gf2x_ctx** out, int device) {
     if (e == hipSuccess) e = hipMemcpy(ctx->d_lam, lam, sizeof(lam), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(ctx->d_phi, phi.data(), phi.size() * sizeof(uint4), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(ctx->d_psi, psi.data(), psi.size() * sizeof(uint4), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMalloc((void**)&ctx->d_layers, ctx->pool.host.size() * sizeof(BcLayer));
+    if (e == hipSuccess)
+        e = hipMemcpy(ctx->d_layers, ctx->pool.host.data(), ctx->pool.host.size() * sizeof(BcLayer), hipMemcpyHostToDevice);
+    ctx->pool.base = ctx->d_layers;
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&ctx->own_stream, hipStreamNonBlocking);
     if (e != hipSuccess) {
         (void)hipGetLastError();
@@ -412,6 +961,8 @@ void gf2x_ctx_destroy(gf2x_ctx* ctx) {
     if (ctx->d_lam) (void)hipFree(ctx->d_lam);
     if (ctx->d_phi) (void)hipFree(ctx->d_phi);
     if (ctx->d_psi) (void)hipFree(ctx->d_psi);
+    if (ctx->d_layers) (void)hipFree(ctx->d_layers);
+    if (ctx->transient) batch_free(ctx->transient);
     if (ctx->ws) (void)hipFree(ctx->ws);
     if (ctx->io) (void)hipFree(ctx->io);
     if (ctx->own_stream) (void)hipStreamDestroy(ctx->own_stream);
@@ -461,7 +1012,7 @@ int gf2x_mul_dev(gf2x_ctx* ctx, const uint64_t* a, uint64_t na_bits, const uint6
     int rc = ensure_ws(ctx, w.bytes, st);
     if (rc) return rc;
     std::vector<Op> ops;
-    plan_mul(ops, s, a, b, c, ctx->ws);
+    plan_mul(ops, ctx->pool, ctx->params, s, a, b, c, ctx->ws);
     return run_ops(ctx, ops, st);
 }
 
@@ -478,7 +1029,7 @@ int gf2x_forward_dev(gf2x_ctx* ctx, const uint64_t* a, uint64_t na_bits, int log
     int rc = ensure_ws(ctx, align256(8ull << m_a), st);
     if (rc) return rc;
     std::vector<Op> ops;
-    emit_forward(ops, a, na_bits, (uint64_t*)ctx->ws, m_a, (uint4*)spec, log2n);
+    emit_forward(ops, ctx->pool, ctx->params, a, na_bits, (uint64_t*)ctx->ws, m_a, (uint4*)spec, log2n);
     return run_ops(ctx, ops, st);
 }
 
@@ -503,7 +1054,7 @@ int gf2x_inverse_dev(gf2x_ctx* ctx, void* spec, int log2n, uint64_t* c, uint64_t
         return fail(ctx, GF2X_EINVAL, "output overlaps the spectrum");
     DeviceGuard g(ctx->device);
     std::vector<Op> ops;
-    emit_inverse(ops, (uint4*)spec, log2n, c, nc_bits);
+    emit_inverse(ops, ctx->pool, ctx->params, (uint4*)spec, log2n, c, nc_bits);
     return run_ops(ctx, ops, (hipStream_t)stream);
 }
 
@@ -514,7 +1065,7 @@ int gf2x_basiscvt_dev(gf2x_ctx* ctx, uint64_t* words, int log2n, int inverse, vo
     if (log2n < 0 || log2n > 40) return fail(ctx, GF2X_ERANGE, "log2n out of range");
     DeviceGuard g(ctx->device);
     std::vector<Op> ops;
-    emit_bc(ops, words, 0, log2n, inverse ? 1 : 0);
+    emit_bc(ops, ctx->pool, words, 0, log2n, inverse ? 1 : 0);
     return run_ops(ctx, ops, (hipStream_t)stream);
 }
 
@@ -523,28 +1074,113 @@ int gf2x_mul_batch(gf2x_ctx* ctx, const gf2x_job* jobs, size_t njobs, void* stre
     ctx->err.clear();
     if (njobs == 0) return GF2X_OK;
     if (!jobs) return fail(ctx, GF2X_EINVAL, "NULL job array");
-    std::vector<Sizes> sz(njobs);
-    std::vector<size_t> off(njobs);
-    size_t total = 0;
-    for (size_t j = 0; j < njobs; ++j) {
-        const gf2x_job& J = jobs[j];
-        sz[j] = make_sizes(J.na_bits, J.nb_bits);
-        if (!sz[j].out_words) continue;
-        if (!J.a || !J.b || !J.c) return fail(ctx, GF2X_EINVAL, "NULL pointer in job " + std::to_string(j));
-        if (sz[j].m > kMaxLog2N) return fail(ctx, GF2X_ERANGE, "job " + std::to_string(j) + " too long");
-        off[j] = total;
-        total += workspace_for(sz[j]).bytes;
-    }
+    int rc = check_jobs(ctx, jobs, njobs);
+    if (rc) return rc;
     DeviceGuard g(ctx->device);
     hipStream_t st = (hipStream_t)stream;
-    int rc = ensure_ws(ctx, total, st);
-    if (rc) return rc;
-    std::vector<Op> ops;
-    for (size_t j = 0; j < njobs; ++j) {
-        if (!sz[j].out_words) continue;
-        plan_mul(ops, sz[j], jobs[j].a, jobs[j].b, jobs[j].c, ctx->ws + off[j]);
+    // the previous call's batch may still be running on its stream
+    if (ctx->transient) {
+        hipError_t e = hipStreamSynchronize(ctx->transient_stream);
+        if (e != hipSuccess) return hip_fail(ctx, e, "hipStreamSynchronize");
+        batch_free(ctx->transient);
+        ctx->transient = nullptr;
     }
-    return run_ops(ctx, ops, st);
+    gf2x_batch* B = nullptr;
+    rc = batch_build(ctx, jobs, njobs, GF2X_BATCH_STAGED, &B);
+    if (rc) return rc;
+    ctx->transient = B;
+    ctx->transient_stream = st;
+    return batch_launch_groups(B, st);
+}
+
+int gf2x_batch_create(gf2x_ctx* ctx, const gf2x_job* jobs, size_t njobs, int mode, gf2x_batch** out) {
+    if (check_ctx(ctx) || !out) return GF2X_EINVAL;
+    if (mode != GF2X_BATCH_STAGED && mode != GF2X_BATCH_PERSISTENT) return fail(ctx, GF2X_EINVAL, "unknown batch mode");
+    ctx->err.clear();
+    *out = nullptr;
+    if (njobs && !jobs) return fail(ctx, GF2X_EINVAL, "NULL job array");
+    int rc = check_jobs(ctx, jobs, njobs);
+    if (rc) return rc;
+    DeviceGuard g(ctx->device);
+    return batch_build(ctx, jobs, njobs, mode, out);
+}
+
+int gf2x_batch_run(gf2x_batch* B, void* stream) {
+    if (!B) return GF2X_EINVAL;
+    gf2x_ctx* ctx = B->ctx;
+    ctx->err.clear();
+    DeviceGuard g(ctx->device);
+    hipStream_t st = (hipStream_t)stream;
+    if (B->groups.empty()) return GF2X_OK;
+    auto launch = [&](hipStream_t s) {
+        return B->mode == GF2X_BATCH_PERSISTENT ? batch_launch_persistent(B, s) : batch_launch_groups(B, s);
+    };
+    if (!B->use_graph || ctx->trace_mask) return launch(st);
+    if (!B->exec) {
+        // record the launch sequence once on the context's own stream
+        hipStream_t cs = ctx->own_stream;
+        hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+        if (e != hipSuccess) return hip_fail(ctx, e, "hipStreamBeginCapture");
+        int rc = launch(cs);
+        hipGraph_t graph = nullptr;
+        e = hipStreamEndCapture(cs, &graph);
+        if (rc) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return rc;
+        }
+        if (e != hipSuccess) return hip_fail(ctx, e, "hipStreamEndCapture");
+        B->graph = graph;
+        e = hipGraphInstantiate(&B->exec, graph, nullptr, nullptr, 0);
+        if (e != hipSuccess) return hip_fail(ctx, e, "hipGraphInstantiate");
+    }
+    hipError_t e = hipGraphLaunch(B->exec, st);
+    if (e != hipSuccess) return hip_fail(ctx, e, "hipGraphLaunch");
+    return GF2X_OK;
+}
+
+int gf2x_batch_info(const gf2x_batch* B, gf2x_batch_stats* st) {
+    if (!B || !st) return GF2X_EINVAL;
+    st->launches = 0;
+    for (const auto& G : B->groups) st->launches += G.kind == OpKind::BcLayer ? (uint64_t)G.nops : 1;
+    if (B->mode == GF2X_BATCH_PERSISTENT) st->launches = 2;  // state clear + the persistent kernel
+    st->ops = B->plan.ops.size();
+    st->ranks = B->plan.max_rank;
+    st->workspace_bytes = B->plan.ws_bytes;
+    uint64_t tiles = 0;
+    for (const auto& G : B->groups) tiles += G.total;
+    st->tiles = tiles;
+    return GF2X_OK;
+}
+
+int gf2x_batch_set_spin_limit(gf2x_batch* B, uint32_t polls) {
+    if (!B) return GF2X_EINVAL;
+    B->spin_limit = polls;
+    if (B->exec) {  // the limit is a kernel argument: record the graph again
+        (void)hipGraphExecDestroy(B->exec);
+        (void)hipGraphDestroy(B->graph);
+        B->exec = nullptr;
+        B->graph = nullptr;
+    }
+    return GF2X_OK;
+}
+
+int gf2x_batch_check(gf2x_batch* B) {
+    if (!B) return GF2X_EINVAL;
+    if (B->mode != GF2X_BATCH_PERSISTENT || !B->pdesc) return GF2X_OK;
+    DeviceGuard g(B->ctx->device);
+    uint32_t flag = 0;
+    hipError_t e = hipDeviceSynchronize();
+    if (e == hipSuccess) e = hipMemcpy(&flag, B->pdesc + B->p_state_off, 4, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(B->ctx, e, "gf2x_batch_check");
+    if (flag) return fail(B->ctx, GF2X_EDEVICE, "persistent batch: a dependency wait timed out; results incomplete");
+    return GF2X_OK;
+}
+
+void gf2x_batch_destroy(gf2x_batch* B) {
+    if (!B) return;
+    DeviceGuard g(B->ctx->device);
+    (void)hipDeviceSynchronize();
+    batch_free(B);
 }
 
 int gf2x_mul(const uint64_t* a, uint64_t na_bits, const uint64_t* b, uint64_t nb_bits, uint64_t* c) {

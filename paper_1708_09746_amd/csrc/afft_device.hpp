@@ -24,18 +24,11 @@
 
 namespace gf2x {
 
-constexpr int kMaxBcLayers = 96;
-
 struct BcLayer {
     uint32_t log_d;  // D = 2^log_d units
     uint32_t log_k;  // k = 2^log_k units
     uint32_t log_u;  // unit = 2^log_u elements
     uint32_t pad;
-};
-
-struct BcLayerList {
-    int n;
-    BcLayer l[kMaxBcLayers];
 };
 
 // ------------------------------------------------------------ GF(256) table

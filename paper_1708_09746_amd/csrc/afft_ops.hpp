@@ -11,7 +11,6 @@ namespace gf2x {
 
 constexpr int kThreads = 1024;    // threads per block in every kernel
 constexpr int kFftTileLog = 11;   // FFT tile: up to 2^11 elements (32 KiB)
-constexpr int kFftColRowsLog = 8; // strided passes: up to 2^8 rows per tile
 constexpr int kBcTileLog64 = 13;  // BasisCvt tile on 64-bit words: 64 KiB
 constexpr int kBcTileLog128 = 12; // BasisCvt tile on 128-bit elements: 64 KiB
 constexpr int kPmulTile = 1024;
@@ -113,8 +112,8 @@ struct BcTileOp {
     uint32_t log_rows, log_stride, log_tc;
     uint32_t wide;     // 0: 64-bit words, 1: 128-bit elements
     uint32_t inverse;  // run the layers (and their two parts) in reverse
-    uint32_t pad;
-    BcLayerList layers;
+    uint32_t nlayers;
+    const BcLayer* layers;  // nlayers entries (device memory shared by all ops)
 };
 
 struct BcLayerOp {
@@ -149,9 +148,9 @@ AFFT_HD void bc_tile(int tid, int nt, uint64_t tile, const BcTileOp& B, T* lds) 
         }
     }
     AFFT_SYNC();
-    int n = B.layers.n;
+    const int n = (int)B.nlayers;
     for (int li = 0; li < n; ++li) {
-        const BcLayer& L = B.layers.l[B.inverse ? n - 1 - li : li];
+        const BcLayer L = B.layers[B.inverse ? n - 1 - li : li];
         for (int part = 0; part < 2; ++part) {
             bc_part_lds<T>(tid, nt, lds, ne, L, B.inverse ? 1 - part : part);
             AFFT_SYNC();
@@ -520,6 +519,26 @@ AFFT_HD void psi_tile(int tid, int nt, uint64_t tile, const PsiOp& P, const uint
         if (k == P.nwords - 1 && (P.nbits % 64)) w &= ~0ull >> (64 - P.nbits % 64);
         P.out[k] = w;
     }
+}
+
+// ------------------------------------------------------- op arrays (batches)
+// prefix[o] is the first tile of op o and prefix[nops] the total; op_of_tile
+// returns the op holding tile g, walking forward from `hint` (tiles are
+// visited in increasing order) or searching when hint < 0.
+AFFT_HD int op_of_tile(const uint64_t* prefix, int nops, uint64_t g, int hint) {
+    if (hint < 0) {
+        int lo = 0, hi = nops - 1;
+        while (lo < hi) {
+            int mid = (lo + hi + 1) >> 1;
+            if (prefix[mid] <= g)
+                lo = mid;
+            else
+                hi = mid - 1;
+        }
+        return lo;
+    }
+    while (hint + 1 < nops && prefix[hint + 1] <= g) ++hint;
+    return hint;
 }
 
 }  // namespace gf2x

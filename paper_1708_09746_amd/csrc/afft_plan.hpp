@@ -1,5 +1,6 @@
 // Planning: sizes of a product and the op list that computes it (Alg. 5).
 #pragma once
+#include <algorithm>
 #include <cstdint>
 #include <vector>
 
@@ -68,28 +69,56 @@ inline void bc_layer_list(int m, int log_u, std::vector<BcLayer>& out) {
 
 inline uint64_t bc_span_log(const BcLayer& L) { return L.log_d + 1 + L.log_u; }
 
+// Every layer list a tile op can run (BasisCvt of 2^m units of 2^log_u
+// elements with both at most kPoolMax), stored once; ops point into it.
+constexpr int kPoolMax = 16;
+struct LayerPool {
+    std::vector<BcLayer> host;
+    uint32_t off[kPoolMax + 1][kPoolMax + 1];
+    uint32_t cnt[kPoolMax + 1][kPoolMax + 1];
+    const BcLayer* base = nullptr;  // where the executing side reads `host`
+    LayerPool() {
+        for (int m = 0; m <= kPoolMax; ++m)
+            for (int u = 0; u <= kPoolMax; ++u) {
+                std::vector<BcLayer> L;
+                bc_layer_list(m, u, L);
+                off[m][u] = (uint32_t)host.size();
+                cnt[m][u] = (uint32_t)L.size();
+                host.insert(host.end(), L.begin(), L.end());
+            }
+    }
+    const BcLayer* get(int m, int log_u, uint32_t& n) const {
+        n = cnt[m][log_u];
+        return base + off[m][log_u];
+    }
+};
+
+// Tunable shape of the FFT passes (the autotuner picks them per size class).
+struct PlanParams {
+    int fft_bottom_log = 11;    // contiguous bottom pass: up to 2^this elements
+    int fft_col_rows_log = 8;   // strided passes: up to 2^this rows
+};
+
 struct BcPlanner {
     void* data;
     int wide;
     uint64_t n;         // elements
     int cap_log;        // LDS capacity of a tile, log2 elements
+    const LayerPool* pool;
     std::vector<Op> ops;
 
-    void tile_pass(int log_rows, int log_stride, int log_tc, const std::vector<BcLayer>& L) {
-        for (size_t i = 0; i < L.size(); i += kMaxBcLayers) {
-            Op op{};
-            op.kind = OpKind::BcTile;
-            op.bct.data = data;
-            op.bct.nelem = n;
-            op.bct.log_rows = (uint32_t)log_rows;
-            op.bct.log_stride = (uint32_t)log_stride;
-            op.bct.log_tc = (uint32_t)log_tc;
-            op.bct.wide = (uint32_t)wide;
-            size_t e = std::min(L.size(), i + (size_t)kMaxBcLayers);
-            op.bct.layers.n = (int)(e - i);
-            for (size_t t = i; t < e; ++t) op.bct.layers.l[t - i] = L[t];
-            ops.push_back(op);
-        }
+    // the layers of BasisCvt on 2^m units of 2^log_u LDS elements, on tiles
+    void tile_pass(int log_rows, int log_stride, int log_tc, int m, int log_u) {
+        Op op{};
+        op.kind = OpKind::BcTile;
+        op.bct.data = data;
+        op.bct.nelem = n;
+        op.bct.log_rows = (uint32_t)log_rows;
+        op.bct.log_stride = (uint32_t)log_stride;
+        op.bct.log_tc = (uint32_t)log_tc;
+        op.bct.wide = (uint32_t)wide;
+        op.bct.layers = pool->get(m, log_u, op.bct.nlayers);
+        if (op.bct.nlayers) ops.push_back(op);
     }
 
     void global_layer(const BcLayer& L) {
@@ -111,18 +140,14 @@ struct BcPlanner {
         const int blk_log = m + log_u;
         if (blk_log <= cap_log) {
             // whole blocks fit: a contiguous tile holds 2^(T - blk_log) of them
-            std::vector<BcLayer> L;
-            bc_layer_list(m, log_u, L);
             int T = std::min<int>(cap_log, ceil_log2(n));
-            tile_pass(T, 0, 0, L);
+            tile_pass(T, 0, 0, m, log_u);
             return;
         }
         if (log_u > 0 && m + std::min(log_u, 3) <= cap_log) {
             // strided "column" tiles: all 2^m rows of up to 2^log_tc columns
             int log_tc = std::min(log_u, cap_log - m);
-            std::vector<BcLayer> L;
-            bc_layer_list(m, log_tc, L);  // row units scaled to LDS elements
-            tile_pass(m, log_u, log_tc, L);
+            tile_pass(m, log_u, log_tc, m, log_tc);  // row units scaled to LDS elements
             return;
         }
         int K = 1;
@@ -153,8 +178,8 @@ struct BcPlanner {
 
 // Emit BasisCvt (or its inverse) of 2^m elements at `data`: the forward op
 // list, reversed (each op running its layers backwards) for the inverse.
-inline void emit_bc(std::vector<Op>& ops, void* data, int wide, int m, int inverse) {
-    BcPlanner P{data, wide, 1ull << m, wide ? kBcTileLog128 : kBcTileLog64, {}};
+inline void emit_bc(std::vector<Op>& ops, const LayerPool& pool, void* data, int wide, int m, int inverse) {
+    BcPlanner P{data, wide, 1ull << m, wide ? kBcTileLog128 : kBcTileLog64, &pool, {}};
     P.cvt(m, 0);
     if (!inverse) {
         for (auto& op : P.ops) ops.push_back(op);
@@ -171,11 +196,12 @@ inline void emit_bc(std::vector<Op>& ops, void* data, int wide, int m, int inver
 
 // Layer ranges of the FFT passes: a contiguous bottom pass of up to 2^11
 // elements, and strided passes of up to 2^8 rows above it.
-inline std::vector<std::pair<int, int>> fft_pass_ranges(int M) {
+inline std::vector<std::pair<int, int>> fft_pass_ranges(int M, const PlanParams& pp) {
     std::vector<std::pair<int, int>> col;
-    int bottom = std::min(M, kFftTileLog);
+    int bottom = std::min(M, std::min(pp.fft_bottom_log, kFftTileLog));
     int rem = M - bottom;
-    int ncol = (rem + kFftColRowsLog - 1) / kFftColRowsLog;
+    int rows = std::min(pp.fft_col_rows_log, kFftTileLog);
+    int ncol = (rem + rows - 1) / rows;
     int lo = bottom;
     for (int c = 0; c < ncol; ++c) {
         int sz = rem / ncol + (c < rem % ncol ? 1 : 0);
@@ -195,8 +221,9 @@ inline uint32_t fft_log_tc(int lo, int hi) {
 
 // Forward transform of one operand: `words` holds 2^M converted words; the
 // spectrum has 2^(M + log_cosets) elements.
-inline void emit_fft_forward(std::vector<Op>& ops, const uint64_t* words, uint4* spec, int M, int log_cosets) {
-    auto ranges = fft_pass_ranges(M);
+inline void emit_fft_forward(std::vector<Op>& ops, const PlanParams& pp, const uint64_t* words, uint4* spec, int M,
+                             int log_cosets) {
+    auto ranges = fft_pass_ranges(M, pp);
     for (size_t r = ranges.size(); r-- > 0;) {
         Op op{};
         op.kind = OpKind::Fft;
@@ -215,8 +242,8 @@ inline void emit_fft_forward(std::vector<Op>& ops, const uint64_t* words, uint4*
     }
 }
 
-inline void emit_fft_inverse(std::vector<Op>& ops, uint4* spec, int m) {
-    auto ranges = fft_pass_ranges(m);
+inline void emit_fft_inverse(std::vector<Op>& ops, const PlanParams& pp, uint4* spec, int m) {
+    auto ranges = fft_pass_ranges(m, pp);
     for (size_t r = 0; r < ranges.size(); ++r) {
         if (ranges[r].first == ranges[r].second) continue;
         Op op{};
@@ -281,32 +308,131 @@ inline Workspace workspace_for(const Sizes& s) {
 
 // Forward transform of one operand into an N-point spectrum (Split, BasisCvt
 // on 64-bit words, changeRepr, FFT_LCH at 0).  `words` is scratch of 2^m_op words.
-inline void emit_forward(std::vector<Op>& ops, const uint64_t* src, uint64_t nbits, uint64_t* words, int m_op, uint4* spec,
-                         int m) {
+inline void emit_forward(std::vector<Op>& ops, const LayerPool& pool, const PlanParams& pp, const uint64_t* src,
+                         uint64_t nbits, uint64_t* words, int m_op, uint4* spec, int m) {
     emit_pack(ops, src, nbits, words, 1ull << m_op);
-    emit_bc(ops, words, 0, m_op, 0);
-    emit_fft_forward(ops, words, spec, m_op, m - m_op);
+    emit_bc(ops, pool, words, 0, m_op, 0);
+    emit_fft_forward(ops, pp, words, spec, m_op, m - m_op);
 }
 
 // Inverse transform of an N-point spectrum into nc_bits product bits
 // (iFFT_LCH, iBasisCvt, changeRepr back, InterleavedCombine).
-inline void emit_inverse(std::vector<Op>& ops, uint4* spec, int m, uint64_t* out, uint64_t nc_bits) {
-    emit_fft_inverse(ops, spec, m);
-    emit_bc(ops, spec, 1, m, 1);
+inline void emit_inverse(std::vector<Op>& ops, const LayerPool& pool, const PlanParams& pp, uint4* spec, int m,
+                         uint64_t* out, uint64_t nc_bits) {
+    emit_fft_inverse(ops, pp, spec, m);
+    emit_bc(ops, pool, spec, 1, m, 1);
     emit_psi(ops, spec, 1ull << m, out, nc_bits);
 }
 
 // The whole product c = a * b with the workspace at `ws`.
-inline void plan_mul(std::vector<Op>& ops, const Sizes& s, const uint64_t* a, const uint64_t* b, uint64_t* c, char* ws) {
+inline void plan_mul(std::vector<Op>& ops, const LayerPool& pool, const PlanParams& pp, const Sizes& s, const uint64_t* a,
+                     const uint64_t* b, uint64_t* c, char* ws) {
     Workspace w = workspace_for(s);
     uint64_t* wa = (uint64_t*)(ws + w.off_wa);
     uint64_t* wb = (uint64_t*)(ws + w.off_wb);
     uint4* sa = (uint4*)(ws + w.off_sa);
     uint4* sb = (uint4*)(ws + w.off_sb);
-    emit_forward(ops, a, s.na_bits, wa, s.m_a, sa, s.m);
-    emit_forward(ops, b, s.nb_bits, wb, s.m_b, sb, s.m);
+    emit_forward(ops, pool, pp, a, s.na_bits, wa, s.m_a, sa, s.m);
+    emit_forward(ops, pool, pp, b, s.nb_bits, wb, s.m_b, sb, s.m);
     emit_pmul(ops, sa, sb, sb, 1ull << s.m);
-    emit_inverse(ops, sb, s.m, c, s.nc_bits);
+    emit_inverse(ops, pool, pp, sb, s.m, c, s.nc_bits);
+}
+
+}  // namespace gf2x
+
+namespace gf2x {
+
+// ------------------------------------------------------------------ batches
+// A batch of independent products is planned job by job; op r of every job
+// has rank r.  Ops of one rank and kind run in one launch (a "group"), and
+// groups launch rank by rank, so op r of a job starts after op r - 1 of the
+// same job has finished.
+
+struct BatchJob {
+    const uint64_t* a;
+    uint64_t na_bits;
+    const uint64_t* b;
+    uint64_t nb_bits;
+    uint64_t* c;
+};
+
+struct BatchGroup {
+    OpKind kind;
+    int wide;
+    std::vector<uint32_t> ops;  // indices into BatchPlan::ops
+};
+
+struct BatchPlan {
+    std::vector<Op> ops;
+    std::vector<uint32_t> job_of;
+    std::vector<uint32_t> rank_of;
+    std::vector<BatchGroup> groups;
+    std::vector<size_t> ws_off;  // per job
+    size_t ws_bytes = 0;
+    uint32_t max_rank = 0;
+};
+
+inline uint64_t op_tiles(const Op& op) {
+    switch (op.kind) {
+        case OpKind::Pack: return pack_tiles(op.pack);
+        case OpKind::BcTile: return bc_tiles(op.bct);
+        case OpKind::BcLayer: return 1;
+        case OpKind::Fft: return fft_tiles(op.fft);
+        case OpKind::Pmul: return pmul_tiles(op.pmul);
+        case OpKind::Psi: return psi_tiles(op.psi);
+        case OpKind::BcClass: return bc_class_tiles(op.bcc);
+    }
+    return 0;
+}
+
+inline int op_wide(const Op& op) {
+    if (op.kind == OpKind::BcTile) return (int)op.bct.wide;
+    if (op.kind == OpKind::BcClass) return (int)op.bcc.wide;
+    if (op.kind == OpKind::BcLayer) return (int)op.bcl.wide;
+    return 0;
+}
+
+// Workspace sizes first (ws == nullptr), then the ops with real addresses.
+inline void plan_batch(BatchPlan& P, const LayerPool& pool, const PlanParams& pp, const BatchJob* jobs, size_t njobs,
+                       char* ws) {
+    P = BatchPlan();
+    P.ws_off.assign(njobs, 0);
+    size_t total = 0;
+    for (size_t j = 0; j < njobs; ++j) {
+        Sizes s = make_sizes(jobs[j].na_bits, jobs[j].nb_bits);
+        P.ws_off[j] = total;
+        if (s.out_words) total += workspace_for(s).bytes;
+    }
+    P.ws_bytes = total;
+    if (!ws) return;
+    std::vector<std::vector<Op>> per(njobs);
+    for (size_t j = 0; j < njobs; ++j) {
+        Sizes s = make_sizes(jobs[j].na_bits, jobs[j].nb_bits);
+        if (!s.out_words) continue;
+        plan_mul(per[j], pool, pp, s, jobs[j].a, jobs[j].b, jobs[j].c, ws + P.ws_off[j]);
+        P.max_rank = std::max<uint32_t>(P.max_rank, (uint32_t)per[j].size());
+    }
+    for (uint32_t r = 0; r < P.max_rank; ++r) {
+        std::vector<BatchGroup> g;
+        for (size_t j = 0; j < njobs; ++j) {
+            if (r >= per[j].size()) continue;
+            const Op& op = per[j][r];
+            uint32_t idx = (uint32_t)P.ops.size();
+            P.ops.push_back(op);
+            P.job_of.push_back((uint32_t)j);
+            P.rank_of.push_back(r);
+            int w = op_wide(op);
+            BatchGroup* G = nullptr;
+            for (auto& x : g)
+                if (x.kind == op.kind && x.wide == w) G = &x;
+            if (!G) {
+                g.push_back(BatchGroup{op.kind, w, {}});
+                G = &g.back();
+            }
+            G->ops.push_back(idx);
+        }
+        for (auto& x : g) P.groups.push_back(std::move(x));
+    }
 }
 
 }  // namespace gf2x
