@@ -151,6 +151,163 @@ def bench_batched(ctx, njobs=4096, reps=5):
     return res
 
 
+def bench_serving(ctx, nreq=10000, fracs=(0.1, 0.25, 0.5, 0.75, 0.9), arena_gib=16):
+    """Serving: requests with operand lengths floor(2^u), u ~ U[10, 24] bits
+    independently for a and b, Poisson arrivals.  First the saturation
+    throughput of the continuous-batching server (all requests queued at
+    once) for a few engine settings; then, for the best one, open-loop
+    Poisson streams at fractions of that saturation rate, with latency taken
+    from the scheduled arrival to the observed completion (first 10 % of each
+    stream discarded).  The same streams go through the plain path (one
+    gf2x_mul_dev call per request, FIFO on one stream) for comparison."""
+    import math
+    from collections import deque
+
+    import numpy as np
+    import torch
+
+    import paper_1708_09746_amd as P
+    from paper_1708_09746_amd import inputs
+
+    spec = inputs.serve_workload(nreq, 0, 10, 24)
+    # operands are windows of one seeded pool (timing does not depend on the
+    # bits); every request has its own output buffer
+    max_words = (1 << 24) // 64
+    pool_words = 4 * max_words
+    pool = torch.from_numpy(inputs.random_poly(inputs.SERVE_POOL_SEED, 64 * pool_words).view(np.int64).copy()).cuda()
+    offs = inputs.splitmix64(inputs.SERVE_POOL_SEED + 1, 2 * nreq) % np.uint64(pool_words - max_words)
+    ow = [P.out_words(na, nb) for na, nb, *_ in spec]
+    cbuf = torch.empty(sum(ow) + 1, dtype=torch.int64, device="cuda")
+    reqs, pos = [], 0
+    for r, (na, nb, _sa, _sb, _u) in enumerate(spec):
+        oa, ob = int(offs[2 * r]), int(offs[2 * r + 1])
+        a = pool[oa: oa + (na + 63) // 64]
+        b = pool[ob: ob + (nb + 63) // 64]
+        reqs.append((a, na, b, nb, cbuf[pos: pos + ow[r]]))
+        pos += ow[r]
+    gaps = np.array([-math.log1p(-u) for *_x, u in spec])  # unit-rate exponential gaps
+    torch.cuda.synchronize()
+    arena = min(arena_gib << 30, int(torch.cuda.mem_get_info()[0] * 0.25))
+
+    def saturate(levels, persistent):
+        srv = ctx.server(arena, max_active=4096, levels_per_iter=levels, persistent=persistent)
+        t0 = time.perf_counter()
+        for i, (a, na, b, nb, c) in enumerate(reqs):
+            srv.submit(a, na, b, nb, c, i)
+        done = srv.drain()
+        t = time.perf_counter() - t0
+        st = srv.stats()
+        srv.close()
+        assert len(done) == nreq and all(d["status"] == 0 for d in done)
+        return nreq / t, st
+
+    def open_loop(rate, submit, poll, idle):
+        """Latencies (ms) of one Poisson stream at `rate` requests/s."""
+        t0 = P.now_ns() + 2_000_000
+        arr = t0 + np.cumsum(gaps / rate * 1e9).astype(np.int64)
+        lat = np.zeros(nreq)
+        got, i = 0, 0
+        while got < nreq:
+            now = P.now_ns()
+            while i < nreq and arr[i] <= now:
+                submit(i)
+                i += 1
+            for tag, t_done in poll():
+                lat[tag] = (t_done - arr[tag]) / 1e6
+                got += 1
+            idle(int(arr[i]) if i < nreq else now + 1_000_000)
+        span = (arr[-1] - arr[nreq // 10]) / 1e9
+        keep = lat[nreq // 10:]
+        return dict(offered_per_s=round(rate, 1),
+                    achieved_per_s=round(float(len(keep) / max(span, 1e-9)), 1),
+                    p50_ms=round(float(np.percentile(keep, 50)), 3),
+                    p99_ms=round(float(np.percentile(keep, 99)), 3))
+
+    res = {"requests": nreq, "lengths": "floor(2^u), u ~ U[10, 24] bits, a and b independent",
+           "arrivals": "Poisson (open loop), latency from scheduled arrival to completion, first 10 % discarded",
+           "arena_bytes": arena}
+    # engine settings: dependency levels per iteration x execution mode
+    tune = {}
+    for persistent in (False, True):
+        for levels in (2, 4, 8):
+            rate, st = saturate(levels, persistent)
+            key = f"{'persistent' if persistent else 'staged'}_L{levels}"
+            tune[key] = round(rate, 1)
+            log(f"bench: serving saturation {key}: {rate:.0f} products/s, {st['iterations']} iterations")
+    res["saturation_products_per_s"] = tune
+    best = max(tune, key=tune.get)
+    mode, lv = best.split("_L")
+    res["engine"] = {"mode": mode, "levels_per_iter": int(lv), "inflight": 2}
+    sat = tune[best]
+    srv = ctx.server(arena, max_active=4096, levels_per_iter=int(lv), persistent=(mode == "persistent"))
+
+    def s_submit(i):
+        a, na, b, nb, c = reqs[i]
+        srv.submit(a, na, b, nb, c, i)
+
+    def s_poll():
+        return [(d["tag"], d["t_done_ns"]) for d in srv.poll()]
+
+    rates = []
+    for f in fracs:
+        r = open_loop(f * sat, s_submit, s_poll, lambda until: srv.step(until))
+        r["fraction_of_saturation"] = f
+        rates.append(r)
+        log(f"bench: serving at {f:.2f} x saturation: {r}")
+    srv.close()
+    res["server"] = rates
+
+    # plain path: one gf2x_mul_dev per request as it arrives, FIFO on one stream
+    stream = torch.cuda.Stream()
+    pending = deque()
+
+    def p_submit(i):
+        a, na, b, nb, c = reqs[i]
+        ctx.mul_into(a, na, b, nb, c, stream)
+        ev = torch.cuda.Event()
+        ev.record(stream)
+        pending.append((i, ev))
+
+    def p_poll():
+        out = []
+        while pending and pending[0][1].query():
+            out.append((pending[0][0], P.now_ns()))
+            pending.popleft()
+        return out
+
+    def p_idle(until):
+        while P.now_ns() < until and not (pending and pending[0][1].query()):
+            pass
+
+    t0 = time.perf_counter()
+    for i in range(nreq):
+        p_submit(i)
+    stream.synchronize()
+    pending.clear()
+    plain_sat = nreq / (time.perf_counter() - t0)
+    res["plain_saturation_products_per_s"] = round(plain_sat, 1)
+    plain = []
+    for f in fracs:
+        rate = f * sat
+        if rate > 0.95 * plain_sat:
+            plain.append({"offered_per_s": round(rate, 1), "fraction_of_saturation": f,
+                          "note": "above the plain path's saturation rate: its queue grows without bound"})
+            continue
+        r = open_loop(rate, p_submit, p_poll, p_idle)
+        r["fraction_of_saturation"] = f
+        plain.append(r)
+        log(f"bench: plain path at {f:.2f} x saturation: {r}")
+    res["plain"] = plain
+    res["speedup_saturation_vs_plain"] = round(sat / plain_sat, 2)
+    # spot check: a few requests against a fresh single-call product
+    for k in (0, nreq // 3, nreq - 1):
+        a, na, b, nb, c = reqs[k]
+        ref = ctx.mul(a, na, b, nb)
+        torch.cuda.synchronize()
+        assert torch.equal(ref, c), f"served request {k} differs from the single-call product"
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -160,6 +317,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-products measurement")
     ap.add_argument("--batch-jobs", type=int, default=4096)
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving measurement")
+    ap.add_argument("--serve-requests", type=int, default=10000)
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="first run a plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -271,6 +430,9 @@ def main():
     if not args.no_batch:
         log(f"bench: batched products ({args.batch_jobs} jobs)")
         out["batched"] = bench_batched(ctx, args.batch_jobs)
+    if not args.no_serve:
+        log(f"bench: serving ({args.serve_requests} requests per stream)")
+        out["serving"] = bench_serving(ctx, args.serve_requests)
     if not args.no_cpu_baseline:
         log("bench: timing the oracle on a bounded sample")
         out["cpu_baseline"] = cpu_baseline(n, seeds)

@@ -192,6 +192,78 @@ int gf2x_batch_info(const gf2x_batch *batch, gf2x_batch_stats *stats);
 /* Synchronizes the device, then frees the batch. NULL is ignored. */
 void gf2x_batch_destroy(gf2x_batch *batch);
 
+/* ------------------------------------------------------------------ serving
+ * A request loop with continuous batching (not part of the paper: a serving
+ * pattern around its product).  Requests are products whose operands and
+ * result buffer live in device memory owned by the caller, who keeps them
+ * valid until the request completes.  Each request is admitted when its
+ * device footprint (the two converted operands and the two N-point spectra,
+ * gf2x_workspace_bytes) fits in the server's arena and a slot is free; its
+ * state then stays on the device until it completes.  The engine runs
+ * iterations: every admitted request advances by up to `levels_per_iter`
+ * dependency levels of its product, the ops of all requests at one level run
+ * together in multi-op launches (STAGED) or in one persistent launch per
+ * iteration (PERSISTENT), and requests that arrive meanwhile join at the next
+ * iteration as memory and slots free up.  Admission is first come, first
+ * served.  A request's result is the same bits as gf2x_mul_dev gives it alone.
+ *
+ * A server borrows ctx's tables; ctx, the server and its requests are used
+ * from one host thread.  Timestamps are CLOCK_MONOTONIC nanoseconds
+ * (gf2x_now_ns). */
+typedef struct gf2x_server gf2x_server;
+
+typedef struct {
+    uint64_t arena_bytes;     /* device memory for request state (one allocation) */
+    uint32_t max_active;      /* admitted requests at most (slots) */
+    uint32_t levels_per_iter; /* dependency levels each request advances per iteration (>= 1) */
+    uint32_t inflight;        /* iterations queued on the device at once (1..4) */
+    int32_t mode;             /* GF2X_BATCH_STAGED or GF2X_BATCH_PERSISTENT */
+} gf2x_server_cfg;
+
+typedef struct {
+    uint64_t tag;        /* the caller's tag from gf2x_server_submit */
+    int32_t status;      /* GF2X_OK, or GF2X_EDEVICE when its iteration failed */
+    uint32_t iterations; /* iterations the request took part in */
+    uint64_t t_submit_ns, t_admit_ns, t_done_ns;
+} gf2x_done;
+
+typedef struct {
+    uint64_t submitted, admitted, completed, iterations, launches;
+    uint64_t queued, active;            /* now */
+    uint64_t arena_used, arena_peak;    /* bytes */
+    uint64_t active_peak;
+} gf2x_server_stats;
+
+uint64_t gf2x_now_ns(void);
+
+/* Allocates the arena and per-iteration descriptor buffers on ctx's device.
+ * ENOMEM if the arena does not fit; EINVAL for a zero field or a bad mode. */
+int gf2x_server_create(gf2x_ctx *ctx, const gf2x_server_cfg *cfg, gf2x_server **server);
+
+/* Queues c = a * b (device pointers, sizes in bits as for gf2x_mul_dev).
+ * Returns at once: EINVAL for NULL pointers with nonzero sizes or overlap of
+ * c with a or b, ERANGE for N > 2^32, ENOMEM if the request's footprint
+ * exceeds the whole arena (it could never be admitted); the request is then
+ * not queued.  An empty product is complete at once (nothing is written). */
+int gf2x_server_submit(gf2x_server *server, const uint64_t *a, uint64_t na_bits, const uint64_t *b, uint64_t nb_bits,
+                       uint64_t *c, uint64_t tag);
+
+/* Runs the engine until gf2x_now_ns() >= until_ns or there is nothing left
+ * to do: records completions, admits queued requests, builds and launches
+ * iterations (at most cfg.inflight queued at once).  Returns EDEVICE after a
+ * device error (the requests involved complete with that status). */
+int gf2x_server_step(gf2x_server *server, uint64_t until_ns);
+
+/* Moves up to `max` completion records, oldest first, into out; returns how
+ * many. */
+size_t gf2x_server_poll(gf2x_server *server, gf2x_done *out, size_t max);
+
+int gf2x_server_info(const gf2x_server *server, gf2x_server_stats *stats);
+
+/* Waits for the device, then frees the server (queued requests are dropped).
+ * NULL is ignored. */
+void gf2x_server_destroy(gf2x_server *server);
+
 /* Name of a status code. */
 const char *gf2x_strerror(int status);
 

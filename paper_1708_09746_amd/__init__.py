@@ -44,6 +44,21 @@ class BatchStats(ctypes.Structure):
                 ("tiles", ctypes.c_uint64), ("workspace_bytes", ctypes.c_uint64)]
 
 
+class ServerCfg(ctypes.Structure):
+    _fields_ = [("arena_bytes", ctypes.c_uint64), ("max_active", ctypes.c_uint32),
+                ("levels_per_iter", ctypes.c_uint32), ("inflight", ctypes.c_uint32), ("mode", ctypes.c_int32)]
+
+
+class Done(ctypes.Structure):
+    _fields_ = [("tag", ctypes.c_uint64), ("status", ctypes.c_int32), ("iterations", ctypes.c_uint32),
+                ("t_submit_ns", ctypes.c_uint64), ("t_admit_ns", ctypes.c_uint64), ("t_done_ns", ctypes.c_uint64)]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_uint64) for k in ("submitted", "admitted", "completed", "iterations", "launches",
+                                              "queued", "active", "arena_used", "arena_peak", "active_peak")]
+
+
 class Job(ctypes.Structure):
     _fields_ = [("a", ctypes.c_void_p), ("na_bits", ctypes.c_uint64), ("b", ctypes.c_void_p),
                 ("nb_bits", ctypes.c_uint64), ("c", ctypes.c_void_p)]
@@ -76,6 +91,13 @@ def lib():
             "gf2x_batch_run": (i32, [vp, vp]),
             "gf2x_batch_info": (i32, [vp, ctypes.POINTER(BatchStats)]),
             "gf2x_batch_destroy": (None, [vp]),
+            "gf2x_now_ns": (u64, []),
+            "gf2x_server_create": (i32, [vp, ctypes.POINTER(ServerCfg), ctypes.POINTER(vp)]),
+            "gf2x_server_submit": (i32, [vp, vp, u64, vp, u64, vp, u64]),
+            "gf2x_server_step": (i32, [vp, u64]),
+            "gf2x_server_poll": (sz, [vp, ctypes.POINTER(Done), sz]),
+            "gf2x_server_info": (i32, [vp, ctypes.POINTER(ServerStats)]),
+            "gf2x_server_destroy": (None, [vp]),
             "gf2x_trace_begin": (i32, [vp, ctypes.c_uint32]),
             "gf2x_trace_read": (ctypes.c_int64, [vp, ctypes.POINTER(TraceRec), sz]),
             "gf2x_strerror": (ctypes.c_char_p, [i32]),
@@ -178,6 +200,11 @@ class Context:
         """A reusable Batch of (a, na_bits, b, nb_bits, c) device-tensor jobs."""
         return Batch(self, jobs, persistent)
 
+    def server(self, arena_bytes: int, max_active: int = 4096, levels_per_iter: int = 4, inflight: int = 2,
+               persistent: bool = False):
+        """A continuous-batching request loop (Server) on this context."""
+        return Server(self, arena_bytes, max_active, levels_per_iter, inflight, persistent)
+
     # ---- tracing
     def trace_begin(self, kind_mask: int = 0x7F):
         self._check(lib().gf2x_trace_begin(self._h, kind_mask), "gf2x_trace_begin")
@@ -275,6 +302,71 @@ class Batch:
     def close(self):
         if getattr(self, "_h", None):
             lib().gf2x_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def now_ns() -> int:
+    """The library's clock (CLOCK_MONOTONIC, ns), the one completion times use."""
+    return int(lib().gf2x_now_ns())
+
+
+class Server:
+    """Continuous batching of products (gf2x_server_*): submit requests whose
+    device tensors stay alive until they complete, drive the engine with
+    step(), collect completion records with poll()."""
+
+    def __init__(self, ctx: "Context", arena_bytes: int, max_active: int, levels_per_iter: int, inflight: int,
+                 persistent: bool):
+        self.ctx = ctx
+        cfg = ServerCfg(arena_bytes, max_active, levels_per_iter, inflight, 1 if persistent else 0)
+        h = ctypes.c_void_p()
+        ctx._check(lib().gf2x_server_create(ctx.handle, ctypes.byref(cfg), ctypes.byref(h)), "gf2x_server_create")
+        self._h = h
+        self._buf = (Done * 4096)()
+
+    def submit(self, a, na_bits: int, b, nb_bits: int, c, tag: int):
+        rc = lib().gf2x_server_submit(self._h, _ptr(a), na_bits, _ptr(b), nb_bits, _ptr(c), tag)
+        self.ctx._check(rc, "gf2x_server_submit")
+
+    def step(self, until_ns: int = 0):
+        """Run the engine until now_ns() >= until_ns or nothing is left to do."""
+        self.ctx._check(lib().gf2x_server_step(self._h, until_ns), "gf2x_server_step")
+
+    def poll(self):
+        """Completion records since the last poll: dicts with tag, status,
+        iterations and the submit/admit/done times in ns."""
+        out = []
+        while True:
+            n = lib().gf2x_server_poll(self._h, self._buf, len(self._buf))
+            out.extend(dict(tag=d.tag, status=d.status, iterations=d.iterations, t_submit_ns=d.t_submit_ns,
+                            t_admit_ns=d.t_admit_ns, t_done_ns=d.t_done_ns) for d in self._buf[:n])
+            if n < len(self._buf):
+                return out
+
+    def drain(self):
+        """Step until every submitted request has completed; return their records."""
+        done = []
+        while True:
+            self.step(now_ns() + 10_000_000)
+            done.extend(self.poll())
+            st = self.stats()
+            if st["queued"] == 0 and st["active"] == 0 and st["completed"] == st["submitted"]:
+                return done
+
+    def stats(self) -> dict:
+        st = ServerStats()
+        lib().gf2x_server_info(self._h, ctypes.byref(st))
+        return {k: int(getattr(st, k)) for k, _ in ServerStats._fields_}
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().gf2x_server_destroy(self._h)
             self._h = None
 
     def __del__(self):

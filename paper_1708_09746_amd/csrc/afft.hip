@@ -4,13 +4,17 @@
 #include <algorithm>
 #include <cstdio>
 #include <cstring>
+#include <ctime>
+#include <deque>
 #include <mutex>
+#include <thread>
 #include <type_traits>
 #include <string>
 #include <vector>
 
 #include "../../include/gf2x_afft.h"
 #include "afft_plan.hpp"
+#include "arena.hpp"
 #include "tower_host.hpp"
 
 using namespace gf2x;
@@ -273,6 +277,13 @@ struct PersistArgs {
     uint32_t spin_limit;
 };
 
+// Where the parts of a persistent launch's descriptor image sit.
+struct PersistLayout {
+    size_t ops_off = 0, prefix_off = 0, rank_off = 0, state_off = 0, state_words = 0, bytes = 0;
+    int nops = 0, nranks = 0;
+    uint64_t items = 0;
+};
+
 __global__ __launch_bounds__(kThreads) void k_zero_u32(uint32_t* p, uint64_t n) {
     for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x) p[i] = 0;
 }
@@ -421,24 +432,59 @@ struct gf2x_batch {
     char* ws = nullptr;
     char* desc = nullptr;
     size_t desc_bytes = 0;
-    struct Group {
-        OpKind kind;
-        int wide;
-        size_t ops_off, prefix_off;
-        int nops;
-        uint64_t total;
-    };
-    std::vector<Group> groups;
+    std::vector<gf2x::LaunchGroup> groups;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     bool use_graph = true;
     // persistent mode: ops in item order, their item prefix, scheduler state
     char* pdesc = nullptr;
-    size_t p_ops_off = 0, p_prefix_off = 0, p_rank_off = 0, p_state_off = 0, p_state_words = 0;
-    int p_nops = 0, p_nranks = 0;
-    uint64_t p_items = 0;
+    PersistLayout play;
     uint32_t spin_limit = 1u << 26;
 };
+
+// Serving engine state (host side); see gf2x_server_* in the header.
+struct gf2x_server {
+    gf2x_ctx* ctx = nullptr;
+    gf2x_server_cfg cfg{};
+    hipStream_t st = nullptr;
+    char* arena = nullptr;
+    gf2x::Arena alloc;
+    struct Req {
+        const uint64_t* a = nullptr;
+        const uint64_t* b = nullptr;
+        uint64_t* c = nullptr;
+        uint64_t na = 0, nb = 0, tag = 0, t_submit = 0, t_admit = 0;
+        size_t off = 0, bytes = 0;
+        std::vector<gf2x::Op> ops;
+        uint32_t levels = 0, next = 0, iters = 0;
+    };
+    std::deque<Req> queue;
+    std::vector<Req> active;
+    // one descriptor buffer pair per iteration that can be queued at once
+    struct Slot {
+        char* host = nullptr;  // pinned
+        char* dev = nullptr;
+        size_t cap = 0;
+        hipEvent_t ev = nullptr;
+        std::vector<gf2x_done> fin;  // requests whose last op is in this iteration
+        size_t abort_off = 0;        // persistent mode: the abort word is copied back here
+        bool persistent = false;
+    };
+    std::vector<Slot> slots;
+    std::deque<int> inflight;  // slots in launch order
+    std::vector<int> free_slots;
+    std::deque<gf2x_done> done;
+    gf2x_server_stats stats{};
+    int sticky = GF2X_OK;
+    uint32_t spin_limit = 1u << 26;
+    // per-iteration scratch, reused
+    std::vector<gf2x::Op> it_ops;
+    std::vector<uint32_t> it_rank;
+    std::vector<gf2x::BatchGroup> it_groups;
+    std::vector<gf2x::LaunchGroup> it_launch;
+    std::vector<char> it_host;
+};
+
 
 namespace {
 
@@ -610,59 +656,54 @@ int run_ops(gf2x_ctx* ctx, const std::vector<Op>& ops, hipStream_t st) {
 }
 
 // Upload every group's op array and tile prefix sums in one copy.
-int batch_upload(gf2x_batch* B) {
-    gf2x_ctx* ctx = B->ctx;
-    std::vector<char> host;
+// Descriptor image of a list of groups: per group the op records of its kind
+// and their tile prefix sums, at 256-byte aligned offsets of `host`.
+void pack_groups(const std::vector<Op>& ops, const std::vector<BatchGroup>& groups, std::vector<char>& host,
+                 std::vector<LaunchGroup>& out) {
     auto put = [&](const void* p, size_t n) {
         size_t off = (host.size() + 255) & ~(size_t)255;
         host.resize(off + n);
         memcpy(host.data() + off, p, n);
         return off;
     };
-    B->groups.clear();
-    for (const BatchGroup& G : B->plan.groups) {
-        gf2x_batch::Group d{};
+    std::vector<uint64_t> prefix;
+    for (const BatchGroup& G : groups) {
+        LaunchGroup d{};
         d.kind = G.kind;
         d.wide = G.wide;
         d.nops = (int)G.ops.size();
-        std::vector<uint64_t> prefix(G.ops.size() + 1, 0);
-        for (size_t i = 0; i < G.ops.size(); ++i) prefix[i + 1] = prefix[i] + op_tiles(B->plan.ops[G.ops[i]]);
+        prefix.assign(G.ops.size() + 1, 0);
+        for (size_t i = 0; i < G.ops.size(); ++i) prefix[i + 1] = prefix[i] + op_tiles(ops[G.ops[i]]);
         d.total = prefix.back();
         auto gather = [&](auto member) {
-            using T = std::decay_t<decltype(B->plan.ops[0].*member)>;
+            using T = std::decay_t<decltype(ops[0].*member)>;
             std::vector<T> v;
-            for (uint32_t i : G.ops) v.push_back(B->plan.ops[i].*member);
+            v.reserve(G.ops.size());
+            for (uint32_t i : G.ops) v.push_back(ops[i].*member);
             return put(v.data(), v.size() * sizeof(T));
         };
         switch (G.kind) {
             case OpKind::Pack: d.ops_off = gather(&Op::pack); break;
             case OpKind::BcTile: d.ops_off = gather(&Op::bct); break;
-            case OpKind::BcLayer: d.ops_off = gather(&Op::bcl); break;
+            case OpKind::BcLayer:
+                for (uint32_t i : G.ops) d.layers.push_back(ops[i].bcl);
+                break;
             case OpKind::Fft: d.ops_off = gather(&Op::fft); break;
             case OpKind::Pmul: d.ops_off = gather(&Op::pmul); break;
             case OpKind::Psi: d.ops_off = gather(&Op::psi); break;
             case OpKind::BcClass: d.ops_off = gather(&Op::bcc); break;
         }
         d.prefix_off = put(prefix.data(), prefix.size() * sizeof(uint64_t));
-        B->groups.push_back(d);
+        out.push_back(std::move(d));
     }
-    B->desc_bytes = host.size();
-    hipError_t e = hipMalloc((void**)&B->desc, std::max<size_t>(host.size(), 256));
-    if (e != hipSuccess) {
-        (void)hipGetLastError();
-        return fail(ctx, GF2X_ENOMEM, "batch descriptors");
-    }
-    e = hipMemcpy(B->desc, host.data(), host.size(), hipMemcpyHostToDevice);
-    if (e != hipSuccess) return hip_fail(ctx, e, "batch descriptor upload");
-    return GF2X_OK;
 }
 
-int batch_launch_groups(gf2x_batch* B, hipStream_t st) {
-    gf2x_ctx* ctx = B->ctx;
+// One multi-op launch per group, in order, reading the descriptor image at `desc`.
+int launch_groups(gf2x_ctx* ctx, const std::vector<LaunchGroup>& groups, const char* desc, hipStream_t st) {
     const uint64_t ncu = (uint64_t)ctx->ncu;
-    for (const auto& G : B->groups) {
-        const uint64_t* prefix = (const uint64_t*)(B->desc + G.prefix_off);
-        const void* ops = B->desc + G.ops_off;
+    for (const auto& G : groups) {
+        const uint64_t* prefix = (const uint64_t*)(desc + G.prefix_off);
+        const void* ops = desc + G.ops_off;
         switch (G.kind) {
             case OpKind::Pack:
                 hipLaunchKernelGGL(k_pack_multi, dim3(grid_for(G.total, 8 * ncu)), dim3(kThreads), 0, st,
@@ -684,18 +725,16 @@ int batch_launch_groups(gf2x_batch* B, hipStream_t st) {
                     hipLaunchKernelGGL(k_bc_class_multi<0>, dim3(grid_for(G.total, 2 * ncu)), dim3(kThreads), 0, st,
                                        (const BcClassOp*)ops, prefix, G.nops, G.total);
                 break;
-            case OpKind::BcLayer: {
+            case OpKind::BcLayer:
                 // global layers (only for very long jobs): one launch per op
-                for (int i = 0; i < G.nops; ++i) {
-                    const Op& op = B->plan.ops[B->plan.groups[&G - &B->groups[0]].ops[i]];
-                    uint64_t blocks = (op.bcl.nelem / 2 + kThreads - 1) / kThreads;
-                    if (op.bcl.wide)
-                        hipLaunchKernelGGL(k_bc_layer<1>, dim3(grid_for(blocks, 16 * ncu)), dim3(kThreads), 0, st, op.bcl);
+                for (const BcLayerOp& L : G.layers) {
+                    uint64_t blocks = (L.nelem / 2 + kThreads - 1) / kThreads;
+                    if (L.wide)
+                        hipLaunchKernelGGL(k_bc_layer<1>, dim3(grid_for(blocks, 16 * ncu)), dim3(kThreads), 0, st, L);
                     else
-                        hipLaunchKernelGGL(k_bc_layer<0>, dim3(grid_for(blocks, 16 * ncu)), dim3(kThreads), 0, st, op.bcl);
+                        hipLaunchKernelGGL(k_bc_layer<0>, dim3(grid_for(blocks, 16 * ncu)), dim3(kThreads), 0, st, L);
                 }
                 break;
-            }
             case OpKind::Fft:
                 hipLaunchKernelGGL(k_fft_multi, dim3(grid_for(G.total, ncu)), dim3(kThreads), 0, st, (const FftPass*)ops,
                                    prefix, G.nops, G.total, (const uint8_t*)ctx->d_mt, (const uint32_t*)ctx->d_lam,
@@ -716,21 +755,41 @@ int batch_launch_groups(gf2x_batch* B, hipStream_t st) {
     return GF2X_OK;
 }
 
-// Persistent mode: one array of DevOp in item order (group after group, so
-// rank by rank), the op and rank item prefixes, then the scheduler words
-// (abort flag, per-rank arrive counters, per-rank 64-bit item counters).
-int batch_upload_persistent(gf2x_batch* B) {
+int batch_upload(gf2x_batch* B) {
     gf2x_ctx* ctx = B->ctx;
-    const BatchPlan& P = B->plan;
+    std::vector<char> host;
+    B->groups.clear();
+    pack_groups(B->plan.ops, B->plan.groups, host, B->groups);
+    B->desc_bytes = host.size();
+    hipError_t e = hipMalloc((void**)&B->desc, std::max<size_t>(host.size(), 256));
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(ctx, GF2X_ENOMEM, "batch descriptors");
+    }
+    if (!host.empty()) {
+        e = hipMemcpy(B->desc, host.data(), host.size(), hipMemcpyHostToDevice);
+        if (e != hipSuccess) return hip_fail(ctx, e, "batch descriptor upload");
+    }
+    return GF2X_OK;
+}
+
+int batch_launch_groups(gf2x_batch* B, hipStream_t st) { return launch_groups(B->ctx, B->groups, B->desc, st); }
+
+// Persistent descriptor image: one array of DevOp in item order (group after
+// group, so rank by rank), the op and rank item prefixes, then the scheduler
+// words (abort flag, per-rank arrive counters, per-rank 64-bit item counters).
+// The image is appended to `host` at a 256-byte aligned offset `base`.
+void pack_persistent(const std::vector<Op>& ops, const std::vector<uint32_t>& rank_of,
+                     const std::vector<BatchGroup>& groups, std::vector<char>& host, size_t& base, PersistLayout& L) {
     std::vector<DevOp> dops;
     std::vector<uint64_t> prefix(1, 0);
     std::vector<uint64_t> rank_first;
     uint32_t cur_rank = ~0u;
-    for (const BatchGroup& G : P.groups)
+    for (const BatchGroup& G : groups)
         for (uint32_t i : G.ops) {
-            const Op& op = P.ops[i];
-            if (P.rank_of[i] != cur_rank) {
-                cur_rank = P.rank_of[i];
+            const Op& op = ops[i];
+            if (rank_of[i] != cur_rank) {
+                cur_rank = rank_of[i];
                 rank_first.push_back(prefix.back());
             }
             DevOp d;
@@ -751,66 +810,80 @@ int batch_upload_persistent(gf2x_batch* B) {
             prefix.push_back(prefix.back() + d.tiles);
         }
     rank_first.push_back(prefix.back());
-    const int nranks = (int)rank_first.size() - 1;
+    L = PersistLayout();
+    L.nranks = (int)rank_first.size() - 1;
+    L.nops = (int)dops.size();
+    L.items = prefix.back();
     size_t off = 0;
-    B->p_ops_off = off;
+    L.ops_off = off;
     off = align256(off + dops.size() * sizeof(DevOp));
-    B->p_prefix_off = off;
+    L.prefix_off = off;
     off = align256(off + prefix.size() * sizeof(uint64_t));
-    B->p_rank_off = off;
+    L.rank_off = off;
     off = align256(off + rank_first.size() * sizeof(uint64_t));
-    B->p_state_off = off;
-    B->p_state_words = 2 + (size_t)nranks + 2 * (size_t)nranks;  // abort, pad, arrive[], next[] (64-bit)
-    if (B->p_state_words & 1) ++B->p_state_words;
-    off = align256(off + B->p_state_words * sizeof(uint32_t));
-    hipError_t e = hipMalloc((void**)&B->pdesc, off);
-    if (e != hipSuccess) {
-        (void)hipGetLastError();
-        return fail(ctx, GF2X_ENOMEM, "persistent batch descriptors");
-    }
-    std::vector<char> host(off, 0);
-    memcpy(host.data() + B->p_ops_off, dops.data(), dops.size() * sizeof(DevOp));
-    memcpy(host.data() + B->p_prefix_off, prefix.data(), prefix.size() * sizeof(uint64_t));
-    memcpy(host.data() + B->p_rank_off, rank_first.data(), rank_first.size() * sizeof(uint64_t));
-    e = hipMemcpy(B->pdesc, host.data(), off, hipMemcpyHostToDevice);
-    if (e != hipSuccess) return hip_fail(ctx, e, "persistent descriptor upload");
-    B->p_nops = (int)dops.size();
-    B->p_nranks = nranks;
-    B->p_items = prefix.back();
-    return GF2X_OK;
+    L.state_off = off;
+    L.state_words = 2 + 3 * (size_t)L.nranks;  // abort, pad, arrive[nranks], next[nranks] (64-bit)
+    if (L.state_words & 1) ++L.state_words;
+    off = align256(off + L.state_words * sizeof(uint32_t));
+    L.bytes = off;
+    base = align256(host.size());
+    host.resize(base + off, 0);
+    char* h = host.data() + base;
+    memcpy(h + L.ops_off, dops.data(), dops.size() * sizeof(DevOp));
+    memcpy(h + L.prefix_off, prefix.data(), prefix.size() * sizeof(uint64_t));
+    memcpy(h + L.rank_off, rank_first.data(), rank_first.size() * sizeof(uint64_t));
 }
 
-PersistArgs persist_args(gf2x_batch* B) {
+PersistArgs persist_args(const char* dev, const PersistLayout& L, uint32_t spin_limit) {
     PersistArgs a;
-    a.ops = (const DevOp*)(B->pdesc + B->p_ops_off);
-    a.prefix = (const uint64_t*)(B->pdesc + B->p_prefix_off);
-    a.rank_first = (const uint64_t*)(B->pdesc + B->p_rank_off);
-    a.nops = B->p_nops;
-    a.nranks = B->p_nranks;
-    a.items = B->p_items;
-    uint32_t* st = (uint32_t*)(B->pdesc + B->p_state_off);
+    a.ops = (const DevOp*)(dev + L.ops_off);
+    a.prefix = (const uint64_t*)(dev + L.prefix_off);
+    a.rank_first = (const uint64_t*)(dev + L.rank_off);
+    a.nops = L.nops;
+    a.nranks = L.nranks;
+    a.items = L.items;
+    uint32_t* st = (uint32_t*)(dev + L.state_off);
     a.abort = st;
     a.arrive = st + 2;
-    size_t nxt = 2 + (size_t)B->p_nranks;
+    size_t nxt = 2 + (size_t)L.nranks;
     if (nxt & 1) ++nxt;
     a.next = (unsigned long long*)(st + nxt);
-    a.spin_limit = B->spin_limit;
+    a.spin_limit = spin_limit;
     return a;
 }
 
-int batch_launch_persistent(gf2x_batch* B, hipStream_t st) {
-    gf2x_ctx* ctx = B->ctx;
-    PersistArgs a = persist_args(B);
-    uint64_t nstate = B->p_state_words;
-    // scheduler state is cleared by a kernel (kept inside graphs)
-    hipLaunchKernelGGL(k_zero_u32, dim3(grid_for((nstate + kThreads - 1) / kThreads, 64)), dim3(kThreads), 0, st,
-                       (uint32_t*)(B->pdesc + B->p_state_off), nstate);
+// Clears the scheduler words with a kernel (so the sequence can sit inside a
+// graph), then launches one persistent block per CU.
+int launch_persistent(gf2x_ctx* ctx, char* dev, const PersistLayout& L, uint32_t spin_limit, hipStream_t st) {
+    if (!L.items) return GF2X_OK;
+    PersistArgs a = persist_args(dev, L, spin_limit);
+    hipLaunchKernelGGL(k_zero_u32, dim3(grid_for((L.state_words + kThreads - 1) / kThreads, 64)), dim3(kThreads), 0, st,
+                       (uint32_t*)(dev + L.state_off), (uint64_t)L.state_words);
     hipLaunchKernelGGL(k_persistent, dim3((unsigned)std::max(1, ctx->ncu)), dim3(kThreads), 0, st, a,
                        (const uint8_t*)ctx->d_mt, (const uint32_t*)ctx->d_lam, (const uint4*)ctx->d_phi,
                        (const uint4*)ctx->d_psi);
     hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return hip_fail(ctx, e, "persistent batch launch");
+    if (e != hipSuccess) return hip_fail(ctx, e, "persistent launch");
     return GF2X_OK;
+}
+
+int batch_upload_persistent(gf2x_batch* B) {
+    gf2x_ctx* ctx = B->ctx;
+    std::vector<char> host;
+    size_t base = 0;
+    pack_persistent(B->plan.ops, B->plan.rank_of, B->plan.groups, host, base, B->play);
+    hipError_t e = hipMalloc((void**)&B->pdesc, std::max<size_t>(host.size(), 256));
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(ctx, GF2X_ENOMEM, "persistent batch descriptors");
+    }
+    e = hipMemcpy(B->pdesc, host.data(), host.size(), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail(ctx, e, "persistent descriptor upload");
+    return GF2X_OK;
+}
+
+int batch_launch_persistent(gf2x_batch* B, hipStream_t st) {
+    return launch_persistent(B->ctx, B->pdesc, B->play, B->spin_limit, st);
 }
 
 void batch_free(gf2x_batch* B) {
@@ -868,6 +941,195 @@ int check_ctx(gf2x_ctx* ctx) { return ctx ? GF2X_OK : GF2X_EINVAL; }
 
 std::mutex g_default_mu;
 gf2x_ctx* g_default = nullptr;
+
+// ------------------------------------------------------------------ serving
+uint64_t now_ns() {
+    timespec ts;
+    clock_gettime(CLOCK_MONOTONIC, &ts);
+    return (uint64_t)ts.tv_sec * 1000000000ull + (uint64_t)ts.tv_nsec;
+}
+
+void server_free(gf2x_server* S) {
+    if (!S) return;
+    for (auto& sl : S->slots) {
+        if (sl.host) (void)hipHostFree(sl.host);
+        if (sl.dev) (void)hipFree(sl.dev);
+        if (sl.ev) (void)hipEventDestroy(sl.ev);
+    }
+    if (S->arena) (void)hipFree(S->arena);
+    if (S->st) (void)hipStreamDestroy(S->st);
+    delete S;
+}
+
+// After a device failure every request still held completes with `status`
+// and the server accepts no more work.
+void server_fail_all(gf2x_server* S, int status) {
+    S->sticky = status;
+    const uint64_t t = now_ns();
+    for (int i : S->inflight) {
+        for (auto d : S->slots[i].fin) {
+            d.status = status;
+            d.t_done_ns = t;
+            S->done.push_back(d);
+            ++S->stats.completed;
+        }
+        S->slots[i].fin.clear();
+    }
+    auto finish = [&](gf2x_server::Req& r) {
+        S->done.push_back(gf2x_done{r.tag, status, r.iters, r.t_submit, r.t_admit, t});
+        ++S->stats.completed;
+    };
+    for (auto& r : S->active) finish(r);
+    for (auto& r : S->queue) finish(r);
+    S->active.clear();
+    S->queue.clear();
+}
+
+// Completes every finished iteration, oldest first.
+int server_retire(gf2x_server* S) {
+    while (!S->inflight.empty()) {
+        const int i = S->inflight.front();
+        gf2x_server::Slot& sl = S->slots[i];
+        hipError_t e = hipEventQuery(sl.ev);
+        if (e == hipErrorNotReady) break;
+        int status = GF2X_OK;
+        if (e != hipSuccess)
+            status = hip_fail(S->ctx, e, "serving iteration");
+        else if (sl.persistent && *(volatile uint32_t*)(sl.host + sl.abort_off))
+            status = fail(S->ctx, GF2X_EDEVICE, "serving iteration: a persistent barrier wait timed out");
+        const uint64_t t = now_ns();
+        for (auto d : sl.fin) {
+            d.status = status;
+            d.t_done_ns = t;
+            S->done.push_back(d);
+            ++S->stats.completed;
+        }
+        sl.fin.clear();
+        S->inflight.pop_front();
+        S->free_slots.push_back(i);
+        if (status) {
+            server_fail_all(S, status);
+            return status;
+        }
+    }
+    return GF2X_OK;
+}
+
+// First come, first served: admits the head of the queue while a slot is free
+// and its footprint fits in the arena.
+void server_admit(gf2x_server* S) {
+    gf2x_ctx* ctx = S->ctx;
+    while (!S->queue.empty() && S->active.size() < S->cfg.max_active) {
+        gf2x_server::Req& q = S->queue.front();
+        const size_t off = S->alloc.alloc(q.bytes);
+        if (off == Arena::npos) break;
+        q.off = off;
+        q.t_admit = now_ns();
+        const Sizes s = make_sizes(q.na, q.nb);
+        q.ops.clear();
+        plan_mul(q.ops, ctx->pool, ctx->params, s, q.a, q.b, q.c, S->arena + off);
+        q.levels = plan_levels(q.ops);
+        S->active.push_back(std::move(q));
+        S->queue.pop_front();
+        ++S->stats.admitted;
+    }
+    S->stats.active_peak = std::max<uint64_t>(S->stats.active_peak, S->active.size());
+    S->stats.arena_peak = std::max<uint64_t>(S->stats.arena_peak, S->alloc.used());
+}
+
+int server_ensure_slot(gf2x_server* S, gf2x_server::Slot& sl, size_t need) {
+    if (need <= sl.cap) return GF2X_OK;
+    const size_t cap = std::max<size_t>(need, 2 * sl.cap);
+    if (sl.host) (void)hipHostFree(sl.host);
+    if (sl.dev) (void)hipFree(sl.dev);
+    sl.host = nullptr;
+    sl.dev = nullptr;
+    sl.cap = 0;
+    hipError_t e = hipHostMalloc((void**)&sl.host, cap, hipHostMallocDefault);
+    if (e == hipSuccess) e = hipMalloc((void**)&sl.dev, cap);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(S->ctx, GF2X_ENOMEM, "serving descriptor buffers");
+    }
+    sl.cap = cap;
+    return GF2X_OK;
+}
+
+// Admits, then advances every admitted request by up to levels_per_iter
+// levels in one iteration queued on the server's stream.  Arena space of a
+// request that finishes here is reused at once: later iterations run after
+// this one on the same stream.
+int server_iterate(gf2x_server* S, bool& launched) {
+    launched = false;
+    server_admit(S);
+    if (S->active.empty()) return GF2X_OK;
+    launched = true;
+    const int si = S->free_slots.back();
+    gf2x_server::Slot& sl = S->slots[si];
+    const uint32_t L = S->cfg.levels_per_iter;
+    S->it_ops.clear();
+    S->it_rank.clear();
+    std::vector<gf2x_server::Req> keep;
+    keep.reserve(S->active.size());
+    for (auto& r : S->active) {
+        for (const Op& op : r.ops)
+            if (op.level >= r.next && op.level - r.next < L) {
+                S->it_ops.push_back(op);
+                S->it_rank.push_back(op.level - r.next);
+            }
+        r.next += L;
+        ++r.iters;
+        if (r.next >= r.levels) {
+            sl.fin.push_back(gf2x_done{r.tag, GF2X_OK, r.iters, r.t_submit, r.t_admit, 0});
+            S->alloc.release(r.off, r.bytes);
+        } else {
+            keep.push_back(std::move(r));
+        }
+    }
+    S->active.swap(keep);
+    S->it_groups.clear();
+    group_by_rank(S->it_ops, S->it_rank, 0, L, S->it_groups);
+    S->it_host.clear();
+    S->it_launch.clear();
+    PersistLayout PL;
+    size_t base = 0;
+    const bool pers = S->cfg.mode == GF2X_BATCH_PERSISTENT;
+    if (pers)
+        pack_persistent(S->it_ops, S->it_rank, S->it_groups, S->it_host, base, PL);
+    else
+        pack_groups(S->it_ops, S->it_groups, S->it_host, S->it_launch);
+    const size_t image = S->it_host.size();
+    sl.abort_off = align256(image);
+    // queued from here on: a failure below reports this iteration's requests
+    S->free_slots.pop_back();
+    S->inflight.push_back(si);
+    int rc = server_ensure_slot(S, sl, sl.abort_off + 256);
+    if (rc) return rc;
+    sl.persistent = pers;
+    memcpy(sl.host, S->it_host.data(), image);
+    *(uint32_t*)(sl.host + sl.abort_off) = 0;
+    hipStream_t st = S->st;
+    hipError_t e = hipSuccess;
+    if (image) e = hipMemcpyAsync(sl.dev, sl.host, image, hipMemcpyHostToDevice, st);
+    if (e != hipSuccess) return hip_fail(S->ctx, e, "serving descriptor upload");
+    if (pers) {
+        rc = launch_persistent(S->ctx, sl.dev, PL, S->spin_limit, st);
+        if (rc) return rc;
+        if (PL.items) {
+            e = hipMemcpyAsync(sl.host + sl.abort_off, sl.dev + PL.state_off, 4, hipMemcpyDeviceToHost, st);
+            if (e != hipSuccess) return hip_fail(S->ctx, e, "serving abort flag copy");
+            S->stats.launches += 2;
+        }
+    } else {
+        rc = launch_groups(S->ctx, S->it_launch, sl.dev, st);
+        if (rc) return rc;
+        for (const auto& G : S->it_launch) S->stats.launches += G.kind == OpKind::BcLayer ? G.layers.size() : 1;
+    }
+    e = hipEventRecord(sl.ev, st);
+    if (e != hipSuccess) return hip_fail(S->ctx, e, "serving event");
+    ++S->stats.iterations;
+    return GF2X_OK;
+}
 
 }  // namespace
 
@@ -1170,9 +1432,9 @@ int gf2x_batch_check(gf2x_batch* B) {
     DeviceGuard g(B->ctx->device);
     uint32_t flag = 0;
     hipError_t e = hipDeviceSynchronize();
-    if (e == hipSuccess) e = hipMemcpy(&flag, B->pdesc + B->p_state_off, 4, hipMemcpyDeviceToHost);
+    if (e == hipSuccess) e = hipMemcpy(&flag, B->pdesc + B->play.state_off, 4, hipMemcpyDeviceToHost);
     if (e != hipSuccess) return hip_fail(B->ctx, e, "gf2x_batch_check");
-    if (flag) return fail(B->ctx, GF2X_EDEVICE, "persistent batch: a dependency wait timed out; results incomplete");
+    if (flag) return fail(B->ctx, GF2X_EDEVICE, "persistent batch: a barrier wait timed out; results incomplete");
     return GF2X_OK;
 }
 
@@ -1222,6 +1484,132 @@ int gf2x_mul(const uint64_t* a, uint64_t na_bits, const uint64_t* b, uint64_t nb
     if (e == hipSuccess) e = hipStreamSynchronize(st);
     if (e != hipSuccess) return hip_fail(ctx, e, "copy product");
     return GF2X_OK;
+}
+
+uint64_t gf2x_now_ns(void) { return now_ns(); }
+
+int gf2x_server_create(gf2x_ctx* ctx, const gf2x_server_cfg* cfg, gf2x_server** out) {
+    if (check_ctx(ctx) || !cfg || !out) return GF2X_EINVAL;
+    ctx->err.clear();
+    *out = nullptr;
+    if (!cfg->arena_bytes || !cfg->max_active || !cfg->levels_per_iter || cfg->inflight < 1 || cfg->inflight > 4)
+        return fail(ctx, GF2X_EINVAL, "server configuration: zero field or inflight outside 1..4");
+    if (cfg->mode != GF2X_BATCH_STAGED && cfg->mode != GF2X_BATCH_PERSISTENT)
+        return fail(ctx, GF2X_EINVAL, "server configuration: unknown mode");
+    DeviceGuard g(ctx->device);
+    gf2x_server* S = new gf2x_server();
+    S->ctx = ctx;
+    S->cfg = *cfg;
+    hipError_t e = hipStreamCreateWithFlags(&S->st, hipStreamNonBlocking);
+    if (e != hipSuccess) {
+        server_free(S);
+        return hip_fail(ctx, e, "server stream");
+    }
+    e = hipMalloc((void**)&S->arena, cfg->arena_bytes);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        server_free(S);
+        return fail(ctx, GF2X_ENOMEM, "server arena");
+    }
+    S->alloc.reset(cfg->arena_bytes);
+    S->slots.resize(cfg->inflight);
+    for (uint32_t i = 0; i < cfg->inflight; ++i) {
+        e = hipEventCreateWithFlags(&S->slots[i].ev, hipEventDisableTiming);
+        if (e != hipSuccess) {
+            server_free(S);
+            return hip_fail(ctx, e, "server events");
+        }
+        int rc = server_ensure_slot(S, S->slots[i], 1 << 20);
+        if (rc) {
+            server_free(S);
+            return rc;
+        }
+        S->free_slots.push_back((int)(cfg->inflight - 1 - i));
+    }
+    *out = S;
+    return GF2X_OK;
+}
+
+int gf2x_server_submit(gf2x_server* S, const uint64_t* a, uint64_t na_bits, const uint64_t* b, uint64_t nb_bits,
+                       uint64_t* c, uint64_t tag) {
+    if (!S) return GF2X_EINVAL;
+    gf2x_ctx* ctx = S->ctx;
+    ctx->err.clear();
+    if (S->sticky) return fail(ctx, S->sticky, "server stopped after a device error");
+    const Sizes s = make_sizes(na_bits, nb_bits);
+    const uint64_t t = now_ns();
+    if (!s.out_words) {
+        S->done.push_back(gf2x_done{tag, GF2X_OK, 0, t, t, t});
+        ++S->stats.submitted;
+        ++S->stats.completed;
+        return GF2X_OK;
+    }
+    gf2x_job j{a, na_bits, b, nb_bits, c};
+    int rc = check_jobs(ctx, &j, 1);
+    if (rc) return rc;
+    gf2x_server::Req r;
+    r.a = a;
+    r.b = b;
+    r.c = c;
+    r.na = na_bits;
+    r.nb = nb_bits;
+    r.tag = tag;
+    r.t_submit = t;
+    r.bytes = workspace_for(s).bytes;
+    if (Arena::round(r.bytes) > S->alloc.capacity())
+        return fail(ctx, GF2X_ENOMEM, "request footprint exceeds the server arena");
+    S->queue.push_back(std::move(r));
+    ++S->stats.submitted;
+    return GF2X_OK;
+}
+
+int gf2x_server_step(gf2x_server* S, uint64_t until_ns) {
+    if (!S) return GF2X_EINVAL;
+    if (S->sticky) return S->sticky;
+    DeviceGuard g(S->ctx->device);
+    while (true) {
+        int rc = server_retire(S);
+        if (rc) return rc;
+        const bool work = !S->queue.empty() || !S->active.empty();
+        if (work && !S->free_slots.empty()) {
+            bool launched = false;
+            rc = server_iterate(S, launched);
+            if (rc) {
+                server_fail_all(S, rc);
+                return rc;
+            }
+            if (launched) continue;
+        }
+        if (!work && S->inflight.empty()) return GF2X_OK;
+        if (now_ns() >= until_ns) return GF2X_OK;
+        std::this_thread::yield();
+    }
+}
+
+size_t gf2x_server_poll(gf2x_server* S, gf2x_done* out, size_t max) {
+    if (!S || !out) return 0;
+    size_t n = 0;
+    while (n < max && !S->done.empty()) {
+        out[n++] = S->done.front();
+        S->done.pop_front();
+    }
+    return n;
+}
+
+int gf2x_server_info(const gf2x_server* S, gf2x_server_stats* st) {
+    if (!S || !st) return GF2X_EINVAL;
+    *st = S->stats;
+    st->queued = S->queue.size();
+    st->active = S->active.size();
+    st->arena_used = S->alloc.used();
+    return GF2X_OK;
+}
+
+void gf2x_server_destroy(gf2x_server* S) {
+    if (!S) return;
+    DeviceGuard g(S->ctx->device);
+    if (S->st) (void)hipStreamSynchronize(S->st);
+    server_free(S);
 }
 
 }  // extern "C"

@@ -12,6 +12,7 @@ enum class OpKind : int { Pack, BcTile, BcLayer, Fft, Pmul, Psi, BcClass };
 
 struct Op {
     OpKind kind;
+    uint32_t level;  // dependency level inside one product: an op needs every op of lower level done
     PackOp pack;
     BcTileOp bct;
     BcLayerOp bcl;
@@ -332,10 +333,25 @@ inline void plan_mul(std::vector<Op>& ops, const LayerPool& pool, const PlanPara
     uint64_t* wb = (uint64_t*)(ws + w.off_wb);
     uint4* sa = (uint4*)(ws + w.off_sa);
     uint4* sb = (uint4*)(ws + w.off_sb);
+    // the two forward transforms are independent and share levels
+    const size_t a0 = ops.size();
     emit_forward(ops, pool, pp, a, s.na_bits, wa, s.m_a, sa, s.m);
+    const size_t b0 = ops.size();
     emit_forward(ops, pool, pp, b, s.nb_bits, wb, s.m_b, sb, s.m);
+    const size_t p0 = ops.size();
+    for (size_t i = a0; i < b0; ++i) ops[i].level = (uint32_t)(i - a0);
+    for (size_t i = b0; i < p0; ++i) ops[i].level = (uint32_t)(i - b0);
+    const uint32_t lp = (uint32_t)std::max(b0 - a0, p0 - b0);
     emit_pmul(ops, sa, sb, sb, 1ull << s.m);
     emit_inverse(ops, pool, pp, sb, s.m, c, s.nc_bits);
+    for (size_t i = p0; i < ops.size(); ++i) ops[i].level = lp + (uint32_t)(i - p0);
+}
+
+// Number of dependency levels of a planned product.
+inline uint32_t plan_levels(const std::vector<Op>& ops) {
+    uint32_t l = 0;
+    for (const Op& op : ops) l = std::max(l, op.level + 1);
+    return l;
 }
 
 }  // namespace gf2x
@@ -360,6 +376,17 @@ struct BatchGroup {
     OpKind kind;
     int wide;
     std::vector<uint32_t> ops;  // indices into BatchPlan::ops
+};
+
+// A group's descriptor image: offsets of its op records and tile prefix sums
+// (global BasisCvt layers are launched one by one, from host copies).
+struct LaunchGroup {
+    OpKind kind;
+    int wide;
+    size_t ops_off, prefix_off;
+    int nops;
+    uint64_t total;
+    std::vector<BcLayerOp> layers;
 };
 
 struct BatchPlan {
@@ -392,6 +419,30 @@ inline int op_wide(const Op& op) {
     return 0;
 }
 
+// Groups of ops[first..] by (rank, kind, wide), rank by rank; rank_of gives
+// each op's rank, and ranks run from 0 to nranks - 1.
+inline void group_by_rank(const std::vector<Op>& ops, const std::vector<uint32_t>& rank_of, size_t first,
+                          uint32_t nranks, std::vector<BatchGroup>& out) {
+    std::vector<std::vector<uint32_t>> by_rank(nranks);
+    for (size_t i = first; i < ops.size(); ++i) by_rank[rank_of[i]].push_back((uint32_t)i);
+    for (uint32_t r = 0; r < nranks; ++r) {
+        std::vector<BatchGroup> g;
+        for (uint32_t idx : by_rank[r]) {
+            const Op& op = ops[idx];
+            const int w = op_wide(op);
+            BatchGroup* G = nullptr;
+            for (auto& x : g)
+                if (x.kind == op.kind && x.wide == w) G = &x;
+            if (!G) {
+                g.push_back(BatchGroup{op.kind, w, {}});
+                G = &g.back();
+            }
+            G->ops.push_back(idx);
+        }
+        for (auto& x : g) out.push_back(std::move(x));
+    }
+}
+
 // Workspace sizes first (ws == nullptr), then the ops with real addresses.
 inline void plan_batch(BatchPlan& P, const LayerPool& pool, const PlanParams& pp, const BatchJob* jobs, size_t njobs,
                        char* ws) {
@@ -405,34 +456,18 @@ inline void plan_batch(BatchPlan& P, const LayerPool& pool, const PlanParams& pp
     }
     P.ws_bytes = total;
     if (!ws) return;
-    std::vector<std::vector<Op>> per(njobs);
     for (size_t j = 0; j < njobs; ++j) {
         Sizes s = make_sizes(jobs[j].na_bits, jobs[j].nb_bits);
         if (!s.out_words) continue;
-        plan_mul(per[j], pool, pp, s, jobs[j].a, jobs[j].b, jobs[j].c, ws + P.ws_off[j]);
-        P.max_rank = std::max<uint32_t>(P.max_rank, (uint32_t)per[j].size());
-    }
-    for (uint32_t r = 0; r < P.max_rank; ++r) {
-        std::vector<BatchGroup> g;
-        for (size_t j = 0; j < njobs; ++j) {
-            if (r >= per[j].size()) continue;
-            const Op& op = per[j][r];
-            uint32_t idx = (uint32_t)P.ops.size();
-            P.ops.push_back(op);
+        const size_t first = P.ops.size();
+        plan_mul(P.ops, pool, pp, s, jobs[j].a, jobs[j].b, jobs[j].c, ws + P.ws_off[j]);
+        for (size_t i = first; i < P.ops.size(); ++i) {
             P.job_of.push_back((uint32_t)j);
-            P.rank_of.push_back(r);
-            int w = op_wide(op);
-            BatchGroup* G = nullptr;
-            for (auto& x : g)
-                if (x.kind == op.kind && x.wide == w) G = &x;
-            if (!G) {
-                g.push_back(BatchGroup{op.kind, w, {}});
-                G = &g.back();
-            }
-            G->ops.push_back(idx);
+            P.rank_of.push_back(P.ops[i].level);
+            P.max_rank = std::max<uint32_t>(P.max_rank, P.ops[i].level + 1);
         }
-        for (auto& x : g) P.groups.push_back(std::move(x));
     }
+    group_by_rank(P.ops, P.rank_of, 0, P.max_rank, P.groups);
 }
 
 }  // namespace gf2x

@@ -29,6 +29,9 @@ BATCH_LEN_SEED = 0x4096
 BATCH_OPERAND_BASE = 0x4000_0000
 SERVE_LEN_SEED = 0x5000
 SERVE_OPERAND_BASE = 0x5000_0000
+# Timing streams of many requests take operands as windows of one pool
+# (stream SERVE_POOL_SEED) at offsets drawn from stream SERVE_POOL_SEED + 1.
+SERVE_POOL_SEED = 0x5EED_0000
 
 
 def splitmix64(seed: int, count: int, offset: int = 0) -> np.ndarray:

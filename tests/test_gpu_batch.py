@@ -112,7 +112,7 @@ def test_batch_results_independent_of_neighbours(ctx):
 
 def test_persistent_wait_timeout_is_reported(ctx):
     """Forced from the host: a spin limit of 0 abandons the run at its first
-    dependency wait; the kernel exits and the error is reported."""
+    barrier wait; the kernel exits and the error is reported."""
     spec = inputs.batch_workload(16, 10, 14)
     jobs, ref = make_jobs(spec)
     B = ctx.batch(jobs, persistent=True)
