@@ -128,15 +128,24 @@ def bench_batched(ctx, njobs=4096, reps=5):
     t_loop = timed(loop)
     res["loop_products_per_s"] = round(njobs / t_loop, 1)
     out = {}
-    for name, persistent in (("staged_graph", False), ("persistent_graph", True)):
-        B = ctx.batch(jobs, persistent=persistent)
-        t = timed(lambda: B.run(stream))
-        B.check()
-        st = B.stats()
-        out[name] = t
-        res[f"{name}_products_per_s"] = round(njobs / t, 1)
-        res[f"{name}_launches"] = st["launches"]
-        B.close()
+
+    def batches(tag):
+        for name, persistent in (("staged_graph", False), ("persistent_graph", True)):
+            B = ctx.batch(jobs, persistent=persistent)
+            t = timed(lambda: B.run(stream))
+            B.check()
+            st = B.stats()
+            out[f"{name}{tag}"] = t
+            res[f"{name}{tag}_products_per_s"] = round(njobs / t, 1)
+            res[f"{name}_launches"] = st["launches"]
+            B.close()
+
+    batches("_default_schedule")
+    # the autotuner picks an FFT pass schedule per transform size, then the
+    # batches are planned again with it
+    tuned = ctx.autotune(6, 20, reps=3)
+    res["schedule"] = {str(r["m"]): [r["bottom_log"], r["col_rows_log"]] for r in tuned}
+    batches("")
     best = min(out, key=out.get)
     res["best"] = best
     res["speedup_vs_loop"] = round(t_loop / out[best], 2)
@@ -350,20 +359,26 @@ def main():
     c = torch.empty(P.out_words(n, n), dtype=torch.int64, device="cuda")
     stream = torch.cuda.current_stream()
 
-    # warmup, traced for every kernel kind: per-stage times and the dominant kernel
-    ctx.trace_begin(0x7F)
+    # FFT pass schedules for this product's transform sizes (operand and product)
+    m = P.fft_log2(n, n)
+    m_op = max(1, (((n + 63) // 64) - 1).bit_length())
+    sched = ctx.autotune(min(m_op, m), m, reps=3) if m <= 26 else []
+    log(f"bench: tuned FFT schedules {sched}")
+    # warmup untraced, then one traced product: per-stage times and the dominant kernel
     for _ in range(args.warmup):
         ctx.mul_into(a, n, b, n, c, stream)
+    torch.cuda.synchronize()
+    ctx.trace_begin(0x7F)
+    ctx.mul_into(a, n, b, n, c, stream)
     torch.cuda.synchronize()
     recs = ctx.trace_end()
     per_kernel = {}
     for r in recs:
         per_kernel[r["kernel"]] = per_kernel.get(r["kernel"], 0.0) + r["ms"]
-    w = max(args.warmup, 1)
-    stages = {k: round(v / w, 4) for k, v in sorted(per_kernel.items(), key=lambda kv: -kv[1])}
+    stages = {k: round(v, 4) for k, v in sorted(per_kernel.items(), key=lambda kv: -kv[1])}
     dominant = max(per_kernel, key=per_kernel.get) if per_kernel else "k_fft"
     kind_bit = 1 << P.KERNEL_OF_KIND.index(dominant)
-    log(f"bench: per-kernel ms per product (warmup, traced): {stages}")
+    log(f"bench: per-kernel ms per product (one traced product after warmup): {stages}")
 
     # timed region: only the dominant kernel is bracketed by events
     ctx.trace_begin(kind_bit)
@@ -426,6 +441,7 @@ def main():
         },
         "roofline": roofline,
         "stages_ms": stages,
+        "fft_schedule": {str(r["m"]): [r["bottom_log"], r["col_rows_log"]] for r in sched},
     }
     if not args.no_batch:
         log(f"bench: batched products ({args.batch_jobs} jobs)")

@@ -192,6 +192,37 @@ int gf2x_batch_info(const gf2x_batch *batch, gf2x_batch_stats *stats);
 /* Synchronizes the device, then frees the batch. NULL is ignored. */
 void gf2x_batch_destroy(gf2x_batch *batch);
 
+/* ---------------------------------------------------------------- schedules
+ * FFT pass schedule per transform size 2^m: the bottom pass runs the layers
+ * below bottom_log on contiguous tiles of 2^bottom_log points, and the layers
+ * above are split evenly into strided passes of at most 2^col_rows_log rows
+ * (both in 1..11; 2^11 points fill one LDS tile).  Every schedule computes the
+ * same bits; schedules differ in the number of passes over memory and in tile
+ * shape.  Default 11 and 8 for every m.  A schedule applies to products
+ * planned after it is set (a gf2x_batch keeps the plan it was created with). */
+typedef struct {
+    int32_t m;            /* transform size 2^m */
+    int32_t bottom_log;   /* chosen schedule */
+    int32_t col_rows_log;
+    int32_t copies;       /* transforms timed together */
+    int32_t candidates;   /* distinct schedules timed */
+    float us_default;     /* forward + inverse time per launch set, default schedule (us) */
+    float us_best;        /* the same for the chosen schedule */
+} gf2x_tune_rec;
+
+/* EINVAL for m outside 1..32 or a value outside 1..11. */
+int gf2x_set_schedule(gf2x_ctx *ctx, int m, int bottom_log, int col_rows_log);
+int gf2x_get_schedule(gf2x_ctx *ctx, int m, int *bottom_log, int *col_rows_log);
+
+/* Autotuner: for each m in [m_lo, m_hi] (1 <= m_lo <= m_hi <= 26) times every
+ * distinct candidate schedule (bottom_log in 7..11, col_rows_log in 3..11,
+ * capped at m) on a forward and an inverse FFT of max(1, 2^(21-m)) transforms
+ * at once, one multi-op launch per pass as in batches, `reps` times each;
+ * keeps the fastest in ctx and writes one record per m to `out` (NULL
+ * allowed).  Blocking; uses a temporary device buffer (ENOMEM if it does
+ * not fit). */
+int gf2x_autotune(gf2x_ctx *ctx, int m_lo, int m_hi, int reps, gf2x_tune_rec *out);
+
 /* ------------------------------------------------------------------ serving
  * A request loop with continuous batching (not part of the paper: a serving
  * pattern around its product).  Requests are products whose operands and

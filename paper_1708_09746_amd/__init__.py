@@ -44,6 +44,12 @@ class BatchStats(ctypes.Structure):
                 ("tiles", ctypes.c_uint64), ("workspace_bytes", ctypes.c_uint64)]
 
 
+class TuneRec(ctypes.Structure):
+    _fields_ = [("m", ctypes.c_int32), ("bottom_log", ctypes.c_int32), ("col_rows_log", ctypes.c_int32),
+                ("copies", ctypes.c_int32), ("candidates", ctypes.c_int32), ("us_default", ctypes.c_float),
+                ("us_best", ctypes.c_float)]
+
+
 class ServerCfg(ctypes.Structure):
     _fields_ = [("arena_bytes", ctypes.c_uint64), ("max_active", ctypes.c_uint32),
                 ("levels_per_iter", ctypes.c_uint32), ("inflight", ctypes.c_uint32), ("mode", ctypes.c_int32)]
@@ -91,6 +97,9 @@ def lib():
             "gf2x_batch_run": (i32, [vp, vp]),
             "gf2x_batch_info": (i32, [vp, ctypes.POINTER(BatchStats)]),
             "gf2x_batch_destroy": (None, [vp]),
+            "gf2x_set_schedule": (i32, [vp, i32, i32, i32]),
+            "gf2x_get_schedule": (i32, [vp, i32, ctypes.POINTER(i32), ctypes.POINTER(i32)]),
+            "gf2x_autotune": (i32, [vp, i32, i32, i32, ctypes.POINTER(TuneRec)]),
             "gf2x_now_ns": (u64, []),
             "gf2x_server_create": (i32, [vp, ctypes.POINTER(ServerCfg), ctypes.POINTER(vp)]),
             "gf2x_server_submit": (i32, [vp, vp, u64, vp, u64, vp, u64]),
@@ -204,6 +213,22 @@ class Context:
                persistent: bool = False):
         """A continuous-batching request loop (Server) on this context."""
         return Server(self, arena_bytes, max_active, levels_per_iter, inflight, persistent)
+
+    # ---- FFT pass schedules
+    def set_schedule(self, m: int, bottom_log: int, col_rows_log: int):
+        self._check(lib().gf2x_set_schedule(self._h, m, bottom_log, col_rows_log), "gf2x_set_schedule")
+
+    def get_schedule(self, m: int):
+        b, r = ctypes.c_int(), ctypes.c_int()
+        self._check(lib().gf2x_get_schedule(self._h, m, ctypes.byref(b), ctypes.byref(r)), "gf2x_get_schedule")
+        return b.value, r.value
+
+    def autotune(self, m_lo: int, m_hi: int, reps: int = 5):
+        """Pick the fastest FFT pass schedule for each size 2^m, m in [m_lo, m_hi]."""
+        out = (TuneRec * (m_hi - m_lo + 1))()
+        self._check(lib().gf2x_autotune(self._h, m_lo, m_hi, reps, out), "gf2x_autotune")
+        return [{k: (round(getattr(r, k), 2) if k.startswith("us") else int(getattr(r, k)))
+                 for k, _ in TuneRec._fields_} for r in out]
 
     # ---- tracing
     def trace_begin(self, kind_mask: int = 0x7F):

@@ -1131,6 +1131,76 @@ int server_iterate(gf2x_server* S, bool& launched) {
     return GF2X_OK;
 }
 
+// ------------------------------------------------------------------ autotuner
+// Forward + inverse FFT passes of `copies` independent 2^M-point transforms
+// laid out in `scratch`, grouped by pass as a batch would run them.
+void tune_ops(const PlanParams& pp, int M, int copies, char* scratch, std::vector<Op>& ops,
+              std::vector<BatchGroup>& groups) {
+    const size_t wbytes = align256(8ull << M), per = wbytes + align256(16ull << M);
+    std::vector<uint32_t> rank;
+    ops.clear();
+    groups.clear();
+    uint32_t nr = 0;
+    for (int c = 0; c < copies; ++c) {
+        uint64_t* words = (uint64_t*)(scratch + (size_t)c * per);
+        uint4* spec = (uint4*)(scratch + (size_t)c * per + wbytes);
+        const size_t f = ops.size();
+        emit_fft_forward(ops, pp, words, spec, M, 0);
+        emit_fft_inverse(ops, pp, spec, M);
+        for (size_t i = f; i < ops.size(); ++i) rank.push_back((uint32_t)(i - f));
+        nr = std::max<uint32_t>(nr, (uint32_t)(ops.size() - f));
+    }
+    group_by_rank(ops, rank, 0, nr, groups);
+}
+
+struct TuneBuffers {
+    char* scratch = nullptr;
+    char* desc = nullptr;
+    size_t desc_cap = 0;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    ~TuneBuffers() {
+        if (scratch) (void)hipFree(scratch);
+        if (desc) (void)hipFree(desc);
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+    }
+};
+
+// Average time (us) of one run of the candidate's launches, or < 0 on error.
+int tune_time(gf2x_ctx* ctx, TuneBuffers& T, const PlanParams& pp, int M, int copies, int reps, float& us) {
+    std::vector<Op> ops;
+    std::vector<BatchGroup> groups;
+    tune_ops(pp, M, copies, T.scratch, ops, groups);
+    std::vector<char> host;
+    std::vector<LaunchGroup> launch;
+    pack_groups(ops, groups, host, launch);
+    if (host.size() > T.desc_cap) {
+        if (T.desc) (void)hipFree(T.desc);
+        T.desc = nullptr;
+        T.desc_cap = 0;
+        if (hipMalloc((void**)&T.desc, host.size()) != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(ctx, GF2X_ENOMEM, "autotune descriptors");
+        }
+        T.desc_cap = host.size();
+    }
+    hipStream_t st = ctx->own_stream;
+    hipError_t e = hipMemcpy(T.desc, host.data(), host.size(), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail(ctx, e, "autotune upload");
+    int rc = launch_groups(ctx, launch, T.desc, st);  // warm-up
+    if (rc) return rc;
+    e = hipEventRecord(T.e0, st);
+    for (int r = 0; r < reps && e == hipSuccess && !rc; ++r) rc = launch_groups(ctx, launch, T.desc, st);
+    if (rc) return rc;
+    if (e == hipSuccess) e = hipEventRecord(T.e1, st);
+    if (e == hipSuccess) e = hipEventSynchronize(T.e1);
+    float ms = 0;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, T.e0, T.e1);
+    if (e != hipSuccess) return hip_fail(ctx, e, "autotune timing");
+    us = 1000.0f * ms / (float)reps;
+    return GF2X_OK;
+}
+
 }  // namespace
 
 // ------------------------------------------------------------------ C ABI
@@ -1610,6 +1680,81 @@ void gf2x_server_destroy(gf2x_server* S) {
     DeviceGuard g(S->ctx->device);
     if (S->st) (void)hipStreamSynchronize(S->st);
     server_free(S);
+}
+
+int gf2x_set_schedule(gf2x_ctx* ctx, int m, int bottom_log, int col_rows_log) {
+    if (check_ctx(ctx)) return GF2X_EINVAL;
+    if (m < 1 || m > PlanParams::kMaxM || bottom_log < 1 || bottom_log > kFftTileLog || col_rows_log < 1 ||
+        col_rows_log > kFftTileLog)
+        return fail(ctx, GF2X_EINVAL, "schedule outside its range");
+    ctx->params.fft_bottom_log[m] = (int8_t)bottom_log;
+    ctx->params.fft_col_rows_log[m] = (int8_t)col_rows_log;
+    return GF2X_OK;
+}
+
+int gf2x_get_schedule(gf2x_ctx* ctx, int m, int* bottom_log, int* col_rows_log) {
+    if (check_ctx(ctx) || !bottom_log || !col_rows_log) return GF2X_EINVAL;
+    if (m < 1 || m > PlanParams::kMaxM) return fail(ctx, GF2X_EINVAL, "m outside 1..32");
+    *bottom_log = ctx->params.bottom(m);
+    *col_rows_log = ctx->params.rows(m);
+    return GF2X_OK;
+}
+
+int gf2x_autotune(gf2x_ctx* ctx, int m_lo, int m_hi, int reps, gf2x_tune_rec* out) {
+    if (check_ctx(ctx)) return GF2X_EINVAL;
+    ctx->err.clear();
+    if (m_lo < 1 || m_hi > 26 || m_lo > m_hi || reps < 1) return fail(ctx, GF2X_EINVAL, "autotune range");
+    DeviceGuard g(ctx->device);
+    TuneBuffers T;
+    size_t need = 0;
+    for (int M = m_lo; M <= m_hi; ++M) {
+        const int copies = M >= 21 ? 1 : 1 << (21 - M);
+        need = std::max(need, (size_t)copies * (align256(8ull << M) + align256(16ull << M)));
+    }
+    hipError_t e = hipMalloc((void**)&T.scratch, need);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(ctx, GF2X_ENOMEM, "autotune scratch");
+    }
+    e = hipMemset(T.scratch, 0, need);
+    if (e == hipSuccess) e = hipEventCreate(&T.e0);
+    if (e == hipSuccess) e = hipEventCreate(&T.e1);
+    if (e != hipSuccess) return hip_fail(ctx, e, "autotune setup");
+    for (int M = m_lo; M <= m_hi; ++M) {
+        const int copies = M >= 21 ? 1 : 1 << (21 - M);
+        PlanParams pp = ctx->params;
+        std::vector<std::vector<std::pair<int, int>>> seen;
+        float best = 0, dflt = 0;
+        int best_b = 11, best_r = 8, ncand = 0;
+        // the default first, then the candidates; schedules with the same
+        // passes are timed once
+        std::vector<std::pair<int, int>> cands{{11, 8}};
+        for (int b = 11; b >= 7; --b)
+            for (int r = 3; r <= 11; ++r) cands.push_back({b, r});
+        for (auto [b, r] : cands) {
+            pp.fft_bottom_log[M] = (int8_t)b;
+            pp.fft_col_rows_log[M] = (int8_t)r;
+            auto ranges = fft_pass_ranges(M, pp);
+            bool dup = false;
+            for (auto& x : seen) dup |= x == ranges;
+            if (dup) continue;
+            seen.push_back(ranges);
+            float us = 0;
+            int rc = tune_time(ctx, T, pp, M, copies, reps, us);
+            if (rc) return rc;
+            ++ncand;
+            if (ncand == 1) dflt = us;
+            if (ncand == 1 || us < best) {
+                best = us;
+                best_b = b;
+                best_r = r;
+            }
+        }
+        ctx->params.fft_bottom_log[M] = (int8_t)best_b;
+        ctx->params.fft_col_rows_log[M] = (int8_t)best_r;
+        if (out) out[M - m_lo] = gf2x_tune_rec{M, best_b, best_r, copies, ncand, dflt, best};
+    }
+    return GF2X_OK;
 }
 
 }  // extern "C"

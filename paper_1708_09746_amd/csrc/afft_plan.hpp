@@ -95,9 +95,21 @@ struct LayerPool {
 };
 
 // Tunable shape of the FFT passes (the autotuner picks them per size class).
+// FFT pass schedule, per transform size M (2^M points, M <= 32): the bottom
+// pass covers layers [0, b) on contiguous tiles of 2^b elements, and the
+// layers above it are split evenly into strided passes of at most 2^r rows.
 struct PlanParams {
-    int fft_bottom_log = 11;    // contiguous bottom pass: up to 2^this elements
-    int fft_col_rows_log = 8;   // strided passes: up to 2^this rows
+    static constexpr int kMaxM = 32;
+    int8_t fft_bottom_log[kMaxM + 1];
+    int8_t fft_col_rows_log[kMaxM + 1];
+    PlanParams() {
+        for (int m = 0; m <= kMaxM; ++m) {
+            fft_bottom_log[m] = 11;
+            fft_col_rows_log[m] = 8;
+        }
+    }
+    int bottom(int M) const { return fft_bottom_log[std::min(std::max(M, 0), kMaxM)]; }
+    int rows(int M) const { return fft_col_rows_log[std::min(std::max(M, 0), kMaxM)]; }
 };
 
 struct BcPlanner {
@@ -195,13 +207,14 @@ inline void emit_bc(std::vector<Op>& ops, const LayerPool& pool, void* data, int
     }
 }
 
-// Layer ranges of the FFT passes: a contiguous bottom pass of up to 2^11
-// elements, and strided passes of up to 2^8 rows above it.
+// Layer ranges of the FFT passes: a contiguous bottom pass of up to 2^b
+// elements, and strided passes of up to 2^r rows above it (b, r from the
+// schedule for M, both at most the 2^11-element tile).
 inline std::vector<std::pair<int, int>> fft_pass_ranges(int M, const PlanParams& pp) {
     std::vector<std::pair<int, int>> col;
-    int bottom = std::min(M, std::min(pp.fft_bottom_log, kFftTileLog));
+    int bottom = std::min(M, std::max(1, std::min(pp.bottom(M), kFftTileLog)));
     int rem = M - bottom;
-    int rows = std::min(pp.fft_col_rows_log, kFftTileLog);
+    int rows = std::max(1, std::min(pp.rows(M), kFftTileLog));
     int ncol = (rem + rows - 1) / rows;
     int lo = bottom;
     for (int c = 0; c < ncol; ++c) {
