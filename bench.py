@@ -328,6 +328,7 @@ def main():
     ap.add_argument("--batch-jobs", type=int, default=4096)
     ap.add_argument("--no-serve", action="store_true", help="skip the serving measurement")
     ap.add_argument("--serve-requests", type=int, default=10000)
+    ap.add_argument("--no-tune", action="store_true", help="keep the default FFT pass schedules")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="first run a plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -362,7 +363,7 @@ def main():
     # FFT pass schedules for this product's transform sizes (operand and product)
     m = P.fft_log2(n, n)
     m_op = max(1, (((n + 63) // 64) - 1).bit_length())
-    sched = ctx.autotune(min(m_op, m), m, reps=3) if m <= 26 else []
+    sched = ctx.autotune(min(m_op, m), m, reps=3) if m <= 26 and not args.no_tune else []
     log(f"bench: tuned FFT schedules {sched}")
     # warmup untraced, then one traced product: per-stage times and the dominant kernel
     for _ in range(args.warmup):

@@ -196,9 +196,9 @@ void gf2x_batch_destroy(gf2x_batch *batch);
  * FFT pass schedule per transform size 2^m: the bottom pass runs the layers
  * below bottom_log on contiguous tiles of 2^bottom_log points, and the layers
  * above are split evenly into strided passes of at most 2^col_rows_log rows
- * (both in 1..11; 2^11 points fill one LDS tile).  Every schedule computes the
+ * (both in 1..12; 2^12 points fill one LDS tile).  Every schedule computes the
  * same bits; schedules differ in the number of passes over memory and in tile
- * shape.  Default 11 and 8 for every m.  A schedule applies to products
+ * shape.  Default 12 and 6 for every m.  A schedule applies to products
  * planned after it is set (a gf2x_batch keeps the plan it was created with). */
 typedef struct {
     int32_t m;            /* transform size 2^m */
@@ -210,12 +210,12 @@ typedef struct {
     float us_best;        /* the same for the chosen schedule */
 } gf2x_tune_rec;
 
-/* EINVAL for m outside 1..32 or a value outside 1..11. */
+/* EINVAL for m outside 1..32 or a value outside 1..12. */
 int gf2x_set_schedule(gf2x_ctx *ctx, int m, int bottom_log, int col_rows_log);
 int gf2x_get_schedule(gf2x_ctx *ctx, int m, int *bottom_log, int *col_rows_log);
 
 /* Autotuner: for each m in [m_lo, m_hi] (1 <= m_lo <= m_hi <= 26) times every
- * distinct candidate schedule (bottom_log in 7..11, col_rows_log in 3..11,
+ * distinct candidate schedule (bottom_log in 7..12, col_rows_log in 3..12,
  * capped at m) on a forward and an inverse FFT of max(1, 2^(21-m)) transforms
  * at once, one multi-op launch per pass as in batches, `reps` times each;
  * keeps the fastest in ctx and writes one record per m to `out` (NULL

@@ -64,13 +64,16 @@ __global__ __launch_bounds__(kThreads) void k_bc_layer(BcLayerOp L) {
 // pass's local mu-sets once, and prefetches the next tile's elements into
 // registers while the current tile's layers run.
 constexpr int kFftPrefetch = (1 << kFftTileLog) / kThreads;
+static_assert(kFftPrefetch * kThreads == (1 << kFftTileLog), "every tile element has a prefetch slot");
+static_assert(((1 << kFftTileLog) >> kFftRL) <= kThreads, "one group of kFftRL layers per thread");
+static_assert(16 * ((1 << kFftTileLog) + kMuEntries) + 65536 + 4096 + 16 * 32 + 64 <= 163840, "FFT kernels fit in LDS");
 
 __global__ __launch_bounds__(kThreads) void k_fft(FftPass A, const uint8_t* g_mt, const uint32_t* g_lam,
                                                   const uint4* g_phi) {
     __shared__ __align__(16) uint8_t mt[65536];
     __shared__ uint32_t lam[1024];
     __shared__ uint4 tl[1 << kFftTileLog];
-    __shared__ uint4 mu[1 << kFftTileLog];
+    __shared__ uint4 mu[kMuEntries];
     __shared__ uint4 mu_tile[32];
     const int tid = threadIdx.x, nt = blockDim.x;
     copy_words(tid, nt, (uint32_t*)mt, (const uint32_t*)g_mt, 16384);
@@ -104,7 +107,7 @@ __global__ __launch_bounds__(kThreads) void k_fft(FftPass A, const uint8_t* g_mt
                 if (e < Gn.nel) pre[j] = fft_load(A, g_phi, Gn, e);
             }
         }
-        fft_tile_layers<1>(tid, nt, A, G, mt, lam, tl, mu, mu_tile);
+        fft_tile_layers<kFftRL>(tid, nt, A, G, mt, lam, tl, mu, mu_tile);
         for (uint32_t e = tid; e < G.nel; e += nt) A.dst[G.gbase | fft_elem_index(A, G, e)] = tl[e];
         if (tn >= ntiles) break;
         __syncthreads();
@@ -191,7 +194,7 @@ __global__ __launch_bounds__(kThreads) void k_fft_multi(const FftPass* ops, cons
     __shared__ __align__(16) uint8_t mt[65536];
     __shared__ uint32_t lam[1024];
     __shared__ uint4 tl[1 << kFftTileLog];
-    __shared__ uint4 mu[1 << kFftTileLog];
+    __shared__ uint4 mu[kMuEntries];
     __shared__ uint4 mu_tile[32];
     const int tid = threadIdx.x, nt = blockDim.x;
     copy_words(tid, nt, (uint32_t*)mt, (const uint32_t*)g_mt, 16384);
@@ -210,7 +213,7 @@ __global__ __launch_bounds__(kThreads) void k_fft_multi(const FftPass* ops, cons
             cur_lo = A.lo;
             cur_hi = A.hi;
         }
-        fft_tile<1>(tid, nt, g - prefix[o], A, mt, lam, g_phi, tl, mu, mu_tile);
+        fft_tile<kFftRL>(tid, nt, g - prefix[o], A, mt, lam, g_phi, tl, mu, mu_tile);
     }
 }
 
@@ -292,7 +295,7 @@ __global__ __launch_bounds__(kThreads) void k_persistent(PersistArgs P, const ui
                                                          const uint4* g_phi, const uint4* g_psi) {
     __shared__ __align__(16) uint8_t mt[65536];
     __shared__ uint32_t lam[1024];
-    __shared__ uint4 work[2 << kFftTileLog];  // FFT tile + local mu-sets, a BasisCvt tile, or the Psi table
+    __shared__ uint4 work[(1 << kFftTileLog) + kMuEntries];  // FFT tile + mu-set tables, a BasisCvt tile, or the Psi table
     __shared__ uint4 mu_tile[32];
     __shared__ uint64_t s_item;
     __shared__ int s_stop;
@@ -354,7 +357,7 @@ __global__ __launch_bounds__(kThreads) void k_persistent(PersistArgs P, const ui
                         cur_lo = A.lo;
                         cur_hi = A.hi;
                     }
-                    fft_tile<1>(tid, nt, t, A, mt, lam, g_phi, tl, mu, mu_tile);
+                    fft_tile<kFftRL>(tid, nt, t, A, mt, lam, g_phi, tl, mu, mu_tile);
                     break;
                 }
                 case OpKind::Pmul: pmul_tile(tid, nt, t, D.pmul, mt); break;
@@ -1725,12 +1728,13 @@ int gf2x_autotune(gf2x_ctx* ctx, int m_lo, int m_hi, int reps, gf2x_tune_rec* ou
         PlanParams pp = ctx->params;
         std::vector<std::vector<std::pair<int, int>>> seen;
         float best = 0, dflt = 0;
-        int best_b = 11, best_r = 8, ncand = 0;
+        const PlanParams dflt_pp;
+        int best_b = dflt_pp.bottom(M), best_r = dflt_pp.rows(M), ncand = 0;
         // the default first, then the candidates; schedules with the same
         // passes are timed once
-        std::vector<std::pair<int, int>> cands{{11, 8}};
-        for (int b = 11; b >= 7; --b)
-            for (int r = 3; r <= 11; ++r) cands.push_back({b, r});
+        std::vector<std::pair<int, int>> cands{{best_b, best_r}};
+        for (int b = kFftTileLog; b >= 7; --b)
+            for (int r = 3; r <= kFftTileLog; ++r) cands.push_back({b, r});
         for (auto [b, r] : cands) {
             pp.fft_bottom_log[M] = (int8_t)b;
             pp.fft_col_rows_log[M] = (int8_t)r;

@@ -158,13 +158,59 @@ AFFT_HD uint32_t mul16k(const uint8_t* mt, uint32_t e, uint32_t k) {
     return (t1 ^ t2) | ((t3 ^ t1) << 8);
 }
 
-// word times lambda; mode 0: lambda in GF(256), 1: TGF(2^16), 2: TGF(2^32)
+// Byte permute of the pair (hi, lo): byte i of the result is selected by
+// byte i of sel: 0..3 take bytes 0..3 of lo, 4..7 bytes 0..3 of hi, 0x0c
+// gives 0 (the other selector values are not used here).  One v_perm_b32.
+AFFT_HD uint32_t perm32(uint32_t hi, uint32_t lo, uint32_t sel) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    return __builtin_amdgcn_perm(hi, lo, sel);
+#else
+    uint32_t r = 0;
+    for (int i = 0; i < 4; ++i) {
+        uint32_t v = (sel >> (8 * i)) & 255u, b = 0;
+        if (v < 4)
+            b = (lo >> (8 * v)) & 255u;
+        else if (v < 8)
+            b = (hi >> (8 * (v - 4))) & 255u;
+        r |= b << (8 * i);
+    }
+    return r;
+#endif
+}
+
+// Table index (k << 8) | e with k = byte kb of kw and e = byte eb of ew.
+#define AFFT_IX(kw, kb, ew, eb) perm32((kw), (ew), 0x0c0c0000u | ((4u + (kb)) << 8) | (eb))
+
+// word times lambda; mode 0: lambda in GF(256), 1: TGF(2^16), 2: TGF(2^32).
+// Same products as mul16k above, arranged so that every lookup index is one
+// byte permute of a mu-set word and a data word, and the byte results are
+// placed and summed with permutes and XORs (no shifts or masks):
+//   mode 2, with a = (a.b0..a.b3), p1 = a0 k3(l0), p2 = a1 k3(c32 l1),
+//   p3 = (a0 + a1) k3(l0 + l1), each p = (t1 + t2) + (t3 + t1) x4:
+//   out = [t1a t1a t1a t1a] + [t2a t3a t2a t3a] + [t1b t1b t1c t1c]
+//       + [t2b t3b 0 0] + [0 0 t2c t3c]     (bytes 0..3)
 AFFT_HD uint32_t mul_word_k(const uint8_t* mt, const uint4& m, uint32_t a, int mode) {
-    if (mode == 0) return mul_mu8(mt, m.x & 255u, a);
-    if (mode == 1) return mul16k(mt, a & 0xffffu, m.x) | (mul16k(mt, a >> 16, m.x) << 16);
-    uint32_t a0 = a & 0xffffu, a1 = a >> 16;
-    uint32_t p1 = mul16k(mt, a0, m.x), p2 = mul16k(mt, a1, m.y), p3 = mul16k(mt, a0 ^ a1, m.z);
-    return (p1 ^ p2) | ((p3 ^ p1) << 16);
+    if (mode == 0) {
+        const uint32_t t0 = mt[AFFT_IX(m.x, 0, a, 0)], t1 = mt[AFFT_IX(m.x, 0, a, 1)];
+        const uint32_t t2 = mt[AFFT_IX(m.x, 0, a, 2)], t3 = mt[AFFT_IX(m.x, 0, a, 3)];
+        return perm32(t1, t0, 0x0c0c0400u) | perm32(t3, t2, 0x04000c0cu);
+    }
+    const uint32_t dd = a ^ (a >> 8);  // byte 0: a.b0 + a.b1, byte 2: a.b2 + a.b3
+    const uint32_t t1a = mt[AFFT_IX(m.x, 0, a, 0)], t2a = mt[AFFT_IX(m.x, 1, a, 1)];
+    const uint32_t t3a = mt[AFFT_IX(m.x, 2, dd, 0)];
+    if (mode == 1) {
+        const uint32_t t1b = mt[AFFT_IX(m.x, 0, a, 2)], t2b = mt[AFFT_IX(m.x, 1, a, 3)];
+        const uint32_t t3b = mt[AFFT_IX(m.x, 2, dd, 2)];
+        return perm32(t1b, t1a, 0x04040000u) ^ perm32(t2b, t2a, 0x0c040c00u) ^ perm32(t3b, t3a, 0x040c000cu);
+    }
+    const uint32_t sw = a ^ (a >> 16);   // low half: a0 + a1
+    const uint32_t sd = sw ^ (sw >> 8);  // byte 0: its two bytes summed
+    const uint32_t t1b = mt[AFFT_IX(m.y, 0, a, 2)], t2b = mt[AFFT_IX(m.y, 1, a, 3)];
+    const uint32_t t3b = mt[AFFT_IX(m.y, 2, dd, 2)];
+    const uint32_t t1c = mt[AFFT_IX(m.z, 0, sw, 0)], t2c = mt[AFFT_IX(m.z, 1, sw, 1)];
+    const uint32_t t3c = mt[AFFT_IX(m.z, 2, sd, 0)];
+    return perm32(t1a, t1a, 0x00000000u) ^ perm32(t3a, t2a, 0x04000400u) ^ perm32(t1c, t1b, 0x04040000u) ^
+           perm32(t3b, t2b, 0x0c0c0400u) ^ perm32(t3c, t2c, 0x04000c0cu);
 }
 
 AFFT_HD uint4 mul_sub_k(const uint8_t* mt, const uint4& m, const uint4& v, int mode) {

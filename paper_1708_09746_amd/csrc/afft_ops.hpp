@@ -10,7 +10,15 @@
 namespace gf2x {
 
 constexpr int kThreads = 1024;    // threads per block in every kernel
-constexpr int kFftTileLog = 11;   // FFT tile: up to 2^11 elements (32 KiB)
+constexpr int kFftTileLog = 12;   // FFT tile: up to 2^12 elements (64 KiB)
+constexpr int kFftRL = 2;         // FFT layers per LDS round trip (4 elements per thread)
+// Local mu-set tables of an FFT pass (see fft_local_mu): per local layer a
+// table over the low 6 block bits and one over the high block bits (at most
+// kFftTileLog - 7 of them), the latter kept twice (pass part, pass + tile part).
+constexpr int kMuLo = 64, kMuHi = 32;
+constexpr int kMuHiBase = kFftTileLog * kMuLo;
+constexpr int kMuHiCur = kMuHiBase + kFftTileLog * kMuHi;
+constexpr int kMuEntries = kMuHiCur + kFftTileLog * kMuHi;
 constexpr int kBcTileLog64 = 13;  // BasisCvt tile on 64-bit words: 64 KiB
 constexpr int kBcTileLog128 = 12; // BasisCvt tile on 128-bit elements: 64 KiB
 constexpr int kPmulTile = 1024;
@@ -313,6 +321,11 @@ AFFT_HD uint4 phi_word(const uint4* phi_tab, uint64_t w) {
     return r;
 }
 
+// mu-set of local layer li for block row bits b (b < 2^(rlog - li - 1))
+AFFT_HD uint4 fft_mu(const uint4* mu, int li, uint32_t b) {
+    return xor4(mu[li * kMuLo + (int)(b & 63u)], mu[kMuHiCur + li * kMuHi + (int)(b >> 6)]);
+}
+
 // One step of RL consecutive layers [i0, i0 + RL) held in registers: a thread
 // owns the 2^RL elements whose rows differ only in the bits (i0 - lo) ..
 // (i0 - lo + RL - 1) (same column) and runs all their butterflies.
@@ -333,13 +346,13 @@ AFFT_HD void fft_step(int tid, int nt, const FftPass& A, int i0, const uint8_t* 
         for (int s = 0; s < RL; ++s) {
             const int l = INV ? s : RL - 1 - s;  // layer i0 + l
             const int i = i0 + l;
+            const int li = i - (int)A.lo;
             const int mode = width_mode((int)A.log_total - i);
-            const uint32_t off = (1u << (A.hi - 1 - i)) - 1;
 #pragma unroll
             for (int j = 0; j < (1 << RL); ++j) {
                 if (j & (1 << l)) continue;
                 uint32_t r0 = base_r | ((uint32_t)j << h0);
-                uint4 m = mu[off + (r0 >> (i - (int)A.lo + 1))];
+                uint4 m = fft_mu(mu, li, r0 >> (li + 1));
                 uint4 u = x[j], v = x[j | (1 << l)];
                 if (!INV) {
                     u = u ^ mul_sub_k(mt, m, v, mode);
@@ -360,20 +373,29 @@ AFFT_HD void fft_step(int tid, int nt, const FftPass& A, int i0, const uint8_t* 
 // The multiplier of layer i for the block starting at global index s is
 // lambda = s_i(s̄) = XOR of lam[i][t] over the set bits t of s.  Inside a tile,
 // s = S | (b << (i + 1)) with S the tile's bits at and above `hi` and b the
-// block's row bits, and the mu-set of lambda is GF(2)-linear in lambda, so
-//   mu(lambda) = mu(s_i(S̄)) + mu(s_i(b << (i + 1)))
-// with the second term the same for every tile of the pass.  Entry E of the
-// local table <-> layer i = hi - 1 - floor(log2(E + 1)), block
-// b = E + 1 - 2^floor(log2(E + 1)).
+// block's row bits (nb = hi - i - 1 of them), and the mu-set of lambda is
+// GF(2)-linear in lambda, so
+//   mu(lambda) = mu(s_i(S̄)) + mu(s_i(low 6 bits of b)) + mu(s_i(high bits of b))
+// (each s_i of its bits of b placed at their positions in s).  The middle term
+// is table lo[li][b & 63], the others table hi[li][b >> 6]: its pass part is
+// the same for every tile of the pass (written here), and each tile adds its
+// own tile part (fft_tile_layers).  li = i - lo is the local layer.
 AFFT_HD void fft_local_mu(int tid, int nt, const FftPass& A, const uint8_t* mt, const uint32_t* lam, uint4* mu) {
-    const uint32_t nmu = (1u << (A.hi - A.lo)) - 1;
-    for (uint32_t E = tid; E < nmu; E += nt) {
-        uint32_t q = E + 1;
-        int lg = 31 - __builtin_clz(q);
-        int i = (int)A.hi - 1 - lg;
+    const int rlog = (int)(A.hi - A.lo);
+    for (int E = tid; E < kFftTileLog * (kMuLo + kMuHi); E += nt) {
+        const bool hi = E >= kFftTileLog * kMuLo;
+        const int F = hi ? E - kFftTileLog * kMuLo : E;
+        const int li = hi ? F / kMuHi : F / kMuLo;
+        const uint32_t x = hi ? (uint32_t)(F % kMuHi) : (uint32_t)(F % kMuLo);
+        if (li >= rlog) continue;
+        const int nb = rlog - li - 1;
+        const int lob = nb < 6 ? nb : 6;
+        if (x >= (1u << (hi ? nb - lob : lob))) continue;
+        const int i = (int)A.lo + li;
+        const int t0 = i + 1 + (hi ? 6 : 0);
         uint32_t lv = 0;
-        for (uint32_t b = q - (1u << lg); b; b &= b - 1) lv ^= lam[i * 32 + i + 1 + __builtin_ctz(b)];
-        mu[E] = make_mu_k(mt, lv);
+        for (uint32_t q = x; q; q &= q - 1) lv ^= lam[i * 32 + t0 + __builtin_ctz(q)];
+        mu[hi ? kMuHiBase + li * kMuHi + (int)x : li * kMuLo + (int)x] = make_mu_k(mt, lv);
     }
 }
 
@@ -406,10 +428,10 @@ AFFT_HD uint4 fft_load(const FftPass& A, const uint4* phi_tab, const FftTileGeom
     return A.dst[G.gbase | p];
 }
 
-// Layers [lo, hi) of one tile already in LDS (tl); mu holds the local
-// mu-sets (fft_local_mu), which hold the tile's full mu-sets while its layers
-// run and are restored afterwards; mu_tile (32 entries) takes the tile parts.
-// RL: layers kept in registers per LDS round trip.
+// Layers [lo, hi) of one tile already in LDS (tl); mu holds the pass's local
+// mu-set tables (fft_local_mu), completed here with the tile part of every
+// layer (mu_tile, up to 32 entries).  RL: layers kept in registers per LDS
+// round trip.
 template <int RL>
 AFFT_HD void fft_tile_layers(int tid, int nt, const FftPass& A, const FftTileGeom& G, const uint8_t* mt,
                              const uint32_t* lam, uint4* tl, uint4* mu, uint4* mu_tile) {
@@ -421,12 +443,13 @@ AFFT_HD void fft_tile_layers(int tid, int nt, const FftPass& A, const FftTileGeo
         mu_tile[li] = make_mu_k(mt, lv);
     }
     AFFT_SYNC();
-    // full mu-sets of this tile: add the tile part of each layer into the
-    // shared local table in place (undone below: XOR is an involution)
-    const uint32_t nmu = (1u << rlog) - 1;
-    for (uint32_t E = tid; E < nmu; E += nt) mu[E] = mu[E] ^ mu_tile[rlog - 1 - (31 - __builtin_clz(E + 1))];
+    // high tables of this tile: pass part + tile part
+    for (int E = tid; E < rlog * kMuHi; E += nt) {
+        const int li = E / kMuHi, y = E % kMuHi;
+        const int nb = rlog - li - 1;
+        if (y < (1 << (nb > 6 ? nb - 6 : 0))) mu[kMuHiCur + E] = xor4(mu[kMuHiBase + E], mu_tile[li]);
+    }
     AFFT_SYNC();
-    uint4* muf = mu;
     int done = 0;
     while (done < rlog) {
         int r = rlog - done;
@@ -434,23 +457,22 @@ AFFT_HD void fft_tile_layers(int tid, int nt, const FftPass& A, const FftTileGeo
         int i0 = A.inverse ? (int)A.lo + done : (int)A.hi - done - R;
         if (A.inverse) {
             if (R == 3)
-                fft_step<3, true>(tid, nt, A, i0, mt, tl, muf);
+                fft_step<3, true>(tid, nt, A, i0, mt, tl, mu);
             else if (R == 2)
-                fft_step<2, true>(tid, nt, A, i0, mt, tl, muf);
+                fft_step<2, true>(tid, nt, A, i0, mt, tl, mu);
             else
-                fft_step<1, true>(tid, nt, A, i0, mt, tl, muf);
+                fft_step<1, true>(tid, nt, A, i0, mt, tl, mu);
         } else {
             if (R == 3)
-                fft_step<3, false>(tid, nt, A, i0, mt, tl, muf);
+                fft_step<3, false>(tid, nt, A, i0, mt, tl, mu);
             else if (R == 2)
-                fft_step<2, false>(tid, nt, A, i0, mt, tl, muf);
+                fft_step<2, false>(tid, nt, A, i0, mt, tl, mu);
             else
-                fft_step<1, false>(tid, nt, A, i0, mt, tl, muf);
+                fft_step<1, false>(tid, nt, A, i0, mt, tl, mu);
         }
         AFFT_SYNC();
         done += R;
     }
-    for (uint32_t E = tid; E < nmu; E += nt) mu[E] = mu[E] ^ mu_tile[rlog - 1 - (31 - __builtin_clz(E + 1))];
 }
 
 // One whole tile: load, layers, store (the sequential form; the GPU kernel

@@ -94,7 +94,6 @@ struct LayerPool {
     }
 };
 
-// Tunable shape of the FFT passes (the autotuner picks them per size class).
 // FFT pass schedule, per transform size M (2^M points, M <= 32): the bottom
 // pass covers layers [0, b) on contiguous tiles of 2^b elements, and the
 // layers above it are split evenly into strided passes of at most 2^r rows.
@@ -104,8 +103,8 @@ struct PlanParams {
     int8_t fft_col_rows_log[kMaxM + 1];
     PlanParams() {
         for (int m = 0; m <= kMaxM; ++m) {
-            fft_bottom_log[m] = 11;
-            fft_col_rows_log[m] = 8;
+            fft_bottom_log[m] = 12;
+            fft_col_rows_log[m] = 6;
         }
     }
     int bottom(int M) const { return fft_bottom_log[std::min(std::max(M, 0), kMaxM)]; }
@@ -209,7 +208,7 @@ inline void emit_bc(std::vector<Op>& ops, const LayerPool& pool, void* data, int
 
 // Layer ranges of the FFT passes: a contiguous bottom pass of up to 2^b
 // elements, and strided passes of up to 2^r rows above it (b, r from the
-// schedule for M, both at most the 2^11-element tile).
+// schedule for M, both at most the 2^12-element tile).
 inline std::vector<std::pair<int, int>> fft_pass_ranges(int M, const PlanParams& pp) {
     std::vector<std::pair<int, int>> col;
     int bottom = std::min(M, std::max(1, std::min(pp.bottom(M), kFftTileLog)));

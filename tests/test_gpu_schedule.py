@@ -42,7 +42,7 @@ def case(na, nb):
     return CASES[(na, nb)]
 
 
-@pytest.mark.parametrize("sched", [(11, 8), (11, 11), (10, 5), (9, 3), (7, 11), (3, 2), (1, 1)])
+@pytest.mark.parametrize("sched", [(12, 6), (12, 12), (11, 8), (10, 5), (9, 3), (7, 11), (3, 2), (1, 1)])
 def test_every_schedule_is_exact(ctx, sched):
     b, r = sched
     for m in range(1, 33):
@@ -55,7 +55,7 @@ def test_every_schedule_is_exact(ctx, sched):
             assert np.array_equal(got, ref), (sched, na, nb)
     finally:
         for m in range(1, 33):
-            ctx.set_schedule(m, 11, 8)
+            ctx.set_schedule(m, 12, 6)
 
 
 def test_autotune_then_products(ctx):
@@ -64,7 +64,7 @@ def test_autotune_then_products(ctx):
     assert [r["m"] for r in recs] == list(range(6, 19))
     for r in recs:
         assert ctx.get_schedule(r["m"]) == (r["bottom_log"], r["col_rows_log"])
-        assert 1 <= r["bottom_log"] <= 11 and 1 <= r["col_rows_log"] <= 11
+        assert 1 <= r["bottom_log"] <= 12 and 1 <= r["col_rows_log"] <= 12
         assert r["candidates"] >= 1 and r["us_best"] <= r["us_default"]
     for na, nb in SIZES:
         a, bb, ref = case(na, nb)
@@ -81,11 +81,11 @@ def test_autotune_then_products(ctx):
     for (da, na, db, nb, c), ref in zip(jobs, refs):
         assert np.array_equal(host(c), ref), (na, nb)
     for m in range(1, 33):
-        ctx.set_schedule(m, 11, 8)
+        ctx.set_schedule(m, 12, 6)
 
 
 def test_schedule_range_checks(ctx):
-    for bad in [(0, 11, 8), (33, 11, 8), (10, 0, 8), (10, 12, 8), (10, 11, 0), (10, 11, 12)]:
+    for bad in [(0, 11, 8), (33, 11, 8), (10, 0, 8), (10, 13, 8), (10, 11, 0), (10, 11, 13)]:
         with pytest.raises(P.Gf2xError) as e:
             ctx.set_schedule(*bad)
         assert e.value.code == P.GF2X_EINVAL
