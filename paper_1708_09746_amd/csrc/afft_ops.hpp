@@ -24,7 +24,6 @@ constexpr int kBcTileLog128 = 12; // BasisCvt tile on 128-bit elements: 64 KiB
 constexpr int kPmulTile = 1024;
 constexpr int kPsiTile = 1024;
 constexpr int kPackTile = 4096;
-constexpr int kGatherUnroll = 1;  // global loads kept in flight per thread (more was slower)
 
 // ------------------------------------------------------------------ pack
 // Split (Alg. 5 first step, w = 64): the operand's words, bits at and above
@@ -134,28 +133,26 @@ struct BcLayerOp {
 
 AFFT_HD uint64_t bc_tiles(const BcTileOp& B) { return B.nelem >> (B.log_rows + B.log_tc); }
 
-template <typename T>
-AFFT_HD void bc_tile(int tid, int nt, uint64_t tile, const BcTileOp& B, T* lds) {
+// Tile geometry: element e of a tile sits at base + off(e).
+struct BcTileGeom {
+    uint64_t base;  // element index of the tile's first element
+    uint32_t ne;    // elements in the tile
+};
+
+AFFT_HD BcTileGeom bc_tile_geom(const BcTileOp& B, uint64_t tile) {
     const uint32_t ncb_log = B.log_stride - B.log_tc;
     const uint64_t cb = tile & ((1ull << ncb_log) - 1);
     const uint64_t o = tile >> ncb_log;
-    T* g = (T*)B.data + (o << (B.log_rows + B.log_stride)) + (cb << B.log_tc);
-    const uint32_t ne = 1u << (B.log_rows + B.log_tc);
-    const uint32_t cmask = (1u << B.log_tc) - 1;
-    for (uint32_t e0 = tid; e0 < ne; e0 += nt * kGatherUnroll) {
-        T v[kGatherUnroll];
-#pragma unroll
-        for (int u = 0; u < kGatherUnroll; ++u) {
-            uint32_t e = e0 + u * nt;
-            v[u] = e < ne ? g[((uint64_t)(e >> B.log_tc) << B.log_stride) + (e & cmask)] : zero_elem<T>();
-        }
-#pragma unroll
-        for (int u = 0; u < kGatherUnroll; ++u) {
-            uint32_t e = e0 + u * nt;
-            if (e < ne) lds[e] = v[u];
-        }
-    }
-    AFFT_SYNC();
+    return BcTileGeom{(o << (B.log_rows + B.log_stride)) + (cb << B.log_tc), 1u << (B.log_rows + B.log_tc)};
+}
+
+AFFT_HD uint64_t bc_tile_off(const BcTileOp& B, uint32_t e) {
+    return ((uint64_t)(e >> B.log_tc) << B.log_stride) + (e & ((1u << B.log_tc) - 1));
+}
+
+// The tile's layers on its LDS copy.
+template <typename T>
+AFFT_HD void bc_tile_layers(int tid, int nt, const BcTileOp& B, uint32_t ne, T* lds) {
     const int n = (int)B.nlayers;
     for (int li = 0; li < n; ++li) {
         const BcLayer L = B.layers[B.inverse ? n - 1 - li : li];
@@ -164,19 +161,18 @@ AFFT_HD void bc_tile(int tid, int nt, uint64_t tile, const BcTileOp& B, T* lds) 
             AFFT_SYNC();
         }
     }
-    for (uint32_t e0 = tid; e0 < ne; e0 += nt * kGatherUnroll) {
-        T v[kGatherUnroll];
-#pragma unroll
-        for (int u = 0; u < kGatherUnroll; ++u) {
-            uint32_t e = e0 + u * nt;
-            v[u] = e < ne ? lds[e] : zero_elem<T>();
-        }
-#pragma unroll
-        for (int u = 0; u < kGatherUnroll; ++u) {
-            uint32_t e = e0 + u * nt;
-            if (e < ne) g[((uint64_t)(e >> B.log_tc) << B.log_stride) + (e & cmask)] = v[u];
-        }
-    }
+}
+
+// One whole tile: gather, layers, scatter (the GPU kernel overlaps the next
+// tile's gather with these layers).
+template <typename T>
+AFFT_HD void bc_tile(int tid, int nt, uint64_t tile, const BcTileOp& B, T* lds) {
+    const BcTileGeom G = bc_tile_geom(B, tile);
+    T* g = (T*)B.data + G.base;
+    for (uint32_t e = tid; e < G.ne; e += nt) lds[e] = g[bc_tile_off(B, e)];
+    AFFT_SYNC();
+    bc_tile_layers<T>(tid, nt, B, G.ne, lds);
+    for (uint32_t e = tid; e < G.ne; e += nt) g[bc_tile_off(B, e)] = lds[e];
     AFFT_SYNC();
 }
 
@@ -204,87 +200,86 @@ AFFT_HD uint64_t bc_class_tiles(const BcClassOp& C) {
     return (C.nelem >> (C.m + C.log_u)) * bc_class_tiles_per_block(C);
 }
 
-template <typename T>
-AFFT_HD void bc_class_tile(int tid, int nt, uint64_t tile, const BcClassOp& C, T* lds) {
-    const uint64_t P = (1ull << C.K) - 1;
-    const uint64_t X = P << C.log_u;
+// Class tile geometry: position (q, xw) of the tile (e = q W + xw) holds
+// unit t = q P + ((x0 + xw) >> log_u) of block blk; it is absent (zero in the
+// tile, never stored) if x0 + xw >= X or t >= 2^m.
+struct BcClassGeom {
+    uint64_t base;  // element index of the block's first element
+    uint64_t x0;    // first position of the tile
+    uint32_t ne;    // Q W
+};
+
+AFFT_HD BcClassGeom bc_class_geom(const BcClassOp& C, uint64_t tile) {
     const uint64_t tpb = bc_class_tiles_per_block(C);
     const uint64_t blk = tile / tpb;
-    const uint64_t x0 = (tile - blk * tpb) << C.log_w;
+    return BcClassGeom{blk << (C.m + C.log_u), (tile - blk * tpb) << C.log_w, C.q_rows << C.log_w};
+}
+
+// Offset of element e in its block, or ~0 if it is absent.
+AFFT_HD uint64_t bc_class_off(const BcClassOp& C, const BcClassGeom& G, uint32_t e) {
+    const uint64_t P = (1ull << C.K) - 1, X = P << C.log_u;
+    const uint64_t q = e >> C.log_w, x = G.x0 + (e & ((1u << C.log_w) - 1));
+    if (x >= X || q * P + (x >> C.log_u) >= (1ull << C.m)) return ~0ull;
+    return q * X + x;
+}
+
+template <typename T>
+AFFT_HD void bc_class_layers(int tid, int nt, const BcClassOp& C, const BcClassGeom& G, T* lds) {
+    const uint64_t P = (1ull << C.K) - 1;
+    const uint64_t X = P << C.log_u;
     const uint32_t lw = C.log_w, wm = (1u << lw) - 1;
     const uint64_t nunits = 1ull << C.m;
-    T* g = (T*)C.data + (blk << (C.m + C.log_u));
-    const uint32_t ne = C.q_rows << lw;
-    // position (q, xw) holds unit t = q P + ((x0 + xw) >> log_u); absent if
-    // x0 + xw >= X or t >= 2^m
-    for (uint32_t e0 = tid; e0 < ne; e0 += nt * kGatherUnroll) {
-        T v[kGatherUnroll];
-#pragma unroll
-        for (int u = 0; u < kGatherUnroll; ++u) {
-            uint32_t e = e0 + u * nt;
-            uint64_t q = e >> lw, x = x0 + (e & wm);
-            v[u] = zero_elem<T>();
-            if (e < ne && x < X && q * P + (x >> C.log_u) < nunits) v[u] = g[q * X + x];
+    const uint32_t ne = G.ne;
+    const int nl = (int)(C.m - C.K);
+    // Layer j moves unit t to t - (D - k) = t - k P (the same position x of
+    // row q - k) for t = 2D-1 down to D in every 2D-unit block.  A target is
+    // itself a source only for t in [2D-k, 2D), and its own target then lies
+    // below D, so the layer is a set of independent chains t -> t' -> t''
+    // and single moves (t in [D+k, 2D-k)): one sweep, each element starting a
+    // chain, a single move or nothing, a chain run by one thread in the
+    // layer's order (reversed for the inverse).
+    for (int li = 0; li < nl; ++li) {
+        const int j = C.inverse ? li : nl - 1 - li;
+        const uint64_t D = 1ull << (C.K + j), k = 1ull << j;
+        const uint32_t rs = (uint32_t)k << lw;  // k rows
+        for (uint32_t e = tid; e < ne; e += nt) {
+            const uint64_t x = G.x0 + (e & wm);
+            if (x >= X) continue;
+            const uint64_t t = (uint64_t)(e >> lw) * P + (x >> C.log_u);
+            if (t >= nunits) continue;
+            const uint64_t pos = t & (2 * D - 1);
+            if (pos >= 2 * D - k) {
+                const uint32_t e1 = e - rs, e2 = e1 - rs;
+                if (!C.inverse) {
+                    const T v = lds[e1] ^ lds[e];
+                    lds[e1] = v;
+                    lds[e2] = lds[e2] ^ v;
+                } else {
+                    const T v = lds[e1];
+                    lds[e2] = lds[e2] ^ v;
+                    lds[e1] = v ^ lds[e];
+                }
+            } else if (pos >= D + k) {
+                lds[e - rs] = lds[e - rs] ^ lds[e];
+            }
         }
-#pragma unroll
-        for (int u = 0; u < kGatherUnroll; ++u) {
-            uint32_t e = e0 + u * nt;
-            if (e < ne) lds[e] = v[u];
-        }
+        AFFT_SYNC();
+    }
+}
+
+template <typename T>
+AFFT_HD void bc_class_tile(int tid, int nt, uint64_t tile, const BcClassOp& C, T* lds) {
+    const BcClassGeom G = bc_class_geom(C, tile);
+    T* g = (T*)C.data + G.base;
+    for (uint32_t e = tid; e < G.ne; e += nt) {
+        const uint64_t o = bc_class_off(C, G, e);
+        lds[e] = o != ~0ull ? g[o] : zero_elem<T>();
     }
     AFFT_SYNC();
-    const int nl = (int)(C.m - C.K);
-    const uint64_t xend = x0 + (1ull << lw) < X ? x0 + (1ull << lw) : X;
-    for (int li = 0; li < nl; ++li) {
-        int j = C.inverse ? li : nl - 1 - li;
-        const uint64_t D = 1ull << (C.K + j), k = 1ull << j;
-        for (int part = 0; part < 2; ++part) {
-            int which = C.inverse ? 1 - part : part;
-            if (which == 0) {
-                // sources: the top k units of every 2D block, 2^(m-K-1) of them
-                // per block; only those whose class lies in this tile act here
-                const uint64_t nsrc = nunits >> (C.K + 1);
-                for (uint64_t w = tid; w < nsrc; w += nt) {
-                    uint64_t t = ((w >> j) << (C.K + j + 1)) + 2 * D - k + (w & (k - 1));
-                    uint64_t q = t / P, r = t - q * P;
-                    uint64_t xa = r << C.log_u, xb = xa + (1ull << C.log_u);
-                    if (xa < x0) xa = x0;
-                    if (xb > xend) xb = xend;
-                    for (uint64_t x = xa; x < xb; ++x) {
-                        uint32_t e = ((uint32_t)q << lw) + (uint32_t)(x - x0);
-                        uint32_t tgt = e - ((uint32_t)k << lw);
-                        lds[tgt] = lds[tgt] ^ lds[e];
-                    }
-                }
-            } else {
-                const uint64_t hi = 2 * D - k;
-                for (uint32_t e = tid; e < ne; e += nt) {
-                    uint64_t x = x0 + (e & wm);
-                    if (x >= X) continue;
-                    uint64_t t = (uint64_t)(e >> lw) * P + (x >> C.log_u);
-                    if (t >= nunits) continue;
-                    uint64_t pos = t & (2 * D - 1);
-                    if (pos < D || pos >= hi) continue;
-                    uint32_t tgt = e - ((uint32_t)k << lw);
-                    lds[tgt] = lds[tgt] ^ lds[e];
-                }
-            }
-            AFFT_SYNC();
-        }
-    }
-    for (uint32_t e0 = tid; e0 < ne; e0 += nt * kGatherUnroll) {
-        T v[kGatherUnroll];
-#pragma unroll
-        for (int u = 0; u < kGatherUnroll; ++u) {
-            uint32_t e = e0 + u * nt;
-            v[u] = e < ne ? lds[e] : zero_elem<T>();
-        }
-#pragma unroll
-        for (int u = 0; u < kGatherUnroll; ++u) {
-            uint32_t e = e0 + u * nt;
-            uint64_t q = e >> lw, x = x0 + (e & wm);
-            if (e < ne && x < X && q * P + (x >> C.log_u) < nunits) g[q * X + x] = v[u];
-        }
+    bc_class_layers<T>(tid, nt, C, G, lds);
+    for (uint32_t e = tid; e < G.ne; e += nt) {
+        const uint64_t o = bc_class_off(C, G, e);
+        if (o != ~0ull) g[o] = lds[e];
     }
     AFFT_SYNC();
 }
