@@ -29,6 +29,7 @@ WORKLOADS = {
     "c3b": (1 << 29, "2^29 x 2^29-bit product"),
 }
 COUNTERS = os.path.join(ROOT, "profiles", "k_fft_c3a_counters.txt")
+UTILISATION = os.path.join(ROOT, "profiles", "c3a_utilisation.md")
 
 
 def log(*a):
@@ -63,6 +64,25 @@ def counter_traffic(kernel):
         return float(kv["hbm_bytes_per_launch"])
     except (KeyError, ValueError):
         return None
+
+
+def counter_utilisation(kernel):
+    """VALU/LDS utilisation of `kernel` from the committed rocprofv3 counter
+    table, if it was taken on the current kernel sources; else None."""
+    if not os.path.exists(UTILISATION):
+        return None
+    digest, row = None, None
+    with open(UTILISATION) as f:
+        for line in f:
+            if line.startswith("source_digest:"):
+                digest = line.split(":", 1)[1].strip()
+            cells = [c.strip() for c in line.strip().strip("|").split("|")]
+            if len(cells) == 8 and cells[0] == kernel:
+                row = cells
+    if row is None or digest != source_digest():
+        return None
+    return {"valu_issue": float(row[4]), "lds_busy": float(row[5]), "lds_bank_conflict_share": float(row[6]),
+            "waves_waiting": float(row[7]), "source": "profiles/c3a_utilisation.md"}
 
 
 def cpu_baseline(na, seeds, sample_log2=25):
@@ -369,7 +389,7 @@ def main():
     for _ in range(args.warmup):
         ctx.mul_into(a, n, b, n, c, stream)
     torch.cuda.synchronize()
-    ctx.trace_begin(0x7F)
+    ctx.trace_begin(0xFF)
     ctx.mul_into(a, n, b, n, c, stream)
     torch.cuda.synchronize()
     recs = ctx.trace_end()
@@ -408,6 +428,7 @@ def main():
         "launches": len(recs),
         "avg_launch_ms": round(tot_ms / nl, 5),
         "alg_bytes_per_launch": int(tot_bytes / nl),
+        "utilisation": counter_utilisation(dominant),
     }
 
     # bit-exactness spot check of the timed product (two words from the oracle)

@@ -138,7 +138,7 @@ int gf2x_mul_batch(gf2x_ctx *ctx, const gf2x_job *jobs, size_t njobs, void *stre
  * launch stream; gf2x_trace_read() waits for them and returns one record per
  * launch.  Kinds (bit = 1 << kind): 0 pack, 1 BasisCvt tile, 2 BasisCvt global
  * layer, 3 FFT pass, 4 pointmul, 5 changeRepr back + combine, 6 BasisCvt
- * VarSubs class pass. */
+ * VarSubs class pass, 7 truncated-transform step. */
 typedef struct {
     int kind;            /* one of the kinds above */
     uint64_t elements;   /* elements (words or 16-byte field elements) the launch covers */
@@ -222,6 +222,26 @@ int gf2x_get_schedule(gf2x_ctx *ctx, int m, int *bottom_log, int *col_rows_log);
  * allowed).  Blocking; uses a temporary device buffer (ENOMEM if it does
  * not fit). */
 int gf2x_autotune(gf2x_ctx *ctx, int m_lo, int m_hi, int reps, gf2x_tune_rec *out);
+
+/* --------------------------------------------------- truncated transforms
+ * A product of n_c = ceil(na/64) + ceil(nb/64) - 1 word coefficients needs
+ * N = 2^m >= n_c evaluation points; with truncation the two forward
+ * transforms evaluate only the first M points, n_c rounded up to a multiple
+ * of 2^max(m - levels, 6), pointmul runs on M points, and the inverse
+ * recovers the coefficients from those M values (the coefficients at M and
+ * beyond are zero by the degree bound): the butterflies of Alg. 1 restricted
+ * to the needed points, and their inverse run on the values below M and the
+ * known coefficients above it.  Only transforms of at least 2^min_log2n
+ * points are truncated: each step of the recursion is a pass of its own,
+ * which smaller transforms do not repay.  levels = 0 turns truncation off
+ * (M = N); the default is 3 levels from 2^22 points on.  The product bits
+ * are the same either way. */
+
+/* Truncation for products planned afterwards: levels in 0..16, min_log2n in
+ * 1..32 (EINVAL outside). */
+int gf2x_set_truncation(gf2x_ctx *ctx, int levels, int min_log2n);
+/* Points M a product of these sizes is evaluated at on ctx (0 if empty). */
+uint64_t gf2x_eval_points(gf2x_ctx *ctx, uint64_t na_bits, uint64_t nb_bits);
 
 /* ------------------------------------------------------------------ serving
  * A request loop with continuous batching (not part of the paper: a serving

@@ -35,8 +35,9 @@ class TraceRec(ctypes.Structure):
                 ("bytes_written", ctypes.c_uint64), ("ms", ctypes.c_float)]
 
 
-KIND_NAMES = ["pack", "basiscvt_tile", "basiscvt_layer", "fft_pass", "pointmul", "psi_combine", "basiscvt_class"]
-KERNEL_OF_KIND = ["k_pack", "k_bc_tile", "k_bc_layer", "k_fft", "k_pmul", "k_psi", "k_bc_class"]
+KIND_NAMES = ["pack", "basiscvt_tile", "basiscvt_layer", "fft_pass", "pointmul", "psi_combine", "basiscvt_class",
+              "spine"]
+KERNEL_OF_KIND = ["k_pack", "k_bc_tile", "k_bc_layer", "k_fft", "k_pmul", "k_psi", "k_bc_class", "k_spine"]
 
 
 class BatchStats(ctypes.Structure):
@@ -100,6 +101,8 @@ def lib():
             "gf2x_set_schedule": (i32, [vp, i32, i32, i32]),
             "gf2x_get_schedule": (i32, [vp, i32, ctypes.POINTER(i32), ctypes.POINTER(i32)]),
             "gf2x_autotune": (i32, [vp, i32, i32, i32, ctypes.POINTER(TuneRec)]),
+            "gf2x_set_truncation": (i32, [vp, i32, i32]),
+            "gf2x_eval_points": (u64, [vp, u64, u64]),
             "gf2x_now_ns": (u64, []),
             "gf2x_server_create": (i32, [vp, ctypes.POINTER(ServerCfg), ctypes.POINTER(vp)]),
             "gf2x_server_submit": (i32, [vp, vp, u64, vp, u64, vp, u64]),
@@ -214,6 +217,15 @@ class Context:
         """A continuous-batching request loop (Server) on this context."""
         return Server(self, arena_bytes, max_active, levels_per_iter, inflight, persistent)
 
+    # ---- truncated transforms
+    def set_truncation(self, levels: int, min_log2n: int = 22):
+        """Evaluate products of at least 2^min_log2n points at n_c rounded up
+        to a multiple of 2^(m - levels) points (levels 0: all N)."""
+        self._check(lib().gf2x_set_truncation(self._h, levels, min_log2n), "gf2x_set_truncation")
+
+    def eval_points(self, na_bits: int, nb_bits: int) -> int:
+        return int(lib().gf2x_eval_points(self._h, na_bits, nb_bits))
+
     # ---- FFT pass schedules
     def set_schedule(self, m: int, bottom_log: int, col_rows_log: int):
         self._check(lib().gf2x_set_schedule(self._h, m, bottom_log, col_rows_log), "gf2x_set_schedule")
@@ -231,7 +243,7 @@ class Context:
                  for k, _ in TuneRec._fields_} for r in out]
 
     # ---- tracing
-    def trace_begin(self, kind_mask: int = 0x7F):
+    def trace_begin(self, kind_mask: int = 0xFF):
         self._check(lib().gf2x_trace_begin(self._h, kind_mask), "gf2x_trace_begin")
 
     def trace_end(self):

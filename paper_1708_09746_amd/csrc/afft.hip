@@ -132,6 +132,14 @@ __global__ __launch_bounds__(kThreads) void k_psi(PsiOp P, const uint4* g_psi) {
     for (uint64_t t = blockIdx.x; t < nt; t += gridDim.x) psi_tile(threadIdx.x, blockDim.x, t, P, tab);
 }
 
+__global__ __launch_bounds__(kThreads) void k_spine(SpineOp S, const uint8_t* g_mt, const uint4* g_phi) {
+    __shared__ __align__(16) uint8_t mt[65536];
+    copy_words(threadIdx.x, blockDim.x, (uint32_t*)mt, (const uint32_t*)g_mt, 16384);
+    __syncthreads();
+    const uint64_t nt = spine_tiles(S);
+    for (uint64_t t = blockIdx.x; t < nt; t += gridDim.x) spine_tile(threadIdx.x, blockDim.x, t, S, mt, g_phi);
+}
+
 // ------------------------------------------------------- multi-op kernels
 // One launch runs the tiles of an array of ops of one kind (a batch group).
 // Block b takes a contiguous chunk of the tiles, so consecutive tiles mostly
@@ -231,6 +239,20 @@ __global__ __launch_bounds__(kThreads) void k_pmul_multi(const PmulOp* ops, cons
     }
 }
 
+__global__ __launch_bounds__(kThreads) void k_spine_multi(const SpineOp* ops, const uint64_t* prefix, int nops,
+                                                          uint64_t total, const uint8_t* g_mt, const uint4* g_phi) {
+    __shared__ __align__(16) uint8_t mt[65536];
+    copy_words(threadIdx.x, blockDim.x, (uint32_t*)mt, (const uint32_t*)g_mt, 16384);
+    __syncthreads();
+    uint64_t g0, g1;
+    block_chunk(total, g0, g1);
+    int o = -1;
+    for (uint64_t g = g0; g < g1; ++g) {
+        o = op_of_tile(prefix, nops, g, o);
+        spine_tile(threadIdx.x, blockDim.x, g - prefix[o], ops[o], mt, g_phi);
+    }
+}
+
 __global__ __launch_bounds__(kThreads) void k_psi_multi(const PsiOp* ops, const uint64_t* prefix, int nops,
                                                         uint64_t total, const uint4* g_psi) {
     __shared__ uint4 tab[16 * 256];
@@ -264,6 +286,7 @@ struct DevOp {
         PmulOp pmul;
         PsiOp psi;
         BcClassOp bcc;
+        SpineOp spn;
     };
 };
 
@@ -369,6 +392,7 @@ __global__ __launch_bounds__(kThreads) void k_persistent(PersistArgs P, const ui
                     }
                     psi_tile(tid, nt, t, D.psi, work);
                     break;
+                case OpKind::Spine: spine_tile(tid, nt, t, D.spn, mt, g_phi); break;
             }
         }
         // grid barrier between ranks: release this block's writes, arrive,
@@ -418,7 +442,9 @@ struct gf2x_ctx {
     hipStream_t transient_stream = nullptr;
     LayerPool pool;  // BasisCvt layer lists; pool.base points at d_layers
     BcLayer* d_layers = nullptr;
-    PlanParams params;
+    PlanParams params;  // params.lam / params.mt point at the host tables below
+    uint32_t h_lam[32 * 32];
+    std::vector<uint8_t> h_mt;
     // tracing
     uint32_t trace_mask = 0;
     struct Pending {
@@ -574,7 +600,7 @@ void op_traffic(const Op& op, gf2x_trace_rec& r) {
             break;
         }
         case OpKind::Fft: {
-            uint64_t n = 1ull << (op.fft.log_m + op.fft.log_cosets);
+            uint64_t n = (uint64_t)op.fft.ncosets << op.fft.log_m;
             r.elements = n;
             r.bytes_read = op.fft.phi_in ? 8 * n : 16 * n;
             r.bytes_written = 16 * n;
@@ -594,6 +620,14 @@ void op_traffic(const Op& op, gf2x_trace_rec& r) {
             r.bytes_read = 16 * std::min(op.psi.nwords, op.psi.nspec);
             r.bytes_written = 8 * op.psi.nwords;
             break;
+        case OpKind::Spine: {
+            const uint64_t n = op.spn.n;
+            const uint32_t md = op.spn.mode;
+            r.elements = n;
+            r.bytes_read = md == kSpineZero ? 0 : md == kSpinePhi ? 8 * n : md == kSpineHalf || md == kSpineAdd ? 32 * n : 32 * n;
+            r.bytes_written = md == kSpineFwd || md == kSpineInv ? 32 * n : 16 * n;
+            break;
+        }
     }
 }
 
@@ -646,6 +680,10 @@ int run_ops(gf2x_ctx* ctx, const std::vector<Op>& ops, hipStream_t st) {
                 hipLaunchKernelGGL(k_psi, dim3(grid_for(psi_tiles(op.psi), 2 * ncu)), dim3(kThreads), 0, st, op.psi,
                                    (const uint4*)ctx->d_psi);
                 break;
+            case OpKind::Spine:
+                hipLaunchKernelGGL(k_spine, dim3(grid_for(spine_tiles(op.spn), 2 * ncu)), dim3(kThreads), 0, st, op.spn,
+                                   (const uint8_t*)ctx->d_mt, (const uint4*)ctx->d_phi);
+                break;
         }
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return hip_fail(ctx, e, "kernel launch");
@@ -695,6 +733,7 @@ void pack_groups(const std::vector<Op>& ops, const std::vector<BatchGroup>& grou
             case OpKind::Pmul: d.ops_off = gather(&Op::pmul); break;
             case OpKind::Psi: d.ops_off = gather(&Op::psi); break;
             case OpKind::BcClass: d.ops_off = gather(&Op::bcc); break;
+            case OpKind::Spine: d.ops_off = gather(&Op::spn); break;
         }
         d.prefix_off = put(prefix.data(), prefix.size() * sizeof(uint64_t));
         out.push_back(std::move(d));
@@ -750,6 +789,11 @@ int launch_groups(gf2x_ctx* ctx, const std::vector<LaunchGroup>& groups, const c
             case OpKind::Psi:
                 hipLaunchKernelGGL(k_psi_multi, dim3(grid_for(G.total, 2 * ncu)), dim3(kThreads), 0, st,
                                    (const PsiOp*)ops, prefix, G.nops, G.total, (const uint4*)ctx->d_psi);
+                break;
+            case OpKind::Spine:
+                hipLaunchKernelGGL(k_spine_multi, dim3(grid_for(G.total, 2 * ncu)), dim3(kThreads), 0, st,
+                                   (const SpineOp*)ops, prefix, G.nops, G.total, (const uint8_t*)ctx->d_mt,
+                                   (const uint4*)ctx->d_phi);
                 break;
         }
         hipError_t e = hipGetLastError();
@@ -808,6 +852,7 @@ void pack_persistent(const std::vector<Op>& ops, const std::vector<uint32_t>& ra
                 case OpKind::Pmul: d.pmul = op.pmul; break;
                 case OpKind::Psi: d.psi = op.psi; break;
                 case OpKind::BcClass: d.bcc = op.bcc; break;
+                case OpKind::Spine: d.spn = op.spn; break;
             }
             dops.push_back(d);
             prefix.push_back(prefix.back() + d.tiles);
@@ -1256,6 +1301,10 @@ int gf2x_ctx_create(gf2x_ctx** out, int device) {
         for (int b = 0; b < 256; ++b) mt[a * 256 + b] = T.mt8[a][b];
     uint32_t lam[32][32];
     build_lambda(T, lam);
+    memcpy(ctx->h_lam, lam, sizeof(lam));
+    ctx->h_mt = mt;
+    ctx->params.lam = ctx->h_lam;
+    ctx->params.mt = ctx->h_mt.data();
     ReprTables R = build_repr(T);
     if (!R.ok) {
         delete ctx;
@@ -1364,7 +1413,7 @@ int gf2x_forward_dev(gf2x_ctx* ctx, const uint64_t* a, uint64_t na_bits, int log
     int rc = ensure_ws(ctx, align256(8ull << m_a), st);
     if (rc) return rc;
     std::vector<Op> ops;
-    emit_forward(ops, ctx->pool, ctx->params, a, na_bits, (uint64_t*)ctx->ws, m_a, (uint4*)spec, log2n);
+    emit_forward(ops, ctx->pool, ctx->params, a, na_bits, (uint64_t*)ctx->ws, m_a, (uint4*)spec, log2n, 1ull << log2n);
     return run_ops(ctx, ops, st);
 }
 
@@ -1389,7 +1438,7 @@ int gf2x_inverse_dev(gf2x_ctx* ctx, void* spec, int log2n, uint64_t* c, uint64_t
         return fail(ctx, GF2X_EINVAL, "output overlaps the spectrum");
     DeviceGuard g(ctx->device);
     std::vector<Op> ops;
-    emit_inverse(ops, ctx->pool, ctx->params, (uint4*)spec, log2n, c, nc_bits);
+    emit_inverse(ops, ctx->pool, ctx->params, (uint4*)spec, log2n, 1ull << log2n, c, nc_bits);
     return run_ops(ctx, ops, (hipStream_t)stream);
 }
 
@@ -1759,6 +1808,22 @@ int gf2x_autotune(gf2x_ctx* ctx, int m_lo, int m_hi, int reps, gf2x_tune_rec* ou
         if (out) out[M - m_lo] = gf2x_tune_rec{M, best_b, best_r, copies, ncand, dflt, best};
     }
     return GF2X_OK;
+}
+
+int gf2x_set_truncation(gf2x_ctx* ctx, int levels, int min_log2n) {
+    if (check_ctx(ctx)) return GF2X_EINVAL;
+    if (levels < 0 || levels > 16) return fail(ctx, GF2X_EINVAL, "truncation levels outside 0..16");
+    if (min_log2n < 1 || min_log2n > 32) return fail(ctx, GF2X_EINVAL, "truncation size outside 1..32");
+    ctx->params.trunc_levels = levels;
+    ctx->params.trunc_min_log = min_log2n;
+    return GF2X_OK;
+}
+
+uint64_t gf2x_eval_points(gf2x_ctx* ctx, uint64_t na_bits, uint64_t nb_bits) {
+    if (!ctx) return 0;
+    const Sizes s = make_sizes(na_bits, nb_bits);
+    if (!s.out_words) return 0;
+    return eval_points(s, ctx->params);
 }
 
 }  // extern "C"

@@ -288,22 +288,26 @@ AFFT_HD void bc_class_tile(int tid, int nt, uint64_t tile, const BcClassOp& C, T
 // One pass runs layers [lo, hi) of an in-place LCH FFT (or its inverse) of
 // length 2^log_m.  Element index p = (outer << hi) | (row << lo) | col, with
 // row in [0, 2^(hi-lo)) and col in [0, 2^lo); a tile holds all rows of
-// 2^log_tc consecutive columns.  The forward FFT of an operand converted at
-// length 2^log_m evaluates at 2^log_cosets cosets S + V_log_m (S = c << log_m):
-// the top layers of the full transform are fan-outs, so each coset is an
-// independent FFT whose multipliers use the global block index S | s.
-// The block of layer i starting at global index s uses lambda = s_i(s̄) =
-// XOR of lam[i][t] over the set bits t of s.  Butterfly (Alg. 1):
+// 2^log_tc consecutive columns.  The pass covers the aligned blocks (cosets)
+// coset0 .. coset0 + ncosets - 1 of length 2^log_m of the whole transform:
+// the forward FFT of an operand converted at length 2^log_m evaluates at the
+// cosets S + V_log_m (S = c << log_m), because the top layers of the full
+// transform are fan-outs, and a sub-block of a truncated transform is one
+// such block.  Each block is an independent FFT whose multipliers use the
+// global block index S | s: the block of layer i starting at global index s
+// uses lambda = s_i(s̄) = XOR of lam[i][t] over the set bits t of s.
+// Butterfly (Alg. 1):
 //   forward: u += lambda v; v += u        inverse: v += u; u += lambda v.
 struct FftPass {
     const void* src;  // phi_in: 64-bit words (2^log_m of them); else == dst
-    uint4* dst;       // 2^(log_m + log_cosets) elements
+    uint4* dst;       // the whole transform; blocks are at (coset0 + c) << log_m
     uint32_t log_m, lo, hi, log_tc;
-    uint32_t log_cosets, inverse, phi_in, log_total;
+    uint32_t ncosets, coset0, inverse, phi_in;
+    uint32_t log_total, pad0, pad1, pad2;  // log_total: log2 of the whole transform's length
 };
 
 AFFT_HD uint64_t fft_tiles(const FftPass& A) {
-    return 1ull << (A.log_cosets + (A.log_m - A.hi) + (A.lo - A.log_tc));
+    return (uint64_t)A.ncosets << ((A.log_m - A.hi) + (A.lo - A.log_tc));
 }
 
 AFFT_HD int width_mode(int w) { return w <= 8 ? 0 : (w <= 16 ? 1 : 2); }
@@ -407,7 +411,7 @@ AFFT_HD FftTileGeom fft_geom(const FftPass& A, uint64_t tile) {
     const uint64_t coset = rest >> (A.log_m - A.hi);
     FftTileGeom G;
     G.base_p = (outer << A.hi) | (cb << A.log_tc);
-    G.gbase = coset << A.log_m;
+    G.gbase = ((uint64_t)A.coset0 + coset) << A.log_m;
     G.s_hi = G.gbase | (outer << A.hi);
     G.nel = 1u << (A.hi - A.lo + A.log_tc);
     return G;
@@ -482,21 +486,74 @@ AFFT_HD void fft_tile(int tid, int nt, uint64_t tile, const FftPass& A, const ui
     AFFT_SYNC();
 }
 
+// ------------------------------------------------------- truncated transforms
+// Element-wise steps of a truncated transform (evaluation at the first M
+// points only, and its inverse), all with one multiplier lambda per op:
+//   kSpineHalf:  x += lambda y            (half butterfly)
+//   kSpineAdd:   y += x
+//   kSpineFwd:   x += lambda y; y += x    (forward butterfly)
+//   kSpineInv:   y += x; x += lambda y    (inverse butterfly)
+//   kSpineZero:  x = 0
+//   kSpinePhi:   x = changeRepr(words)    (the coefficients of one coset)
+// over x[p], y[p] for p < n.
+enum : uint32_t { kSpineHalf = 0, kSpineAdd = 1, kSpineFwd = 2, kSpineInv = 3, kSpineZero = 4, kSpinePhi = 5 };
+constexpr int kSpineTile = 4096;
+
+struct SpineOp {
+    uint4* x;
+    uint4* y;
+    const uint64_t* words;  // kSpinePhi
+    uint64_t n;
+    uint4 mu;               // mu-set of lambda (make_mu_k)
+    uint32_t mode, width;   // width: width_mode of lambda
+    uint32_t pad0, pad1;
+};
+
+AFFT_HD uint64_t spine_tiles(const SpineOp& S) { return (S.n + kSpineTile - 1) / kSpineTile; }
+
+AFFT_HD void spine_tile(int tid, int nt, uint64_t tile, const SpineOp& S, const uint8_t* mt, const uint4* phi_tab) {
+    for (int e = tid; e < kSpineTile; e += nt) {
+        const uint64_t p = tile * kSpineTile + e;
+        if (p >= S.n) break;
+        switch (S.mode) {
+            case kSpineHalf: S.x[p] = xor4(S.x[p], mul_sub_k(mt, S.mu, S.y[p], (int)S.width)); break;
+            case kSpineAdd: S.y[p] = xor4(S.y[p], S.x[p]); break;
+            case kSpineFwd: {
+                const uint4 u = xor4(S.x[p], mul_sub_k(mt, S.mu, S.y[p], (int)S.width));
+                S.x[p] = u;
+                S.y[p] = xor4(S.y[p], u);
+                break;
+            }
+            case kSpineInv: {
+                const uint4 v = xor4(S.y[p], S.x[p]);
+                S.y[p] = v;
+                S.x[p] = xor4(S.x[p], mul_sub_k(mt, S.mu, v, (int)S.width));
+                break;
+            }
+            case kSpineZero: S.x[p] = make_uint4(0, 0, 0, 0); break;
+            default: S.x[p] = phi_word(phi_tab, S.words[p]); break;
+        }
+    }
+}
+
 // ------------------------------------------------------------- pointmul
+// c_j = a_j b_j for j < n; c_j = 0 for n <= j < n_out (the coefficients a
+// truncated inverse starts from).
 struct PmulOp {
     const uint4* a;
     const uint4* b;
     uint4* c;
     uint64_t n;
+    uint64_t n_out;
 };
 
-AFFT_HD uint64_t pmul_tiles(const PmulOp& P) { return (P.n + kPmulTile - 1) / kPmulTile; }
+AFFT_HD uint64_t pmul_tiles(const PmulOp& P) { return (P.n_out + kPmulTile - 1) / kPmulTile; }
 
 AFFT_HD void pmul_tile(int tid, int nt, uint64_t tile, const PmulOp& P, const uint8_t* mt) {
     for (int e = tid; e < kPmulTile; e += nt) {
         uint64_t j = tile * kPmulTile + e;
-        if (j >= P.n) break;
-        P.c[j] = gm128(mt, P.a[j], P.b[j]);
+        if (j >= P.n_out) break;
+        P.c[j] = j < P.n ? gm128(mt, P.a[j], P.b[j]) : make_uint4(0, 0, 0, 0);
     }
 }
 

@@ -8,7 +8,7 @@
 
 namespace gf2x {
 
-enum class OpKind : int { Pack, BcTile, BcLayer, Fft, Pmul, Psi, BcClass };
+enum class OpKind : int { Pack, BcTile, BcLayer, Fft, Pmul, Psi, BcClass, Spine };
 
 struct Op {
     OpKind kind;
@@ -20,6 +20,7 @@ struct Op {
     PmulOp pmul;
     PsiOp psi;
     BcClassOp bcc;
+    SpineOp spn;
 };
 
 inline int ceil_log2(uint64_t n) {
@@ -101,6 +102,21 @@ struct PlanParams {
     static constexpr int kMaxM = 32;
     int8_t fft_bottom_log[kMaxM + 1];
     int8_t fft_col_rows_log[kMaxM + 1];
+    // Truncated transforms: a product of n_c = n_a + n_b - 1 word coefficients
+    // is evaluated at M points, n_c rounded up to a multiple of
+    // 2^max(m - trunc_levels, kTruncMinLog) (M = N when trunc_levels = 0 or
+    // m < trunc_min_log).
+    // The spine steps need the multipliers on the host: the 32 x 32 table
+    // lam[i][t] = s_i(v_t) and the GF(256) product table (both owned by the
+    // caller; no truncation while either is null).
+    // Only transforms of at least 2^trunc_min_log points are truncated (each
+    // step of the recursion is a pass of its own, which smaller transforms
+    // do not repay).
+    static constexpr int kTruncMinLog = 6;
+    int trunc_levels = 3;
+    int trunc_min_log = 22;
+    const uint32_t* lam = nullptr;
+    const uint8_t* mt = nullptr;
     PlanParams() {
         for (int m = 0; m <= kMaxM; ++m) {
             fft_bottom_log[m] = 12;
@@ -232,47 +248,132 @@ inline uint32_t fft_log_tc(int lo, int hi) {
     return (uint32_t)std::min(lo, kFftTileLog - (hi - lo));
 }
 
-// Forward transform of one operand: `words` holds 2^M converted words; the
-// spectrum has 2^(M + log_cosets) elements.
-inline void emit_fft_forward(std::vector<Op>& ops, const PlanParams& pp, const uint64_t* words, uint4* spec, int M,
-                             int log_cosets) {
-    auto ranges = fft_pass_ranges(M, pp);
-    for (size_t r = ranges.size(); r-- > 0;) {
+// FFT passes over the aligned blocks coset0 .. coset0 + ncosets - 1 of
+// length 2^log_m of a transform of length 2^log_total at `spec`: forward
+// (top layers first; the first pass reads the 2^log_m converted words at
+// `words` and applies changeRepr, unless words is null) or inverse.
+inline void emit_fft_block(std::vector<Op>& ops, const PlanParams& pp, const uint64_t* words, uint4* spec, int log_m,
+                           uint32_t coset0, uint32_t ncosets, int log_total, bool inverse) {
+    auto ranges = fft_pass_ranges(log_m, pp);
+    const size_t nr = ranges.size();
+    for (size_t q = 0; q < nr; ++q) {
+        const size_t r = inverse ? q : nr - 1 - q;
+        const bool phi = !inverse && words && q == 0;  // a pass with no layers still converts the words
+        if (ranges[r].first == ranges[r].second && !phi) continue;
         Op op{};
         op.kind = OpKind::Fft;
         FftPass& A = op.fft;
-        A.phi_in = (r == ranges.size() - 1) ? 1u : 0u;
+        A.phi_in = phi ? 1u : 0u;
         A.src = A.phi_in ? (const void*)words : (const void*)spec;
         A.dst = spec;
-        A.log_m = (uint32_t)M;
+        A.log_m = (uint32_t)log_m;
         A.lo = (uint32_t)ranges[r].first;
         A.hi = (uint32_t)ranges[r].second;
         A.log_tc = fft_log_tc(ranges[r].first, ranges[r].second);
-        A.log_cosets = (uint32_t)log_cosets;
-        A.inverse = 0;
-        A.log_total = (uint32_t)(M + log_cosets);
+        A.ncosets = ncosets;
+        A.coset0 = coset0;
+        A.inverse = inverse ? 1u : 0u;
+        A.log_total = (uint32_t)log_total;
         ops.push_back(op);
     }
 }
 
+// Forward transform of one operand: `words` holds 2^M converted words; the
+// spectrum has 2^(M + log_cosets) elements (all cosets).
+inline void emit_fft_forward(std::vector<Op>& ops, const PlanParams& pp, const uint64_t* words, uint4* spec, int M,
+                             int log_cosets) {
+    emit_fft_block(ops, pp, words, spec, M, 0, 1u << log_cosets, M + log_cosets, false);
+}
+
 inline void emit_fft_inverse(std::vector<Op>& ops, const PlanParams& pp, uint4* spec, int m) {
-    auto ranges = fft_pass_ranges(m, pp);
-    for (size_t r = 0; r < ranges.size(); ++r) {
-        if (ranges[r].first == ranges[r].second) continue;
-        Op op{};
-        op.kind = OpKind::Fft;
-        FftPass& A = op.fft;
-        A.src = spec;
-        A.dst = spec;
-        A.log_m = (uint32_t)m;
-        A.lo = (uint32_t)ranges[r].first;
-        A.hi = (uint32_t)ranges[r].second;
-        A.log_tc = fft_log_tc(ranges[r].first, ranges[r].second);
-        A.log_cosets = 0;
-        A.inverse = 1;
-        A.phi_in = 0;
-        A.log_total = (uint32_t)m;
-        ops.push_back(op);
+    emit_fft_block(ops, pp, nullptr, spec, m, 0, 1, m, true);
+}
+
+// ----------------------------------------------------- truncated transforms
+// Points evaluated for a product of sizes s (see PlanParams).
+inline uint64_t eval_points(const Sizes& s, const PlanParams& pp) {
+    const uint64_t N = 1ull << s.m;
+    if (pp.trunc_levels <= 0 || s.m < pp.trunc_min_log || !pp.lam || !pp.mt) return N;
+    const int g = std::max(s.m - pp.trunc_levels, PlanParams::kTruncMinLog);
+    if (g >= s.m) return N;
+    const uint64_t nc = s.n_a + s.n_b - 1;
+    return ((nc + (1ull << g) - 1) >> g) << g;
+}
+
+// lambda of layer i for the block starting at global index s (a multiple of 2^(i+1))
+inline uint32_t host_lambda(const PlanParams& pp, int i, uint64_t s) {
+    uint32_t l = 0;
+    for (uint64_t b = s >> (i + 1); b; b &= b - 1) l ^= pp.lam[i * 32 + i + 1 + __builtin_ctzll(b)];
+    return l;
+}
+
+inline void emit_spine(std::vector<Op>& ops, const PlanParams& pp, uint32_t mode, uint4* x, uint4* y, uint64_t n,
+                       uint32_t lambda, const uint64_t* words = nullptr) {
+    Op op{};
+    op.kind = OpKind::Spine;
+    SpineOp& S = op.spn;
+    S.x = x;
+    S.y = y;
+    S.words = words;
+    S.n = n;
+    S.mode = mode;
+    S.mu = make_mu_k(pp.mt, lambda);
+    const int w = lambda ? 32 - __builtin_clz(lambda) : 0;
+    S.width = (uint32_t)width_mode(w);
+    ops.push_back(op);
+}
+
+// Values at the first Mb points of the block of 2^n points at global index s
+// of a transform of length 2^log_total whose coefficients are in place
+// (Alg. 1 truncated): at each level only the half-blocks holding needed
+// points are transformed further; a half whose points are all beyond Mb only
+// needs the u side of its butterfly.
+inline void emit_fwd_spine(std::vector<Op>& ops, const PlanParams& pp, uint4* spec, uint64_t s, int n, uint64_t Mb,
+                           int log_total) {
+    if (Mb == (1ull << n)) {
+        emit_fft_block(ops, pp, nullptr, spec, n, (uint32_t)(s >> n), 1, log_total, false);
+        return;
+    }
+    const uint64_t h = 1ull << (n - 1);
+    const uint32_t lam = host_lambda(pp, n - 1, s);
+    if (Mb > h) {
+        emit_spine(ops, pp, kSpineFwd, spec + s, spec + s + h, h, lam);
+        emit_fwd_spine(ops, pp, spec, s, n - 1, h, log_total);
+        emit_fwd_spine(ops, pp, spec, s + h, n - 1, Mb - h, log_total);
+    } else {
+        if (lam) emit_spine(ops, pp, kSpineHalf, spec + s, spec + s + h, h, lam);
+        emit_fwd_spine(ops, pp, spec, s, n - 1, Mb, log_total);
+    }
+}
+
+// Coefficients of the block of 2^n points at global index s from its values
+// at the first mk points and its coefficients at the other positions, all in
+// place (the inverse of the truncated Alg. 1).  Write the block's
+// coefficients as halves (U, V), transformed by the top butterfly into
+// U' = U + lambda V (first half) and V' = U' + V (second half).
+//   mk <= h: U' is known beyond mk (U and V are), the first half is the same
+//     problem one level down; then U = U' + lambda V.
+//   mk > h: the first half is a full inverse transform (U'); V' = U' + V is
+//     known beyond mk - h, the second half is the same problem one level down;
+//     then the inverse butterfly V = V' + U', U = U' + lambda V.
+inline void emit_inv_spine(std::vector<Op>& ops, const PlanParams& pp, uint4* spec, uint64_t s, int n, uint64_t mk,
+                           int log_total) {
+    if (mk == 0) return;
+    if (mk == (1ull << n)) {
+        emit_fft_block(ops, pp, nullptr, spec, n, (uint32_t)(s >> n), 1, log_total, true);
+        return;
+    }
+    const uint64_t h = 1ull << (n - 1);
+    const uint32_t lam = host_lambda(pp, n - 1, s);
+    if (mk <= h) {
+        if (lam && mk < h) emit_spine(ops, pp, kSpineHalf, spec + s + mk, spec + s + h + mk, h - mk, lam);
+        emit_inv_spine(ops, pp, spec, s, n - 1, mk, log_total);
+        if (lam) emit_spine(ops, pp, kSpineHalf, spec + s, spec + s + h, h, lam);
+    } else {
+        emit_fft_block(ops, pp, nullptr, spec, n - 1, (uint32_t)(s >> (n - 1)), 1, log_total, true);
+        if (mk < 2 * h) emit_spine(ops, pp, kSpineAdd, spec + s + mk - h, spec + s + mk, 2 * h - mk, 0);
+        emit_inv_spine(ops, pp, spec, s + h, n - 1, mk - h, log_total);
+        emit_spine(ops, pp, kSpineInv, spec + s, spec + s + h, h, lam);
     }
 }
 
@@ -283,10 +384,11 @@ inline void emit_pack(std::vector<Op>& ops, const uint64_t* src, uint64_t nbits,
     ops.push_back(op);
 }
 
-inline void emit_pmul(std::vector<Op>& ops, const uint4* a, const uint4* b, uint4* c, uint64_t n) {
+inline void emit_pmul(std::vector<Op>& ops, const uint4* a, const uint4* b, uint4* c, uint64_t n,
+                      uint64_t n_out = 0) {
     Op op{};
     op.kind = OpKind::Pmul;
-    op.pmul = PmulOp{a, b, c, n};
+    op.pmul = PmulOp{a, b, c, n, n_out > n ? n_out : n};
     ops.push_back(op);
 }
 
@@ -321,18 +423,35 @@ inline Workspace workspace_for(const Sizes& s) {
 
 // Forward transform of one operand into an N-point spectrum (Split, BasisCvt
 // on 64-bit words, changeRepr, FFT_LCH at 0).  `words` is scratch of 2^m_op words.
+// Values at the first M of N = 2^m points: the cosets of length 2^m_op
+// entirely below M are full transforms, the one holding M is truncated.
 inline void emit_forward(std::vector<Op>& ops, const LayerPool& pool, const PlanParams& pp, const uint64_t* src,
-                         uint64_t nbits, uint64_t* words, int m_op, uint4* spec, int m) {
+                         uint64_t nbits, uint64_t* words, int m_op, uint4* spec, int m, uint64_t M) {
     emit_pack(ops, src, nbits, words, 1ull << m_op);
     emit_bc(ops, pool, words, 0, m_op, 0);
-    emit_fft_forward(ops, pp, words, spec, m_op, m - m_op);
+    if (M == (1ull << m)) {
+        emit_fft_forward(ops, pp, words, spec, m_op, m - m_op);
+        return;
+    }
+    const uint64_t full = M >> m_op, rem = M - (full << m_op);
+    if (full) emit_fft_block(ops, pp, words, spec, m_op, 0, (uint32_t)full, m, false);
+    if (rem) {
+        const uint64_t s0 = full << m_op;
+        emit_spine(ops, pp, kSpinePhi, spec + s0, nullptr, 1ull << m_op, 0, words);
+        emit_fwd_spine(ops, pp, spec, s0, m_op, rem, m);
+    }
 }
 
-// Inverse transform of an N-point spectrum into nc_bits product bits
-// (iFFT_LCH, iBasisCvt, changeRepr back, InterleavedCombine).
+// Inverse transform of the values at the first M of N = 2^m points into
+// nc_bits product bits (iFFT_LCH, iBasisCvt, changeRepr back,
+// InterleavedCombine); positions M and beyond hold the (zero) coefficients
+// there.
 inline void emit_inverse(std::vector<Op>& ops, const LayerPool& pool, const PlanParams& pp, uint4* spec, int m,
-                         uint64_t* out, uint64_t nc_bits) {
-    emit_fft_inverse(ops, pp, spec, m);
+                         uint64_t M, uint64_t* out, uint64_t nc_bits) {
+    if (M == (1ull << m))
+        emit_fft_inverse(ops, pp, spec, m);
+    else
+        emit_inv_spine(ops, pp, spec, 0, m, M, m);  // pointmul wrote zeros at M and beyond
     emit_bc(ops, pool, spec, 1, m, 1);
     emit_psi(ops, spec, 1ull << m, out, nc_bits);
 }
@@ -347,15 +466,16 @@ inline void plan_mul(std::vector<Op>& ops, const LayerPool& pool, const PlanPara
     uint4* sb = (uint4*)(ws + w.off_sb);
     // the two forward transforms are independent and share levels
     const size_t a0 = ops.size();
-    emit_forward(ops, pool, pp, a, s.na_bits, wa, s.m_a, sa, s.m);
+    const uint64_t M = eval_points(s, pp);
+    emit_forward(ops, pool, pp, a, s.na_bits, wa, s.m_a, sa, s.m, M);
     const size_t b0 = ops.size();
-    emit_forward(ops, pool, pp, b, s.nb_bits, wb, s.m_b, sb, s.m);
+    emit_forward(ops, pool, pp, b, s.nb_bits, wb, s.m_b, sb, s.m, M);
     const size_t p0 = ops.size();
     for (size_t i = a0; i < b0; ++i) ops[i].level = (uint32_t)(i - a0);
     for (size_t i = b0; i < p0; ++i) ops[i].level = (uint32_t)(i - b0);
     const uint32_t lp = (uint32_t)std::max(b0 - a0, p0 - b0);
-    emit_pmul(ops, sa, sb, sb, 1ull << s.m);
-    emit_inverse(ops, pool, pp, sb, s.m, c, s.nc_bits);
+    emit_pmul(ops, sa, sb, sb, M, 1ull << s.m);
+    emit_inverse(ops, pool, pp, sb, s.m, M, c, s.nc_bits);
     for (size_t i = p0; i < ops.size(); ++i) ops[i].level = lp + (uint32_t)(i - p0);
 }
 
@@ -420,6 +540,7 @@ inline uint64_t op_tiles(const Op& op) {
         case OpKind::Pmul: return pmul_tiles(op.pmul);
         case OpKind::Psi: return psi_tiles(op.psi);
         case OpKind::BcClass: return bc_class_tiles(op.bcc);
+        case OpKind::Spine: return spine_tiles(op.spn);
     }
     return 0;
 }

@@ -1,0 +1,119 @@
+"""Truncated transforms on the GPU: products evaluated at M < N points (the
+forward butterflies restricted to the needed points, the inverse run on the
+values below M and the zero coefficients above it) equal the oracle's, for
+several truncation depths, on sizes that take every branch of the
+recursion; batches and the stage entry points are unaffected."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_1708_09746_amd as P
+from helpers import dev, host
+from paper_1708_09746_amd import inputs
+
+torch = pytest.importorskip("torch")
+pytestmark = [pytest.mark.gpu,
+              pytest.mark.skipif(not torch.cuda.is_available(), reason="needs a GPU")]
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = P.Context(0)
+    yield c
+    torch.cuda.synchronize()
+    c.close()
+
+
+def words(bits):
+    return (bits + 63) // 64
+
+
+# (na, nb): n_c just above a power of two, 3/4 and 5/8 of the next one,
+# unbalanced pairs where one operand's coset is cut, one-word operands, and
+# sizes where the cut falls inside a tile and between tiles
+SIZES = [
+    (64 * 1025, 64 * 1024),          # n_c = 2048 = N: no truncation
+    (64 * 1025, 64 * 1025),          # n_c = 2049 -> N = 4096
+    (64 * 1536, 64 * 1536 + 7),      # 3/4
+    (64 * 1280, 64 * 1280),          # 5/8
+    (64 * 3000 + 5, 64 * 10),        # one long operand, coset cut
+    (64 * 2049, 1),                  # one-word operand
+    (64 * 40000 + 3, 64 * 30000),    # N = 2^17, several levels
+    (64 * 300 + 1, 64 * 250 + 2),    # small N
+    (1 << 20, (1 << 19) + 64),       # 2^14 + 2^13 + 1 words
+]
+
+
+@pytest.mark.parametrize("levels", [0, 1, 3, 8])
+def test_truncated_products(ctx, levels):
+    ctx.set_truncation(levels, 1)
+    try:
+        for na, nb in SIZES:
+            a = inputs.random_poly(0x7A0 + na % 101, na)
+            b = inputs.random_poly(0x7A1 + nb % 103, nb)
+            nc = words(na) + words(nb) - 1
+            N = 1 << max(1, (nc - 1).bit_length())
+            M = ctx.eval_points(na, nb)
+            g = max((N.bit_length() - 1) - levels, 6)
+            assert nc <= M <= N
+            if levels == 0 or g >= N.bit_length() - 1:
+                assert M == N
+            else:
+                assert M % (1 << g) == 0 and M - nc < (1 << g)
+            say(f"case truncation {levels}: {na} x {nb} bits, N {N}, M {M}")
+            got = host(ctx.mul(dev(a), na, dev(b), nb))
+            assert np.array_equal(got, oracle.mul(a, na, b, nb)), (levels, na, nb, M, N)
+    finally:
+        ctx.set_truncation(3, 22)
+
+
+def test_truncated_batch_matches_single_calls(ctx):
+    ctx.set_truncation(3, 1)
+    spec = inputs.batch_workload(64, 10, 18)
+    jobs, refs = [], []
+    for na, nb, sa, sb in spec:
+        a, b = inputs.random_poly(sa, na), inputs.random_poly(sb, nb)
+        jobs.append((dev(a), na, dev(b), nb, torch.zeros(P.out_words(na, nb), dtype=torch.int64, device="cuda")))
+        refs.append(oracle.mul(a, na, b, nb))
+    assert any(ctx.eval_points(na, nb) < (1 << P.fft_log2(na, nb)) for na, nb, _, _ in spec)
+    for persistent in (False, True):
+        for j in jobs:
+            j[4].zero_()
+        say(f"case truncated batch, persistent={persistent}")
+        B = ctx.batch(jobs, persistent=persistent)
+        B.run()
+        torch.cuda.synchronize()
+        B.check()
+        B.close()
+        for (da, na, db, nb, c), ref in zip(jobs, refs):
+            assert np.array_equal(host(c), ref), (persistent, na, nb)
+    ctx.set_truncation(3, 22)
+
+
+def test_truncation_range_and_stage_calls(ctx):
+    with pytest.raises(P.Gf2xError):
+        ctx.set_truncation(-1)
+    with pytest.raises(P.Gf2xError):
+        ctx.set_truncation(17)
+    with pytest.raises(P.Gf2xError):
+        ctx.set_truncation(3, 0)
+    assert ctx.eval_points(0, 100) == 0
+    # by default only transforms of 2^22 points and more are truncated
+    assert ctx.eval_points(64 * 1280, 64 * 1280) == 4096
+    assert ctx.eval_points(64 * 5 * 2**19, 64 * 5 * 2**19) == 5 * 2**20
+    # the stage entry points always transform all 2^log2n points
+    na = 64 * 1500
+    a = inputs.random_poly(0x7A9, na)
+    ctx.set_truncation(3, 1)
+    full = host(ctx.forward(dev(a), na, 12))
+    ctx.set_truncation(0)
+    again = host(ctx.forward(dev(a), na, 12))
+    ctx.set_truncation(3, 22)
+    assert np.array_equal(full, again)
