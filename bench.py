@@ -430,6 +430,16 @@ def main():
         "alg_bytes_per_launch": int(tot_bytes / nl),
         "utilisation": counter_utilisation(dominant),
     }
+    # the unit that bounds the FFT passes: random byte lookups into LDS tables
+    lk = sum(r["lookups"] for r in recs)
+    if lk and tot_ms > 0:
+        peak_lk = ctx.lookup_rate()
+        ach_lk = lk / (tot_ms * 1e-3)
+        roofline["lds_lookups"] = {"achieved": round(ach_lk / 1e12, 3), "peak": round(peak_lk / 1e12, 3),
+                                   "unit": "T lookups/s", "frac": round(ach_lk / peak_lk, 4),
+                                   "per_launch": int(lk / nl),
+                                   "peak_source": "gf2x_lookup_rate: random byte lookups into a 64 KiB LDS "
+                                                  "table on every CU, measured in this run"}
 
     # bit-exactness spot check of the timed product (two words from the oracle)
     import oracle

@@ -144,8 +144,14 @@ typedef struct {
     uint64_t elements;   /* elements (words or 16-byte field elements) the launch covers */
     uint64_t bytes_read; /* bytes the launch must read from memory (algorithmic) */
     uint64_t bytes_written;
+    uint64_t lookups;    /* GF(256) product-table lookups of its subfield products (FFT passes; else 0) */
     float ms;            /* hipEventElapsedTime between the two events */
 } gf2x_trace_rec;
+
+/* Calibration: the rate of random byte lookups into a 64 KiB LDS table over
+ * the whole device (one kernel, every CU busy, every address in bounds), the
+ * unit that bounds the FFT passes.  Blocking. */
+int gf2x_lookup_rate(gf2x_ctx *ctx, double *lookups_per_s);
 
 /* Start recording launches of the kinds in `kind_mask` (0 stops; records kept). */
 int gf2x_trace_begin(gf2x_ctx *ctx, uint32_t kind_mask);

@@ -32,7 +32,7 @@ class Gf2xError(RuntimeError):
 
 class TraceRec(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int), ("elements", ctypes.c_uint64), ("bytes_read", ctypes.c_uint64),
-                ("bytes_written", ctypes.c_uint64), ("ms", ctypes.c_float)]
+                ("bytes_written", ctypes.c_uint64), ("lookups", ctypes.c_uint64), ("ms", ctypes.c_float)]
 
 
 KIND_NAMES = ["pack", "basiscvt_tile", "basiscvt_layer", "fft_pass", "pointmul", "psi_combine", "basiscvt_class",
@@ -103,6 +103,7 @@ def lib():
             "gf2x_autotune": (i32, [vp, i32, i32, i32, ctypes.POINTER(TuneRec)]),
             "gf2x_set_truncation": (i32, [vp, i32, i32]),
             "gf2x_eval_points": (u64, [vp, u64, u64]),
+            "gf2x_lookup_rate": (i32, [vp, ctypes.POINTER(ctypes.c_double)]),
             "gf2x_now_ns": (u64, []),
             "gf2x_server_create": (i32, [vp, ctypes.POINTER(ServerCfg), ctypes.POINTER(vp)]),
             "gf2x_server_submit": (i32, [vp, vp, u64, vp, u64, vp, u64]),
@@ -217,6 +218,12 @@ class Context:
         """A continuous-batching request loop (Server) on this context."""
         return Server(self, arena_bytes, max_active, levels_per_iter, inflight, persistent)
 
+    def lookup_rate(self) -> float:
+        """Measured rate of random byte lookups into an LDS table (per second, whole device)."""
+        v = ctypes.c_double()
+        self._check(lib().gf2x_lookup_rate(self._h, ctypes.byref(v)), "gf2x_lookup_rate")
+        return v.value
+
     # ---- truncated transforms
     def set_truncation(self, levels: int, min_log2n: int = 22):
         """Evaluate products of at least 2^min_log2n points at n_c rounded up
@@ -260,7 +267,7 @@ class Context:
         if got < 0:
             self._check(int(got), "gf2x_trace_read")
         return [dict(kind=KIND_NAMES[r.kind], kernel=KERNEL_OF_KIND[r.kind], elements=r.elements,
-                     bytes_read=r.bytes_read, bytes_written=r.bytes_written, ms=r.ms)
+                     bytes_read=r.bytes_read, bytes_written=r.bytes_written, lookups=r.lookups, ms=r.ms)
                 for r in buf[:min(got, n)]]
 
     # ---- stages

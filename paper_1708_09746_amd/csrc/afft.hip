@@ -132,6 +132,27 @@ __global__ __launch_bounds__(kThreads) void k_psi(PsiOp P, const uint4* g_psi) {
     for (uint64_t t = blockIdx.x; t < nt; t += gridDim.x) psi_tile(threadIdx.x, blockDim.x, t, P, tab);
 }
 
+// Random byte lookups into a 64 KiB LDS table: 8 independent address streams
+// per thread (a linear congruential sequence each), every address masked to
+// the table.
+constexpr int kLookupIters = 2000;
+__global__ __launch_bounds__(kThreads) void k_lookup_rate(const uint8_t* g_mt, uint32_t* out) {
+    __shared__ __align__(16) uint8_t mt[65536];
+    copy_words(threadIdx.x, blockDim.x, (uint32_t*)mt, (const uint32_t*)g_mt, 16384);
+    __syncthreads();
+    const uint32_t id = blockIdx.x * blockDim.x + threadIdx.x;
+    uint32_t st[8], acc = 0;
+    for (int j = 0; j < 8; ++j) st[j] = id * 2654435761u + 40503u * (uint32_t)j + 1u;
+    for (int it = 0; it < kLookupIters; ++it) {
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            st[j] = st[j] * 1664525u + 1013904223u;
+            acc += mt[st[j] >> 16];
+        }
+    }
+    out[id] = acc;
+}
+
 __global__ __launch_bounds__(kThreads) void k_spine(SpineOp S, const uint8_t* g_mt, const uint4* g_phi) {
     __shared__ __align__(16) uint8_t mt[65536];
     copy_words(threadIdx.x, blockDim.x, (uint32_t*)mt, (const uint32_t*)g_mt, 16384);
@@ -580,6 +601,7 @@ unsigned grid_for(uint64_t tiles, uint64_t cap) {
 // covers is read once and written once), and the elements it covers.
 void op_traffic(const Op& op, gf2x_trace_rec& r) {
     r.kind = (int)op.kind;
+    r.lookups = 0;
     switch (op.kind) {
         case OpKind::Pack:
             r.elements = op.pack.ndst;
@@ -604,6 +626,10 @@ void op_traffic(const Op& op, gf2x_trace_rec& r) {
             r.elements = n;
             r.bytes_read = op.fft.phi_in ? 8 * n : 16 * n;
             r.bytes_written = 16 * n;
+            // per butterfly: 4 words, 4 / 6 / 9 lookups per word for 8/16/32-bit multipliers
+            static const uint64_t per_word[3] = {4, 6, 9};
+            for (uint32_t i = op.fft.lo; i < op.fft.hi; ++i)
+                r.lookups += (n / 2) * 4 * per_word[width_mode((int)op.fft.log_total - (int)i)];
             break;
         }
         case OpKind::Pmul:
@@ -1824,6 +1850,36 @@ uint64_t gf2x_eval_points(gf2x_ctx* ctx, uint64_t na_bits, uint64_t nb_bits) {
     const Sizes s = make_sizes(na_bits, nb_bits);
     if (!s.out_words) return 0;
     return eval_points(s, ctx->params);
+}
+
+int gf2x_lookup_rate(gf2x_ctx* ctx, double* lookups_per_s) {
+    if (check_ctx(ctx) || !lookups_per_s) return GF2X_EINVAL;
+    ctx->err.clear();
+    DeviceGuard g(ctx->device);
+    const unsigned blocks = 2u * (unsigned)std::max(1, ctx->ncu);
+    uint32_t* out = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipError_t e = hipMalloc((void**)&out, (size_t)blocks * kThreads * sizeof(uint32_t));
+    if (e == hipSuccess) e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    float ms = 0;
+    hipStream_t st = ctx->own_stream;
+    for (int rep = 0; rep < 2 && e == hipSuccess; ++rep) {  // the first run warms up
+        e = hipEventRecord(e0, st);
+        if (e == hipSuccess) {
+            hipLaunchKernelGGL(k_lookup_rate, dim3(blocks), dim3(kThreads), 0, st, (const uint8_t*)ctx->d_mt, out);
+            e = hipGetLastError();
+        }
+        if (e == hipSuccess) e = hipEventRecord(e1, st);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+    }
+    if (out) (void)hipFree(out);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (e != hipSuccess) return hip_fail(ctx, e, "lookup rate");
+    *lookups_per_s = (double)blocks * kThreads * kLookupIters * 8 / (ms * 1e-3);
+    return GF2X_OK;
 }
 
 }  // extern "C"
