@@ -144,7 +144,7 @@ typedef struct {
     uint64_t elements;   /* elements (words or 16-byte field elements) the launch covers */
     uint64_t bytes_read; /* bytes the launch must read from memory (algorithmic) */
     uint64_t bytes_written;
-    uint64_t lookups;    /* GF(256) product-table lookups of its subfield products (FFT passes; else 0) */
+    uint64_t lookups;    /* LDS table reads of its subfield products (FFT passes; else 0) */
     float ms;            /* hipEventElapsedTime between the two events */
 } gf2x_trace_rec;
 

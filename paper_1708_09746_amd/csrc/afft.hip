@@ -66,7 +66,8 @@ __global__ __launch_bounds__(kThreads) void k_bc_layer(BcLayerOp L) {
 constexpr int kFftPrefetch = (1 << kFftTileLog) / kThreads;
 static_assert(kFftPrefetch * kThreads == (1 << kFftTileLog), "every tile element has a prefetch slot");
 static_assert(((1 << kFftTileLog) >> kFftRL) <= kThreads, "one group of kFftRL layers per thread");
-static_assert(16 * ((1 << kFftTileLog) + kMuEntries) + 65536 + 4096 + 16 * 32 + 64 <= 163840, "FFT kernels fit in LDS");
+static_assert(16 * ((1 << kFftTileLog) + kMuEntries) + 65536 + 4096 + 16 * 32 + 8 * 768 + 64 <= 163840,
+              "FFT kernels fit in LDS");
 
 __global__ __launch_bounds__(kThreads) void k_fft(FftPass A, const uint8_t* g_mt, const uint32_t* g_lam,
                                                   const uint4* g_phi) {
@@ -75,10 +76,12 @@ __global__ __launch_bounds__(kThreads) void k_fft(FftPass A, const uint8_t* g_mt
     __shared__ uint4 tl[1 << kFftTileLog];
     __shared__ uint4 mu[kMuEntries];
     __shared__ uint4 mu_tile[32];
+    __shared__ uint2 mt3[768];
     const int tid = threadIdx.x, nt = blockDim.x;
     copy_words(tid, nt, (uint32_t*)mt, (const uint32_t*)g_mt, 16384);
     copy_words(tid, nt, lam, g_lam, 1024);
     __syncthreads();
+    build_mt3(tid, nt, mt, mt3);
     fft_local_mu(tid, nt, A, mt, lam, mu);
     const uint64_t ntiles = fft_tiles(A);
     uint64_t t = blockIdx.x;
@@ -107,7 +110,7 @@ __global__ __launch_bounds__(kThreads) void k_fft(FftPass A, const uint8_t* g_mt
                 if (e < Gn.nel) pre[j] = fft_load(A, g_phi, Gn, e);
             }
         }
-        fft_tile_layers<kFftRL>(tid, nt, A, G, mt, lam, tl, mu, mu_tile);
+        fft_tile_layers<kFftRL>(tid, nt, A, G, mt, mt3, lam, tl, mu, mu_tile);
         for (uint32_t e = tid; e < G.nel; e += nt) A.dst[G.gbase | fft_elem_index(A, G, e)] = tl[e];
         if (tn >= ntiles) break;
         __syncthreads();
@@ -225,9 +228,12 @@ __global__ __launch_bounds__(kThreads) void k_fft_multi(const FftPass* ops, cons
     __shared__ uint4 tl[1 << kFftTileLog];
     __shared__ uint4 mu[kMuEntries];
     __shared__ uint4 mu_tile[32];
+    __shared__ uint2 mt3[768];
     const int tid = threadIdx.x, nt = blockDim.x;
     copy_words(tid, nt, (uint32_t*)mt, (const uint32_t*)g_mt, 16384);
     copy_words(tid, nt, lam, g_lam, 1024);
+    __syncthreads();
+    build_mt3(tid, nt, mt, mt3);
     __syncthreads();
     uint64_t g0, g1;
     block_chunk(total, g0, g1);
@@ -242,7 +248,7 @@ __global__ __launch_bounds__(kThreads) void k_fft_multi(const FftPass* ops, cons
             cur_lo = A.lo;
             cur_hi = A.hi;
         }
-        fft_tile<kFftRL>(tid, nt, g - prefix[o], A, mt, lam, g_phi, tl, mu, mu_tile);
+        fft_tile<kFftRL>(tid, nt, g - prefix[o], A, mt, mt3, lam, g_phi, tl, mu, mu_tile);
     }
 }
 
@@ -341,11 +347,14 @@ __global__ __launch_bounds__(kThreads) void k_persistent(PersistArgs P, const ui
     __shared__ uint32_t lam[1024];
     __shared__ uint4 work[(1 << kFftTileLog) + kMuEntries];  // FFT tile + mu-set tables, a BasisCvt tile, or the Psi table
     __shared__ uint4 mu_tile[32];
+    __shared__ uint2 mt3[768];
     __shared__ uint64_t s_item;
     __shared__ int s_stop;
     const int tid = threadIdx.x, nt = blockDim.x;
     copy_words(tid, nt, (uint32_t*)mt, (const uint32_t*)g_mt, 16384);
     copy_words(tid, nt, lam, g_lam, 1024);
+    __syncthreads();
+    build_mt3(tid, nt, mt, mt3);  // visible after the item loop's first barrier
     uint4* tl = work;
     uint4* mu = work + (1 << kFftTileLog);
     // what `work` holds: 0 nothing reusable, 1 FFT local mu-sets of (cur_lo, cur_hi), 2 the Psi table
@@ -401,7 +410,7 @@ __global__ __launch_bounds__(kThreads) void k_persistent(PersistArgs P, const ui
                         cur_lo = A.lo;
                         cur_hi = A.hi;
                     }
-                    fft_tile<kFftRL>(tid, nt, t, A, mt, lam, g_phi, tl, mu, mu_tile);
+                    fft_tile<kFftRL>(tid, nt, t, A, mt, mt3, lam, g_phi, tl, mu, mu_tile);
                     break;
                 }
                 case OpKind::Pmul: pmul_tile(tid, nt, t, D.pmul, mt); break;
@@ -626,10 +635,12 @@ void op_traffic(const Op& op, gf2x_trace_rec& r) {
             r.elements = n;
             r.bytes_read = op.fft.phi_in ? 8 * n : 16 * n;
             r.bytes_written = 16 * n;
-            // per butterfly: 4 words, 4 / 6 / 9 lookups per word for 8/16/32-bit multipliers
-            static const uint64_t per_word[3] = {4, 6, 9};
+            // LDS table reads per butterfly: 6 or 9 byte lookups per word (4 words) for
+            // 16/32-bit multipliers; 3 table reads for 8-bit ones (their bytes are
+            // looked up in registers)
+            static const uint64_t per_bfly[3] = {3, 24, 36};
             for (uint32_t i = op.fft.lo; i < op.fft.hi; ++i)
-                r.lookups += (n / 2) * 4 * per_word[width_mode((int)op.fft.log_total - (int)i)];
+                r.lookups += (n / 2) * per_bfly[width_mode((int)op.fft.log_total - (int)i)];
             break;
         }
         case OpKind::Pmul:

@@ -12,13 +12,18 @@ namespace gf2x {
 constexpr int kThreads = 1024;    // threads per block in every kernel
 constexpr int kFftTileLog = 12;   // FFT tile: up to 2^12 elements (64 KiB)
 constexpr int kFftRL = 2;         // FFT layers per LDS round trip (4 elements per thread)
-// Local mu-set tables of an FFT pass (see fft_local_mu): per local layer a
-// table over the low 6 block bits and one over the high block bits (at most
-// kFftTileLog - 7 of them), the latter kept twice (pass part, pass + tile part).
-constexpr int kMuLo = 64, kMuHi = 32;
-constexpr int kMuHiBase = kFftTileLog * kMuLo;
-constexpr int kMuHiCur = kMuHiBase + kFftTileLog * kMuHi;
-constexpr int kMuEntries = kMuHiCur + kFftTileLog * kMuHi;
+// Local mu-set tables of an FFT pass (see fft_local_mu): local layer li has
+// nb <= kFftTileLog - 1 - li block bits, a table over the low min(nb, 6) of
+// them (mu_lo_off) and one over the rest (mu_hi_off), the latter kept twice
+// (pass part, pass + tile part); tables packed back to back, sized for 4096-
+// point tiles.
+static_assert(kFftTileLog == 12, "mu-set table offsets are written for 4096-point tiles");
+AFFT_HD int mu_lo_off(int li) { return li <= 5 ? 64 * li : 448 - (1 << (12 - li)); }
+AFFT_HD int mu_hi_off(int li) { return li <= 5 ? 64 - (64 >> li) : 57 + li; }
+constexpr int kMuLoN = 447, kMuHiN = 69;
+constexpr int kMuHiBase = kMuLoN;
+constexpr int kMuHiCur = kMuHiBase + kMuHiN;
+constexpr int kMuEntries = kMuHiCur + kMuHiN;
 constexpr int kBcTileLog64 = 13;  // BasisCvt tile on 64-bit words: 64 KiB
 constexpr int kBcTileLog128 = 12; // BasisCvt tile on 128-bit elements: 64 KiB
 constexpr int kPmulTile = 1024;
@@ -320,16 +325,50 @@ AFFT_HD uint4 phi_word(const uint4* phi_tab, uint64_t w) {
     return r;
 }
 
+// Products by an 8-bit multiplier without table lookups per byte: for each
+// lambda in GF(256) three small tables of lambda times the 3-bit groups of a
+// byte, T0[y] = lambda y, T1[y] = lambda (y << 3) (y < 8), T2[y] = lambda (y << 6)
+// (y < 4), so lambda e = T0[e & 7] + T1[(e >> 3) & 7] + T2[e >> 6]; one
+// v_perm_b32 looks up a group of all four bytes of a word at once.  mt3 holds
+// the three tables of every lambda (3 uint2 per lambda, 6 KiB).
+AFFT_HD void build_mt3(int tid, int nt, const uint8_t* mt, uint2* mt3) {
+    for (int l = tid; l < 256; l += nt) {
+        const uint8_t* row = mt + (l << 8);
+        uint32_t t[5] = {0, 0, 0, 0, 0};
+        for (int y = 0; y < 8; ++y) {
+            t[y >> 2] |= (uint32_t)row[y] << (8 * (y & 3));
+            t[2 + (y >> 2)] |= (uint32_t)row[y << 3] << (8 * (y & 3));
+        }
+        for (int y = 0; y < 4; ++y) t[4] |= (uint32_t)row[y << 6] << (8 * y);
+        mt3[3 * l] = make_uint2(t[0], t[1]);
+        mt3[3 * l + 1] = make_uint2(t[2], t[3]);
+        mt3[3 * l + 2] = make_uint2(t[4], 0);
+    }
+}
+
+AFFT_HD uint32_t mul_word8_t(const uint2& t0, const uint2& t1, uint32_t t2, uint32_t a) {
+    return perm32(t0.y, t0.x, a & 0x07070707u) ^ perm32(t1.y, t1.x, (a >> 3) & 0x07070707u) ^
+           perm32(0u, t2, (a >> 6) & 0x03030303u);
+}
+
+AFFT_HD uint4 mul_sub8_t(const uint2* mt3, uint32_t lam8, const uint4& v) {
+    const uint2 t0 = mt3[3 * lam8], t1 = mt3[3 * lam8 + 1];
+    const uint32_t t2 = mt3[3 * lam8 + 2].x;
+    return make_uint4(mul_word8_t(t0, t1, t2, v.x), mul_word8_t(t0, t1, t2, v.y), mul_word8_t(t0, t1, t2, v.z),
+                      mul_word8_t(t0, t1, t2, v.w));
+}
+
 // mu-set of local layer li for block row bits b (b < 2^(rlog - li - 1))
 AFFT_HD uint4 fft_mu(const uint4* mu, int li, uint32_t b) {
-    return xor4(mu[li * kMuLo + (int)(b & 63u)], mu[kMuHiCur + li * kMuHi + (int)(b >> 6)]);
+    return xor4(mu[mu_lo_off(li) + (int)(b & 63u)], mu[kMuHiCur + mu_hi_off(li) + (int)(b >> 6)]);
 }
 
 // One step of RL consecutive layers [i0, i0 + RL) held in registers: a thread
 // owns the 2^RL elements whose rows differ only in the bits (i0 - lo) ..
 // (i0 - lo + RL - 1) (same column) and runs all their butterflies.
 template <int RL, bool INV>
-AFFT_HD void fft_step(int tid, int nt, const FftPass& A, int i0, const uint8_t* mt, uint4* tl, const uint4* mu) {
+AFFT_HD void fft_step(int tid, int nt, const FftPass& A, int i0, const uint8_t* mt, const uint2* mt3, uint4* tl,
+                      const uint4* mu) {
     const uint32_t nel = 1u << (A.hi - A.lo + A.log_tc);
     const uint32_t groups = nel >> RL;
     const uint32_t tcm = (1u << A.log_tc) - 1;
@@ -354,11 +393,11 @@ AFFT_HD void fft_step(int tid, int nt, const FftPass& A, int i0, const uint8_t* 
                 uint4 m = fft_mu(mu, li, r0 >> (li + 1));
                 uint4 u = x[j], v = x[j | (1 << l)];
                 if (!INV) {
-                    u = u ^ mul_sub_k(mt, m, v, mode);
+                    u = u ^ (mode == 0 ? mul_sub8_t(mt3, m.w & 255u, v) : mul_sub_k(mt, m, v, mode));
                     v = v ^ u;
                 } else {
                     v = v ^ u;
-                    u = u ^ mul_sub_k(mt, m, v, mode);
+                    u = u ^ (mode == 0 ? mul_sub8_t(mt3, m.w & 255u, v) : mul_sub_k(mt, m, v, mode));
                 }
                 x[j] = u;
                 x[j | (1 << l)] = v;
@@ -381,11 +420,12 @@ AFFT_HD void fft_step(int tid, int nt, const FftPass& A, int i0, const uint8_t* 
 // own tile part (fft_tile_layers).  li = i - lo is the local layer.
 AFFT_HD void fft_local_mu(int tid, int nt, const FftPass& A, const uint8_t* mt, const uint32_t* lam, uint4* mu) {
     const int rlog = (int)(A.hi - A.lo);
-    for (int E = tid; E < kFftTileLog * (kMuLo + kMuHi); E += nt) {
-        const bool hi = E >= kFftTileLog * kMuLo;
-        const int F = hi ? E - kFftTileLog * kMuLo : E;
-        const int li = hi ? F / kMuHi : F / kMuLo;
-        const uint32_t x = hi ? (uint32_t)(F % kMuHi) : (uint32_t)(F % kMuLo);
+    for (int E = tid; E < kMuLoN + kMuHiN; E += nt) {
+        const bool hi = E >= kMuLoN;
+        const int F = hi ? E - kMuLoN : E;
+        int li = 0;
+        while (li + 1 < kFftTileLog && (hi ? mu_hi_off(li + 1) : mu_lo_off(li + 1)) <= F) ++li;
+        const uint32_t x = (uint32_t)(F - (hi ? mu_hi_off(li) : mu_lo_off(li)));
         if (li >= rlog) continue;
         const int nb = rlog - li - 1;
         const int lob = nb < 6 ? nb : 6;
@@ -394,7 +434,7 @@ AFFT_HD void fft_local_mu(int tid, int nt, const FftPass& A, const uint8_t* mt, 
         const int t0 = i + 1 + (hi ? 6 : 0);
         uint32_t lv = 0;
         for (uint32_t q = x; q; q &= q - 1) lv ^= lam[i * 32 + t0 + __builtin_ctz(q)];
-        mu[hi ? kMuHiBase + li * kMuHi + (int)x : li * kMuLo + (int)x] = make_mu_k(mt, lv);
+        mu[hi ? kMuHiBase + F : F] = make_mu_k(mt, lv);
     }
 }
 
@@ -433,7 +473,7 @@ AFFT_HD uint4 fft_load(const FftPass& A, const uint4* phi_tab, const FftTileGeom
 // round trip.
 template <int RL>
 AFFT_HD void fft_tile_layers(int tid, int nt, const FftPass& A, const FftTileGeom& G, const uint8_t* mt,
-                             const uint32_t* lam, uint4* tl, uint4* mu, uint4* mu_tile) {
+                             const uint2* mt3, const uint32_t* lam, uint4* tl, uint4* mu, uint4* mu_tile) {
     const int rlog = (int)(A.hi - A.lo);
     for (int li = tid; li < rlog; li += nt) {
         int i = (int)A.lo + li;
@@ -443,10 +483,11 @@ AFFT_HD void fft_tile_layers(int tid, int nt, const FftPass& A, const FftTileGeo
     }
     AFFT_SYNC();
     // high tables of this tile: pass part + tile part
-    for (int E = tid; E < rlog * kMuHi; E += nt) {
-        const int li = E / kMuHi, y = E % kMuHi;
-        const int nb = rlog - li - 1;
-        if (y < (1 << (nb > 6 ? nb - 6 : 0))) mu[kMuHiCur + E] = xor4(mu[kMuHiBase + E], mu_tile[li]);
+    for (int E = tid; E < kMuHiN; E += nt) {
+        int li = 0;
+        while (li + 1 < kFftTileLog && mu_hi_off(li + 1) <= E) ++li;
+        const int y = E - mu_hi_off(li), nb = rlog - li - 1;
+        if (li < rlog && y < (1 << (nb > 6 ? nb - 6 : 0))) mu[kMuHiCur + E] = xor4(mu[kMuHiBase + E], mu_tile[li]);
     }
     AFFT_SYNC();
     int done = 0;
@@ -456,18 +497,18 @@ AFFT_HD void fft_tile_layers(int tid, int nt, const FftPass& A, const FftTileGeo
         int i0 = A.inverse ? (int)A.lo + done : (int)A.hi - done - R;
         if (A.inverse) {
             if (R == 3)
-                fft_step<3, true>(tid, nt, A, i0, mt, tl, mu);
+                fft_step<3, true>(tid, nt, A, i0, mt, mt3, tl, mu);
             else if (R == 2)
-                fft_step<2, true>(tid, nt, A, i0, mt, tl, mu);
+                fft_step<2, true>(tid, nt, A, i0, mt, mt3, tl, mu);
             else
-                fft_step<1, true>(tid, nt, A, i0, mt, tl, mu);
+                fft_step<1, true>(tid, nt, A, i0, mt, mt3, tl, mu);
         } else {
             if (R == 3)
-                fft_step<3, false>(tid, nt, A, i0, mt, tl, mu);
+                fft_step<3, false>(tid, nt, A, i0, mt, mt3, tl, mu);
             else if (R == 2)
-                fft_step<2, false>(tid, nt, A, i0, mt, tl, mu);
+                fft_step<2, false>(tid, nt, A, i0, mt, mt3, tl, mu);
             else
-                fft_step<1, false>(tid, nt, A, i0, mt, tl, mu);
+                fft_step<1, false>(tid, nt, A, i0, mt, mt3, tl, mu);
         }
         AFFT_SYNC();
         done += R;
@@ -477,11 +518,11 @@ AFFT_HD void fft_tile_layers(int tid, int nt, const FftPass& A, const FftTileGeo
 // One whole tile: load, layers, store (the sequential form; the GPU kernel
 // overlaps the next tile's loads with these layers).
 template <int RL>
-AFFT_HD void fft_tile(int tid, int nt, uint64_t tile, const FftPass& A, const uint8_t* mt, const uint32_t* lam,
-                      const uint4* phi_tab, uint4* tl, uint4* mu, uint4* mu_tile) {
+AFFT_HD void fft_tile(int tid, int nt, uint64_t tile, const FftPass& A, const uint8_t* mt, const uint2* mt3,
+                      const uint32_t* lam, const uint4* phi_tab, uint4* tl, uint4* mu, uint4* mu_tile) {
     FftTileGeom G = fft_geom(A, tile);
     for (uint32_t e = tid; e < G.nel; e += nt) tl[e] = fft_load(A, phi_tab, G, e);
-    fft_tile_layers<RL>(tid, nt, A, G, mt, lam, tl, mu, mu_tile);
+    fft_tile_layers<RL>(tid, nt, A, G, mt, mt3, lam, tl, mu, mu_tile);
     for (uint32_t e = tid; e < G.nel; e += nt) A.dst[G.gbase | fft_elem_index(A, G, e)] = tl[e];
     AFFT_SYNC();
 }
