@@ -258,7 +258,8 @@ uint64_t gf2x_eval_points(gf2x_ctx *ctx, uint64_t na_bits, uint64_t nb_bits);
  * gf2x_workspace_bytes) fits in the server's arena and a slot is free; its
  * state then stays on the device until it completes.  The engine runs
  * iterations: every admitted request advances by up to `levels_per_iter`
- * dependency levels of its product, the ops of all requests at one level run
+ * dependency levels of its product (fewer when `iter_tiles` bounds the
+ * iteration's work, so that iterations stay short under load), the ops of all requests at one level run
  * together in multi-op launches (STAGED) or in one persistent launch per
  * iteration (PERSISTENT), and requests that arrive meanwhile join at the next
  * iteration as memory and slots free up.  Admission is first come, first
@@ -274,8 +275,17 @@ typedef struct {
     uint32_t max_active;      /* admitted requests at most (slots) */
     uint32_t levels_per_iter; /* dependency levels each request advances per iteration (>= 1) */
     uint32_t inflight;        /* iterations queued on the device at once (1..4) */
-    int32_t mode;             /* GF2X_BATCH_STAGED or GF2X_BATCH_PERSISTENT */
+    int32_t mode;             /* GF2X_BATCH_STAGED, GF2X_BATCH_PERSISTENT or GF2X_SERVER_ADAPTIVE */
+    uint64_t iter_tiles;      /* work bound: an iteration stops adding levels (beyond the first)
+                                 once its tiles would exceed this; 0 = no bound */
 } gf2x_server_cfg;
+
+/* Server mode GF2X_SERVER_ADAPTIVE: an iteration runs as one persistent
+ * launch while at least GF2X_SERVER_ADAPTIVE_ACTIVE requests are admitted and
+ * fewer than GF2X_SERVER_ADAPTIVE_BACKLOG wait in the queue (no launch tails:
+ * the lowest latency under load), and staged otherwise (few requests: the
+ * lowest latency alone; a long queue: the highest throughput). */
+enum { GF2X_SERVER_ADAPTIVE = 2, GF2X_SERVER_ADAPTIVE_ACTIVE = 8, GF2X_SERVER_ADAPTIVE_BACKLOG = 1024 };
 
 typedef struct {
     uint64_t tag;        /* the caller's tag from gf2x_server_submit */

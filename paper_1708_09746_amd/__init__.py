@@ -53,7 +53,8 @@ class TuneRec(ctypes.Structure):
 
 class ServerCfg(ctypes.Structure):
     _fields_ = [("arena_bytes", ctypes.c_uint64), ("max_active", ctypes.c_uint32),
-                ("levels_per_iter", ctypes.c_uint32), ("inflight", ctypes.c_uint32), ("mode", ctypes.c_int32)]
+                ("levels_per_iter", ctypes.c_uint32), ("inflight", ctypes.c_uint32), ("mode", ctypes.c_int32),
+                ("iter_tiles", ctypes.c_uint64)]
 
 
 class Done(ctypes.Structure):
@@ -214,9 +215,10 @@ class Context:
         return Batch(self, jobs, persistent)
 
     def server(self, arena_bytes: int, max_active: int = 4096, levels_per_iter: int = 4, inflight: int = 2,
-               persistent: bool = False):
-        """A continuous-batching request loop (Server) on this context."""
-        return Server(self, arena_bytes, max_active, levels_per_iter, inflight, persistent)
+               persistent=False, iter_tiles: int = 0):
+        """A continuous-batching request loop (Server) on this context;
+        persistent: False (staged), True, or "adaptive"."""
+        return Server(self, arena_bytes, max_active, levels_per_iter, inflight, persistent, iter_tiles)
 
     def lookup_rate(self) -> float:
         """Measured rate of random byte lookups into an LDS table (per second, whole device)."""
@@ -366,9 +368,10 @@ class Server:
     step(), collect completion records with poll()."""
 
     def __init__(self, ctx: "Context", arena_bytes: int, max_active: int, levels_per_iter: int, inflight: int,
-                 persistent: bool):
+                 persistent: bool, iter_tiles: int = 0):
         self.ctx = ctx
-        cfg = ServerCfg(arena_bytes, max_active, levels_per_iter, inflight, 1 if persistent else 0)
+        mode = 2 if persistent == "adaptive" else (1 if persistent else 0)
+        cfg = ServerCfg(arena_bytes, max_active, levels_per_iter, inflight, mode, iter_tiles)
         h = ctypes.c_void_p()
         ctx._check(lib().gf2x_server_create(ctx.handle, ctypes.byref(cfg), ctypes.byref(h)), "gf2x_server_create")
         self._h = h

@@ -425,15 +425,19 @@ __global__ __launch_bounds__(kThreads) void k_persistent(PersistArgs P, const ui
                 case OpKind::Spine: spine_tile(tid, nt, t, D.spn, mt, g_phi); break;
             }
         }
-        // grid barrier between ranks: release this block's writes, arrive,
-        // wait for every block, acquire
-        __threadfence();
+        // grid barrier between ranks.  After the workgroup barrier every store
+        // of this block has completed; one thread releases them at agent
+        // scope with its arrival (an agent-scope fence writes back the whole
+        // L2 of this XCD, so one per block suffices, and one per wave would
+        // repeat it 16 times), polls with relaxed loads (an acquiring poll
+        // would invalidate the L2 on every iteration), and acquires once; the
+        // second workgroup barrier orders the block's later loads after it.
         __syncthreads();
         if (tid == 0) {
             int stop = 0;
             __hip_atomic_fetch_add(&P.arrive[r], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
             uint32_t spins = 0;
-            while (__hip_atomic_load(&P.arrive[r], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < gridDim.x) {
+            while (__hip_atomic_load(&P.arrive[r], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < gridDim.x) {
                 if (__hip_atomic_load(P.abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
                     stop = 1;
                     break;
@@ -445,11 +449,11 @@ __global__ __launch_bounds__(kThreads) void k_persistent(PersistArgs P, const ui
                 }
                 __builtin_amdgcn_s_sleep(2);
             }
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
             s_stop = stop;
         }
         __syncthreads();
         if (s_stop) break;
-        __threadfence();
     }
 }
 
@@ -515,6 +519,7 @@ struct gf2x_server {
         uint64_t na = 0, nb = 0, tag = 0, t_submit = 0, t_admit = 0;
         size_t off = 0, bytes = 0;
         std::vector<gf2x::Op> ops;
+        std::vector<uint64_t> level_tiles;  // tiles of each dependency level
         uint32_t levels = 0, next = 0, iters = 0;
     };
     std::deque<Req> queue;
@@ -1114,6 +1119,8 @@ void server_admit(gf2x_server* S) {
         q.ops.clear();
         plan_mul(q.ops, ctx->pool, ctx->params, s, q.a, q.b, q.c, S->arena + off);
         q.levels = plan_levels(q.ops);
+        q.level_tiles.assign(q.levels, 0);
+        for (const Op& op : q.ops) q.level_tiles[op.level] += op_tiles(op);
         S->active.push_back(std::move(q));
         S->queue.pop_front();
         ++S->stats.admitted;
@@ -1151,7 +1158,21 @@ int server_iterate(gf2x_server* S, bool& launched) {
     launched = true;
     const int si = S->free_slots.back();
     gf2x_server::Slot& sl = S->slots[si];
-    const uint32_t L = S->cfg.levels_per_iter;
+    uint32_t L = S->cfg.levels_per_iter;
+    if (S->cfg.iter_tiles) {
+        // as many levels as fit the work bound (at least one)
+        uint64_t acc = 0;
+        uint32_t l = 0;
+        while (l < L) {
+            uint64_t add = 0;
+            for (const auto& r : S->active)
+                if (r.next + l < r.levels) add += r.level_tiles[r.next + l];
+            if (add == 0 || (l > 0 && acc + add > S->cfg.iter_tiles)) break;
+            acc += add;
+            ++l;
+        }
+        L = std::max<uint32_t>(l, 1);
+    }
     S->it_ops.clear();
     S->it_rank.clear();
     std::vector<gf2x_server::Req> keep;
@@ -1178,7 +1199,10 @@ int server_iterate(gf2x_server* S, bool& launched) {
     S->it_launch.clear();
     PersistLayout PL;
     size_t base = 0;
-    const bool pers = S->cfg.mode == GF2X_BATCH_PERSISTENT;
+    const size_t admitted = S->active.size() + sl.fin.size();
+    const bool pers = S->cfg.mode == GF2X_BATCH_PERSISTENT ||
+                      (S->cfg.mode == GF2X_SERVER_ADAPTIVE && admitted >= GF2X_SERVER_ADAPTIVE_ACTIVE &&
+                       S->queue.size() < GF2X_SERVER_ADAPTIVE_BACKLOG);
     if (pers)
         pack_persistent(S->it_ops, S->it_rank, S->it_groups, S->it_host, base, PL);
     else
@@ -1653,7 +1677,7 @@ int gf2x_server_create(gf2x_ctx* ctx, const gf2x_server_cfg* cfg, gf2x_server** 
     *out = nullptr;
     if (!cfg->arena_bytes || !cfg->max_active || !cfg->levels_per_iter || cfg->inflight < 1 || cfg->inflight > 4)
         return fail(ctx, GF2X_EINVAL, "server configuration: zero field or inflight outside 1..4");
-    if (cfg->mode != GF2X_BATCH_STAGED && cfg->mode != GF2X_BATCH_PERSISTENT)
+    if (cfg->mode != GF2X_BATCH_STAGED && cfg->mode != GF2X_BATCH_PERSISTENT && cfg->mode != GF2X_SERVER_ADAPTIVE)
         return fail(ctx, GF2X_EINVAL, "server configuration: unknown mode");
     DeviceGuard g(ctx->device);
     gf2x_server* S = new gf2x_server();
