@@ -1,0 +1,234 @@
+// Host-side check of the planner and the kernel bodies: the op lists the
+// library plans (single products, batches by level and kind, truncated
+// transforms, BasisCvt tile and class passes) are executed sequentially on
+// the CPU (thread 0 of 1, the same tile bodies the kernels run) and every
+// product is compared with the oracle.  No GPU is involved.
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <random>
+#include <string>
+#include <vector>
+
+#include "afft_plan.hpp"
+#include "tower_host.hpp"
+
+using namespace gf2x;
+
+extern "C" int oracle_mul(const uint64_t* a, size_t na_bits, const uint64_t* b, size_t nb_bits, uint64_t* c,
+                          int threads);
+
+namespace {
+
+std::vector<uint8_t> MT(65536);
+std::vector<uint32_t> LAM(1024);
+std::vector<uint4> PHI(2048), PSI(4096);
+std::vector<uint2> MT3(768);
+LayerPool POOL;
+PlanParams PP;
+
+uint4 to_u4(u128 v) { return make_uint4((uint32_t)v, (uint32_t)(v >> 32), (uint32_t)(v >> 64), (uint32_t)(v >> 96)); }
+
+bool init() {
+    POOL.base = POOL.host.data();
+    HostTower T;
+    for (int a = 0; a < 256; ++a)
+        for (int b = 0; b < 256; ++b) MT[a * 256 + b] = T.mt8[a][b];
+    uint32_t lam[32][32];
+    build_lambda(T, lam);
+    memcpy(LAM.data(), lam, sizeof(lam));
+    ReprTables R = build_repr(T);
+    if (!R.ok) return false;
+    for (int i = 0; i < 2048; ++i) PHI[i] = to_u4(R.phi[i]);
+    for (int i = 0; i < 4096; ++i) PSI[i] = to_u4(R.psi[i]);
+    PP.lam = LAM.data();
+    PP.mt = MT.data();
+    build_mt3(0, 1, MT.data(), MT3.data());
+    return true;
+}
+
+struct Scratch {
+    std::vector<uint4> tl = std::vector<uint4>(1 << kFftTileLog), mu = std::vector<uint4>(kMuEntries),
+                       mut = std::vector<uint4>(32);
+    std::vector<uint64_t> l64 = std::vector<uint64_t>(1 << kBcTileLog64);
+    std::vector<uint4> l128 = std::vector<uint4>(1 << kBcTileLog128);
+};
+
+void run_tile(const Op& op, uint64_t t, Scratch& S) {
+    switch (op.kind) {
+        case OpKind::Pack: pack_tile(0, 1, t, op.pack); break;
+        case OpKind::BcTile:
+            if (op.bct.wide)
+                bc_tile<uint4>(0, 1, t, op.bct, S.l128.data());
+            else
+                bc_tile<uint64_t>(0, 1, t, op.bct, S.l64.data());
+            break;
+        case OpKind::BcLayer:
+            if (op.bcl.wide)
+                bc_part<uint4>(0, 1, (uint4*)op.bcl.data, op.bcl.nelem, op.bcl.layer, (int)op.bcl.which);
+            else
+                bc_part<uint64_t>(0, 1, (uint64_t*)op.bcl.data, op.bcl.nelem, op.bcl.layer, (int)op.bcl.which);
+            break;
+        case OpKind::Fft:
+            fft_local_mu(0, 1, op.fft, MT.data(), LAM.data(), S.mu.data());
+            fft_tile<kFftRL>(0, 1, t, op.fft, MT.data(), MT3.data(), LAM.data(), PHI.data(), S.tl.data(), S.mu.data(),
+                             S.mut.data());
+            break;
+        case OpKind::Pmul: pmul_tile(0, 1, t, op.pmul, MT.data()); break;
+        case OpKind::Psi: psi_tile(0, 1, t, op.psi, PSI.data()); break;
+        case OpKind::BcClass:
+            if (op.bcc.wide)
+                bc_class_tile<uint4>(0, 1, t, op.bcc, S.l128.data());
+            else
+                bc_class_tile<uint64_t>(0, 1, t, op.bcc, S.l64.data());
+            break;
+        case OpKind::Spine: spine_tile(0, 1, t, op.spn, MT.data(), PHI.data()); break;
+    }
+}
+
+void run_ops(const std::vector<Op>& ops) {
+    Scratch S;
+    for (const Op& op : ops) {
+        const uint64_t n = op_tiles(op);
+        for (uint64_t t = 0; t < n; ++t) run_tile(op, t, S);
+    }
+}
+
+std::vector<uint64_t> rand_words(std::mt19937_64& g, uint64_t nbits) {
+    std::vector<uint64_t> w((nbits + 63) / 64);
+    for (auto& x : w) x = g();
+    return w;
+}
+
+// one product through the planner, compared with the oracle
+bool check_product(std::mt19937_64& g, uint64_t na, uint64_t nb) {
+    Sizes s = make_sizes(na, nb);
+    Workspace w = workspace_for(s);
+    std::vector<char> ws(w.bytes, 0x5a);  // garbage: the plan must not read what it did not write
+    auto a = rand_words(g, na), b = rand_words(g, nb);
+    std::vector<uint64_t> c(s.out_words + 1, 0xdead), r(s.out_words + 1, 0);
+    std::vector<Op> ops;
+    plan_mul(ops, POOL, PP, s, a.data(), b.data(), c.data(), ws.data());
+    run_ops(ops);
+    oracle_mul(a.data(), na, b.data(), nb, r.data(), 4);
+    const bool ok = memcmp(c.data(), r.data(), 8 * s.out_words) == 0 && c[s.out_words] == 0xdead;
+    if (!ok)
+        printf("MISMATCH %llu x %llu bits (N = 2^%d, M = %llu, truncation %d)\n", (unsigned long long)na,
+               (unsigned long long)nb, s.m, (unsigned long long)eval_points(s, PP), PP.trunc_levels);
+    return ok;
+}
+
+// a batch run group by group, tiles mapped to ops by the prefix sums as the
+// multi-op kernels do
+bool check_batch(std::mt19937_64& g, int njobs) {
+    std::vector<BatchJob> jobs(njobs);
+    std::vector<std::vector<uint64_t>> A(njobs), B(njobs), C(njobs);
+    for (int j = 0; j < njobs; ++j) {
+        uint64_t na = 1 + g() % (1ull << (1 + g() % 17)), nb = 1 + g() % (1ull << (1 + g() % 17));
+        A[j] = rand_words(g, na);
+        B[j] = rand_words(g, nb);
+        C[j].assign((na + nb - 1 + 63) / 64 + 1, 0xdead);
+        jobs[j] = BatchJob{A[j].data(), na, B[j].data(), nb, C[j].data()};
+    }
+    BatchPlan P;
+    plan_batch(P, POOL, PP, jobs.data(), njobs, nullptr);
+    std::vector<char> ws(P.ws_bytes + 16, 0x5a);
+    plan_batch(P, POOL, PP, jobs.data(), njobs, ws.data());
+    Scratch S;
+    for (const BatchGroup& G : P.groups) {
+        std::vector<uint64_t> prefix(G.ops.size() + 1, 0);
+        for (size_t i = 0; i < G.ops.size(); ++i) prefix[i + 1] = prefix[i] + op_tiles(P.ops[G.ops[i]]);
+        int o = -1;
+        for (uint64_t t = 0; t < prefix.back(); ++t) {
+            o = op_of_tile(prefix.data(), (int)G.ops.size(), t, o);
+            run_tile(P.ops[G.ops[o]], t - prefix[o], S);
+        }
+    }
+    int bad = 0;
+    for (int j = 0; j < njobs; ++j) {
+        const uint64_t ow = (jobs[j].na_bits + jobs[j].nb_bits - 1 + 63) / 64;
+        std::vector<uint64_t> r(ow + 1, 0);
+        oracle_mul(A[j].data(), jobs[j].na_bits, B[j].data(), jobs[j].nb_bits, r.data(), 4);
+        if (memcmp(r.data(), C[j].data(), 8 * ow) || C[j][ow] != 0xdead) ++bad;
+    }
+    if (bad) printf("batch MISMATCH in %d of %d jobs\n", bad, njobs);
+    return bad == 0;
+}
+
+// BasisCvt as tile and class passes against the flat layer list, both directions
+template <typename T>
+T rnd_elem(std::mt19937_64& g);
+template <>
+uint64_t rnd_elem<uint64_t>(std::mt19937_64& g) {
+    return g();
+}
+template <>
+uint4 rnd_elem<uint4>(std::mt19937_64& g) {
+    const uint64_t a = g(), b = g();
+    return make_uint4((uint32_t)a, (uint32_t)(a >> 32), (uint32_t)b, (uint32_t)(b >> 32));
+}
+bool same(uint64_t a, uint64_t b) { return a == b; }
+bool same(uint4 a, uint4 b) { return a.x == b.x && a.y == b.y && a.z == b.z && a.w == b.w; }
+
+template <typename T>
+bool check_basiscvt(int m) {
+    std::mt19937_64 g(1000 + m);
+    const uint64_t n = 1ull << m;
+    std::vector<T> a(n), flat, orig;
+    for (auto& x : a) x = rnd_elem<T>(g);
+    flat = a;
+    orig = a;
+    const int wide = sizeof(T) == 16;
+    std::vector<Op> ops;
+    emit_bc(ops, POOL, a.data(), wide, m, 0);
+    run_ops(ops);
+    std::vector<BcLayer> L;
+    bc_layer_list(m, 0, L);
+    for (const BcLayer& l : L)
+        for (int part = 0; part < 2; ++part) bc_part<T>(0, 1, flat.data(), n, l, part);
+    bool ok = true;
+    for (uint64_t i = 0; i < n && ok; ++i) ok = same(a[i], flat[i]);
+    std::vector<Op> inv;
+    emit_bc(inv, POOL, a.data(), wide, m, 1);
+    run_ops(inv);
+    for (uint64_t i = 0; i < n && ok; ++i) ok = same(a[i], orig[i]);
+    if (!ok) printf("BasisCvt MISMATCH m = %d, %s\n", m, wide ? "128-bit" : "64-bit");
+    return ok;
+}
+
+}  // namespace
+
+int main(int argc, char** argv) {
+    if (!init()) {
+        printf("table construction failed\n");
+        return 2;
+    }
+    const std::string what = argc > 1 ? argv[1] : "all";
+    int bad = 0;
+    std::mt19937_64 g(20261202);
+    if (what == "all" || what == "products") {
+        const uint64_t fixed[][2] = {{1, 1},         {64, 64},           {65, 64},           {1, 700},
+                                     {1000, 999},    {64 * 33, 64 * 31}, {5000, 70},         {1 << 16, 1 << 16},
+                                     {100000, 3},    {64 * 5000 + 7, 64 * 3000 + 1},        {1 << 20, 1 << 20},
+                                     {1 << 21, 1 << 19}};
+        for (auto& p : fixed) bad += !check_product(g, p[0], p[1]);
+        for (int i = 0; i < 60; ++i) bad += !check_product(g, 1 + g() % (1ull << (1 + g() % 18)), 1 + g() % (1ull << (1 + g() % 18)));
+    }
+    if (what == "all" || what == "batch") bad += !check_batch(g, 60);
+    if (what == "all" || what == "trunc") {
+        PP.trunc_min_log = 1;
+        for (int i = 0; i < 300; ++i) {
+            PP.trunc_levels = i % 9;
+            bad += !check_product(g, 1 + g() % (1ull << (1 + g() % 17)), 1 + g() % (1ull << (1 + g() % 17)));
+        }
+        PP.trunc_levels = 3;
+        bad += !check_batch(g, 40);
+        PP.trunc_min_log = 22;
+    }
+    if (what == "all" || what == "basiscvt") {
+        for (int m : {0, 1, 2, 5, 12, 13, 14, 16, 17, 20}) bad += !check_basiscvt<uint64_t>(m);
+        for (int m : {11, 12, 13, 16, 19}) bad += !check_basiscvt<uint4>(m);
+    }
+    printf(bad ? "host exec: %d failures\n" : "host exec ok\n", bad);
+    return bad ? 1 : 0;
+}
