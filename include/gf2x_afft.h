@@ -134,9 +134,9 @@ int gf2x_mul_batch(gf2x_ctx *ctx, const gf2x_job *jobs, size_t njobs, void *stre
 
 /* ---- tracing: per-kernel timing with HIP events (Sec. "Results" profiles the
  * same stages per component).  While a mask is set, every launch of a kernel
- * kind whose bit is in the mask is bracketed by two hipEvents recorded on the
- * launch stream; gf2x_trace_read() waits for them and returns one record per
- * launch.  Kinds (bit = 1 << kind): 0 pack, 1 BasisCvt tile, 2 BasisCvt global
+ * kind whose bit is in the mask carries two hipEvents in its own dispatch
+ * (hipExtLaunchKernelGGL), so their interval is the kernel's execution time;
+ * gf2x_trace_read() waits for them and returns one record per launch.  Kinds (bit = 1 << kind): 0 pack, 1 BasisCvt tile, 2 BasisCvt global
  * layer, 3 FFT pass, 4 pointmul, 5 changeRepr back + combine, 6 BasisCvt
  * VarSubs class pass, 7 truncated-transform step. */
 typedef struct {
