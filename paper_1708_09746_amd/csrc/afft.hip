@@ -32,10 +32,11 @@ __global__ __launch_bounds__(kThreads) void k_bc_tile(BcTileOp B) {
     __shared__ uint4 lds[1 << kBcTileLog128];  // 64 KiB
     const uint64_t nt = bc_tiles(B);
     for (uint64_t t = blockIdx.x; t < nt; t += gridDim.x) {
+        const uint64_t tile = xcd_tile(t, gridDim.x, nt);
         if (WIDE)
-            bc_tile<uint4>(threadIdx.x, blockDim.x, t, B, lds);
+            bc_tile<uint4>(threadIdx.x, blockDim.x, tile, B, lds);
         else
-            bc_tile<uint64_t>(threadIdx.x, blockDim.x, t, B, (uint64_t*)lds);
+            bc_tile<uint64_t>(threadIdx.x, blockDim.x, tile, B, (uint64_t*)lds);
     }
 }
 
@@ -44,10 +45,11 @@ __global__ __launch_bounds__(kThreads) void k_bc_class(BcClassOp C) {
     __shared__ uint4 lds[1 << kBcTileLog128];  // 64 KiB
     const uint64_t nt = bc_class_tiles(C);
     for (uint64_t t = blockIdx.x; t < nt; t += gridDim.x) {
+        const uint64_t tile = xcd_tile(t, gridDim.x, nt);
         if (WIDE)
-            bc_class_tile<uint4>(threadIdx.x, blockDim.x, t, C, lds);
+            bc_class_tile<uint4>(threadIdx.x, blockDim.x, tile, C, lds);
         else
-            bc_class_tile<uint64_t>(threadIdx.x, blockDim.x, t, C, (uint64_t*)lds);
+            bc_class_tile<uint64_t>(threadIdx.x, blockDim.x, tile, C, (uint64_t*)lds);
     }
 }
 
@@ -61,15 +63,21 @@ __global__ __launch_bounds__(kThreads) void k_bc_layer(BcLayerOp L) {
         bc_part<uint64_t>(tid, nt, (uint64_t*)L.data, L.nelem, L.layer, (int)L.which);
 }
 
-// Tiles of one FFT pass, block-strided; each block loads the tables and the
-// pass's local mu-sets once, and prefetches the next tile's elements into
-// registers while the current tile's layers run.
+// Tiles of one FFT pass, block-strided (XCD-aware order); each block loads the
+// tables and the pass's local mu-sets once, and prefetches the next tile's
+// input (elements, or words for a changeRepr pass) into registers while the
+// current tile's layers run.  Every slot of a full tile is loaded, written to
+// LDS and stored, also in a smaller tile (slots past its end repeat its last
+// element: same address, same value), so each tile issues a fixed number of
+// loads and stores, and the wait for the next tile's loads (issued before
+// this tile's stores) does not wait for the stores.
 constexpr int kFftPrefetch = (1 << kFftTileLog) / kThreads;
 static_assert(kFftPrefetch * kThreads == (1 << kFftTileLog), "every tile element has a prefetch slot");
 static_assert(((1 << kFftTileLog) >> kFftRL) <= kThreads, "one group of kFftRL layers per thread");
-static_assert(16 * ((1 << kFftTileLog) + kMuEntries) + 65536 + 4096 + 16 * 32 + 8 * 768 + 64 <= 163840,
+static_assert(16 * ((1 << kFftTileLog) + kMuEntries) + 65536 + 4096 + 16 * 32 + 8 * 768 + 16 * kPhiNib + 64 <= 163840,
               "FFT kernels fit in LDS");
 
+template <bool PHI>
 __global__ __launch_bounds__(kThreads) void k_fft(FftPass A, const uint8_t* g_mt, const uint32_t* g_lam,
                                                   const uint4* g_phi) {
     __shared__ __align__(16) uint8_t mt[65536];
@@ -78,43 +86,59 @@ __global__ __launch_bounds__(kThreads) void k_fft(FftPass A, const uint8_t* g_mt
     __shared__ uint4 mu[kMuEntries];
     __shared__ uint4 mu_tile[32];
     __shared__ uint2 mt3[768];
-    const int tid = threadIdx.x, nt = blockDim.x;
+    __shared__ uint4 phin[kPhiNib];
+    const uint32_t tid = threadIdx.x;
+    const int nt = kThreads;  // the launch uses kThreads threads per block
     copy_words(tid, nt, (uint32_t*)mt, (const uint32_t*)g_mt, 16384);
     copy_words(tid, nt, lam, g_lam, 1024);
+    if (PHI) build_phin(tid, nt, g_phi, phin);
     __syncthreads();
     build_mt3(tid, nt, mt, mt3);
     fft_local_mu(tid, nt, A, mt, lam, mu);
     const uint64_t ntiles = fft_tiles(A);
     uint64_t t = blockIdx.x;
     if (t >= ntiles) return;
-    FftTileGeom G = fft_geom(A, t);
-    uint4 pre[kFftPrefetch];
-#pragma unroll
-    for (int j = 0; j < kFftPrefetch; ++j) {
-        uint32_t e = tid + j * nt;
-        if (e < G.nel) pre[j] = fft_load(A, g_phi, G, e);
-    }
-    while (true) {
+    FftTileGeom G = fft_geom(A, xcd_tile(t, gridDim.x, ntiles));
+    // prefetch registers: the words of a changeRepr pass (PHI), else elements
+    std::conditional_t<PHI, uint64_t, uint4> pre[kFftPrefetch];
+    auto fetch = [&](const FftTileGeom& Gx) {
 #pragma unroll
         for (int j = 0; j < kFftPrefetch; ++j) {
-            uint32_t e = tid + j * nt;
-            if (e < G.nel) tl[e] = pre[j];
+            const uint32_t e = min(tid + j * kThreads, Gx.nel - 1);
+            if constexpr (PHI)
+                pre[j] = fft_word(A, Gx, e);
+            else
+                pre[j] = fft_spec(A, Gx, e);
         }
-        __syncthreads();
-        const uint64_t tn = t + gridDim.x;
-        FftTileGeom Gn = G;
-        if (tn < ntiles) {
-            Gn = fft_geom(A, tn);
+    };
+    auto fill = [&]() {
 #pragma unroll
-            for (int j = 0; j < kFftPrefetch; ++j) {
-                uint32_t e = tid + j * nt;
-                if (e < Gn.nel) pre[j] = fft_load(A, g_phi, Gn, e);
-            }
+        for (int j = 0; j < kFftPrefetch; ++j) {
+            if constexpr (PHI)
+                tl[tid + j * kThreads] = phi_word(phin, pre[j]);
+            else
+                tl[tid + j * kThreads] = pre[j];
         }
-        fft_tile_layers<kFftRL>(tid, nt, A, G, mt, mt3, lam, tl, mu, mu_tile);
-        for (uint32_t e = tid; e < G.nel; e += nt) A.dst[G.gbase | fft_elem_index(A, G, e)] = tl[e];
-        if (tn >= ntiles) break;
+    };
+    fetch(G);
+    fill();
+    while (true) {
         __syncthreads();
+        // the next tile; the last one fetches its own tile again, unused, so
+        // that every iteration issues the same loads
+        const uint64_t tn = t + gridDim.x;
+        const bool more = tn < ntiles;
+        const FftTileGeom Gn = fft_geom(A, xcd_tile(more ? tn : t, gridDim.x, ntiles));
+        fetch(Gn);
+        fft_tile_layers<kFftRL>(tid, nt, A, G, mt, mt3, lam, tl, mu, mu_tile);
+#pragma unroll
+        for (int j = 0; j < kFftPrefetch; ++j) {
+            const uint32_t e = min(tid + j * kThreads, G.nel - 1);
+            A.dst[G.gbase | fft_elem_index(A, G, e)] = tl[e];
+        }
+        if (!more) break;
+        __syncthreads();
+        fill();
         t = tn;
         G = Gn;
     }
@@ -159,10 +183,12 @@ __global__ __launch_bounds__(kThreads) void k_lookup_rate(const uint8_t* g_mt, u
 
 __global__ __launch_bounds__(kThreads) void k_spine(SpineOp S, const uint8_t* g_mt, const uint4* g_phi) {
     __shared__ __align__(16) uint8_t mt[65536];
+    __shared__ uint4 phin[kPhiNib];
     copy_words(threadIdx.x, blockDim.x, (uint32_t*)mt, (const uint32_t*)g_mt, 16384);
+    build_phin(threadIdx.x, blockDim.x, g_phi, phin);
     __syncthreads();
     const uint64_t nt = spine_tiles(S);
-    for (uint64_t t = blockIdx.x; t < nt; t += gridDim.x) spine_tile(threadIdx.x, blockDim.x, t, S, mt, g_phi);
+    for (uint64_t t = blockIdx.x; t < nt; t += gridDim.x) spine_tile(threadIdx.x, blockDim.x, t, S, mt, phin);
 }
 
 // ------------------------------------------------------- multi-op kernels
@@ -230,9 +256,11 @@ __global__ __launch_bounds__(kThreads) void k_fft_multi(const FftPass* ops, cons
     __shared__ uint4 mu[kMuEntries];
     __shared__ uint4 mu_tile[32];
     __shared__ uint2 mt3[768];
+    __shared__ uint4 phin[kPhiNib];
     const int tid = threadIdx.x, nt = blockDim.x;
     copy_words(tid, nt, (uint32_t*)mt, (const uint32_t*)g_mt, 16384);
     copy_words(tid, nt, lam, g_lam, 1024);
+    build_phin(tid, nt, g_phi, phin);
     __syncthreads();
     build_mt3(tid, nt, mt, mt3);
     __syncthreads();
@@ -249,7 +277,7 @@ __global__ __launch_bounds__(kThreads) void k_fft_multi(const FftPass* ops, cons
             cur_lo = A.lo;
             cur_hi = A.hi;
         }
-        fft_tile<kFftRL>(tid, nt, g - prefix[o], A, mt, mt3, lam, g_phi, tl, mu, mu_tile);
+        fft_tile<kFftRL>(tid, nt, g - prefix[o], A, mt, mt3, lam, phin, tl, mu, mu_tile);
     }
 }
 
@@ -270,14 +298,16 @@ __global__ __launch_bounds__(kThreads) void k_pmul_multi(const PmulOp* ops, cons
 __global__ __launch_bounds__(kThreads) void k_spine_multi(const SpineOp* ops, const uint64_t* prefix, int nops,
                                                           uint64_t total, const uint8_t* g_mt, const uint4* g_phi) {
     __shared__ __align__(16) uint8_t mt[65536];
+    __shared__ uint4 phin[kPhiNib];
     copy_words(threadIdx.x, blockDim.x, (uint32_t*)mt, (const uint32_t*)g_mt, 16384);
+    build_phin(threadIdx.x, blockDim.x, g_phi, phin);
     __syncthreads();
     uint64_t g0, g1;
     block_chunk(total, g0, g1);
     int o = -1;
     for (uint64_t g = g0; g < g1; ++g) {
         o = op_of_tile(prefix, nops, g, o);
-        spine_tile(threadIdx.x, blockDim.x, g - prefix[o], ops[o], mt, g_phi);
+        spine_tile(threadIdx.x, blockDim.x, g - prefix[o], ops[o], mt, phin);
     }
 }
 
@@ -349,11 +379,13 @@ __global__ __launch_bounds__(kThreads) void k_persistent(PersistArgs P, const ui
     __shared__ uint4 work[(1 << kFftTileLog) + kMuEntries];  // FFT tile + mu-set tables, a BasisCvt tile, or the Psi table
     __shared__ uint4 mu_tile[32];
     __shared__ uint2 mt3[768];
+    __shared__ uint4 phin[kPhiNib];
     __shared__ uint64_t s_item;
     __shared__ int s_stop;
     const int tid = threadIdx.x, nt = blockDim.x;
     copy_words(tid, nt, (uint32_t*)mt, (const uint32_t*)g_mt, 16384);
     copy_words(tid, nt, lam, g_lam, 1024);
+    build_phin(tid, nt, g_phi, phin);
     __syncthreads();
     build_mt3(tid, nt, mt, mt3);  // visible after the item loop's first barrier
     uint4* tl = work;
@@ -411,7 +443,7 @@ __global__ __launch_bounds__(kThreads) void k_persistent(PersistArgs P, const ui
                         cur_lo = A.lo;
                         cur_hi = A.hi;
                     }
-                    fft_tile<kFftRL>(tid, nt, t, A, mt, mt3, lam, g_phi, tl, mu, mu_tile);
+                    fft_tile<kFftRL>(tid, nt, t, A, mt, mt3, lam, phin, tl, mu, mu_tile);
                     break;
                 }
                 case OpKind::Pmul: pmul_tile(tid, nt, t, D.pmul, mt); break;
@@ -423,7 +455,7 @@ __global__ __launch_bounds__(kThreads) void k_persistent(PersistArgs P, const ui
                     }
                     psi_tile(tid, nt, t, D.psi, work);
                     break;
-                case OpKind::Spine: spine_tile(tid, nt, t, D.spn, mt, g_phi); break;
+                case OpKind::Spine: spine_tile(tid, nt, t, D.spn, mt, phin); break;
             }
         }
         // grid barrier between ranks.  After the workgroup barrier every store
@@ -716,8 +748,12 @@ int run_ops(gf2x_ctx* ctx, const std::vector<Op>& ops, hipStream_t st) {
                 break;
             }
             case OpKind::Fft:
-                GF2X_LAUNCH(k_fft, dim3(grid_for(fft_tiles(op.fft), ncu)), op.fft,
-                                   (const uint8_t*)ctx->d_mt, (const uint32_t*)ctx->d_lam, (const uint4*)ctx->d_phi);
+                if (op.fft.phi_in)
+                    GF2X_LAUNCH(k_fft<true>, dim3(grid_for(fft_tiles(op.fft), ncu)), op.fft,
+                                (const uint8_t*)ctx->d_mt, (const uint32_t*)ctx->d_lam, (const uint4*)ctx->d_phi);
+                else
+                    GF2X_LAUNCH(k_fft<false>, dim3(grid_for(fft_tiles(op.fft), ncu)), op.fft,
+                                (const uint8_t*)ctx->d_mt, (const uint32_t*)ctx->d_lam, (const uint4*)ctx->d_phi);
                 break;
             case OpKind::Pmul:
                 GF2X_LAUNCH(k_pmul, dim3(grid_for(pmul_tiles(op.pmul), 2 * ncu)), op.pmul,

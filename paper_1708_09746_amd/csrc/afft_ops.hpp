@@ -317,11 +317,22 @@ AFFT_HD uint64_t fft_tiles(const FftPass& A) {
 
 AFFT_HD int width_mode(int w) { return w <= 8 ? 0 : (w <= 16 ? 1 : 2); }
 
-// changeRepr into the tower (Sec. 4.3): M4R over the 8 bytes of the word
-AFFT_HD uint4 phi_word(const uint4* phi_tab, uint64_t w) {
+// changeRepr into the tower (Sec. 4.3), M4R over the 16 nibbles of the word:
+// phin[16 k + v] = Phi(v << 4k), 4 KiB, small enough to sit in LDS beside the
+// GF(256) table (the byte-indexed tables, 32 KiB, are not).  build_phin derives
+// it from the byte-indexed tables phi_tab[256 j + y] = Phi(y << 8j) by
+// linearity.
+constexpr int kPhiNib = 256;
+AFFT_HD void build_phin(int tid, int nt, const uint4* phi_tab, uint4* phin) {
+    for (int i = tid; i < kPhiNib; i += nt) {
+        const int k = i >> 4, v = i & 15;
+        phin[i] = phi_tab[(k >> 1) * 256 + (v << (4 * (k & 1)))];
+    }
+}
+AFFT_HD uint4 phi_word(const uint4* phin, uint64_t w) {
     uint4 r = make_uint4(0, 0, 0, 0);
 #pragma unroll
-    for (int k = 0; k < 8; ++k) r = r ^ phi_tab[k * 256 + ((w >> (8 * k)) & 255u)];
+    for (int k = 0; k < 16; ++k) r = r ^ phin[k * 16 + ((w >> (4 * k)) & 15u)];
     return r;
 }
 
@@ -461,10 +472,16 @@ AFFT_HD uint64_t fft_elem_index(const FftPass& A, const FftTileGeom& G, uint32_t
     return G.base_p | ((uint64_t)(e >> A.log_tc) << A.lo) | (e & ((1u << A.log_tc) - 1));
 }
 
-AFFT_HD uint4 fft_load(const FftPass& A, const uint4* phi_tab, const FftTileGeom& G, uint32_t e) {
-    uint64_t p = fft_elem_index(A, G, e);
-    if (A.phi_in) return phi_word(phi_tab, ((const uint64_t*)A.src)[p]);
-    return A.dst[G.gbase | p];
+// Tile element e: in a pass that applies changeRepr, Phi of its converted
+// word (fft_word), else the element of the spectrum (fft_spec).
+AFFT_HD uint64_t fft_word(const FftPass& A, const FftTileGeom& G, uint32_t e) {
+    return ((const uint64_t*)A.src)[fft_elem_index(A, G, e)];
+}
+AFFT_HD uint4 fft_spec(const FftPass& A, const FftTileGeom& G, uint32_t e) {
+    return A.dst[G.gbase | fft_elem_index(A, G, e)];
+}
+AFFT_HD uint4 fft_load(const FftPass& A, const uint4* phin, const FftTileGeom& G, uint32_t e) {
+    return A.phi_in ? phi_word(phin, fft_word(A, G, e)) : fft_spec(A, G, e);
 }
 
 // Layers [lo, hi) of one tile already in LDS (tl); mu holds the pass's local
@@ -519,9 +536,9 @@ AFFT_HD void fft_tile_layers(int tid, int nt, const FftPass& A, const FftTileGeo
 // overlaps the next tile's loads with these layers).
 template <int RL>
 AFFT_HD void fft_tile(int tid, int nt, uint64_t tile, const FftPass& A, const uint8_t* mt, const uint2* mt3,
-                      const uint32_t* lam, const uint4* phi_tab, uint4* tl, uint4* mu, uint4* mu_tile) {
+                      const uint32_t* lam, const uint4* phin, uint4* tl, uint4* mu, uint4* mu_tile) {
     FftTileGeom G = fft_geom(A, tile);
-    for (uint32_t e = tid; e < G.nel; e += nt) tl[e] = fft_load(A, phi_tab, G, e);
+    for (uint32_t e = tid; e < G.nel; e += nt) tl[e] = fft_load(A, phin, G, e);
     fft_tile_layers<RL>(tid, nt, A, G, mt, mt3, lam, tl, mu, mu_tile);
     for (uint32_t e = tid; e < G.nel; e += nt) A.dst[G.gbase | fft_elem_index(A, G, e)] = tl[e];
     AFFT_SYNC();
@@ -552,7 +569,7 @@ struct SpineOp {
 
 AFFT_HD uint64_t spine_tiles(const SpineOp& S) { return (S.n + kSpineTile - 1) / kSpineTile; }
 
-AFFT_HD void spine_tile(int tid, int nt, uint64_t tile, const SpineOp& S, const uint8_t* mt, const uint4* phi_tab) {
+AFFT_HD void spine_tile(int tid, int nt, uint64_t tile, const SpineOp& S, const uint8_t* mt, const uint4* phin) {
     for (int e = tid; e < kSpineTile; e += nt) {
         const uint64_t p = tile * kSpineTile + e;
         if (p >= S.n) break;
@@ -572,7 +589,7 @@ AFFT_HD void spine_tile(int tid, int nt, uint64_t tile, const SpineOp& S, const 
                 break;
             }
             case kSpineZero: S.x[p] = make_uint4(0, 0, 0, 0); break;
-            default: S.x[p] = phi_word(phi_tab, S.words[p]); break;
+            default: S.x[p] = phi_word(phin, S.words[p]); break;
         }
     }
 }
@@ -634,6 +651,22 @@ AFFT_HD void psi_tile(int tid, int nt, uint64_t tile, const PsiOp& P, const uint
         if (k == P.nwords - 1 && (P.nbits % 64)) w &= ~0ull >> (64 - P.nbits % 64);
         P.out[k] = w;
     }
+}
+
+// ------------------------------------------------ block to tile (XCD aware)
+// The chip dispatches the blocks of a launch to its eight XCDs round robin
+// (block b to XCD b mod 8), and each XCD has an L2 of its own.  Neighbouring
+// tiles of a strided pass share cache lines, so a block-strided loop (tile
+// b, b + grid, ...) would fetch every such line into several L2s.  Within
+// each full round of `grid` tiles, xcd_tile hands the blocks of one XCD a
+// contiguous run of grid/8 tiles; a partial last round, or a grid that is
+// not a multiple of 8, keeps the identity.  A bijection on [0, ntiles).
+constexpr uint32_t kXcds = 8;
+AFFT_HD uint64_t xcd_tile(uint64_t t, uint64_t grid, uint64_t ntiles) {
+    if (grid % kXcds) return t;
+    const uint64_t round = t / grid, r = t - round * grid;
+    if ((round + 1) * grid > ntiles) return t;
+    return round * grid + (r % kXcds) * (grid / kXcds) + r / kXcds;
 }
 
 // ------------------------------------------------------- op arrays (batches)

@@ -22,7 +22,7 @@ namespace {
 
 std::vector<uint8_t> MT(65536);
 std::vector<uint32_t> LAM(1024);
-std::vector<uint4> PHI(2048), PSI(4096);
+std::vector<uint4> PHI(2048), PHIN(kPhiNib), PSI(4096);
 std::vector<uint2> MT3(768);
 LayerPool POOL;
 PlanParams PP;
@@ -41,6 +41,7 @@ bool init() {
     if (!R.ok) return false;
     for (int i = 0; i < 2048; ++i) PHI[i] = to_u4(R.phi[i]);
     for (int i = 0; i < 4096; ++i) PSI[i] = to_u4(R.psi[i]);
+    build_phin(0, 1, PHI.data(), PHIN.data());
     PP.lam = LAM.data();
     PP.mt = MT.data();
     build_mt3(0, 1, MT.data(), MT3.data());
@@ -71,7 +72,7 @@ void run_tile(const Op& op, uint64_t t, Scratch& S) {
             break;
         case OpKind::Fft:
             fft_local_mu(0, 1, op.fft, MT.data(), LAM.data(), S.mu.data());
-            fft_tile<kFftRL>(0, 1, t, op.fft, MT.data(), MT3.data(), LAM.data(), PHI.data(), S.tl.data(), S.mu.data(),
+            fft_tile<kFftRL>(0, 1, t, op.fft, MT.data(), MT3.data(), LAM.data(), PHIN.data(), S.tl.data(), S.mu.data(),
                              S.mut.data());
             break;
         case OpKind::Pmul: pmul_tile(0, 1, t, op.pmul, MT.data()); break;
@@ -82,7 +83,7 @@ void run_tile(const Op& op, uint64_t t, Scratch& S) {
             else
                 bc_class_tile<uint64_t>(0, 1, t, op.bcc, S.l64.data());
             break;
-        case OpKind::Spine: spine_tile(0, 1, t, op.spn, MT.data(), PHI.data()); break;
+        case OpKind::Spine: spine_tile(0, 1, t, op.spn, MT.data(), PHIN.data()); break;
     }
 }
 
@@ -196,6 +197,45 @@ bool check_basiscvt(int m) {
     return ok;
 }
 
+// The XCD-aware block-to-tile order of the block-strided kernels visits every
+// tile exactly once, for grids that are and are not multiples of 8 and tile
+// counts with and without a partial last round.
+bool check_xcd_order(std::mt19937_64& g) {
+    std::vector<uint64_t> grids = {1, 7, 8, 16, 255, 256, 512, 1024, 2048};
+    for (int i = 0; i < 20; ++i) grids.push_back(1 + g() % 3000);
+    for (uint64_t grid : grids) {
+        std::vector<uint64_t> counts = {0, 1, grid - 1, grid, grid + 1, 2 * grid, 8 * grid + 3, 5 * grid};
+        for (int i = 0; i < 10; ++i) counts.push_back(g() % (20 * grid + 1));
+        for (uint64_t nt : counts) {
+            std::vector<uint8_t> seen(nt, 0);
+            for (uint64_t b = 0; b < grid; ++b)
+                for (uint64_t t = b; t < nt; t += grid) {
+                    const uint64_t x = xcd_tile(t, grid, nt);
+                    if (x >= nt || seen[x]++) {
+                        printf("XCD order MISMATCH grid %llu, tiles %llu\n", (unsigned long long)grid,
+                               (unsigned long long)nt);
+                        return false;
+                    }
+                }
+            for (uint64_t x = 0; x < nt; ++x)
+                if (!seen[x]) {
+                    printf("XCD order misses tile %llu (grid %llu, tiles %llu)\n", (unsigned long long)x,
+                           (unsigned long long)grid, (unsigned long long)nt);
+                    return false;
+                }
+        }
+    }
+    // blocks of one XCD (b mod 8 equal) take a contiguous run in a full round
+    const uint64_t grid = 256, nt = 2048;
+    for (uint64_t xcd = 0; xcd < 8; ++xcd)
+        for (uint64_t j = 0; j + 1 < grid / 8; ++j)
+            if (xcd_tile(xcd + 8 * (j + 1), grid, nt) != xcd_tile(xcd + 8 * j, grid, nt) + 1) {
+                printf("XCD order: run of XCD %llu broken\n", (unsigned long long)xcd);
+                return false;
+            }
+    return true;
+}
+
 }  // namespace
 
 int main(int argc, char** argv) {
@@ -225,6 +265,7 @@ int main(int argc, char** argv) {
         bad += !check_batch(g, 40);
         PP.trunc_min_log = 22;
     }
+    if (what == "all" || what == "xcd") bad += !check_xcd_order(g);
     if (what == "all" || what == "basiscvt") {
         for (int m : {0, 1, 2, 5, 12, 13, 14, 16, 17, 20}) bad += !check_basiscvt<uint64_t>(m);
         for (int m : {11, 12, 13, 16, 19}) bad += !check_basiscvt<uint4>(m);
