@@ -25,6 +25,9 @@ Readings of the paper taken here (each also listed in the design notes):
   TGF(2^128) outside TGF(2^64) generates the field (Sec. 2.1 allows any
   irreducible polynomial of degree 2w; Sec. 4.3 leaves the isomorphism matrix
   unprinted), and the product does not depend on the choice.
+* Word width w = 128 (the TGF(2^256) variant of Alg. 5): theta = x_8 (the
+  element 1 << 128), which lies outside TGF(2^128), the only maximal subfield
+  of TGF(2^256), and so generates it.
 * FFT size: N = max(2, 2^ceil(log2(n_a + n_b - 1))) points for operands of
   n_a and n_b words; each operand is converted at its own power-of-two size.
 """
@@ -429,20 +432,24 @@ def ifft_lch(vals: list[int], alpha: int, width: int = 128) -> list[int]:
 # Change of representation (Sec. 2.1 Kronecker segmentation; Sec. 4.3)
 # --------------------------------------------------------------------------
 
-THETA = 1 << 64  # x_7: generates TGF(2^128) (see module docstring)
+def theta_of(width: int) -> int:
+    """The Kronecker point of TGF(2^width): its top generator x_{log2 width},
+    the element 1 << (width / 2) (x_7 for w = 64, x_8 for w = 128)."""
+    return 1 << (width // 2)
 
 
 @lru_cache(maxsize=None)
-def theta_powers() -> tuple[int, ...]:
+def theta_powers(width: int = 128) -> tuple[int, ...]:
+    th = theta_of(width)
     pw = [1]
-    for _ in range(127):
-        pw.append(gf_mul(pw[-1], THETA, 128))
+    for _ in range(width - 1):
+        pw.append(gf_mul(pw[-1], th, width))
     return tuple(pw)
 
 
-def phi(u: int) -> int:
-    """changeRepr into the tower: the polynomial u(z) (deg < 128) at z = theta."""
-    pw = theta_powers()
+def phi(u: int, width: int = 128) -> int:
+    """changeRepr into the tower: the polynomial u(z) (deg < width) at z = theta."""
+    pw = theta_powers(width)
     r = 0
     j = 0
     while u >> j:
@@ -453,13 +460,13 @@ def phi(u: int) -> int:
 
 
 @lru_cache(maxsize=None)
-def _psi_basis():
-    """Row-reduce the 128 x 128 matrix whose column j is theta^j.
+def _psi_basis(width: int = 128):
+    """Row-reduce the width x width matrix whose column j is theta^j.
 
     Returns a list of (pivot_bit, element, combination) with echelon elements,
     so that any tower element can be written as a combination of theta^j.
     """
-    pw = theta_powers()
+    pw = theta_powers(width)
     basis = []  # (pivot, vector, combo)
     for j, v in enumerate(pw):
         combo = 1 << j
@@ -482,10 +489,10 @@ def _psi_basis():
     return basis
 
 
-def psi(e: int) -> int:
-    """changeRepr back: the polynomial u (deg < 128) with u(theta) = e."""
+def psi(e: int, width: int = 128) -> int:
+    """changeRepr back: the polynomial u (deg < width) with u(theta) = e."""
     u = 0
-    for piv, bv, bc in _psi_basis():
+    for piv, bv, bc in _psi_basis(width):
         if (e >> piv) & 1:
             e ^= bv
             u ^= bc
@@ -499,16 +506,17 @@ def psi(e: int) -> int:
 # --------------------------------------------------------------------------
 
 
-def words_of(x: int, nbits: int) -> list[int]:
-    nw = (nbits + 63) // 64
+def words_of(x: int, nbits: int, w: int = 64) -> list[int]:
+    """The w-bit words (Split, Alg. 5) of a polynomial of nbits bits."""
+    nw = (nbits + w - 1) // w
     x &= (1 << nbits) - 1
-    return [(x >> (64 * k)) & ((1 << 64) - 1) for k in range(nw)]
+    return [(x >> (w * k)) & ((1 << w) - 1) for k in range(nw)]
 
 
-def int_of(words: list[int]) -> int:
+def int_of(words: list[int], w: int = 64) -> int:
     r = 0
-    for k, w in enumerate(words):
-        r |= w << (64 * k)
+    for k, x in enumerate(words):
+        r |= x << (w * k)
     return r
 
 
@@ -519,53 +527,57 @@ def next_pow2(n: int) -> int:
     return p
 
 
-def fft_size(na_bits: int, nb_bits: int) -> int:
-    na = (na_bits + 63) // 64
-    nb = (nb_bits + 63) // 64
+def fft_size(na_bits: int, nb_bits: int, w: int = 64) -> int:
+    na = (na_bits + w - 1) // w
+    nb = (nb_bits + w - 1) // w
     return max(2, next_pow2(na + nb - 1))
 
 
-def forward_spectrum(a: int, na_bits: int, npoints: int) -> list[int]:
-    """Split, BasisCvt (64-bit words), changeRepr, FFT_LCH at 0, per Alg. 5.
+def forward_spectrum(a: int, na_bits: int, npoints: int, w: int = 64) -> list[int]:
+    """Split, BasisCvt (w-bit words), changeRepr, FFT_LCH at 0, per Alg. 5,
+    over TGF(2^(2w)).
 
     The operand is converted at its own power-of-two length n'; the FFT over
     npoints >= n' points is FFT_LCH of the converted polynomial, whose
     coefficients beyond n' are zero.
     """
-    words = words_of(a, na_bits)
+    words = words_of(a, na_bits, w)
     n1 = next_pow2(len(words))
     words = words + [0] * (n1 - len(words))
     g = basis_cvt(words)
-    gt = [phi(w) for w in g] + [0] * (npoints - n1)
-    return fft_lch(gt, 0)
+    gt = [phi(x, 2 * w) for x in g] + [0] * (npoints - n1)
+    return fft_lch(gt, 0, 2 * w)
 
 
-def inverse_to_product(spec: list[int], nc_bits: int) -> int:
-    """iFFT_LCH, iBasisCvt, changeRepr back, InterleavedCombine (Alg. 5)."""
-    gc = ifft_lch(spec, 0)
+def inverse_to_product(spec: list[int], nc_bits: int, w: int = 64) -> int:
+    """iFFT_LCH, iBasisCvt, changeRepr back, InterleavedCombine (Alg. 5):
+    the preimage of coefficient k (a polynomial of degree < 2w - 1) is added
+    in at bit w k."""
+    gc = ifft_lch(spec, 0, 2 * w)
     fc = from_novel(gc)
     r = 0
     for k, e in enumerate(fc):
-        r ^= psi(e) << (64 * k)
+        r ^= psi(e, 2 * w) << (w * k)
     return r & ((1 << nc_bits) - 1)
 
 
-def binpolymul_tower(a: int, na_bits: int, b: int, nb_bits: int) -> int:
-    """Alg. 5 binPolyMul with w = 64 over TGF(2^128), for small operands."""
+def binpolymul_tower(a: int, na_bits: int, b: int, nb_bits: int, w: int = 64) -> int:
+    """Alg. 5 binPolyMul with w-bit words over TGF(2^(2w)) (w = 64 or 128),
+    for small operands."""
     if na_bits == 0 or nb_bits == 0:
         return 0
-    N = fft_size(na_bits, nb_bits)
-    fa = forward_spectrum(a, na_bits, N)
-    fb = forward_spectrum(b, nb_bits, N)
-    fc = [gf_mul(x, y, 128) for x, y in zip(fa, fb)]
-    return inverse_to_product(fc, na_bits + nb_bits - 1)
+    N = fft_size(na_bits, nb_bits, w)
+    fa = forward_spectrum(a, na_bits, N, w)
+    fb = forward_spectrum(b, nb_bits, N, w)
+    fc = [gf_mul(x, y, 2 * w) for x, y in zip(fa, fb)]
+    return inverse_to_product(fc, na_bits + nb_bits - 1, w)
 
 
-def spectrum_point(words: list[int], nbits: int, j: int) -> int:
+def spectrum_point(words: list[int], nbits: int, j: int, w: int = 64) -> int:
     """f(j̄) with f(x) = sum_k Φ(a_k) x^k: one point of the forward spectrum,
     by Horner's rule (the definition of the evaluation the FFT computes)."""
-    ws = list(words_of(int_of(words), nbits))
-    return horner([phi(w) for w in ws], j, 128)
+    ws = list(words_of(int_of(words, w), nbits, w))
+    return horner([phi(x, 2 * w) for x in ws], j, 2 * w)
 
 
 # --------------------------------------------------------------------------

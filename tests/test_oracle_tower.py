@@ -301,6 +301,47 @@ def check_change_of_representation():
     assert T.phi(u ^ v) == T.phi(u) ^ T.phi(v)
 
 
+def check_change_of_representation_w128():
+    """w = 128: theta = x_8 in TGF(2^256); the images of two 128-bit blocks
+    multiply to the image of their carry-less product (degree < 255)."""
+    rng = random.Random(14)
+    for _ in range(12):
+        u = rng.getrandbits(256)
+        assert T.psi(T.phi(u, 256), 256) == u
+    for _ in range(12):
+        u, v = rng.getrandbits(128), rng.getrandbits(128)
+        assert T.psi(T.gf_mul(T.phi(u, 256), T.phi(v, 256), 256), 256) == T.clmul_int(u, v)
+    u, v = rng.getrandbits(256), rng.getrandbits(256)
+    assert T.phi(u ^ v, 256) == T.phi(u, 256) ^ T.phi(v, 256)
+    # the fast product at width 256 (Karatsuba with the subfield shortcuts)
+    # against the plain defining relations
+    for _ in range(4):
+        x, y = rng.getrandbits(256), rng.getrandbits(256)
+        assert T.gf_mul(x, y, 256) == T.gf_mul_plain(x, y, 256)
+    # a subfield scalar (Prop. 2: component-wise) against the plain relations
+    x, y = rng.getrandbits(256), rng.getrandbits(20)
+    assert T.gf_mul(x, y, 256) == T.gf_mul_plain(x, y, 256)
+
+
+def check_alg5_end_to_end_w128():
+    """Alg. 5 with 128-bit words over TGF(2^256) against the schoolbook
+    carry-less product, at sizes around the word and power-of-two edges."""
+    rng = random.Random(15)
+    sizes = [(1, 1), (1, 128), (128, 1), (128, 128), (129, 128), (127, 257), (256, 256), (257, 600),
+             (600, 9), (1000, 1000)]
+    for na, nb in sizes:
+        a = rng.getrandbits(na) | (1 << (na - 1))
+        b = rng.getrandbits(nb) | (1 << (nb - 1))
+        assert T.binpolymul_tower(a, na, b, nb, 128) == T.clmul_int(a, b), (na, nb)
+    # the spectrum is the evaluation of sum_k phi(a_k) x^k over TGF(2^256)
+    na = 700
+    a = rng.getrandbits(na)
+    words = T.words_of(a, na, 128)
+    spec = T.forward_spectrum(a, na, 16, 128)
+    for j in (0, 1, 6, 15):
+        assert spec[j] == T.spectrum_point(words, na, j, 128)
+
+
 def check_alg5_end_to_end():
     rng = random.Random(13)
     sizes = [(1, 1), (1, 64), (64, 1), (64, 64), (65, 64), (63, 129), (128, 128), (129, 500), (300, 7), (500, 500)]
@@ -331,6 +372,8 @@ CHECKS = [
     check_fft_is_evaluation,
     check_change_of_representation,
     check_alg5_end_to_end,
+    check_change_of_representation_w128,
+    check_alg5_end_to_end_w128,
 ]
 
 
@@ -385,7 +428,7 @@ MUTATIONS = {
     "tower_constant": ("tower_c", _mut_tower_constant),
     "dropped_hi_term": ("gf_mul_plain", _mut_gf_mul_plain_hi),
     "s_recursion": ("s_eval", _mut_s_eval),
-    "theta_in_subfield": ("THETA", 1 << 63),
+    "theta_in_subfield": ("theta_of", lambda width: 1 << (width // 2 - 1)),
 }
 
 
@@ -393,7 +436,8 @@ MUTATIONS = {
 def test_planted_mistake_is_caught(name, monkeypatch):
     attr, value = MUTATIONS[name]
     fast = [check_defining_relations, check_basis_fixture, check_tab1, check_fig2_multipliers,
-            check_prop1_and_prop3, check_change_of_representation, check_fast_paths_equal_plain]
+            check_prop1_and_prop3, check_change_of_representation, check_fast_paths_equal_plain,
+            check_change_of_representation_w128]
     _clear_caches()
     monkeypatch.setattr(T, attr, value)
     try:
