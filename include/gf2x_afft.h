@@ -249,6 +249,25 @@ int gf2x_set_truncation(gf2x_ctx *ctx, int levels, int min_log2n);
 /* Points M a product of these sizes is evaluated at on ctx (0 if empty). */
 uint64_t gf2x_eval_points(gf2x_ctx *ctx, uint64_t na_bits, uint64_t nb_bits);
 
+/* ---- word width of Split (Alg. 5 with w = 64 or w = 128) ----
+ * Alg. 5 splits the operands into w-bit words and multiplies in TGF(2^2w).
+ * The default w = 64 works in TGF(2^128).  w = 128 works in TGF(2^256): half
+ * as many points (one layer fewer), each a TGF(2^256) element, changeRepr of
+ * 128-bit words at x8 (which generates TGF(2^256): it lies outside
+ * TGF(2^128)), the pointwise products in TGF(2^256), and InterleavedCombine
+ * of 255-bit partial products at 128-bit offsets.  The product bits are the
+ * same for either width.  On the device a TGF(2^256) spectrum is two planes
+ * of TGF(2^128) halves, transformed alone with the same multipliers (Prop. 2:
+ * a subfield multiplier acts on each half).  w = 128 is never truncated.
+ *
+ * gf2x_set_word_bits: the width for products planned afterwards on ctx
+ * (gf2x_mul_dev, batches built afterwards, and requests submitted afterwards
+ * to a server), 64 or 128 (EINVAL otherwise).  The stage entry points
+ * (gf2x_forward_dev ... gf2x_basiscvt_dev) and gf2x_workspace_bytes always
+ * use w = 64.  gf2x_get_word_bits: the current width (0 for a NULL ctx). */
+int gf2x_set_word_bits(gf2x_ctx *ctx, int w);
+int gf2x_get_word_bits(gf2x_ctx *ctx);
+
 /* ------------------------------------------------------------------ serving
  * A request loop with continuous batching (not part of the paper: a serving
  * pattern around its product).  Requests are products whose operands and

@@ -104,6 +104,8 @@ def lib():
             "gf2x_autotune": (i32, [vp, i32, i32, i32, ctypes.POINTER(TuneRec)]),
             "gf2x_set_truncation": (i32, [vp, i32, i32]),
             "gf2x_eval_points": (u64, [vp, u64, u64]),
+            "gf2x_set_word_bits": (i32, [vp, i32]),
+            "gf2x_get_word_bits": (i32, [vp]),
             "gf2x_lookup_rate": (i32, [vp, ctypes.POINTER(ctypes.c_double)]),
             "gf2x_now_ns": (u64, []),
             "gf2x_server_create": (i32, [vp, ctypes.POINTER(ServerCfg), ctypes.POINTER(vp)]),
@@ -234,6 +236,13 @@ class Context:
 
     def eval_points(self, na_bits: int, nb_bits: int) -> int:
         return int(lib().gf2x_eval_points(self._h, na_bits, nb_bits))
+
+    # ---- word width of Split: 64 (TGF(2^128)) or 128 (TGF(2^256))
+    def set_word_bits(self, w: int):
+        self._check(lib().gf2x_set_word_bits(self._h, w), "gf2x_set_word_bits")
+
+    def word_bits(self) -> int:
+        return int(lib().gf2x_get_word_bits(self._h))
 
     # ---- FFT pass schedules
     def set_schedule(self, m: int, bottom_log: int, col_rows_log: int):

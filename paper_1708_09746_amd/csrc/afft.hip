@@ -77,7 +77,9 @@ static_assert(((1 << kFftTileLog) >> kFftRL) <= kThreads, "one group of kFftRL l
 static_assert(16 * ((1 << kFftTileLog) + kMuEntries) + 65536 + 4096 + 16 * 32 + 8 * 768 + 16 * kPhiNib + 64 <= 163840,
               "FFT kernels fit in LDS");
 
-template <bool PHI>
+// PHI: 0 the pass reads the spectrum, 1 64-bit words (kPhi64), 2 128-bit
+// words (kPhi128Lo / kPhi128Hi)
+template <int PHI>
 __global__ __launch_bounds__(kThreads) void k_fft(FftPass A, const uint8_t* g_mt, const uint32_t* g_lam,
                                                   const uint4* g_phi) {
     __shared__ __align__(16) uint8_t mt[65536];
@@ -91,7 +93,7 @@ __global__ __launch_bounds__(kThreads) void k_fft(FftPass A, const uint8_t* g_mt
     const int nt = kThreads;  // the launch uses kThreads threads per block
     copy_words(tid, nt, (uint32_t*)mt, (const uint32_t*)g_mt, 16384);
     copy_words(tid, nt, lam, g_lam, 1024);
-    if (PHI) build_phin(tid, nt, g_phi, phin);
+    if (PHI) copy_words(tid, nt, (uint32_t*)phin, (const uint32_t*)(g_phi + phin_off(A.phi_in)), 4 * phin_len(A.phi_in));
     __syncthreads();
     build_mt3(tid, nt, mt, mt3);
     fft_local_mu(tid, nt, A, mt, lam, mu);
@@ -100,13 +102,15 @@ __global__ __launch_bounds__(kThreads) void k_fft(FftPass A, const uint8_t* g_mt
     if (t >= ntiles) return;
     FftTileGeom G = fft_geom(A, xcd_tile(t, gridDim.x, ntiles));
     // prefetch registers: the words of a changeRepr pass (PHI), else elements
-    std::conditional_t<PHI, uint64_t, uint4> pre[kFftPrefetch];
+    std::conditional_t<PHI == 1, uint64_t, uint4> pre[kFftPrefetch];
     auto fetch = [&](const FftTileGeom& Gx) {
 #pragma unroll
         for (int j = 0; j < kFftPrefetch; ++j) {
             const uint32_t e = min(tid + j * kThreads, Gx.nel - 1);
-            if constexpr (PHI)
+            if constexpr (PHI == 1)
                 pre[j] = fft_word(A, Gx, e);
+            else if constexpr (PHI == 2)
+                pre[j] = fft_word128(A, Gx, e);
             else
                 pre[j] = fft_spec(A, Gx, e);
         }
@@ -114,8 +118,10 @@ __global__ __launch_bounds__(kThreads) void k_fft(FftPass A, const uint8_t* g_mt
     auto fill = [&]() {
 #pragma unroll
         for (int j = 0; j < kFftPrefetch; ++j) {
-            if constexpr (PHI)
+            if constexpr (PHI == 1)
                 tl[tid + j * kThreads] = phi_word(phin, pre[j]);
+            else if constexpr (PHI == 2)
+                tl[tid + j * kThreads] = phi_word128(phin, pre[j]);
             else
                 tl[tid + j * kThreads] = pre[j];
         }
@@ -153,8 +159,9 @@ __global__ __launch_bounds__(kThreads) void k_pmul(PmulOp P, const uint8_t* g_mt
 }
 
 __global__ __launch_bounds__(kThreads) void k_psi(PsiOp P, const uint4* g_psi) {
-    __shared__ uint4 tab[16 * 256];  // 64 KiB
-    copy_words(threadIdx.x, blockDim.x, tab, g_psi, 16 * 256);
+    __shared__ uint4 tab[kPsiTab64];  // 64 KiB
+    static_assert(kPsiTab128 <= kPsiTab64, "both Psi tables fit");
+    copy_words(threadIdx.x, blockDim.x, tab, g_psi + psi_tab_off(P), psi_tab_len(P));
     __syncthreads();
     const uint64_t nt = psi_tiles(P);
     for (uint64_t t = blockIdx.x; t < nt; t += gridDim.x) psi_tile(threadIdx.x, blockDim.x, t, P, tab);
@@ -185,7 +192,7 @@ __global__ __launch_bounds__(kThreads) void k_spine(SpineOp S, const uint8_t* g_
     __shared__ __align__(16) uint8_t mt[65536];
     __shared__ uint4 phin[kPhiNib];
     copy_words(threadIdx.x, blockDim.x, (uint32_t*)mt, (const uint32_t*)g_mt, 16384);
-    build_phin(threadIdx.x, blockDim.x, g_phi, phin);
+    copy_words(threadIdx.x, blockDim.x, (uint32_t*)phin, (const uint32_t*)g_phi, 4 * phin_len(kPhi64));
     __syncthreads();
     const uint64_t nt = spine_tiles(S);
     for (uint64_t t = blockIdx.x; t < nt; t += gridDim.x) spine_tile(threadIdx.x, blockDim.x, t, S, mt, phin);
@@ -260,17 +267,22 @@ __global__ __launch_bounds__(kThreads) void k_fft_multi(const FftPass* ops, cons
     const int tid = threadIdx.x, nt = blockDim.x;
     copy_words(tid, nt, (uint32_t*)mt, (const uint32_t*)g_mt, 16384);
     copy_words(tid, nt, lam, g_lam, 1024);
-    build_phin(tid, nt, g_phi, phin);
     __syncthreads();
     build_mt3(tid, nt, mt, mt3);
     __syncthreads();
     uint64_t g0, g1;
     block_chunk(total, g0, g1);
     int o = -1;
-    uint32_t cur_lo = ~0u, cur_hi = ~0u;
+    uint32_t cur_lo = ~0u, cur_hi = ~0u, cur_phi = kPhiNone;
     for (uint64_t g = g0; g < g1; ++g) {
         o = op_of_tile(prefix, nops, g, o);
         const FftPass A = ops[o];
+        if (A.phi_in != kPhiNone && A.phi_in != cur_phi) {
+            // the changeRepr table of this pass (every thread is past the last tile)
+            copy_words(tid, nt, (uint32_t*)phin, (const uint32_t*)(g_phi + phin_off(A.phi_in)), 4 * phin_len(A.phi_in));
+            __syncthreads();
+            cur_phi = A.phi_in;
+        }
         if (A.lo != cur_lo || A.hi != cur_hi) {
             // the local mu-sets depend only on the layer range of the pass
             fft_local_mu(tid, nt, A, mt, lam, mu);
@@ -300,7 +312,7 @@ __global__ __launch_bounds__(kThreads) void k_spine_multi(const SpineOp* ops, co
     __shared__ __align__(16) uint8_t mt[65536];
     __shared__ uint4 phin[kPhiNib];
     copy_words(threadIdx.x, blockDim.x, (uint32_t*)mt, (const uint32_t*)g_mt, 16384);
-    build_phin(threadIdx.x, blockDim.x, g_phi, phin);
+    copy_words(threadIdx.x, blockDim.x, (uint32_t*)phin, (const uint32_t*)g_phi, 4 * phin_len(kPhi64));
     __syncthreads();
     uint64_t g0, g1;
     block_chunk(total, g0, g1);
@@ -313,14 +325,18 @@ __global__ __launch_bounds__(kThreads) void k_spine_multi(const SpineOp* ops, co
 
 __global__ __launch_bounds__(kThreads) void k_psi_multi(const PsiOp* ops, const uint64_t* prefix, int nops,
                                                         uint64_t total, const uint4* g_psi) {
-    __shared__ uint4 tab[16 * 256];
-    copy_words(threadIdx.x, blockDim.x, tab, g_psi, 16 * 256);
-    __syncthreads();
+    __shared__ uint4 tab[kPsiTab64];
     uint64_t g0, g1;
     block_chunk(total, g0, g1);
-    int o = -1;
+    int o = -1, cur = -1;  // cur: the table in LDS (psi_tab_off), -1 none
     for (uint64_t g = g0; g < g1; ++g) {
         o = op_of_tile(prefix, nops, g, o);
+        if (psi_tab_off(ops[o]) != cur) {
+            __syncthreads();
+            cur = psi_tab_off(ops[o]);
+            copy_words(threadIdx.x, blockDim.x, tab, g_psi + cur, psi_tab_len(ops[o]));
+            __syncthreads();
+        }
         psi_tile(threadIdx.x, blockDim.x, g - prefix[o], ops[o], tab);
     }
 }
@@ -385,14 +401,21 @@ __global__ __launch_bounds__(kThreads) void k_persistent(PersistArgs P, const ui
     const int tid = threadIdx.x, nt = blockDim.x;
     copy_words(tid, nt, (uint32_t*)mt, (const uint32_t*)g_mt, 16384);
     copy_words(tid, nt, lam, g_lam, 1024);
-    build_phin(tid, nt, g_phi, phin);
     __syncthreads();
     build_mt3(tid, nt, mt, mt3);  // visible after the item loop's first barrier
     uint4* tl = work;
     uint4* mu = work + (1 << kFftTileLog);
-    // what `work` holds: 0 nothing reusable, 1 FFT local mu-sets of (cur_lo, cur_hi), 2 the Psi table
+    // what `work` holds: 0 nothing reusable, 1 FFT local mu-sets of (cur_lo,
+    // cur_hi), 2 the w = 64 Psi table, 3 the w = 128 one; phin holds the
+    // changeRepr table of mode cur_phi
     int held = 0;
-    uint32_t cur_lo = ~0u, cur_hi = ~0u;
+    uint32_t cur_lo = ~0u, cur_hi = ~0u, cur_phi = kPhiNone;
+    auto need_phin = [&](uint32_t mode) {
+        if (mode == kPhiNone || mode == cur_phi) return;
+        copy_words(tid, nt, (uint32_t*)phin, (const uint32_t*)(g_phi + phin_off(mode)), 4 * phin_len(mode));
+        __syncthreads();
+        cur_phi = mode;
+    };
     int o = -1;
     for (int r = 0; r < P.nranks; ++r) {
         const uint64_t end = P.rank_first[r + 1];
@@ -437,6 +460,7 @@ __global__ __launch_bounds__(kThreads) void k_persistent(PersistArgs P, const ui
                 }
                 case OpKind::Fft: {
                     const FftPass A = D.fft;
+                    need_phin(A.phi_in);
                     if (held != 1 || A.lo != cur_lo || A.hi != cur_hi) {
                         fft_local_mu(tid, nt, A, mt, lam, mu);
                         held = 1;
@@ -447,15 +471,20 @@ __global__ __launch_bounds__(kThreads) void k_persistent(PersistArgs P, const ui
                     break;
                 }
                 case OpKind::Pmul: pmul_tile(tid, nt, t, D.pmul, mt); break;
-                case OpKind::Psi:
-                    if (held != 2) {
-                        copy_words(tid, nt, work, g_psi, 16 * 256);
+                case OpKind::Psi: {
+                    const int want = D.psi.spech ? 3 : 2;
+                    if (held != want) {
+                        copy_words(tid, nt, work, g_psi + psi_tab_off(D.psi), psi_tab_len(D.psi));
                         __syncthreads();
-                        held = 2;
+                        held = want;
                     }
                     psi_tile(tid, nt, t, D.psi, work);
                     break;
-                case OpKind::Spine: spine_tile(tid, nt, t, D.spn, mt, phin); break;
+                }
+                case OpKind::Spine:
+                    need_phin(kPhi64);
+                    spine_tile(tid, nt, t, D.spn, mt, phin);
+                    break;
             }
         }
         // grid barrier between ranks.  After the workgroup barrier every store
@@ -550,6 +579,7 @@ struct gf2x_server {
         const uint64_t* b = nullptr;
         uint64_t* c = nullptr;
         uint64_t na = 0, nb = 0, tag = 0, t_submit = 0, t_admit = 0;
+        int w = 64;  // word width when submitted (its footprint is for that width)
         size_t off = 0, bytes = 0;
         std::vector<gf2x::Op> ops;
         std::vector<uint64_t> level_tiles;  // tiles of each dependency level
@@ -671,7 +701,7 @@ void op_traffic(const Op& op, gf2x_trace_rec& r) {
         case OpKind::Fft: {
             uint64_t n = (uint64_t)op.fft.ncosets << op.fft.log_m;
             r.elements = n;
-            r.bytes_read = op.fft.phi_in ? 8 * n : 16 * n;
+            r.bytes_read = op.fft.phi_in == kPhi64 ? 8 * n : 16 * n;  // words, 128-bit words or elements
             r.bytes_written = 16 * n;
             // LDS table reads per butterfly: 6 or 9 byte lookups per word (4 words) for
             // 16/32-bit multipliers; 3 table reads for 8-bit ones (their bytes are
@@ -681,18 +711,23 @@ void op_traffic(const Op& op, gf2x_trace_rec& r) {
                 r.lookups += (n / 2) * per_bfly[width_mode((int)op.fft.log_total - (int)i)];
             break;
         }
-        case OpKind::Pmul:
+        case OpKind::Pmul: {
+            const uint64_t eb = op.pmul.ah ? 32 : 16;  // bytes of a TGF(2^256) / TGF(2^128) point
             r.elements = op.pmul.n;
-            r.bytes_read = 32 * op.pmul.n;
-            r.bytes_written = 16 * op.pmul.n;
+            r.bytes_read = 2 * eb * op.pmul.n;
+            r.bytes_written = eb * op.pmul.n;
             break;
+        }
         case OpKind::BcClass:
             r.elements = op.bcc.nelem;
             r.bytes_read = r.bytes_written = op.bcc.nelem * (op.bcc.wide ? 16 : 8);
             break;
         case OpKind::Psi:
             r.elements = op.psi.nwords;
-            r.bytes_read = 16 * std::min(op.psi.nwords, op.psi.nspec);
+            if (op.psi.spech)
+                r.bytes_read = 32 * std::min((op.psi.nwords + 1) / 2, op.psi.nspec);
+            else
+                r.bytes_read = 16 * std::min(op.psi.nwords, op.psi.nspec);
             r.bytes_written = 8 * op.psi.nwords;
             break;
         case OpKind::Spine: {
@@ -748,11 +783,14 @@ int run_ops(gf2x_ctx* ctx, const std::vector<Op>& ops, hipStream_t st) {
                 break;
             }
             case OpKind::Fft:
-                if (op.fft.phi_in)
-                    GF2X_LAUNCH(k_fft<true>, dim3(grid_for(fft_tiles(op.fft), ncu)), op.fft,
+                if (op.fft.phi_in == kPhi64)
+                    GF2X_LAUNCH(k_fft<1>, dim3(grid_for(fft_tiles(op.fft), ncu)), op.fft,
+                                (const uint8_t*)ctx->d_mt, (const uint32_t*)ctx->d_lam, (const uint4*)ctx->d_phi);
+                else if (op.fft.phi_in != kPhiNone)
+                    GF2X_LAUNCH(k_fft<2>, dim3(grid_for(fft_tiles(op.fft), ncu)), op.fft,
                                 (const uint8_t*)ctx->d_mt, (const uint32_t*)ctx->d_lam, (const uint4*)ctx->d_phi);
                 else
-                    GF2X_LAUNCH(k_fft<false>, dim3(grid_for(fft_tiles(op.fft), ncu)), op.fft,
+                    GF2X_LAUNCH(k_fft<0>, dim3(grid_for(fft_tiles(op.fft), ncu)), op.fft,
                                 (const uint8_t*)ctx->d_mt, (const uint32_t*)ctx->d_lam, (const uint4*)ctx->d_phi);
                 break;
             case OpKind::Pmul:
@@ -1032,7 +1070,7 @@ void batch_free(gf2x_batch* B) {
 int check_jobs(gf2x_ctx* ctx, const gf2x_job* jobs, size_t njobs) {
     for (size_t j = 0; j < njobs; ++j) {
         const gf2x_job& J = jobs[j];
-        Sizes s = make_sizes(J.na_bits, J.nb_bits);
+        Sizes s = make_sizes(J.na_bits, J.nb_bits, ctx->params.word_bits);
         if (!s.out_words) continue;
         if (!J.a || !J.b || !J.c) return fail(ctx, GF2X_EINVAL, "NULL pointer in job " + std::to_string(j));
         if (s.m > 32) return fail(ctx, GF2X_ERANGE, "job " + std::to_string(j) + " too long");
@@ -1158,7 +1196,7 @@ void server_admit(gf2x_server* S) {
         if (off == Arena::npos) break;
         q.off = off;
         q.t_admit = now_ns();
-        const Sizes s = make_sizes(q.na, q.nb);
+        const Sizes s = make_sizes(q.na, q.nb, q.w);
         q.ops.clear();
         plan_mul(q.ops, ctx->pool, ctx->params, s, q.a, q.b, q.c, S->arena + off);
         q.levels = plan_levels(q.ops);
@@ -1414,9 +1452,12 @@ int gf2x_ctx_create(gf2x_ctx** out, int device) {
         delete ctx;
         return GF2X_EINVAL;
     }
-    std::vector<uint4> phi(8 * 256), psi(16 * 256);
-    for (int i = 0; i < 8 * 256; ++i) phi[i] = to_u4(R.phi[i]);
-    for (int i = 0; i < 16 * 256; ++i) psi[i] = to_u4(R.psi[i]);
+    // changeRepr: the nibble tables of every mode; changeRepr back: the w = 64
+    // byte tables, then the w = 128 nibble tables
+    std::vector<uint4> phi(kPhinTotal), psi(kPsiTab64 + kPsiTab128);
+    for (int i = 0; i < kPhinTotal; ++i) phi[i] = to_u4(R.phin[i]);
+    for (int i = 0; i < kPsiTab64; ++i) psi[i] = to_u4(R.psi[i]);
+    for (int i = 0; i < kPsiTab128; ++i) psi[kPsiTab64 + i] = to_u4(R.psin[i]);
 
     hipError_t e = hipSuccess;
     if (e == hipSuccess) e = hipMalloc((void**)&ctx->d_mt, 65536);
@@ -1488,7 +1529,7 @@ int gf2x_mul_dev(gf2x_ctx* ctx, const uint64_t* a, uint64_t na_bits, const uint6
                  uint64_t* c, void* stream) {
     if (check_ctx(ctx)) return GF2X_EINVAL;
     ctx->err.clear();
-    Sizes s = make_sizes(na_bits, nb_bits);
+    Sizes s = make_sizes(na_bits, nb_bits, ctx->params.word_bits);
     if (!s.out_words) return GF2X_OK;
     if (!a || !b || !c) return fail(ctx, GF2X_EINVAL, "NULL operand or product pointer");
     if (s.m > kMaxLog2N) return fail(ctx, GF2X_ERANGE, "transform length above 2^32");
@@ -1762,7 +1803,7 @@ int gf2x_server_submit(gf2x_server* S, const uint64_t* a, uint64_t na_bits, cons
     gf2x_ctx* ctx = S->ctx;
     ctx->err.clear();
     if (S->sticky) return fail(ctx, S->sticky, "server stopped after a device error");
-    const Sizes s = make_sizes(na_bits, nb_bits);
+    const Sizes s = make_sizes(na_bits, nb_bits, ctx->params.word_bits);
     const uint64_t t = now_ns();
     if (!s.out_words) {
         S->done.push_back(gf2x_done{tag, GF2X_OK, 0, t, t, t});
@@ -1779,6 +1820,7 @@ int gf2x_server_submit(gf2x_server* S, const uint64_t* a, uint64_t na_bits, cons
     r.c = c;
     r.na = na_bits;
     r.nb = nb_bits;
+    r.w = s.w;
     r.tag = tag;
     r.t_submit = t;
     r.bytes = workspace_for(s).bytes;
@@ -1923,9 +1965,18 @@ int gf2x_set_truncation(gf2x_ctx* ctx, int levels, int min_log2n) {
     return GF2X_OK;
 }
 
+int gf2x_set_word_bits(gf2x_ctx* ctx, int w) {
+    if (check_ctx(ctx)) return GF2X_EINVAL;
+    if (w != 64 && w != 128) return fail(ctx, GF2X_EINVAL, "word width must be 64 or 128");
+    ctx->params.word_bits = w;
+    return GF2X_OK;
+}
+
+int gf2x_get_word_bits(gf2x_ctx* ctx) { return ctx ? ctx->params.word_bits : 0; }
+
 uint64_t gf2x_eval_points(gf2x_ctx* ctx, uint64_t na_bits, uint64_t nb_bits) {
     if (!ctx) return 0;
-    const Sizes s = make_sizes(na_bits, nb_bits);
+    const Sizes s = make_sizes(na_bits, nb_bits, ctx->params.word_bits);
     if (!s.out_words) return 0;
     return eval_points(s, ctx->params);
 }

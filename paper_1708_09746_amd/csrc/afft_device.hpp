@@ -275,6 +275,21 @@ AFFT_HD uint4 gm128(const uint8_t* mt, const uint4& a, const uint4& b) {
     return r;
 }
 
+// TGF(2^256) = TGF(2^128)[x_8]/(x_8^2 + x_8 + c256), elements as two uint4
+// halves (lo, hi); c256 = x_1 ... x_7 = c128 x_7, so for e = e0 + e1 x_7 in
+// TGF(2^128):  e c256 = (e x_7) c128 = c128 c128 e1 + c128 (e0 + e1) x_7.
+AFFT_HD uint4 mulc256(const uint8_t* mt, const uint4& e) {  // e in TGF(2^128), times c256 (bit 127)
+    const uint64_t e0 = e.x | ((uint64_t)e.y << 32), e1 = e.z | ((uint64_t)e.w << 32);
+    const uint64_t lo = mulc128(mt, mulc128(mt, e1)), hi = mulc128(mt, e0 ^ e1);
+    return make_uint4((uint32_t)lo, (uint32_t)(lo >> 32), (uint32_t)hi, (uint32_t)(hi >> 32));
+}
+AFFT_HD void gm256(const uint8_t* mt, const uint4& a0, const uint4& a1, const uint4& b0, const uint4& b1, uint4& c0,
+                   uint4& c1) {
+    const uint4 t = gm128(mt, a1, b1), p0 = gm128(mt, a0, b0), p1 = gm128(mt, xor4(a0, a1), xor4(b0, b1));
+    c0 = xor4(p0, mulc256(mt, t));
+    c1 = xor4(p1, p0);
+}
+
 // ------------------------------------------------------- table loaders
 
 template <typename W>

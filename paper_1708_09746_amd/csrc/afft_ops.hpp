@@ -303,8 +303,13 @@ AFFT_HD void bc_class_tile(int tid, int nt, uint64_t tile, const BcClassOp& C, T
 // uses lambda = s_i(s̄) = XOR of lam[i][t] over the set bits t of s.
 // Butterfly (Alg. 1):
 //   forward: u += lambda v; v += u        inverse: v += u; u += lambda v.
+// phi_in: 0 the pass reads the spectrum; 1 it reads 64-bit words and applies
+// changeRepr into TGF(2^128); 2 / 3 it reads 128-bit words and keeps the low /
+// high TGF(2^128) half of their changeRepr into TGF(2^256) (w = 128: the
+// spectrum is two planes of halves, each transformed alone, Prop. 2).
+enum : uint32_t { kPhiNone = 0, kPhi64 = 1, kPhi128Lo = 2, kPhi128Hi = 3 };
 struct FftPass {
-    const void* src;  // phi_in: 64-bit words (2^log_m of them); else == dst
+    const void* src;  // phi_in: the words (2^log_m of them); else == dst
     uint4* dst;       // the whole transform; blocks are at (coset0 + c) << log_m
     uint32_t log_m, lo, hi, log_tc;
     uint32_t ncosets, coset0, inverse, phi_in;
@@ -317,22 +322,27 @@ AFFT_HD uint64_t fft_tiles(const FftPass& A) {
 
 AFFT_HD int width_mode(int w) { return w <= 8 ? 0 : (w <= 16 ? 1 : 2); }
 
-// changeRepr into the tower (Sec. 4.3), M4R over the 16 nibbles of the word:
-// phin[16 k + v] = Phi(v << 4k), 4 KiB, small enough to sit in LDS beside the
-// GF(256) table (the byte-indexed tables, 32 KiB, are not).  build_phin derives
-// it from the byte-indexed tables phi_tab[256 j + y] = Phi(y << 8j) by
-// linearity.
-constexpr int kPhiNib = 256;
-AFFT_HD void build_phin(int tid, int nt, const uint4* phi_tab, uint4* phin) {
-    for (int i = tid; i < kPhiNib; i += nt) {
-        const int k = i >> 4, v = i & 15;
-        phin[i] = phi_tab[(k >> 1) * 256 + (v << (4 * (k & 1)))];
-    }
-}
+// changeRepr into the tower (Sec. 4.3) by M4R over the nibbles of a word:
+// the table of a mode holds Phi(v << 4k) (or its half) at 16 k + v.  The
+// device table (host-built) is the w = 64 table (16 nibbles, 256 entries)
+// followed by the low and high halves of the w = 128 table (32 nibbles, 512
+// entries each); a kernel keeps the one slice its pass needs in LDS (at most
+// kPhiNib entries, 8 KiB).
+constexpr int kPhiNib = 512;
+constexpr int kPhinTotal = 256 + 2 * 512;
+AFFT_HD int phin_off(uint32_t mode) { return mode <= kPhi64 ? 0 : 256 + 512 * (int)(mode - kPhi128Lo); }
+AFFT_HD int phin_len(uint32_t mode) { return mode <= kPhi64 ? 256 : 512; }
 AFFT_HD uint4 phi_word(const uint4* phin, uint64_t w) {
     uint4 r = make_uint4(0, 0, 0, 0);
 #pragma unroll
     for (int k = 0; k < 16; ++k) r = r ^ phin[k * 16 + ((w >> (4 * k)) & 15u)];
+    return r;
+}
+AFFT_HD uint4 phi_word128(const uint4* phin, const uint4& w) {
+    const uint32_t ws[4] = {w.x, w.y, w.z, w.w};
+    uint4 r = make_uint4(0, 0, 0, 0);
+#pragma unroll
+    for (int k = 0; k < 32; ++k) r = r ^ phin[k * 16 + ((ws[k >> 3] >> (4 * (k & 7))) & 15u)];
     return r;
 }
 
@@ -472,16 +482,22 @@ AFFT_HD uint64_t fft_elem_index(const FftPass& A, const FftTileGeom& G, uint32_t
     return G.base_p | ((uint64_t)(e >> A.log_tc) << A.lo) | (e & ((1u << A.log_tc) - 1));
 }
 
-// Tile element e: in a pass that applies changeRepr, Phi of its converted
-// word (fft_word), else the element of the spectrum (fft_spec).
+// Tile element e: in a pass that applies changeRepr, (the kept half of) Phi
+// of its converted word (fft_word, fft_word128), else the element of the
+// spectrum (fft_spec).  phin is the table of the pass's mode.
 AFFT_HD uint64_t fft_word(const FftPass& A, const FftTileGeom& G, uint32_t e) {
     return ((const uint64_t*)A.src)[fft_elem_index(A, G, e)];
+}
+AFFT_HD uint4 fft_word128(const FftPass& A, const FftTileGeom& G, uint32_t e) {
+    return ((const uint4*)A.src)[fft_elem_index(A, G, e)];
 }
 AFFT_HD uint4 fft_spec(const FftPass& A, const FftTileGeom& G, uint32_t e) {
     return A.dst[G.gbase | fft_elem_index(A, G, e)];
 }
 AFFT_HD uint4 fft_load(const FftPass& A, const uint4* phin, const FftTileGeom& G, uint32_t e) {
-    return A.phi_in ? phi_word(phin, fft_word(A, G, e)) : fft_spec(A, G, e);
+    if (A.phi_in == kPhi64) return phi_word(phin, fft_word(A, G, e));
+    if (A.phi_in >= kPhi128Lo) return phi_word128(phin, fft_word128(A, G, e));
+    return fft_spec(A, G, e);
 }
 
 // Layers [lo, hi) of one tile already in LDS (tl); mu holds the pass's local
@@ -597,12 +613,17 @@ AFFT_HD void spine_tile(int tid, int nt, uint64_t tile, const SpineOp& S, const 
 // ------------------------------------------------------------- pointmul
 // c_j = a_j b_j for j < n; c_j = 0 for n <= j < n_out (the coefficients a
 // truncated inverse starts from).
+// w = 128 (ah != nullptr): the points are TGF(2^256) elements held as two
+// planes (a, ah), (b, bh) -> (c, ch) of low and high halves.
 struct PmulOp {
     const uint4* a;
     const uint4* b;
     uint4* c;
     uint64_t n;
     uint64_t n_out;
+    const uint4* ah;
+    const uint4* bh;
+    uint4* ch;
 };
 
 AFFT_HD uint64_t pmul_tiles(const PmulOp& P) { return (P.n_out + kPmulTile - 1) / kPmulTile; }
@@ -611,21 +632,50 @@ AFFT_HD void pmul_tile(int tid, int nt, uint64_t tile, const PmulOp& P, const ui
     for (int e = tid; e < kPmulTile; e += nt) {
         uint64_t j = tile * kPmulTile + e;
         if (j >= P.n_out) break;
-        P.c[j] = j < P.n ? gm128(mt, P.a[j], P.b[j]) : make_uint4(0, 0, 0, 0);
+        if (P.ah) {
+            uint4 c0 = make_uint4(0, 0, 0, 0), c1 = c0;
+            if (j < P.n) gm256(mt, P.a[j], P.ah[j], P.b[j], P.bh[j], c0, c1);
+            P.c[j] = c0;
+            P.ch[j] = c1;
+        } else {
+            P.c[j] = j < P.n ? gm128(mt, P.a[j], P.b[j]) : make_uint4(0, 0, 0, 0);
+        }
     }
 }
 
 // --------------------------------------- changeRepr back + InterleavedCombine
-// out[k] = lo64(Psi c_k) + hi64(Psi c_{k-1}); c_k = 0 for k >= nspec.
+// w = 64:  out[k] = lo64(Psi c_k) + hi64(Psi c_{k-1}); c_k = 0 for k >= nspec.
+// w = 128 (spech != nullptr, c_k = (spec[k], spech[k]) in TGF(2^256)): the
+// 128-bit output word K (64-bit words 2K, 2K + 1) is
+// lo128(Psi c_K) + hi128(Psi c_{K-1}).
+// The device table of Psi: the w = 64 byte-indexed table (16 x 256 entries)
+// followed by the w = 128 nibble-indexed one, low half then high half (each
+// 64 nibbles x 16 entries).
 struct PsiOp {
     const uint4* spec;
     uint64_t nspec;
     uint64_t* out;
     uint64_t nwords;
     uint64_t nbits;
+    const uint4* spech;
 };
+constexpr int kPsiTab64 = 16 * 256, kPsiTab128 = 2 * 64 * 16;
+AFFT_HD int psi_tab_off(const PsiOp& P) { return P.spech ? kPsiTab64 : 0; }
+AFFT_HD int psi_tab_len(const PsiOp& P) { return P.spech ? kPsiTab128 : kPsiTab64; }
 
-AFFT_HD uint64_t psi_tiles(const PsiOp& P) { return (P.nwords + kPsiTile - 1) / kPsiTile; }
+// 64-bit output words per tile: one per thread (w = 64) or two (w = 128)
+AFFT_HD uint64_t psi_tile_words(const PsiOp& P) { return P.spech ? 2 * kPsiTile : kPsiTile; }
+AFFT_HD uint64_t psi_tiles(const PsiOp& P) { return (P.nwords + psi_tile_words(P) - 1) / psi_tile_words(P); }
+
+// One half of Psi of a TGF(2^256) element (c0, c1) by M4R over its 64
+// nibbles; tab: that half's table.
+AFFT_HD uint4 psi_half(const uint4* tab, const uint4& c0, const uint4& c1) {
+    const uint32_t w[8] = {c0.x, c0.y, c0.z, c0.w, c1.x, c1.y, c1.z, c1.w};
+    uint4 r = make_uint4(0, 0, 0, 0);
+#pragma unroll
+    for (int k = 0; k < 64; ++k) r = r ^ tab[k * 16 + ((w[k >> 3] >> (4 * (k & 7))) & 15u)];
+    return r;
+}
 
 AFFT_HD uint4 psi_elem(const uint4* psi_tab, const uint4& e) {
     uint4 r = make_uint4(0, 0, 0, 0);
@@ -635,7 +685,26 @@ AFFT_HD uint4 psi_elem(const uint4* psi_tab, const uint4& e) {
     return r;
 }
 
+// psi_tab: the table of the op's width (psi_tab_off into the device table)
 AFFT_HD void psi_tile(int tid, int nt, uint64_t tile, const PsiOp& P, const uint4* psi_tab) {
+    if (P.spech) {
+        for (int e = tid; e < kPsiTile; e += nt) {
+            const uint64_t K = tile * kPsiTile + e, k0 = 2 * K;
+            if (k0 >= P.nwords) break;
+            uint4 r = make_uint4(0, 0, 0, 0);
+            if (K < P.nspec) r = r ^ psi_half(psi_tab, P.spec[K], P.spech[K]);
+            if (K >= 1 && K - 1 < P.nspec) r = r ^ psi_half(psi_tab + 64 * 16, P.spec[K - 1], P.spech[K - 1]);
+            uint64_t w0 = (uint64_t)r.x | ((uint64_t)r.y << 32), w1 = (uint64_t)r.z | ((uint64_t)r.w << 32);
+            const uint64_t tail = P.nbits % 64 ? ~0ull >> (64 - P.nbits % 64) : ~0ull;
+            if (k0 == P.nwords - 1) w0 &= tail;
+            P.out[k0] = w0;
+            if (k0 + 1 < P.nwords) {
+                if (k0 + 1 == P.nwords - 1) w1 &= tail;
+                P.out[k0 + 1] = w1;
+            }
+        }
+        return;
+    }
     for (int e = tid; e < kPsiTile; e += nt) {
         uint64_t k = tile * kPsiTile + e;
         if (k >= P.nwords) break;

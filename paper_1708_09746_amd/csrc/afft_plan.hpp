@@ -31,24 +31,31 @@ inline int ceil_log2(uint64_t n) {
 
 // Sizes of one product (readings: operands converted at their own power-of-two
 // length; N = max(2, 2^ceil(log2(n_a + n_b - 1))) evaluation points).
+// Sizes of one product with Split into w-bit words (w = 64: TGF(2^128);
+// w = 128: TGF(2^256), Alg. 5).
 struct Sizes {
     uint64_t na_bits = 0, nb_bits = 0;
-    uint64_t n_a = 0, n_b = 0;    // words
-    int m_a = 0, m_b = 0, m = 0;  // log2 of n'_a, n'_b, N
+    uint64_t n_a = 0, n_b = 0;    // 64-bit words of the operands
+    int w = 64;                   // word width of Split
+    uint64_t k_a = 0, k_b = 0;    // w-bit words of the operands
+    int m_a = 0, m_b = 0, m = 0;  // log2 of k'_a, k'_b (converted lengths), N
     uint64_t out_words = 0;       // ceil((na + nb - 1) / 64)
     uint64_t nc_bits = 0;         // na + nb - 1
 };
 
-inline Sizes make_sizes(uint64_t na_bits, uint64_t nb_bits) {
+inline Sizes make_sizes(uint64_t na_bits, uint64_t nb_bits, int w = 64) {
     Sizes s;
     s.na_bits = na_bits;
     s.nb_bits = nb_bits;
+    s.w = w;
     if (!na_bits || !nb_bits) return s;
     s.n_a = (na_bits + 63) / 64;
     s.n_b = (nb_bits + 63) / 64;
-    s.m_a = ceil_log2(s.n_a);
-    s.m_b = ceil_log2(s.n_b);
-    s.m = ceil_log2(s.n_a + s.n_b - 1);
+    s.k_a = (na_bits + w - 1) / w;
+    s.k_b = (nb_bits + w - 1) / w;
+    s.m_a = ceil_log2(s.k_a);
+    s.m_b = ceil_log2(s.k_b);
+    s.m = ceil_log2(s.k_a + s.k_b - 1);
     if (s.m < 1) s.m = 1;
     s.nc_bits = na_bits + nb_bits - 1;
     s.out_words = (s.nc_bits + 63) / 64;
@@ -115,6 +122,8 @@ struct PlanParams {
     static constexpr int kTruncMinLog = 6;
     int trunc_levels = 3;
     int trunc_min_log = 22;
+    // word width of Split: 64 (TGF(2^128)) or 128 (TGF(2^256), never truncated)
+    int word_bits = 64;
     const uint32_t* lam = nullptr;
     const uint8_t* mt = nullptr;
     PlanParams() {
@@ -252,8 +261,9 @@ inline uint32_t fft_log_tc(int lo, int hi) {
 // length 2^log_m of a transform of length 2^log_total at `spec`: forward
 // (top layers first; the first pass reads the 2^log_m converted words at
 // `words` and applies changeRepr, unless words is null) or inverse.
-inline void emit_fft_block(std::vector<Op>& ops, const PlanParams& pp, const uint64_t* words, uint4* spec, int log_m,
-                           uint32_t coset0, uint32_t ncosets, int log_total, bool inverse) {
+inline void emit_fft_block(std::vector<Op>& ops, const PlanParams& pp, const void* words, uint4* spec, int log_m,
+                           uint32_t coset0, uint32_t ncosets, int log_total, bool inverse,
+                           uint32_t phi_mode = kPhi64) {
     auto ranges = fft_pass_ranges(log_m, pp);
     const size_t nr = ranges.size();
     for (size_t q = 0; q < nr; ++q) {
@@ -263,7 +273,7 @@ inline void emit_fft_block(std::vector<Op>& ops, const PlanParams& pp, const uin
         Op op{};
         op.kind = OpKind::Fft;
         FftPass& A = op.fft;
-        A.phi_in = phi ? 1u : 0u;
+        A.phi_in = phi ? phi_mode : kPhiNone;
         A.src = A.phi_in ? (const void*)words : (const void*)spec;
         A.dst = spec;
         A.log_m = (uint32_t)log_m;
@@ -293,7 +303,7 @@ inline void emit_fft_inverse(std::vector<Op>& ops, const PlanParams& pp, uint4* 
 // Points evaluated for a product of sizes s (see PlanParams).
 inline uint64_t eval_points(const Sizes& s, const PlanParams& pp) {
     const uint64_t N = 1ull << s.m;
-    if (pp.trunc_levels <= 0 || s.m < pp.trunc_min_log || !pp.lam || !pp.mt) return N;
+    if (s.w != 64 || pp.trunc_levels <= 0 || s.m < pp.trunc_min_log || !pp.lam || !pp.mt) return N;
     const int g = std::max(s.m - pp.trunc_levels, PlanParams::kTruncMinLog);
     if (g >= s.m) return N;
     const uint64_t nc = s.n_a + s.n_b - 1;
@@ -406,17 +416,19 @@ struct Workspace {
 
 inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
+// (w = 128: words of 16 bytes, and each spectrum is two planes of N uint4)
 inline Workspace workspace_for(const Sizes& s) {
     Workspace w{};
+    const size_t wb = (size_t)s.w / 8, sb = 16 * ((size_t)s.w / 64);
     size_t o = 0;
     w.off_wa = o;
-    o = align256(o + (8ull << s.m_a));
+    o = align256(o + (wb << s.m_a));
     w.off_wb = o;
-    o = align256(o + (8ull << s.m_b));
+    o = align256(o + (wb << s.m_b));
     w.off_sa = o;
-    o = align256(o + (16ull << s.m));
+    o = align256(o + (sb << s.m));
     w.off_sb = o;
-    o = align256(o + (16ull << s.m));
+    o = align256(o + (sb << s.m));
     w.bytes = o;
     return w;
 }
@@ -456,9 +468,72 @@ inline void emit_inverse(std::vector<Op>& ops, const LayerPool& pool, const Plan
     emit_psi(ops, spec, 1ull << m, out, nc_bits);
 }
 
+// w = 128: the product over TGF(2^256).  A spectrum is two planes of N
+// uint4 (the low and high TGF(2^128) halves of every point); multiplying by a
+// subfield element acts on each half alone (Prop. 2), so each plane runs the
+// w = 64 FFT passes with the same multipliers, the changeRepr pass keeping
+// its half of the image of each 128-bit word.  BasisCvt and its inverse act
+// on whole coefficients, so on 128-bit words, and on each plane alone.  Ops
+// of the two planes are independent and share levels.
+inline void plan_mul128(std::vector<Op>& ops, const LayerPool& pool, const PlanParams& pp, const Sizes& s,
+                        const uint64_t* a, const uint64_t* b, uint64_t* c, char* ws) {
+    const Workspace w = workspace_for(s);
+    const uint64_t N = 1ull << s.m;
+    uint4* wa = (uint4*)(ws + w.off_wa);
+    uint4* wb = (uint4*)(ws + w.off_wb);
+    uint4* sa = (uint4*)(ws + w.off_sa);
+    uint4* sb = (uint4*)(ws + w.off_sb);
+    auto forward = [&](const uint64_t* src, uint64_t nbits, uint4* words, int m_op, uint4* spec) {
+        std::vector<Op> pre, pl[2];
+        emit_pack(pre, src, nbits, (uint64_t*)words, 2ull << m_op);
+        emit_bc(pre, pool, words, 1, m_op, 0);
+        for (int h = 0; h < 2; ++h)
+            emit_fft_block(pl[h], pp, words, spec + h * N, m_op, 0, 1u << (s.m - m_op), s.m, false,
+                           h ? kPhi128Hi : kPhi128Lo);
+        uint32_t l = 0;
+        for (Op op : pre) {
+            op.level = l++;
+            ops.push_back(op);
+        }
+        for (size_t q = 0; q < pl[0].size(); ++q)
+            for (int h = 0; h < 2; ++h) {
+                Op op = pl[h][q];
+                op.level = l + (uint32_t)q;
+                ops.push_back(op);
+            }
+        return l + (uint32_t)pl[0].size();
+    };
+    const uint32_t lp = std::max(forward(a, s.na_bits, wa, s.m_a, sa), forward(b, s.nb_bits, wb, s.m_b, sb));
+    Op pm{};
+    pm.kind = OpKind::Pmul;
+    pm.pmul = PmulOp{sa, sb, sb, N, N, sa + N, sb + N, sb + N};
+    pm.level = lp;
+    ops.push_back(pm);
+    std::vector<Op> inv[2];
+    for (int h = 0; h < 2; ++h) {
+        emit_fft_inverse(inv[h], pp, sb + h * N, s.m);
+        emit_bc(inv[h], pool, sb + h * N, 1, s.m, 1);
+    }
+    for (size_t q = 0; q < inv[0].size(); ++q)
+        for (int h = 0; h < 2; ++h) {
+            Op op = inv[h][q];
+            op.level = lp + 1 + (uint32_t)q;
+            ops.push_back(op);
+        }
+    Op ps{};
+    ps.kind = OpKind::Psi;
+    ps.psi = PsiOp{sb, N, c, s.out_words, s.nc_bits, sb + N};
+    ps.level = lp + 1 + (uint32_t)inv[0].size();
+    ops.push_back(ps);
+}
+
 // The whole product c = a * b with the workspace at `ws`.
 inline void plan_mul(std::vector<Op>& ops, const LayerPool& pool, const PlanParams& pp, const Sizes& s, const uint64_t* a,
                      const uint64_t* b, uint64_t* c, char* ws) {
+    if (s.w == 128) {
+        plan_mul128(ops, pool, pp, s, a, b, c, ws);
+        return;
+    }
     Workspace w = workspace_for(s);
     uint64_t* wa = (uint64_t*)(ws + w.off_wa);
     uint64_t* wb = (uint64_t*)(ws + w.off_wb);
@@ -583,14 +658,14 @@ inline void plan_batch(BatchPlan& P, const LayerPool& pool, const PlanParams& pp
     P.ws_off.assign(njobs, 0);
     size_t total = 0;
     for (size_t j = 0; j < njobs; ++j) {
-        Sizes s = make_sizes(jobs[j].na_bits, jobs[j].nb_bits);
+        Sizes s = make_sizes(jobs[j].na_bits, jobs[j].nb_bits, pp.word_bits);
         P.ws_off[j] = total;
         if (s.out_words) total += workspace_for(s).bytes;
     }
     P.ws_bytes = total;
     if (!ws) return;
     for (size_t j = 0; j < njobs; ++j) {
-        Sizes s = make_sizes(jobs[j].na_bits, jobs[j].nb_bits);
+        Sizes s = make_sizes(jobs[j].na_bits, jobs[j].nb_bits, pp.word_bits);
         if (!s.out_words) continue;
         const size_t first = P.ops.size();
         plan_mul(P.ops, pool, pp, s, jobs[j].a, jobs[j].b, jobs[j].c, ws + P.ws_off[j]);

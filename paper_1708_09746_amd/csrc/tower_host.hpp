@@ -98,6 +98,10 @@ inline void build_lambda(const HostTower& T, uint32_t lam[32][32]) {
 // theta = x7 = v_64, which generates TGF(2^128) since it lies outside
 // TGF(2^64).  Products of two images are images of the carry-less product
 // (degree < 127 < 128), so the inverse map recovers 127-bit partial products.
+//
+// w = 128: a 128-bit block maps into TGF(2^256) = TGF(2^128)[x8]/(x8^2 + x8 +
+// c256), c256 = x1 ... x7 (bit 127), at theta = x8, which lies outside
+// TGF(2^128) and so generates TGF(2^256); elements are (lo, hi) halves.
 struct ReprTables {
     // M4R-8 tables: phi[k][b] = image of byte b placed at byte k (k < 8),
     // psi[k][b] = preimage of byte b placed at byte k of the element (k < 16)
@@ -105,8 +109,82 @@ struct ReprTables {
     std::vector<u128> psi;  // 16 * 256
     u128 theta_pow[128];
     u128 psi_col[128];  // psi of the basis element v_j, as a 128-bit polynomial
+    // M4R-4 tables.  phin: w = 64, phin[16 k + v] = Phi(v << 4k) (k < 16),
+    // then w = 128, the low halves of Phi(v << 4k) (k < 32) at 256 + 16 k + v
+    // and the high halves at 768 + 16 k + v.  psin: w = 128, the low halves
+    // of Psi(v << 4k) (k < 64: nibble k of the element (lo, hi)) at 16 k + v,
+    // the high halves at 1024 + 16 k + v.
+    std::vector<u128> phin;  // 256 + 2 * 512
+    std::vector<u128> psin;  // 2 * 1024
     bool ok = false;
 };
+
+// TGF(2^256) element as (lo, hi)
+struct U256 {
+    u128 lo, hi;
+};
+inline bool bit256(const U256& v, int b) { return b < 128 ? (v.lo >> b) & 1 : (v.hi >> (b - 128)) & 1; }
+inline void xor256(U256& a, const U256& b) {
+    a.lo ^= b.lo;
+    a.hi ^= b.hi;
+}
+
+// w = 128 tables (see ReprTables); false if the powers of theta were dependent
+inline bool build_repr256(const HostTower& T, ReprTables& R) {
+    const u128 c256 = (u128)1 << 127;
+    std::vector<U256> pw(256);
+    pw[0] = U256{1, 0};
+    for (int j = 1; j < 256; ++j) {
+        // (lo + hi x8) x8 = hi c256 + (lo + hi) x8
+        const U256& p = pw[j - 1];
+        pw[j] = U256{T.mul128(p.hi, c256), p.lo ^ p.hi};
+    }
+    // invert the matrix with columns theta^j (Gauss-Jordan, fully reduced)
+    std::vector<U256> val, comb;
+    std::vector<int> piv;
+    for (int j = 0; j < 256; ++j) {
+        U256 v = pw[j], c{0, 0};
+        if (j < 128) c.lo = (u128)1 << j; else c.hi = (u128)1 << (j - 128);
+        for (size_t r = 0; r < piv.size(); ++r)
+            if (bit256(v, piv[r])) { xor256(v, val[r]); xor256(c, comb[r]); }
+        int pb = 255;
+        while (pb >= 0 && !bit256(v, pb)) --pb;
+        if (pb < 0) return false;
+        for (size_t r = 0; r < piv.size(); ++r)
+            if (bit256(val[r], pb)) { xor256(val[r], v); xor256(comb[r], c); }
+        val.push_back(v);
+        comb.push_back(c);
+        piv.push_back(pb);
+    }
+    std::vector<U256> psi_col(256);
+    for (int r = 0; r < 256; ++r) psi_col[piv[r]] = comb[r];
+    R.phin.resize(256 + 2 * 512, 0);
+    for (int k = 0; k < 16; ++k)
+        for (int v = 0; v < 16; ++v) {
+            u128 acc = 0;
+            for (int t = 0; t < 4; ++t)
+                if ((v >> t) & 1) acc ^= R.theta_pow[4 * k + t];
+            R.phin[16 * k + v] = acc;
+        }
+    for (int k = 0; k < 32; ++k)
+        for (int v = 0; v < 16; ++v) {
+            U256 acc{0, 0};
+            for (int t = 0; t < 4; ++t)
+                if ((v >> t) & 1) xor256(acc, pw[4 * k + t]);
+            R.phin[256 + 16 * k + v] = acc.lo;
+            R.phin[768 + 16 * k + v] = acc.hi;
+        }
+    R.psin.assign(2 * 1024, 0);
+    for (int k = 0; k < 64; ++k)
+        for (int v = 0; v < 16; ++v) {
+            U256 acc{0, 0};
+            for (int t = 0; t < 4; ++t)
+                if ((v >> t) & 1) xor256(acc, psi_col[4 * k + t]);
+            R.psin[16 * k + v] = acc.lo;
+            R.psin[1024 + 16 * k + v] = acc.hi;
+        }
+    return true;
+}
 
 inline ReprTables build_repr(const HostTower& T) {
     ReprTables R;
@@ -146,7 +224,7 @@ inline ReprTables build_repr(const HostTower& T) {
                 if ((b >> t) & 1) acc ^= R.psi_col[8 * k + t];
             R.psi[k * 256 + b] = acc;
         }
-    R.ok = true;
+    R.ok = build_repr256(T, R);
     return R;
 }
 

@@ -22,7 +22,7 @@ namespace {
 
 std::vector<uint8_t> MT(65536);
 std::vector<uint32_t> LAM(1024);
-std::vector<uint4> PHI(2048), PHIN(kPhiNib), PSI(4096);
+std::vector<uint4> PHIN(kPhinTotal), PSI(kPsiTab64 + kPsiTab128);
 std::vector<uint2> MT3(768);
 LayerPool POOL;
 PlanParams PP;
@@ -39,9 +39,9 @@ bool init() {
     memcpy(LAM.data(), lam, sizeof(lam));
     ReprTables R = build_repr(T);
     if (!R.ok) return false;
-    for (int i = 0; i < 2048; ++i) PHI[i] = to_u4(R.phi[i]);
-    for (int i = 0; i < 4096; ++i) PSI[i] = to_u4(R.psi[i]);
-    build_phin(0, 1, PHI.data(), PHIN.data());
+    for (int i = 0; i < kPhinTotal; ++i) PHIN[i] = to_u4(R.phin[i]);
+    for (int i = 0; i < kPsiTab64; ++i) PSI[i] = to_u4(R.psi[i]);
+    for (int i = 0; i < kPsiTab128; ++i) PSI[kPsiTab64 + i] = to_u4(R.psin[i]);
     PP.lam = LAM.data();
     PP.mt = MT.data();
     build_mt3(0, 1, MT.data(), MT3.data());
@@ -72,11 +72,12 @@ void run_tile(const Op& op, uint64_t t, Scratch& S) {
             break;
         case OpKind::Fft:
             fft_local_mu(0, 1, op.fft, MT.data(), LAM.data(), S.mu.data());
-            fft_tile<kFftRL>(0, 1, t, op.fft, MT.data(), MT3.data(), LAM.data(), PHIN.data(), S.tl.data(), S.mu.data(),
+            fft_tile<kFftRL>(0, 1, t, op.fft, MT.data(), MT3.data(), LAM.data(), PHIN.data() + phin_off(op.fft.phi_in),
+                             S.tl.data(), S.mu.data(),
                              S.mut.data());
             break;
         case OpKind::Pmul: pmul_tile(0, 1, t, op.pmul, MT.data()); break;
-        case OpKind::Psi: psi_tile(0, 1, t, op.psi, PSI.data()); break;
+        case OpKind::Psi: psi_tile(0, 1, t, op.psi, PSI.data() + psi_tab_off(op.psi)); break;
         case OpKind::BcClass:
             if (op.bcc.wide)
                 bc_class_tile<uint4>(0, 1, t, op.bcc, S.l128.data());
@@ -103,7 +104,7 @@ std::vector<uint64_t> rand_words(std::mt19937_64& g, uint64_t nbits) {
 
 // one product through the planner, compared with the oracle
 bool check_product(std::mt19937_64& g, uint64_t na, uint64_t nb) {
-    Sizes s = make_sizes(na, nb);
+    Sizes s = make_sizes(na, nb, PP.word_bits);
     Workspace w = workspace_for(s);
     std::vector<char> ws(w.bytes, 0x5a);  // garbage: the plan must not read what it did not write
     auto a = rand_words(g, na), b = rand_words(g, nb);
@@ -114,8 +115,8 @@ bool check_product(std::mt19937_64& g, uint64_t na, uint64_t nb) {
     oracle_mul(a.data(), na, b.data(), nb, r.data(), 4);
     const bool ok = memcmp(c.data(), r.data(), 8 * s.out_words) == 0 && c[s.out_words] == 0xdead;
     if (!ok)
-        printf("MISMATCH %llu x %llu bits (N = 2^%d, M = %llu, truncation %d)\n", (unsigned long long)na,
-               (unsigned long long)nb, s.m, (unsigned long long)eval_points(s, PP), PP.trunc_levels);
+        printf("MISMATCH %llu x %llu bits (w = %d, N = 2^%d, M = %llu, truncation %d)\n", (unsigned long long)na,
+               (unsigned long long)nb, s.w, s.m, (unsigned long long)eval_points(s, PP), PP.trunc_levels);
     return ok;
 }
 
@@ -264,6 +265,17 @@ int main(int argc, char** argv) {
         PP.trunc_levels = 3;
         bad += !check_batch(g, 40);
         PP.trunc_min_log = 22;
+    }
+    if (what == "all" || what == "w128") {
+        // Split into 128-bit words, products over TGF(2^256)
+        PP.word_bits = 128;
+        const uint64_t fixed[][2] = {{1, 1},     {128, 128}, {129, 128}, {64, 64},      {1, 700},
+                                     {1000, 999}, {128 * 33, 128 * 31},  {5000, 70},   {1 << 16, 1 << 16},
+                                     {100000, 3}, {1 << 20, 1 << 20},    {1 << 21, 1 << 19}};
+        for (auto& p : fixed) bad += !check_product(g, p[0], p[1]);
+        for (int i = 0; i < 40; ++i) bad += !check_product(g, 1 + g() % (1ull << (1 + g() % 18)), 1 + g() % (1ull << (1 + g() % 18)));
+        bad += !check_batch(g, 30);
+        PP.word_bits = 64;
     }
     if (what == "all" || what == "xcd") bad += !check_xcd_order(g);
     if (what == "all" || what == "basiscvt") {
