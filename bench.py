@@ -338,6 +338,42 @@ def bench_serving(ctx, nreq=10000, fracs=(0.1, 0.25, 0.5, 0.75, 0.9), arena_gib=
     return res
 
 
+def bench_w128(P, a, b, n, ref, steps, warmup, tune):
+    """Alg. 5 with 128-bit words over TGF(2^256) on the same operands: timed
+    like the headline product (tuned schedules, operands resident), and
+    checked equal to the w = 64 product `ref`."""
+    import torch
+
+    ctx = P.Context(0)
+    ctx.set_word_bits(128)
+    k = (n + 127) // 128
+    m = max(1, (2 * k - 2).bit_length())
+    m_op = max(1, (k - 1).bit_length())
+    sched = ctx.autotune(min(m_op, m), m, reps=3) if m <= 26 and tune else []
+    c = torch.empty_like(ref)
+    for _ in range(warmup):
+        ctx.mul_into(a, n, b, n, c)
+    torch.cuda.synchronize()
+    ctx.trace_begin(0xFF)
+    ctx.mul_into(a, n, b, n, c)
+    torch.cuda.synchronize()
+    per_kernel = {}
+    for r in ctx.trace_end():
+        per_kernel[r["kernel"]] = per_kernel.get(r["kernel"], 0.0) + r["ms"]
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        ctx.mul_into(a, n, b, n, c)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    equal = bool(torch.equal(c, ref))
+    ctx.close()
+    assert equal, "the w = 128 product differs from the w = 64 one"
+    return {"field": "TGF(2^256), w = 128", "ms_per_product": round(ms, 4), "fft_points": 1 << m,
+            "stages_ms": {k2: round(v, 4) for k2, v in sorted(per_kernel.items(), key=lambda kv: -kv[1])},
+            "fft_schedule": {str(r["m"]): [r["bottom_log"], r["col_rows_log"]] for r in sched},
+            "equal_to_w64": equal}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -350,6 +386,7 @@ def main():
     ap.add_argument("--no-serve", action="store_true", help="skip the serving measurement")
     ap.add_argument("--serve-requests", type=int, default=10000)
     ap.add_argument("--no-tune", action="store_true", help="keep the default FFT pass schedules")
+    ap.add_argument("--no-w128", action="store_true", help="skip the 128-bit-word (TGF(2^256)) variant")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="first run a plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -476,6 +513,9 @@ def main():
         "stages_ms": stages,
         "fft_schedule": {str(r["m"]): [r["bottom_log"], r["col_rows_log"]] for r in sched},
     }
+    if not args.no_w128:
+        log("bench: the same product with 128-bit words over TGF(2^256)")
+        out["w128"] = bench_w128(P, a, b, n, c, args.steps, args.warmup, not args.no_tune)
     if not args.no_batch:
         log(f"bench: batched products ({args.batch_jobs} jobs)")
         out["batched"] = bench_batched(ctx, args.batch_jobs)
