@@ -338,6 +338,45 @@ def bench_serving(ctx, nreq=10000, fracs=(0.1, 0.25, 0.5, 0.75, 0.9), arena_gib=
     return res
 
 
+def bench_sizes(P, ctx, runs=50):
+    """Single products at the other configured sizes, operands resident: the
+    latency of one call (2^16 and 2^20 bits: launch- and on-chip-bound; median
+    and p99 of `runs` calls, each timed by events on its stream) and the time
+    per product at 2^29 bits."""
+    import numpy as np
+    import torch
+
+    from paper_1708_09746_amd import inputs
+
+    out = {}
+    for name, reps in (("c1", runs), ("c2", runs), ("c3b", 10)):
+        n, desc = WORKLOADS[name]
+        sa, sb = inputs.SEEDS[name]
+        a = torch.from_numpy(inputs.random_poly(sa, n).view(np.int64).copy()).cuda()
+        b = torch.from_numpy(inputs.random_poly(sb, n).view(np.int64).copy()).cuda()
+        c = torch.empty(P.out_words(n, n), dtype=torch.int64, device="cuda")
+        stream = torch.cuda.current_stream()
+        for _ in range(3):
+            ctx.mul_into(a, n, b, n, c, stream)
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            ctx.mul_into(a, n, b, n, c, stream)
+            e1.record(stream)
+            e1.synchronize()
+            ts.append(e0.elapsed_time(e1))
+        ts.sort()
+        out[name] = {"workload": desc, "runs": reps, "median_ms": round(ts[len(ts) // 2], 4),
+                     "p99_ms": round(ts[min(len(ts) - 1, int(0.99 * len(ts)))], 4),
+                     "fft_points": 1 << P.fft_log2(n, n)}
+        if name in PAPER_MS:
+            out[name]["paper_ms"] = PAPER_MS[name]
+        del a, b, c
+    return out
+
+
 def bench_w128(P, a, b, n, ref, steps, warmup, tune):
     """Alg. 5 with 128-bit words over TGF(2^256) on the same operands: timed
     like the headline product (tuned schedules, operands resident), and
@@ -387,6 +426,7 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=10000)
     ap.add_argument("--no-tune", action="store_true", help="keep the default FFT pass schedules")
     ap.add_argument("--no-w128", action="store_true", help="skip the 128-bit-word (TGF(2^256)) variant")
+    ap.add_argument("--no-sizes", action="store_true", help="skip the single products at 2^16, 2^20, 2^29 bits")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="first run a plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -513,6 +553,9 @@ def main():
         "stages_ms": stages,
         "fft_schedule": {str(r["m"]): [r["bottom_log"], r["col_rows_log"]] for r in sched},
     }
+    if not args.no_sizes and args.workload == "c3a":
+        log("bench: single products at 2^16, 2^20 and 2^29 bits")
+        out["sizes"] = bench_sizes(P, ctx)
     if not args.no_w128:
         log("bench: the same product with 128-bit words over TGF(2^256)")
         out["w128"] = bench_w128(P, a, b, n, c, args.steps, args.warmup, not args.no_tune)
