@@ -150,12 +150,14 @@ __global__ __launch_bounds__(kThreads) void k_fft(FftPass A, const uint8_t* g_mt
     }
 }
 
-__global__ __launch_bounds__(kThreads) void k_pmul(PmulOp P, const uint8_t* g_mt) {
+__global__ __launch_bounds__(kThreads) void k_pmul(PmulOp P, const uint8_t* g_mt, const uint32_t* g_ctab) {
     __shared__ __align__(16) uint8_t mt[65536];
+    __shared__ uint32_t ctab[kConstTabWords];
     copy_words(threadIdx.x, blockDim.x, (uint32_t*)mt, (const uint32_t*)g_mt, 16384);
+    copy_words(threadIdx.x, blockDim.x, ctab, g_ctab, kConstTabWords);
     __syncthreads();
     const uint64_t nt = pmul_tiles(P);
-    for (uint64_t t = blockIdx.x; t < nt; t += gridDim.x) pmul_tile(threadIdx.x, blockDim.x, t, P, mt);
+    for (uint64_t t = blockIdx.x; t < nt; t += gridDim.x) pmul_tile(threadIdx.x, blockDim.x, t, P, mt, ctab);
 }
 
 __global__ __launch_bounds__(kThreads) void k_psi(PsiOp P, const uint4* g_psi) {
@@ -294,16 +296,18 @@ __global__ __launch_bounds__(kThreads) void k_fft_multi(const FftPass* ops, cons
 }
 
 __global__ __launch_bounds__(kThreads) void k_pmul_multi(const PmulOp* ops, const uint64_t* prefix, int nops,
-                                                         uint64_t total, const uint8_t* g_mt) {
+                                                         uint64_t total, const uint8_t* g_mt, const uint32_t* g_ctab) {
     __shared__ __align__(16) uint8_t mt[65536];
+    __shared__ uint32_t ctab[kConstTabWords];
     copy_words(threadIdx.x, blockDim.x, (uint32_t*)mt, (const uint32_t*)g_mt, 16384);
+    copy_words(threadIdx.x, blockDim.x, ctab, g_ctab, kConstTabWords);
     __syncthreads();
     uint64_t g0, g1;
     block_chunk(total, g0, g1);
     int o = -1;
     for (uint64_t g = g0; g < g1; ++g) {
         o = op_of_tile(prefix, nops, g, o);
-        pmul_tile(threadIdx.x, blockDim.x, g - prefix[o], ops[o], mt);
+        pmul_tile(threadIdx.x, blockDim.x, g - prefix[o], ops[o], mt, ctab);
     }
 }
 
@@ -388,8 +392,11 @@ __global__ __launch_bounds__(kThreads) void k_zero_u32(uint32_t* p, uint64_t n) 
     for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x) p[i] = 0;
 }
 
+static_assert(kConstTabWords <= 4 * ((1 << kFftTileLog) + kMuEntries), "the pointmul tables fit the work area");
+
 __global__ __launch_bounds__(kThreads) void k_persistent(PersistArgs P, const uint8_t* g_mt, const uint32_t* g_lam,
-                                                         const uint4* g_phi, const uint4* g_psi) {
+                                                         const uint4* g_phi, const uint4* g_psi,
+                                                         const uint32_t* g_ctab) {
     __shared__ __align__(16) uint8_t mt[65536];
     __shared__ uint32_t lam[1024];
     __shared__ uint4 work[(1 << kFftTileLog) + kMuEntries];  // FFT tile + mu-set tables, a BasisCvt tile, or the Psi table
@@ -406,8 +413,9 @@ __global__ __launch_bounds__(kThreads) void k_persistent(PersistArgs P, const ui
     uint4* tl = work;
     uint4* mu = work + (1 << kFftTileLog);
     // what `work` holds: 0 nothing reusable, 1 FFT local mu-sets of (cur_lo,
-    // cur_hi), 2 the w = 64 Psi table, 3 the w = 128 one; phin holds the
-    // changeRepr table of mode cur_phi
+    // cur_hi), 2 the w = 64 Psi table, 3 the w = 128 one, 4 the constant-
+    // multiple tables of pointmul; phin holds the changeRepr table of mode
+    // cur_phi
     int held = 0;
     uint32_t cur_lo = ~0u, cur_hi = ~0u, cur_phi = kPhiNone;
     auto need_phin = [&](uint32_t mode) {
@@ -470,7 +478,14 @@ __global__ __launch_bounds__(kThreads) void k_persistent(PersistArgs P, const ui
                     fft_tile<kFftRL>(tid, nt, t, A, mt, mt3, lam, phin, tl, mu, mu_tile);
                     break;
                 }
-                case OpKind::Pmul: pmul_tile(tid, nt, t, D.pmul, mt); break;
+                case OpKind::Pmul:
+                    if (held != 4) {
+                        copy_words(tid, nt, (uint32_t*)work, g_ctab, kConstTabWords);
+                        __syncthreads();
+                        held = 4;
+                    }
+                    pmul_tile(tid, nt, t, D.pmul, mt, (const uint32_t*)work);
+                    break;
                 case OpKind::Psi: {
                     const int want = D.psi.spech ? 3 : 2;
                     if (held != want) {
@@ -528,6 +543,7 @@ struct gf2x_ctx {
     uint32_t* d_lam = nullptr;
     uint4* d_phi = nullptr;
     uint4* d_psi = nullptr;
+    uint32_t* d_ctab = nullptr;  // constant-multiple tables of the generic product
     char* ws = nullptr;
     size_t ws_bytes = 0;
     char* io = nullptr;  // operand/product staging for the host-pointer entry point
@@ -795,7 +811,7 @@ int run_ops(gf2x_ctx* ctx, const std::vector<Op>& ops, hipStream_t st) {
                 break;
             case OpKind::Pmul:
                 GF2X_LAUNCH(k_pmul, dim3(grid_for(pmul_tiles(op.pmul), 2 * ncu)), op.pmul,
-                                   (const uint8_t*)ctx->d_mt);
+                                   (const uint8_t*)ctx->d_mt, (const uint32_t*)ctx->d_ctab);
                 break;
             case OpKind::BcClass:
                 if (op.bcc.wide)
@@ -907,7 +923,8 @@ int launch_groups(gf2x_ctx* ctx, const std::vector<LaunchGroup>& groups, const c
                 break;
             case OpKind::Pmul:
                 hipLaunchKernelGGL(k_pmul_multi, dim3(grid_for(G.total, 2 * ncu)), dim3(kThreads), 0, st,
-                                   (const PmulOp*)ops, prefix, G.nops, G.total, (const uint8_t*)ctx->d_mt);
+                                   (const PmulOp*)ops, prefix, G.nops, G.total, (const uint8_t*)ctx->d_mt,
+                                   (const uint32_t*)ctx->d_ctab);
                 break;
             case OpKind::Psi:
                 hipLaunchKernelGGL(k_psi_multi, dim3(grid_for(G.total, 2 * ncu)), dim3(kThreads), 0, st,
@@ -1032,7 +1049,7 @@ int launch_persistent(gf2x_ctx* ctx, char* dev, const PersistLayout& L, uint32_t
                        (uint32_t*)(dev + L.state_off), (uint64_t)L.state_words);
     hipLaunchKernelGGL(k_persistent, dim3((unsigned)std::max(1, ctx->ncu)), dim3(kThreads), 0, st, a,
                        (const uint8_t*)ctx->d_mt, (const uint32_t*)ctx->d_lam, (const uint4*)ctx->d_phi,
-                       (const uint4*)ctx->d_psi);
+                       (const uint4*)ctx->d_psi, (const uint32_t*)ctx->d_ctab);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(ctx, e, "persistent launch");
     return GF2X_OK;
@@ -1463,7 +1480,10 @@ int gf2x_ctx_create(gf2x_ctx** out, int device) {
     if (e == hipSuccess) e = hipMalloc((void**)&ctx->d_mt, 65536);
     if (e == hipSuccess) e = hipMalloc((void**)&ctx->d_lam, sizeof(lam));
     if (e == hipSuccess) e = hipMalloc((void**)&ctx->d_phi, phi.size() * sizeof(uint4));
+    const std::vector<uint32_t> ctab = build_const_tabs(T);
     if (e == hipSuccess) e = hipMalloc((void**)&ctx->d_psi, psi.size() * sizeof(uint4));
+    if (e == hipSuccess) e = hipMalloc((void**)&ctx->d_ctab, ctab.size() * sizeof(uint32_t));
+    if (e == hipSuccess) e = hipMemcpy(ctx->d_ctab, ctab.data(), ctab.size() * sizeof(uint32_t), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(ctx->d_mt, mt.data(), 65536, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(ctx->d_lam, lam, sizeof(lam), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(ctx->d_phi, phi.data(), phi.size() * sizeof(uint4), hipMemcpyHostToDevice);
@@ -1490,6 +1510,7 @@ void gf2x_ctx_destroy(gf2x_ctx* ctx) {
     if (ctx->d_lam) (void)hipFree(ctx->d_lam);
     if (ctx->d_phi) (void)hipFree(ctx->d_phi);
     if (ctx->d_psi) (void)hipFree(ctx->d_psi);
+    if (ctx->d_ctab) (void)hipFree(ctx->d_ctab);
     if (ctx->d_layers) (void)hipFree(ctx->d_layers);
     if (ctx->transient) batch_free(ctx->transient);
     if (ctx->ws) (void)hipFree(ctx->ws);

@@ -238,55 +238,60 @@ AFFT_HD uint4 xor4(const uint4& a, const uint4& b) {
 // c_{2W} = x_{log2 W} c_W, so e * c_{2W} = (e * x) * c_W with
 // (e0 + e1 x) x = e1 c_W + (e0 + e1) x:  mulc_{2W}(e) = (c_W c_W e1, c_W (e0 + e1)).
 
-AFFT_HD uint32_t mulc64(const uint8_t* mt, uint32_t e) {  // e in TGF(2^32), times c64 = 0x80000000
-    uint32_t e0 = e & 0xffffu, e1 = e >> 16;
-    return mulc32(mt, mulc32(mt, e1)) | (mulc32(mt, e0 ^ e1) << 16);
-}
-AFFT_HD uint64_t mulc128(const uint8_t* mt, uint64_t e) {  // e in TGF(2^64), times c128 = 1 << 63
-    uint32_t e0 = (uint32_t)e, e1 = (uint32_t)(e >> 32);
-    return (uint64_t)mulc64(mt, mulc64(mt, e1)) | ((uint64_t)mulc64(mt, e0 ^ e1) << 32);
-}
-
 AFFT_HD uint32_t gm16(const uint8_t* mt, uint32_t a, uint32_t b) {
     uint32_t a0 = a & 255u, a1 = a >> 8, b0 = b & 255u, b1 = b >> 8;
     uint32_t t = m8(mt, a1, b1), p0 = m8(mt, a0, b0), p1 = m8(mt, a0 ^ a1, b0 ^ b1);
     return (p0 ^ m8(mt, 0x80u, t)) | ((p1 ^ p0) << 8);
 }
-AFFT_HD uint32_t gm32(const uint8_t* mt, uint32_t a, uint32_t b) {
+// The generic product with its constant multiples by word tables (the
+// pointwise products): the multiples by c32 and c64 are GF(2)-linear, so
+// c32 e = T32[0][e0] + T32[1][e1] over the bytes of e in TGF(2^16) and
+// c64 e = sum_k T64[k][byte k of e] for e in TGF(2^32).  ctab holds T64 (4 x
+// 256 words) then T32 (2 x 256 halfwords), built on the host: 2 + 4 lookups
+// where the byte-level recursion takes 3 + 9.
+constexpr int kConstTabWords = 4 * 256 + 256;
+AFFT_HD uint32_t mulc32_t(const uint32_t* ctab, uint32_t e) {  // e in TGF(2^16), times c32 (bit 15)
+    const uint16_t* t = (const uint16_t*)(ctab + 1024);
+    return (uint32_t)t[e & 255u] ^ (uint32_t)t[256 + ((e >> 8) & 255u)];
+}
+AFFT_HD uint32_t mulc64_t(const uint32_t* ctab, uint32_t e) {  // e in TGF(2^32), times c64 (bit 31)
+    return ctab[e & 255u] ^ ctab[256 + ((e >> 8) & 255u)] ^ ctab[512 + ((e >> 16) & 255u)] ^ ctab[768 + (e >> 24)];
+}
+AFFT_HD uint64_t mulc128_t(const uint32_t* ctab, uint64_t e) {  // e in TGF(2^64), times c128 (bit 63)
+    const uint32_t e0 = (uint32_t)e, e1 = (uint32_t)(e >> 32);
+    return (uint64_t)mulc64_t(ctab, mulc64_t(ctab, e1)) | ((uint64_t)mulc64_t(ctab, e0 ^ e1) << 32);
+}
+AFFT_HD uint32_t gm32_t(const uint8_t* mt, const uint32_t* ctab, uint32_t a, uint32_t b) {
     uint32_t a0 = a & 0xffffu, a1 = a >> 16, b0 = b & 0xffffu, b1 = b >> 16;
     uint32_t t = gm16(mt, a1, b1), p0 = gm16(mt, a0, b0), p1 = gm16(mt, a0 ^ a1, b0 ^ b1);
-    return (p0 ^ mulc32(mt, t)) | ((p1 ^ p0) << 16);
+    return (p0 ^ mulc32_t(ctab, t)) | ((p1 ^ p0) << 16);
 }
-AFFT_HD uint64_t gm64(const uint8_t* mt, uint64_t a, uint64_t b) {
+AFFT_HD uint64_t gm64_t(const uint8_t* mt, const uint32_t* ctab, uint64_t a, uint64_t b) {
     uint32_t a0 = (uint32_t)a, a1 = (uint32_t)(a >> 32), b0 = (uint32_t)b, b1 = (uint32_t)(b >> 32);
-    uint32_t t = gm32(mt, a1, b1), p0 = gm32(mt, a0, b0), p1 = gm32(mt, a0 ^ a1, b0 ^ b1);
-    return (uint64_t)(p0 ^ mulc64(mt, t)) | ((uint64_t)(p1 ^ p0) << 32);
+    uint32_t t = gm32_t(mt, ctab, a1, b1), p0 = gm32_t(mt, ctab, a0, b0), p1 = gm32_t(mt, ctab, a0 ^ a1, b0 ^ b1);
+    return (uint64_t)(p0 ^ mulc64_t(ctab, t)) | ((uint64_t)(p1 ^ p0) << 32);
 }
-AFFT_HD uint4 gm128(const uint8_t* mt, const uint4& a, const uint4& b) {
+AFFT_HD uint4 gm128_t(const uint8_t* mt, const uint32_t* ctab, const uint4& a, const uint4& b) {
     uint64_t a0 = a.x | ((uint64_t)a.y << 32), a1 = a.z | ((uint64_t)a.w << 32);
     uint64_t b0 = b.x | ((uint64_t)b.y << 32), b1 = b.z | ((uint64_t)b.w << 32);
-    uint64_t t = gm64(mt, a1, b1), p0 = gm64(mt, a0, b0), p1 = gm64(mt, a0 ^ a1, b0 ^ b1);
-    uint64_t lo = p0 ^ mulc128(mt, t), hi = p1 ^ p0;
-    uint4 r;
-    r.x = (uint32_t)lo;
-    r.y = (uint32_t)(lo >> 32);
-    r.z = (uint32_t)hi;
-    r.w = (uint32_t)(hi >> 32);
-    return r;
+    uint64_t t = gm64_t(mt, ctab, a1, b1), p0 = gm64_t(mt, ctab, a0, b0), p1 = gm64_t(mt, ctab, a0 ^ a1, b0 ^ b1);
+    uint64_t lo = p0 ^ mulc128_t(ctab, t), hi = p1 ^ p0;
+    return make_uint4((uint32_t)lo, (uint32_t)(lo >> 32), (uint32_t)hi, (uint32_t)(hi >> 32));
 }
 
 // TGF(2^256) = TGF(2^128)[x_8]/(x_8^2 + x_8 + c256), elements as two uint4
 // halves (lo, hi); c256 = x_1 ... x_7 = c128 x_7, so for e = e0 + e1 x_7 in
 // TGF(2^128):  e c256 = (e x_7) c128 = c128 c128 e1 + c128 (e0 + e1) x_7.
-AFFT_HD uint4 mulc256(const uint8_t* mt, const uint4& e) {  // e in TGF(2^128), times c256 (bit 127)
+AFFT_HD uint4 mulc256_t(const uint32_t* ctab, const uint4& e) {  // e in TGF(2^128), times c256 (bit 127)
     const uint64_t e0 = e.x | ((uint64_t)e.y << 32), e1 = e.z | ((uint64_t)e.w << 32);
-    const uint64_t lo = mulc128(mt, mulc128(mt, e1)), hi = mulc128(mt, e0 ^ e1);
+    const uint64_t lo = mulc128_t(ctab, mulc128_t(ctab, e1)), hi = mulc128_t(ctab, e0 ^ e1);
     return make_uint4((uint32_t)lo, (uint32_t)(lo >> 32), (uint32_t)hi, (uint32_t)(hi >> 32));
 }
-AFFT_HD void gm256(const uint8_t* mt, const uint4& a0, const uint4& a1, const uint4& b0, const uint4& b1, uint4& c0,
-                   uint4& c1) {
-    const uint4 t = gm128(mt, a1, b1), p0 = gm128(mt, a0, b0), p1 = gm128(mt, xor4(a0, a1), xor4(b0, b1));
-    c0 = xor4(p0, mulc256(mt, t));
+AFFT_HD void gm256_t(const uint8_t* mt, const uint32_t* ctab, const uint4& a0, const uint4& a1, const uint4& b0,
+                     const uint4& b1, uint4& c0, uint4& c1) {
+    const uint4 t = gm128_t(mt, ctab, a1, b1), p0 = gm128_t(mt, ctab, a0, b0);
+    const uint4 p1 = gm128_t(mt, ctab, xor4(a0, a1), xor4(b0, b1));
+    c0 = xor4(p0, mulc256_t(ctab, t));
     c1 = xor4(p1, p0);
 }
 

@@ -628,17 +628,18 @@ struct PmulOp {
 
 AFFT_HD uint64_t pmul_tiles(const PmulOp& P) { return (P.n_out + kPmulTile - 1) / kPmulTile; }
 
-AFFT_HD void pmul_tile(int tid, int nt, uint64_t tile, const PmulOp& P, const uint8_t* mt) {
+// ctab: the constant-multiple tables (kConstTabWords words)
+AFFT_HD void pmul_tile(int tid, int nt, uint64_t tile, const PmulOp& P, const uint8_t* mt, const uint32_t* ctab) {
     for (int e = tid; e < kPmulTile; e += nt) {
         uint64_t j = tile * kPmulTile + e;
         if (j >= P.n_out) break;
         if (P.ah) {
             uint4 c0 = make_uint4(0, 0, 0, 0), c1 = c0;
-            if (j < P.n) gm256(mt, P.a[j], P.ah[j], P.b[j], P.bh[j], c0, c1);
+            if (j < P.n) gm256_t(mt, ctab, P.a[j], P.ah[j], P.b[j], P.bh[j], c0, c1);
             P.c[j] = c0;
             P.ch[j] = c1;
         } else {
-            P.c[j] = j < P.n ? gm128(mt, P.a[j], P.b[j]) : make_uint4(0, 0, 0, 0);
+            P.c[j] = j < P.n ? gm128_t(mt, ctab, P.a[j], P.b[j]) : make_uint4(0, 0, 0, 0);
         }
     }
 }
@@ -677,12 +678,19 @@ AFFT_HD uint4 psi_half(const uint4* tab, const uint4& c0, const uint4& c1) {
     return r;
 }
 
-AFFT_HD uint4 psi_elem(const uint4* psi_tab, const uint4& e) {
-    uint4 r = make_uint4(0, 0, 0, 0);
+// One 64-bit half (half 0: bits 0..63, half 1: bits 64..127) of Psi of a
+// TGF(2^128) element: only that half of every table entry is read.
+AFFT_HD uint64_t psi_half64(const uint4* psi_tab, const uint4& e, int half) {
+    const uint2* t2 = (const uint2*)psi_tab;
+    uint32_t lo = 0, hi = 0;
     const uint32_t w[4] = {e.x, e.y, e.z, e.w};
 #pragma unroll
-    for (int k = 0; k < 16; ++k) r = r ^ psi_tab[k * 256 + ((w[k >> 2] >> (8 * (k & 3))) & 255u)];
-    return r;
+    for (int k = 0; k < 16; ++k) {
+        const uint2 v = t2[2 * (k * 256 + ((w[k >> 2] >> (8 * (k & 3))) & 255u)) + half];
+        lo ^= v.x;
+        hi ^= v.y;
+    }
+    return (uint64_t)lo | ((uint64_t)hi << 32);
 }
 
 // psi_tab: the table of the op's width (psi_tab_off into the device table)
@@ -709,14 +717,8 @@ AFFT_HD void psi_tile(int tid, int nt, uint64_t tile, const PsiOp& P, const uint
         uint64_t k = tile * kPsiTile + e;
         if (k >= P.nwords) break;
         uint64_t w = 0;
-        if (k < P.nspec) {
-            uint4 r = psi_elem(psi_tab, P.spec[k]);
-            w ^= (uint64_t)r.x | ((uint64_t)r.y << 32);
-        }
-        if (k >= 1 && k - 1 < P.nspec) {
-            uint4 r = psi_elem(psi_tab, P.spec[k - 1]);
-            w ^= (uint64_t)r.z | ((uint64_t)r.w << 32);
-        }
+        if (k < P.nspec) w ^= psi_half64(psi_tab, P.spec[k], 0);
+        if (k >= 1 && k - 1 < P.nspec) w ^= psi_half64(psi_tab, P.spec[k - 1], 1);
         if (k == P.nwords - 1 && (P.nbits % 64)) w &= ~0ull >> (64 - P.nbits % 64);
         P.out[k] = w;
     }

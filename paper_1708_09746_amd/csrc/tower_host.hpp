@@ -93,6 +93,21 @@ inline void build_lambda(const HostTower& T, uint32_t lam[32][32]) {
         for (int t = 0; t < 32; ++t) lam[i][t] = (uint32_t)T.s_eval(i, 1ull << t, 32);
 }
 
+// Constant multiples for the generic product (kConstTabWords words): the
+// multiples by c64 = x1 ... x5 (bit 31) of the bytes of a TGF(2^32) element,
+// T64[k][y] = c64 (y << 8k) (k < 4), then by c32 = x1 ... x4 (bit 15) of the
+// bytes of a TGF(2^16) element, T32[k][y] = c32 (y << 8k) (k < 2) as packed
+// halfwords.
+inline std::vector<uint32_t> build_const_tabs(const HostTower& T) {
+    std::vector<uint32_t> t(4 * 256 + 256, 0);
+    for (int k = 0; k < 4; ++k)
+        for (int y = 0; y < 256; ++y) t[256 * k + y] = (uint32_t)T.mul((uint64_t)y << (8 * k), 1ull << 31, 32);
+    uint16_t* h = (uint16_t*)(t.data() + 1024);
+    for (int k = 0; k < 2; ++k)
+        for (int y = 0; y < 256; ++y) h[256 * k + y] = (uint16_t)T.mul((uint64_t)y << (8 * k), 1ull << 15, 16);
+    return t;
+}
+
 // Kronecker embedding (Sec. 2.1) and its inverse (Sec. 4.3): a 64-bit block u
 // (a polynomial of degree < 64 in z) maps to u(theta) in TGF(2^128) with
 // theta = x7 = v_64, which generates TGF(2^128) since it lies outside

@@ -24,6 +24,7 @@ std::vector<uint8_t> MT(65536);
 std::vector<uint32_t> LAM(1024);
 std::vector<uint4> PHIN(kPhinTotal), PSI(kPsiTab64 + kPsiTab128);
 std::vector<uint2> MT3(768);
+std::vector<uint32_t> CTAB;
 LayerPool POOL;
 PlanParams PP;
 
@@ -42,6 +43,7 @@ bool init() {
     for (int i = 0; i < kPhinTotal; ++i) PHIN[i] = to_u4(R.phin[i]);
     for (int i = 0; i < kPsiTab64; ++i) PSI[i] = to_u4(R.psi[i]);
     for (int i = 0; i < kPsiTab128; ++i) PSI[kPsiTab64 + i] = to_u4(R.psin[i]);
+    CTAB = build_const_tabs(T);
     PP.lam = LAM.data();
     PP.mt = MT.data();
     build_mt3(0, 1, MT.data(), MT3.data());
@@ -76,7 +78,7 @@ void run_tile(const Op& op, uint64_t t, Scratch& S) {
                              S.tl.data(), S.mu.data(),
                              S.mut.data());
             break;
-        case OpKind::Pmul: pmul_tile(0, 1, t, op.pmul, MT.data()); break;
+        case OpKind::Pmul: pmul_tile(0, 1, t, op.pmul, MT.data(), CTAB.data()); break;
         case OpKind::Psi: psi_tile(0, 1, t, op.psi, PSI.data() + psi_tab_off(op.psi)); break;
         case OpKind::BcClass:
             if (op.bcc.wide)
