@@ -247,9 +247,16 @@ AFFT_HD uint32_t gm16(const uint8_t* mt, uint32_t a, uint32_t b) {
 // pointwise products): the multiples by c32 and c64 are GF(2)-linear, so
 // c32 e = T32[0][e0] + T32[1][e1] over the bytes of e in TGF(2^16) and
 // c64 e = sum_k T64[k][byte k of e] for e in TGF(2^32).  ctab holds T64 (4 x
-// 256 words) then T32 (2 x 256 halfwords), built on the host: 2 + 4 lookups
-// where the byte-level recursion takes 3 + 9.
-constexpr int kConstTabWords = 4 * 256 + 256;
+// 256 words), T32 (2 x 256 halfwords), both built on the host (2 + 4 lookups
+// where the byte-level recursion takes 3 + 9), then at kC16Tab the three
+// 3-bit-group tables of multiplication by c16 in GF(256) (5 words, as for an
+// 8-bit FFT multiplier).  The c16 multiple of the innermost level,
+// c16 (a1 b1) = (c16 a1) b1, is taken on the operand: c16 acts byte-wise and
+// linearly, so the scaled bytes of every leaf operand are the same
+// combinations of the bytes of ca = c16 a (one register-table multiply per
+// word of a) as the leaf operands are of a.
+constexpr int kC16Tab = 4 * 256 + 256;
+constexpr int kConstTabWords = kC16Tab + 8;
 AFFT_HD uint32_t mulc32_t(const uint32_t* ctab, uint32_t e) {  // e in TGF(2^16), times c32 (bit 15)
     const uint16_t* t = (const uint16_t*)(ctab + 1024);
     return (uint32_t)t[e & 255u] ^ (uint32_t)t[256 + ((e >> 8) & 255u)];
@@ -261,21 +268,31 @@ AFFT_HD uint64_t mulc128_t(const uint32_t* ctab, uint64_t e) {  // e in TGF(2^64
     const uint32_t e0 = (uint32_t)e, e1 = (uint32_t)(e >> 32);
     return (uint64_t)mulc64_t(ctab, mulc64_t(ctab, e1)) | ((uint64_t)mulc64_t(ctab, e0 ^ e1) << 32);
 }
-AFFT_HD uint32_t gm32_t(const uint8_t* mt, const uint32_t* ctab, uint32_t a, uint32_t b) {
-    uint32_t a0 = a & 0xffffu, a1 = a >> 16, b0 = b & 0xffffu, b1 = b >> 16;
-    uint32_t t = gm16(mt, a1, b1), p0 = gm16(mt, a0, b0), p1 = gm16(mt, a0 ^ a1, b0 ^ b1);
+// a, b in TGF(2^16); ca = c16 a byte-wise
+AFFT_HD uint32_t gm16c(const uint8_t* mt, uint32_t a, uint32_t ca, uint32_t b) {
+    const uint32_t a0 = a & 255u, a1 = a >> 8, b0 = b & 255u, b1 = b >> 8;
+    const uint32_t t = m8(mt, ca >> 8, b1), p0 = m8(mt, a0, b0), p1 = m8(mt, a0 ^ a1, b0 ^ b1);
+    return (p0 ^ t) | ((p1 ^ p0) << 8);
+}
+AFFT_HD uint32_t gm32_t(const uint8_t* mt, const uint32_t* ctab, uint32_t a, uint32_t ca, uint32_t b) {
+    const uint32_t a0 = a & 0xffffu, a1 = a >> 16, c0 = ca & 0xffffu, c1 = ca >> 16, b0 = b & 0xffffu, b1 = b >> 16;
+    const uint32_t t = gm16c(mt, a1, c1, b1), p0 = gm16c(mt, a0, c0, b0), p1 = gm16c(mt, a0 ^ a1, c0 ^ c1, b0 ^ b1);
     return (p0 ^ mulc32_t(ctab, t)) | ((p1 ^ p0) << 16);
 }
-AFFT_HD uint64_t gm64_t(const uint8_t* mt, const uint32_t* ctab, uint64_t a, uint64_t b) {
-    uint32_t a0 = (uint32_t)a, a1 = (uint32_t)(a >> 32), b0 = (uint32_t)b, b1 = (uint32_t)(b >> 32);
-    uint32_t t = gm32_t(mt, ctab, a1, b1), p0 = gm32_t(mt, ctab, a0, b0), p1 = gm32_t(mt, ctab, a0 ^ a1, b0 ^ b1);
+AFFT_HD uint64_t gm64_t(const uint8_t* mt, const uint32_t* ctab, uint64_t a, uint64_t ca, uint64_t b) {
+    const uint32_t a0 = (uint32_t)a, a1 = (uint32_t)(a >> 32), c0 = (uint32_t)ca, c1 = (uint32_t)(ca >> 32);
+    const uint32_t b0 = (uint32_t)b, b1 = (uint32_t)(b >> 32);
+    const uint32_t t = gm32_t(mt, ctab, a1, c1, b1), p0 = gm32_t(mt, ctab, a0, c0, b0);
+    const uint32_t p1 = gm32_t(mt, ctab, a0 ^ a1, c0 ^ c1, b0 ^ b1);
     return (uint64_t)(p0 ^ mulc64_t(ctab, t)) | ((uint64_t)(p1 ^ p0) << 32);
 }
-AFFT_HD uint4 gm128_t(const uint8_t* mt, const uint32_t* ctab, const uint4& a, const uint4& b) {
-    uint64_t a0 = a.x | ((uint64_t)a.y << 32), a1 = a.z | ((uint64_t)a.w << 32);
-    uint64_t b0 = b.x | ((uint64_t)b.y << 32), b1 = b.z | ((uint64_t)b.w << 32);
-    uint64_t t = gm64_t(mt, ctab, a1, b1), p0 = gm64_t(mt, ctab, a0, b0), p1 = gm64_t(mt, ctab, a0 ^ a1, b0 ^ b1);
-    uint64_t lo = p0 ^ mulc128_t(ctab, t), hi = p1 ^ p0;
+AFFT_HD uint4 gm128_t(const uint8_t* mt, const uint32_t* ctab, const uint4& a, const uint4& ca, const uint4& b) {
+    const uint64_t a0 = a.x | ((uint64_t)a.y << 32), a1 = a.z | ((uint64_t)a.w << 32);
+    const uint64_t c0 = ca.x | ((uint64_t)ca.y << 32), c1 = ca.z | ((uint64_t)ca.w << 32);
+    const uint64_t b0 = b.x | ((uint64_t)b.y << 32), b1 = b.z | ((uint64_t)b.w << 32);
+    const uint64_t t = gm64_t(mt, ctab, a1, c1, b1), p0 = gm64_t(mt, ctab, a0, c0, b0);
+    const uint64_t p1 = gm64_t(mt, ctab, a0 ^ a1, c0 ^ c1, b0 ^ b1);
+    const uint64_t lo = p0 ^ mulc128_t(ctab, t), hi = p1 ^ p0;
     return make_uint4((uint32_t)lo, (uint32_t)(lo >> 32), (uint32_t)hi, (uint32_t)(hi >> 32));
 }
 
@@ -287,10 +304,11 @@ AFFT_HD uint4 mulc256_t(const uint32_t* ctab, const uint4& e) {  // e in TGF(2^1
     const uint64_t lo = mulc128_t(ctab, mulc128_t(ctab, e1)), hi = mulc128_t(ctab, e0 ^ e1);
     return make_uint4((uint32_t)lo, (uint32_t)(lo >> 32), (uint32_t)hi, (uint32_t)(hi >> 32));
 }
-AFFT_HD void gm256_t(const uint8_t* mt, const uint32_t* ctab, const uint4& a0, const uint4& a1, const uint4& b0,
-                     const uint4& b1, uint4& c0, uint4& c1) {
-    const uint4 t = gm128_t(mt, ctab, a1, b1), p0 = gm128_t(mt, ctab, a0, b0);
-    const uint4 p1 = gm128_t(mt, ctab, xor4(a0, a1), xor4(b0, b1));
+// (a0, a1), (b0, b1) in TGF(2^256); (ca0, ca1) = c16 (a0, a1) byte-wise
+AFFT_HD void gm256_t(const uint8_t* mt, const uint32_t* ctab, const uint4& a0, const uint4& a1, const uint4& ca0,
+                     const uint4& ca1, const uint4& b0, const uint4& b1, uint4& c0, uint4& c1) {
+    const uint4 t = gm128_t(mt, ctab, a1, ca1, b1), p0 = gm128_t(mt, ctab, a0, ca0, b0);
+    const uint4 p1 = gm128_t(mt, ctab, xor4(a0, a1), xor4(ca0, ca1), xor4(b0, b1));
     c0 = xor4(p0, mulc256_t(ctab, t));
     c1 = xor4(p1, p0);
 }

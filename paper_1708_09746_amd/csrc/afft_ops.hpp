@@ -630,16 +630,29 @@ AFFT_HD uint64_t pmul_tiles(const PmulOp& P) { return (P.n_out + kPmulTile - 1) 
 
 // ctab: the constant-multiple tables (kConstTabWords words)
 AFFT_HD void pmul_tile(int tid, int nt, uint64_t tile, const PmulOp& P, const uint8_t* mt, const uint32_t* ctab) {
+    // multiplication by c16 of every byte of a word (register tables)
+    const uint2 t0 = make_uint2(ctab[kC16Tab], ctab[kC16Tab + 1]), t1 = make_uint2(ctab[kC16Tab + 2], ctab[kC16Tab + 3]);
+    const uint32_t t2 = ctab[kC16Tab + 4];
+    auto c16x = [&](const uint4& v) {
+        return make_uint4(mul_word8_t(t0, t1, t2, v.x), mul_word8_t(t0, t1, t2, v.y), mul_word8_t(t0, t1, t2, v.z),
+                          mul_word8_t(t0, t1, t2, v.w));
+    };
     for (int e = tid; e < kPmulTile; e += nt) {
         uint64_t j = tile * kPmulTile + e;
         if (j >= P.n_out) break;
         if (P.ah) {
             uint4 c0 = make_uint4(0, 0, 0, 0), c1 = c0;
-            if (j < P.n) gm256_t(mt, ctab, P.a[j], P.ah[j], P.b[j], P.bh[j], c0, c1);
+            if (j < P.n) {
+                const uint4 a0 = P.a[j], a1 = P.ah[j];
+                gm256_t(mt, ctab, a0, a1, c16x(a0), c16x(a1), P.b[j], P.bh[j], c0, c1);
+            }
             P.c[j] = c0;
             P.ch[j] = c1;
+        } else if (j < P.n) {
+            const uint4 a = P.a[j];
+            P.c[j] = gm128_t(mt, ctab, a, c16x(a), P.b[j]);
         } else {
-            P.c[j] = j < P.n ? gm128_t(mt, ctab, P.a[j], P.b[j]) : make_uint4(0, 0, 0, 0);
+            P.c[j] = make_uint4(0, 0, 0, 0);
         }
     }
 }

@@ -97,14 +97,23 @@ inline void build_lambda(const HostTower& T, uint32_t lam[32][32]) {
 // multiples by c64 = x1 ... x5 (bit 31) of the bytes of a TGF(2^32) element,
 // T64[k][y] = c64 (y << 8k) (k < 4), then by c32 = x1 ... x4 (bit 15) of the
 // bytes of a TGF(2^16) element, T32[k][y] = c32 (y << 8k) (k < 2) as packed
-// halfwords.
+// halfwords, then the register tables of multiplication by c16 in GF(256).
 inline std::vector<uint32_t> build_const_tabs(const HostTower& T) {
-    std::vector<uint32_t> t(4 * 256 + 256, 0);
+    std::vector<uint32_t> t(4 * 256 + 256 + 8, 0);
     for (int k = 0; k < 4; ++k)
         for (int y = 0; y < 256; ++y) t[256 * k + y] = (uint32_t)T.mul((uint64_t)y << (8 * k), 1ull << 31, 32);
     uint16_t* h = (uint16_t*)(t.data() + 1024);
     for (int k = 0; k < 2; ++k)
         for (int y = 0; y < 256; ++y) h[256 * k + y] = (uint16_t)T.mul((uint64_t)y << (8 * k), 1ull << 15, 16);
+    // c16 = 0x80 times the 3-bit groups of a byte: T0[y] = c16 y, T1[y] = c16 (y << 3)
+    // (y < 8, one byte each, two words per table), T2[y] = c16 (y << 6) (y < 4)
+    const uint8_t* r = T.mt8[0x80];
+    uint32_t* g = t.data() + 1280;
+    for (int y = 0; y < 8; ++y) {
+        g[y >> 2] |= (uint32_t)r[y] << (8 * (y & 3));
+        g[2 + (y >> 2)] |= (uint32_t)r[y << 3] << (8 * (y & 3));
+    }
+    for (int y = 0; y < 4; ++y) g[4] |= (uint32_t)r[y << 6] << (8 * y);
     return t;
 }
 
