@@ -719,10 +719,11 @@ void op_traffic(const Op& op, gf2x_trace_rec& r) {
             r.elements = n;
             r.bytes_read = op.fft.phi_in == kPhi64 ? 8 * n : 16 * n;  // words, 128-bit words or elements
             r.bytes_written = 16 * n;
-            // LDS table reads per butterfly: 6 or 9 byte lookups per word (4 words) for
-            // 16/32-bit multipliers; 3 table reads for 8-bit ones (their bytes are
-            // looked up in registers)
-            static const uint64_t per_bfly[3] = {3, 24, 36};
+            // LDS table reads per butterfly (index: width_mode): 6, 9 or 8 byte
+            // lookups per word (4 words) for 16-bit, 32-bit and 17..24-bit
+            // multipliers; 3 table reads for 8-bit ones (their bytes are looked
+            // up in registers)
+            static const uint64_t per_bfly[4] = {3, 24, 36, 32};
             for (uint32_t i = op.fft.lo; i < op.fft.hi; ++i)
                 r.lookups += (n / 2) * per_bfly[width_mode((int)op.fft.log_total - (int)i)];
             break;

@@ -37,95 +37,19 @@ struct BcLayer {
 AFFT_HD uint32_t m8(const uint8_t* mt, uint32_t x, uint32_t y) { return mt[(x << 8) | y]; }
 
 // ----------------------------------------- multiplication by a subfield scalar
-// For lambda in TGF(2^32) let w_k = lambda * v_{8k} (k = 0..3; v_8 = x4,
-// v_16 = x5, v_24 = x4 x5).  A word a = sum_k a_k v_{8k} with bytes a_k in
-// GF(256) gives a * lambda = sum_k a_k w_k, and a_k w_k is the GF(256) scalar a_k
-// times each byte of w_k.  So byte r of the product is XOR_k a_k * byte_r(w_k).
-// (w_0, w_1, w_2, w_3) is stored as a uint4 "mu-set".
-
 // e * x4 for e in TGF(2^16) = GF(256)[x4]: e0 + e1 x4 -> e1 c16 + (e0 + e1) x4,
 // with c16 = x1 x2 x3 = 0x80.
 AFFT_HD uint32_t mulx4_16(const uint8_t* mt, uint32_t e) {
     uint32_t e0 = e & 255u, e1 = (e >> 8) & 255u;
     return m8(mt, 0x80u, e1) | ((e0 ^ e1) << 8);
 }
-AFFT_HD uint32_t mulx4_32(const uint8_t* mt, uint32_t w) {
-    return mulx4_16(mt, w & 0xffffu) | (mulx4_16(mt, w >> 16) << 16);
-}
 // e * c32 for e in TGF(2^16), c32 = x1 x2 x3 x4 = 0x8000 = c16 * x4
 AFFT_HD uint32_t mulc32(const uint8_t* mt, uint32_t e) {
     uint32_t t = mulx4_16(mt, e);
     return m8(mt, 0x80u, t & 255u) | (m8(mt, 0x80u, t >> 8) << 8);
 }
-// w * x5 for w in TGF(2^32) = TGF(2^16)[x5]: l0 + l1 x5 -> l1 c32 + (l0 + l1) x5
-AFFT_HD uint32_t mulx5(const uint8_t* mt, uint32_t w) {
-    uint32_t l0 = w & 0xffffu, l1 = w >> 16;
-    return mulc32(mt, l1) | ((l0 ^ l1) << 16);
-}
 
-AFFT_HD uint4 make_mu(const uint8_t* mt, uint32_t lam) {
-    uint4 m;
-    m.x = lam;
-    m.y = mulx4_32(mt, lam);
-    m.z = mulx5(mt, lam);
-    m.w = mulx5(mt, m.y);
-    return m;
-}
-
-// a * lambda, lambda arbitrary in TGF(2^32): 16 table lookups
-AFFT_HD uint32_t mul_mu32(const uint8_t* mt, const uint4& m, uint32_t a) {
-    uint32_t a0 = a & 255u, a1 = (a >> 8) & 255u, a2 = (a >> 16) & 255u, a3 = a >> 24;
-    uint32_t out = 0;
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-        uint32_t sh = 8u * r;
-        uint32_t b = m8(mt, (m.x >> sh) & 255u, a0) ^ m8(mt, (m.y >> sh) & 255u, a1) ^
-                     m8(mt, (m.z >> sh) & 255u, a2) ^ m8(mt, (m.w >> sh) & 255u, a3);
-        out |= b << sh;
-    }
-    return out;
-}
-// lambda in TGF(2^16): the two 16-bit halves of a are multiplied separately
-// by the 2x2 GF(256) matrix (w_0, w_1): 8 lookups
-AFFT_HD uint32_t mul_mu16(const uint8_t* mt, const uint4& m, uint32_t a) {
-    uint32_t p0 = m.x & 255u, p1 = (m.x >> 8) & 255u, q0 = m.y & 255u, q1 = (m.y >> 8) & 255u;
-    uint32_t a0 = a & 255u, a1 = (a >> 8) & 255u, a2 = (a >> 16) & 255u, a3 = a >> 24;
-    uint32_t r0 = m8(mt, p0, a0) ^ m8(mt, q0, a1);
-    uint32_t r1 = m8(mt, p1, a0) ^ m8(mt, q1, a1);
-    uint32_t r2 = m8(mt, p0, a2) ^ m8(mt, q0, a3);
-    uint32_t r3 = m8(mt, p1, a2) ^ m8(mt, q1, a3);
-    return r0 | (r1 << 8) | (r2 << 16) | (r3 << 24);
-}
-// lambda in GF(256): bytewise, 4 lookups
-AFFT_HD uint32_t mul_mu8(const uint8_t* mt, uint32_t lam, uint32_t a) {
-    return m8(mt, lam, a & 255u) | (m8(mt, lam, (a >> 8) & 255u) << 8) |
-           (m8(mt, lam, (a >> 16) & 255u) << 16) | (m8(mt, lam, a >> 24) << 24);
-}
-
-// v * lambda for v in TGF(2^128): each word separately (Prop. 2).
-// mode 0: lambda in GF(256), 1: TGF(2^16), 2: TGF(2^32)
-AFFT_HD uint4 mul_sub(const uint8_t* mt, const uint4& m, const uint4& v, int mode) {
-    uint4 r;
-    if (mode == 0) {
-        r.x = mul_mu8(mt, m.x, v.x);
-        r.y = mul_mu8(mt, m.x, v.y);
-        r.z = mul_mu8(mt, m.x, v.z);
-        r.w = mul_mu8(mt, m.x, v.w);
-    } else if (mode == 1) {
-        r.x = mul_mu16(mt, m, v.x);
-        r.y = mul_mu16(mt, m, v.y);
-        r.z = mul_mu16(mt, m, v.z);
-        r.w = mul_mu16(mt, m, v.w);
-    } else {
-        r.x = mul_mu32(mt, m, v.x);
-        r.y = mul_mu32(mt, m, v.y);
-        r.z = mul_mu32(mt, m, v.z);
-        r.w = mul_mu32(mt, m, v.w);
-    }
-    return r;
-}
-
-// ---------------------------------------- Karatsuba form of the same product
+// ---------------------------------------------- Karatsuba form of the product
 // A TGF(2^16) scalar s = s0 + s1 x4 times e = e0 + e1 x4 needs three GF(256)
 // products: t1 = e0 s0, t2 = e1 (c16 s1), t3 = (e0 + e1)(s0 + s1), and then
 // e s = (t1 + t2) + (t3 + t1) x4.  The scalar enters only through the three
@@ -148,14 +72,6 @@ AFFT_HD uint4 make_mu_k(const uint8_t* mt, uint32_t lam) {
     m.z = k3_of(mt, l0 ^ l1);
     m.w = lam;
     return m;
-}
-
-AFFT_HD uint32_t mul16k(const uint8_t* mt, uint32_t e, uint32_t k) {
-    uint32_t e0 = e & 255u, e1 = (e >> 8) & 255u;
-    uint32_t t1 = m8(mt, k & 255u, e0);
-    uint32_t t2 = m8(mt, (k >> 8) & 255u, e1);
-    uint32_t t3 = m8(mt, (k >> 16) & 255u, e0 ^ e1);
-    return (t1 ^ t2) | ((t3 ^ t1) << 8);
 }
 
 // Byte permute of the pair (hi, lo): byte i of the result is selected by
@@ -181,14 +97,17 @@ AFFT_HD uint32_t perm32(uint32_t hi, uint32_t lo, uint32_t sel) {
 // Table index (k << 8) | e with k = byte kb of kw and e = byte eb of ew.
 #define AFFT_IX(kw, kb, ew, eb) perm32((kw), (ew), 0x0c0c0000u | ((4u + (kb)) << 8) | (eb))
 
-// word times lambda; mode 0: lambda in GF(256), 1: TGF(2^16), 2: TGF(2^32).
-// Same products as mul16k above, arranged so that every lookup index is one
+// word times lambda; mode 0: lambda in GF(256), 1: TGF(2^16), 2: TGF(2^32),
+// 3: TGF(2^32) with l1 in GF(256).
+// The Karatsuba products above, arranged so that every lookup index is one
 // byte permute of a mu-set word and a data word, and the byte results are
 // placed and summed with permutes and XORs (no shifts or masks):
 //   mode 2, with a = (a.b0..a.b3), p1 = a0 k3(l0), p2 = a1 k3(c32 l1),
 //   p3 = (a0 + a1) k3(l0 + l1), each p = (t1 + t2) + (t3 + t1) x4:
 //   out = [t1a t1a t1a t1a] + [t2a t3a t2a t3a] + [t1b t1b t1c t1c]
 //       + [t2b t3b 0 0] + [0 0 t2c t3c]     (bytes 0..3)
+// Mode 3: with l1 in GF(256), c32 l1 = (c16 l1) x4 has a zero low byte, so
+// the first byte of k3(c32 l1) is 0 and t1b = 0 (8 lookups instead of 9).
 AFFT_HD uint32_t mul_word_k(const uint8_t* mt, const uint4& m, uint32_t a, int mode) {
     if (mode == 0) {
         const uint32_t t0 = mt[AFFT_IX(m.x, 0, a, 0)], t1 = mt[AFFT_IX(m.x, 0, a, 1)];
@@ -205,7 +124,8 @@ AFFT_HD uint32_t mul_word_k(const uint8_t* mt, const uint4& m, uint32_t a, int m
     }
     const uint32_t sw = a ^ (a >> 16);   // low half: a0 + a1
     const uint32_t sd = sw ^ (sw >> 8);  // byte 0: its two bytes summed
-    const uint32_t t1b = mt[AFFT_IX(m.y, 0, a, 2)], t2b = mt[AFFT_IX(m.y, 1, a, 3)];
+    const uint32_t t1b = mode == 3 ? 0u : (uint32_t)mt[AFFT_IX(m.y, 0, a, 2)];
+    const uint32_t t2b = mt[AFFT_IX(m.y, 1, a, 3)];
     const uint32_t t3b = mt[AFFT_IX(m.y, 2, dd, 2)];
     const uint32_t t1c = mt[AFFT_IX(m.z, 0, sw, 0)], t2c = mt[AFFT_IX(m.z, 1, sw, 1)];
     const uint32_t t3c = mt[AFFT_IX(m.z, 2, sd, 0)];

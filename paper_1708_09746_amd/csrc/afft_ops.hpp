@@ -320,7 +320,10 @@ AFFT_HD uint64_t fft_tiles(const FftPass& A) {
     return (uint64_t)A.ncosets << ((A.log_m - A.hi) + (A.lo - A.log_tc));
 }
 
-AFFT_HD int width_mode(int w) { return w <= 8 ? 0 : (w <= 16 ? 1 : 2); }
+// Multiplication mode of a multiplier of at most w bits: 0 GF(256), 1
+// TGF(2^16), 3 TGF(2^32) with a high TGF(2^16) half in GF(256) (w <= 24), 2
+// the rest of TGF(2^32).
+AFFT_HD int width_mode(int w) { return w <= 8 ? 0 : (w <= 16 ? 1 : (w <= 24 ? 3 : 2)); }
 
 // changeRepr into the tower (Sec. 4.3) by M4R over the nibbles of a word:
 // the table of a mode holds Phi(v << 4k) (or its half) at 16 k + v.  The

@@ -256,6 +256,10 @@ int main(int argc, char** argv) {
                                      {1 << 21, 1 << 19}};
         for (auto& p : fixed) bad += !check_product(g, p[0], p[1]);
         for (int i = 0; i < 60; ++i) bad += !check_product(g, 1 + g() % (1ull << (1 + g() % 18)), 1 + g() % (1ull << (1 + g() % 18)));
+        // 2^17 and 2^18 points: the bottom layers' multipliers have 17 and 18
+        // bits (TGF(2^32) with a high half in GF(256))
+        bad += !check_product(g, 1 << 22, 1 << 22);
+        bad += !check_product(g, (1 << 23) - 77, (1 << 22) + 5);
     }
     if (what == "all" || what == "batch") bad += !check_batch(g, 60);
     if (what == "all" || what == "trunc") {

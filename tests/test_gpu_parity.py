@@ -356,6 +356,30 @@ def test_headline_product(ctx, name):
         assert hashlib.sha256(got.tobytes()).hexdigest() == g[6]
 
 
+def test_product_2p30_widest_multipliers(ctx):
+    """2^30-bit operands: 2^25 points, so the multipliers of the lowest layers
+    have up to 25 bits (the general TGF(2^32) case of the butterflies, whose
+    high TGF(2^16) half is not a byte); sampled words, and the square in full
+    against its closed form."""
+    n = 1 << 30
+    assert P.fft_log2(n, n) == 25
+    a = inputs.random_poly(0x30A, n)
+    b = inputs.random_poly(0x30B, n)
+    da = dev(a)
+    say(f"case product {n}x{n} (2^25 points)")
+    got = host(ctx.mul(da, n, dev(b), n))
+    torch.cuda.synchronize()
+    assert got.size == P.out_words(n, n)
+    rng = random.Random(30)
+    for k in [0, 1, 2, got.size - 2, got.size - 1] + [rng.randrange(got.size) for _ in range(2)]:
+        assert int(got[k]) == oracle.word(a, n, b, n, k), k
+    del got
+    say(f"case squaring {n} (2^25 points)")
+    sq = host(ctx.mul(da, n, da, n))
+    torch.cuda.synchronize()
+    assert np.array_equal(sq, spread_words(a, n))
+
+
 @pytest.mark.parametrize("n", [1 << 28])
 def test_headline_closed_forms(ctx, n):
     a = inputs.random_poly(0x28C, n)
