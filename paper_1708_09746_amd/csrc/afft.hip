@@ -28,8 +28,8 @@ __global__ __launch_bounds__(kThreads) void k_pack(PackOp P) {
 }
 
 template <int WIDE>
-__global__ __launch_bounds__(kThreads) void k_bc_tile(BcTileOp B) {
-    __shared__ uint4 lds[1 << kBcTileLog128];  // 64 KiB
+__global__ __launch_bounds__(kBcThreads) void k_bc_tile(BcTileOp B) {
+    __shared__ uint4 lds[1 << kBcTileLog128];  // 32 KiB
     const uint64_t nt = bc_tiles(B);
     for (uint64_t t = blockIdx.x; t < nt; t += gridDim.x) {
         const uint64_t tile = xcd_tile(t, gridDim.x, nt);
@@ -41,8 +41,8 @@ __global__ __launch_bounds__(kThreads) void k_bc_tile(BcTileOp B) {
 }
 
 template <int WIDE>
-__global__ __launch_bounds__(kThreads) void k_bc_class(BcClassOp C) {
-    __shared__ uint4 lds[1 << kBcTileLog128];  // 64 KiB
+__global__ __launch_bounds__(kBcThreads) void k_bc_class(BcClassOp C) {
+    __shared__ uint4 lds[1 << kBcTileLog128];  // 32 KiB
     const uint64_t nt = bc_class_tiles(C);
     for (uint64_t t = blockIdx.x; t < nt; t += gridDim.x) {
         const uint64_t tile = xcd_tile(t, gridDim.x, nt);
@@ -223,7 +223,7 @@ __global__ __launch_bounds__(kThreads) void k_pack_multi(const PackOp* ops, cons
 }
 
 template <int WIDE>
-__global__ __launch_bounds__(kThreads) void k_bc_tile_multi(const BcTileOp* ops, const uint64_t* prefix, int nops,
+__global__ __launch_bounds__(kBcThreads) void k_bc_tile_multi(const BcTileOp* ops, const uint64_t* prefix, int nops,
                                                             uint64_t total) {
     __shared__ uint4 lds[1 << kBcTileLog128];
     uint64_t g0, g1;
@@ -240,7 +240,7 @@ __global__ __launch_bounds__(kThreads) void k_bc_tile_multi(const BcTileOp* ops,
 }
 
 template <int WIDE>
-__global__ __launch_bounds__(kThreads) void k_bc_class_multi(const BcClassOp* ops, const uint64_t* prefix, int nops,
+__global__ __launch_bounds__(kBcThreads) void k_bc_class_multi(const BcClassOp* ops, const uint64_t* prefix, int nops,
                                                              uint64_t total) {
     __shared__ uint4 lds[1 << kBcTileLog128];
     uint64_t g0, g1;
@@ -761,13 +761,14 @@ void op_traffic(const Op& op, gf2x_trace_rec& r) {
 // A launch of the executor: with tracing on, the start and stop events ride
 // in the dispatch itself (hipExtLaunchKernelGGL), so the recorded time is the
 // kernel's own, as a profiler measures it.
-#define GF2X_LAUNCH(K, GRID, ...)                                                                          \
-    do {                                                                                                   \
-        if (traced)                                                                                        \
-            hipExtLaunchKernelGGL(K, GRID, dim3(kThreads), 0, st, pend.start, pend.stop, 0, __VA_ARGS__); \
-        else                                                                                               \
-            hipLaunchKernelGGL(K, GRID, dim3(kThreads), 0, st, __VA_ARGS__);                               \
+#define GF2X_LAUNCH_N(K, GRID, NT, ...)                                                               \
+    do {                                                                                              \
+        if (traced)                                                                                   \
+            hipExtLaunchKernelGGL(K, GRID, dim3(NT), 0, st, pend.start, pend.stop, 0, __VA_ARGS__); \
+        else                                                                                          \
+            hipLaunchKernelGGL(K, GRID, dim3(NT), 0, st, __VA_ARGS__);                               \
     } while (0)
+#define GF2X_LAUNCH(K, GRID, ...) GF2X_LAUNCH_N(K, GRID, kThreads, __VA_ARGS__)
 
 int run_ops(gf2x_ctx* ctx, const std::vector<Op>& ops, hipStream_t st) {
     const uint64_t ncu = (uint64_t)ctx->ncu;
@@ -786,9 +787,9 @@ int run_ops(gf2x_ctx* ctx, const std::vector<Op>& ops, hipStream_t st) {
                 break;
             case OpKind::BcTile:
                 if (op.bct.wide)
-                    GF2X_LAUNCH(k_bc_tile<1>, dim3(grid_for(bc_tiles(op.bct), 2 * ncu)), op.bct);
+                    GF2X_LAUNCH_N(k_bc_tile<1>, dim3(grid_for(bc_tiles(op.bct), 4 * ncu)), kBcThreads, op.bct);
                 else
-                    GF2X_LAUNCH(k_bc_tile<0>, dim3(grid_for(bc_tiles(op.bct), 2 * ncu)), op.bct);
+                    GF2X_LAUNCH_N(k_bc_tile<0>, dim3(grid_for(bc_tiles(op.bct), 4 * ncu)), kBcThreads, op.bct);
                 break;
             case OpKind::BcLayer: {
                 uint64_t items = op.bcl.nelem / 2;
@@ -816,9 +817,9 @@ int run_ops(gf2x_ctx* ctx, const std::vector<Op>& ops, hipStream_t st) {
                 break;
             case OpKind::BcClass:
                 if (op.bcc.wide)
-                    GF2X_LAUNCH(k_bc_class<1>, dim3(grid_for(bc_class_tiles(op.bcc), 2 * ncu)), op.bcc);
+                    GF2X_LAUNCH_N(k_bc_class<1>, dim3(grid_for(bc_class_tiles(op.bcc), 4 * ncu)), kBcThreads, op.bcc);
                 else
-                    GF2X_LAUNCH(k_bc_class<0>, dim3(grid_for(bc_class_tiles(op.bcc), 2 * ncu)), op.bcc);
+                    GF2X_LAUNCH_N(k_bc_class<0>, dim3(grid_for(bc_class_tiles(op.bcc), 4 * ncu)), kBcThreads, op.bcc);
                 break;
             case OpKind::Psi:
                 GF2X_LAUNCH(k_psi, dim3(grid_for(psi_tiles(op.psi), 2 * ncu)), op.psi,
@@ -893,18 +894,18 @@ int launch_groups(gf2x_ctx* ctx, const std::vector<LaunchGroup>& groups, const c
                 break;
             case OpKind::BcTile:
                 if (G.wide)
-                    hipLaunchKernelGGL(k_bc_tile_multi<1>, dim3(grid_for(G.total, 2 * ncu)), dim3(kThreads), 0, st,
+                    hipLaunchKernelGGL(k_bc_tile_multi<1>, dim3(grid_for(G.total, 4 * ncu)), dim3(kBcThreads), 0, st,
                                        (const BcTileOp*)ops, prefix, G.nops, G.total);
                 else
-                    hipLaunchKernelGGL(k_bc_tile_multi<0>, dim3(grid_for(G.total, 2 * ncu)), dim3(kThreads), 0, st,
+                    hipLaunchKernelGGL(k_bc_tile_multi<0>, dim3(grid_for(G.total, 4 * ncu)), dim3(kBcThreads), 0, st,
                                        (const BcTileOp*)ops, prefix, G.nops, G.total);
                 break;
             case OpKind::BcClass:
                 if (G.wide)
-                    hipLaunchKernelGGL(k_bc_class_multi<1>, dim3(grid_for(G.total, 2 * ncu)), dim3(kThreads), 0, st,
+                    hipLaunchKernelGGL(k_bc_class_multi<1>, dim3(grid_for(G.total, 4 * ncu)), dim3(kBcThreads), 0, st,
                                        (const BcClassOp*)ops, prefix, G.nops, G.total);
                 else
-                    hipLaunchKernelGGL(k_bc_class_multi<0>, dim3(grid_for(G.total, 2 * ncu)), dim3(kThreads), 0, st,
+                    hipLaunchKernelGGL(k_bc_class_multi<0>, dim3(grid_for(G.total, 4 * ncu)), dim3(kBcThreads), 0, st,
                                        (const BcClassOp*)ops, prefix, G.nops, G.total);
                 break;
             case OpKind::BcLayer:
