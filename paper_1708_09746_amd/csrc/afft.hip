@@ -27,9 +27,11 @@ __global__ __launch_bounds__(kThreads) void k_pack(PackOp P) {
     for (uint64_t t = blockIdx.x; t < nt; t += gridDim.x) pack_tile(threadIdx.x, blockDim.x, t, P);
 }
 
-template <int WIDE>
-__global__ __launch_bounds__(kBcThreads) void k_bc_tile(BcTileOp B) {
-    __shared__ uint4 lds[1 << kBcTileLog128];  // 32 KiB
+// SMALL: a 32 KiB tile (single products) on a 512-thread block, else a 64 KiB
+// tile on a 1024-thread block
+template <int WIDE, int SMALL>
+__global__ __launch_bounds__(SMALL ? kBcThreadsSmall : kThreads) void k_bc_tile(BcTileOp B) {
+    __shared__ uint4 lds[(1 << kBcTileLog128) >> (SMALL ? kBcSmallShift : 0)];
     const uint64_t nt = bc_tiles(B);
     for (uint64_t t = blockIdx.x; t < nt; t += gridDim.x) {
         const uint64_t tile = xcd_tile(t, gridDim.x, nt);
@@ -40,9 +42,9 @@ __global__ __launch_bounds__(kBcThreads) void k_bc_tile(BcTileOp B) {
     }
 }
 
-template <int WIDE>
-__global__ __launch_bounds__(kBcThreads) void k_bc_class(BcClassOp C) {
-    __shared__ uint4 lds[1 << kBcTileLog128];  // 32 KiB
+template <int WIDE, int SMALL>
+__global__ __launch_bounds__(SMALL ? kBcThreadsSmall : kThreads) void k_bc_class(BcClassOp C) {
+    __shared__ uint4 lds[(1 << kBcTileLog128) >> (SMALL ? kBcSmallShift : 0)];
     const uint64_t nt = bc_class_tiles(C);
     for (uint64_t t = blockIdx.x; t < nt; t += gridDim.x) {
         const uint64_t tile = xcd_tile(t, gridDim.x, nt);
@@ -223,9 +225,9 @@ __global__ __launch_bounds__(kThreads) void k_pack_multi(const PackOp* ops, cons
 }
 
 template <int WIDE>
-__global__ __launch_bounds__(kBcThreads) void k_bc_tile_multi(const BcTileOp* ops, const uint64_t* prefix, int nops,
+__global__ __launch_bounds__(kThreads) void k_bc_tile_multi(const BcTileOp* ops, const uint64_t* prefix, int nops,
                                                             uint64_t total) {
-    __shared__ uint4 lds[1 << kBcTileLog128];
+    __shared__ uint4 lds[1 << kBcTileLog128];  // 64 KiB
     uint64_t g0, g1;
     block_chunk(total, g0, g1);
     int o = -1;
@@ -240,9 +242,9 @@ __global__ __launch_bounds__(kBcThreads) void k_bc_tile_multi(const BcTileOp* op
 }
 
 template <int WIDE>
-__global__ __launch_bounds__(kBcThreads) void k_bc_class_multi(const BcClassOp* ops, const uint64_t* prefix, int nops,
+__global__ __launch_bounds__(kThreads) void k_bc_class_multi(const BcClassOp* ops, const uint64_t* prefix, int nops,
                                                              uint64_t total) {
-    __shared__ uint4 lds[1 << kBcTileLog128];
+    __shared__ uint4 lds[1 << kBcTileLog128];  // 64 KiB
     uint64_t g0, g1;
     block_chunk(total, g0, g1);
     int o = -1;
@@ -785,12 +787,20 @@ int run_ops(gf2x_ctx* ctx, const std::vector<Op>& ops, hipStream_t st) {
             case OpKind::Pack:
                 GF2X_LAUNCH(k_pack, dim3(grid_for(pack_tiles(op.pack), 8 * ncu)), op.pack);
                 break;
-            case OpKind::BcTile:
-                if (op.bct.wide)
-                    GF2X_LAUNCH_N(k_bc_tile<1>, dim3(grid_for(bc_tiles(op.bct), 4 * ncu)), kBcThreads, op.bct);
+            case OpKind::BcTile: {
+                const bool small = (int)(op.bct.log_rows + op.bct.log_tc) <=
+                                   (op.bct.wide ? kBcTileLog128 : kBcTileLog64) - kBcSmallShift;
+                const dim3 g(grid_for(bc_tiles(op.bct), (small ? 4 : 2) * ncu));
+                if (small && op.bct.wide)
+                    GF2X_LAUNCH_N((k_bc_tile<1, 1>), g, kBcThreadsSmall, op.bct);
+                else if (small)
+                    GF2X_LAUNCH_N((k_bc_tile<0, 1>), g, kBcThreadsSmall, op.bct);
+                else if (op.bct.wide)
+                    GF2X_LAUNCH_N((k_bc_tile<1, 0>), g, kThreads, op.bct);
                 else
-                    GF2X_LAUNCH_N(k_bc_tile<0>, dim3(grid_for(bc_tiles(op.bct), 4 * ncu)), kBcThreads, op.bct);
+                    GF2X_LAUNCH_N((k_bc_tile<0, 0>), g, kThreads, op.bct);
                 break;
+            }
             case OpKind::BcLayer: {
                 uint64_t items = op.bcl.nelem / 2;
                 uint64_t blocks = (items + kThreads - 1) / kThreads;
@@ -815,12 +825,20 @@ int run_ops(gf2x_ctx* ctx, const std::vector<Op>& ops, hipStream_t st) {
                 GF2X_LAUNCH(k_pmul, dim3(grid_for(pmul_tiles(op.pmul), 2 * ncu)), op.pmul,
                                    (const uint8_t*)ctx->d_mt, (const uint32_t*)ctx->d_ctab);
                 break;
-            case OpKind::BcClass:
-                if (op.bcc.wide)
-                    GF2X_LAUNCH_N(k_bc_class<1>, dim3(grid_for(bc_class_tiles(op.bcc), 4 * ncu)), kBcThreads, op.bcc);
+            case OpKind::BcClass: {
+                const bool small = (uint64_t)op.bcc.q_rows << op.bcc.log_w <=
+                                   (1ull << ((op.bcc.wide ? kBcTileLog128 : kBcTileLog64) - kBcSmallShift));
+                const dim3 g(grid_for(bc_class_tiles(op.bcc), (small ? 4 : 2) * ncu));
+                if (small && op.bcc.wide)
+                    GF2X_LAUNCH_N((k_bc_class<1, 1>), g, kBcThreadsSmall, op.bcc);
+                else if (small)
+                    GF2X_LAUNCH_N((k_bc_class<0, 1>), g, kBcThreadsSmall, op.bcc);
+                else if (op.bcc.wide)
+                    GF2X_LAUNCH_N((k_bc_class<1, 0>), g, kThreads, op.bcc);
                 else
-                    GF2X_LAUNCH_N(k_bc_class<0>, dim3(grid_for(bc_class_tiles(op.bcc), 4 * ncu)), kBcThreads, op.bcc);
+                    GF2X_LAUNCH_N((k_bc_class<0, 0>), g, kThreads, op.bcc);
                 break;
+            }
             case OpKind::Psi:
                 GF2X_LAUNCH(k_psi, dim3(grid_for(psi_tiles(op.psi), 2 * ncu)), op.psi,
                                    (const uint4*)ctx->d_psi);
@@ -894,18 +912,18 @@ int launch_groups(gf2x_ctx* ctx, const std::vector<LaunchGroup>& groups, const c
                 break;
             case OpKind::BcTile:
                 if (G.wide)
-                    hipLaunchKernelGGL(k_bc_tile_multi<1>, dim3(grid_for(G.total, 4 * ncu)), dim3(kBcThreads), 0, st,
+                    hipLaunchKernelGGL(k_bc_tile_multi<1>, dim3(grid_for(G.total, 2 * ncu)), dim3(kThreads), 0, st,
                                        (const BcTileOp*)ops, prefix, G.nops, G.total);
                 else
-                    hipLaunchKernelGGL(k_bc_tile_multi<0>, dim3(grid_for(G.total, 4 * ncu)), dim3(kBcThreads), 0, st,
+                    hipLaunchKernelGGL(k_bc_tile_multi<0>, dim3(grid_for(G.total, 2 * ncu)), dim3(kThreads), 0, st,
                                        (const BcTileOp*)ops, prefix, G.nops, G.total);
                 break;
             case OpKind::BcClass:
                 if (G.wide)
-                    hipLaunchKernelGGL(k_bc_class_multi<1>, dim3(grid_for(G.total, 4 * ncu)), dim3(kBcThreads), 0, st,
+                    hipLaunchKernelGGL(k_bc_class_multi<1>, dim3(grid_for(G.total, 2 * ncu)), dim3(kThreads), 0, st,
                                        (const BcClassOp*)ops, prefix, G.nops, G.total);
                 else
-                    hipLaunchKernelGGL(k_bc_class_multi<0>, dim3(grid_for(G.total, 4 * ncu)), dim3(kBcThreads), 0, st,
+                    hipLaunchKernelGGL(k_bc_class_multi<0>, dim3(grid_for(G.total, 2 * ncu)), dim3(kThreads), 0, st,
                                        (const BcClassOp*)ops, prefix, G.nops, G.total);
                 break;
             case OpKind::BcLayer:
@@ -1414,6 +1432,14 @@ int tune_time(gf2x_ctx* ctx, TuneBuffers& T, const PlanParams& pp, int M, int co
 
 // ------------------------------------------------------------------ C ABI
 
+// Plans of single products (run op by op on their own kernels) take the small
+// BasisCvt tiles; batches and the server plan with ctx->params.
+PlanParams single_params(const gf2x_ctx* ctx) {
+    PlanParams pp = ctx->params;
+    pp.bc_small = 1;
+    return pp;
+}
+
 extern "C" {
 
 const char* gf2x_strerror(int status) {
@@ -1564,7 +1590,7 @@ int gf2x_mul_dev(gf2x_ctx* ctx, const uint64_t* a, uint64_t na_bits, const uint6
     int rc = ensure_ws(ctx, w.bytes, st);
     if (rc) return rc;
     std::vector<Op> ops;
-    plan_mul(ops, ctx->pool, ctx->params, s, a, b, c, ctx->ws);
+    plan_mul(ops, ctx->pool, single_params(ctx), s, a, b, c, ctx->ws);
     return run_ops(ctx, ops, st);
 }
 
@@ -1581,7 +1607,8 @@ int gf2x_forward_dev(gf2x_ctx* ctx, const uint64_t* a, uint64_t na_bits, int log
     int rc = ensure_ws(ctx, align256(8ull << m_a), st);
     if (rc) return rc;
     std::vector<Op> ops;
-    emit_forward(ops, ctx->pool, ctx->params, a, na_bits, (uint64_t*)ctx->ws, m_a, (uint4*)spec, log2n, 1ull << log2n);
+    emit_forward(ops, ctx->pool, single_params(ctx), a, na_bits, (uint64_t*)ctx->ws, m_a, (uint4*)spec, log2n,
+                 1ull << log2n);
     return run_ops(ctx, ops, st);
 }
 
@@ -1606,7 +1633,7 @@ int gf2x_inverse_dev(gf2x_ctx* ctx, void* spec, int log2n, uint64_t* c, uint64_t
         return fail(ctx, GF2X_EINVAL, "output overlaps the spectrum");
     DeviceGuard g(ctx->device);
     std::vector<Op> ops;
-    emit_inverse(ops, ctx->pool, ctx->params, (uint4*)spec, log2n, 1ull << log2n, c, nc_bits);
+    emit_inverse(ops, ctx->pool, single_params(ctx), (uint4*)spec, log2n, 1ull << log2n, c, nc_bits);
     return run_ops(ctx, ops, (hipStream_t)stream);
 }
 
@@ -1617,7 +1644,7 @@ int gf2x_basiscvt_dev(gf2x_ctx* ctx, uint64_t* words, int log2n, int inverse, vo
     if (log2n < 0 || log2n > 40) return fail(ctx, GF2X_ERANGE, "log2n out of range");
     DeviceGuard g(ctx->device);
     std::vector<Op> ops;
-    emit_bc(ops, ctx->pool, words, 0, log2n, inverse ? 1 : 0);
+    emit_bc(ops, ctx->pool, words, 0, log2n, inverse ? 1 : 0, 1);
     return run_ops(ctx, ops, (hipStream_t)stream);
 }
 

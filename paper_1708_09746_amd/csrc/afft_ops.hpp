@@ -24,12 +24,16 @@ constexpr int kMuLoN = 447, kMuHiN = 69;
 constexpr int kMuHiBase = kMuLoN;
 constexpr int kMuHiCur = kMuHiBase + kMuHiN;
 constexpr int kMuEntries = kMuHiCur + kMuHiN;
-// BasisCvt tiles (32 KiB) and the blocks of their kernels: the layer sweeps
-// are bound by their barriers, so four blocks of 512 threads per CU, which
-// interleave their barriers, serve them better than two of 1024.
-constexpr int kBcTileLog64 = 12;  // BasisCvt tile on 64-bit words: 32 KiB
-constexpr int kBcTileLog128 = 11; // BasisCvt tile on 128-bit elements: 32 KiB
-constexpr int kBcThreads = 512;   // threads per block of the BasisCvt tile and class kernels
+// BasisCvt tiles: 64 KiB, or 32 KiB for single products (PlanParams::bc_small),
+// whose tile and class passes run on blocks of 512 threads: the layer sweeps
+// are bound by their barriers, and four blocks of 512 threads per CU
+// interleave them better than two of 1024.  Batches and the serving engine
+// keep the 64 KiB tiles: their multi-op and persistent kernels run 1024-thread
+// blocks, for which a halved tile only doubles the barriers per element.
+constexpr int kBcTileLog64 = 13;  // BasisCvt tile on 64-bit words: 64 KiB
+constexpr int kBcTileLog128 = 12; // BasisCvt tile on 128-bit elements: 64 KiB
+constexpr int kBcSmallShift = 1;  // a small tile holds half the elements
+constexpr int kBcThreadsSmall = 512;
 constexpr int kPmulTile = 1024;
 constexpr int kPsiTile = 1024;
 constexpr int kPackTile = 4096;

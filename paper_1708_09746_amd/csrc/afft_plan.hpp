@@ -124,6 +124,8 @@ struct PlanParams {
     int trunc_min_log = 22;
     // word width of Split: 64 (TGF(2^128)) or 128 (TGF(2^256), never truncated)
     int word_bits = 64;
+    // 1: BasisCvt on 32 KiB tiles (single products; see kBcSmallShift)
+    int bc_small = 0;
     const uint32_t* lam = nullptr;
     const uint8_t* mt = nullptr;
     PlanParams() {
@@ -215,8 +217,9 @@ struct BcPlanner {
 
 // Emit BasisCvt (or its inverse) of 2^m elements at `data`: the forward op
 // list, reversed (each op running its layers backwards) for the inverse.
-inline void emit_bc(std::vector<Op>& ops, const LayerPool& pool, void* data, int wide, int m, int inverse) {
-    BcPlanner P{data, wide, 1ull << m, wide ? kBcTileLog128 : kBcTileLog64, &pool, {}};
+inline void emit_bc(std::vector<Op>& ops, const LayerPool& pool, void* data, int wide, int m, int inverse,
+                    int small = 0) {
+    BcPlanner P{data, wide, 1ull << m, (wide ? kBcTileLog128 : kBcTileLog64) - (small ? kBcSmallShift : 0), &pool, {}};
     P.cvt(m, 0);
     if (!inverse) {
         for (auto& op : P.ops) ops.push_back(op);
@@ -440,7 +443,7 @@ inline Workspace workspace_for(const Sizes& s) {
 inline void emit_forward(std::vector<Op>& ops, const LayerPool& pool, const PlanParams& pp, const uint64_t* src,
                          uint64_t nbits, uint64_t* words, int m_op, uint4* spec, int m, uint64_t M) {
     emit_pack(ops, src, nbits, words, 1ull << m_op);
-    emit_bc(ops, pool, words, 0, m_op, 0);
+    emit_bc(ops, pool, words, 0, m_op, 0, pp.bc_small);
     if (M == (1ull << m)) {
         emit_fft_forward(ops, pp, words, spec, m_op, m - m_op);
         return;
@@ -464,7 +467,7 @@ inline void emit_inverse(std::vector<Op>& ops, const LayerPool& pool, const Plan
         emit_fft_inverse(ops, pp, spec, m);
     else
         emit_inv_spine(ops, pp, spec, 0, m, M, m);  // pointmul wrote zeros at M and beyond
-    emit_bc(ops, pool, spec, 1, m, 1);
+    emit_bc(ops, pool, spec, 1, m, 1, pp.bc_small);
     emit_psi(ops, spec, 1ull << m, out, nc_bits);
 }
 
@@ -486,7 +489,7 @@ inline void plan_mul128(std::vector<Op>& ops, const LayerPool& pool, const PlanP
     auto forward = [&](const uint64_t* src, uint64_t nbits, uint4* words, int m_op, uint4* spec) {
         std::vector<Op> pre, pl[2];
         emit_pack(pre, src, nbits, (uint64_t*)words, 2ull << m_op);
-        emit_bc(pre, pool, words, 1, m_op, 0);
+        emit_bc(pre, pool, words, 1, m_op, 0, pp.bc_small);
         for (int h = 0; h < 2; ++h)
             emit_fft_block(pl[h], pp, words, spec + h * N, m_op, 0, 1u << (s.m - m_op), s.m, false,
                            h ? kPhi128Hi : kPhi128Lo);
@@ -512,7 +515,7 @@ inline void plan_mul128(std::vector<Op>& ops, const LayerPool& pool, const PlanP
     std::vector<Op> inv[2];
     for (int h = 0; h < 2; ++h) {
         emit_fft_inverse(inv[h], pp, sb + h * N, s.m);
-        emit_bc(inv[h], pool, sb + h * N, 1, s.m, 1);
+        emit_bc(inv[h], pool, sb + h * N, 1, s.m, 1, pp.bc_small);
     }
     for (size_t q = 0; q < inv[0].size(); ++q)
         for (int h = 0; h < 2; ++h) {

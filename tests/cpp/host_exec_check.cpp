@@ -175,7 +175,7 @@ bool same(uint64_t a, uint64_t b) { return a == b; }
 bool same(uint4 a, uint4 b) { return a.x == b.x && a.y == b.y && a.z == b.z && a.w == b.w; }
 
 template <typename T>
-bool check_basiscvt(int m) {
+bool check_basiscvt(int m, int small) {
     std::mt19937_64 g(1000 + m);
     const uint64_t n = 1ull << m;
     std::vector<T> a(n), flat, orig;
@@ -184,7 +184,7 @@ bool check_basiscvt(int m) {
     orig = a;
     const int wide = sizeof(T) == 16;
     std::vector<Op> ops;
-    emit_bc(ops, POOL, a.data(), wide, m, 0);
+    emit_bc(ops, POOL, a.data(), wide, m, 0, small);
     run_ops(ops);
     std::vector<BcLayer> L;
     bc_layer_list(m, 0, L);
@@ -193,10 +193,10 @@ bool check_basiscvt(int m) {
     bool ok = true;
     for (uint64_t i = 0; i < n && ok; ++i) ok = same(a[i], flat[i]);
     std::vector<Op> inv;
-    emit_bc(inv, POOL, a.data(), wide, m, 1);
+    emit_bc(inv, POOL, a.data(), wide, m, 1, small);
     run_ops(inv);
     for (uint64_t i = 0; i < n && ok; ++i) ok = same(a[i], orig[i]);
-    if (!ok) printf("BasisCvt MISMATCH m = %d, %s\n", m, wide ? "128-bit" : "64-bit");
+    if (!ok) printf("BasisCvt MISMATCH m = %d, %s, %s tiles\n", m, wide ? "128-bit" : "64-bit", small ? "small" : "large");
     return ok;
 }
 
@@ -256,6 +256,10 @@ int main(int argc, char** argv) {
                                      {1 << 21, 1 << 19}};
         for (auto& p : fixed) bad += !check_product(g, p[0], p[1]);
         for (int i = 0; i < 60; ++i) bad += !check_product(g, 1 + g() % (1ull << (1 + g() % 18)), 1 + g() % (1ull << (1 + g() % 18)));
+        // the small BasisCvt tiles of single products
+        PP.bc_small = 1;
+        for (auto& p : fixed) bad += !check_product(g, p[0], p[1]);
+        PP.bc_small = 0;
         // 2^17 and 2^18 points: the bottom layers' multipliers have 17 and 18
         // bits (TGF(2^32) with a high half in GF(256))
         bad += !check_product(g, 1 << 22, 1 << 22);
@@ -287,8 +291,10 @@ int main(int argc, char** argv) {
     if (what == "all" || what == "basiscvt") {
         // 22 and 23: the strided pass of 2^6 / 2^7-row columns above the
         // top class pass, as in products of 2^28-bit operands
-        for (int m : {0, 1, 2, 5, 12, 13, 14, 16, 17, 20, 22}) bad += !check_basiscvt<uint64_t>(m);
-        for (int m : {11, 12, 13, 16, 19, 23}) bad += !check_basiscvt<uint4>(m);
+        for (int small = 0; small < 2; ++small) {
+            for (int m : {0, 1, 2, 5, 12, 13, 14, 16, 17, 20, 22}) bad += !check_basiscvt<uint64_t>(m, small);
+            for (int m : {11, 12, 13, 16, 19, 23}) bad += !check_basiscvt<uint4>(m, small);
+        }
     }
     printf(bad ? "host exec: %d failures\n" : "host exec ok\n", bad);
     return bad ? 1 : 0;
