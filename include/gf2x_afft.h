@@ -76,8 +76,11 @@ size_t gf2x_out_words(uint64_t na_bits, uint64_t nb_bits);
 int gf2x_fft_log2(uint64_t na_bits, uint64_t nb_bits);
 
 /* Device workspace bytes one product of these sizes needs (two N-point spectra
- * plus the converted operand words). */
+ * plus the converted operand words), with Split into 64-bit words. */
 size_t gf2x_workspace_bytes(uint64_t na_bits, uint64_t nb_bits);
+/* The same for a word width w of 64 or 128 bits (0 for any other w): the
+ * footprint a server admits a request by on a context of that width. */
+size_t gf2x_workspace_bytes_w(uint64_t na_bits, uint64_t nb_bits, int w);
 
 /* c = a * b with HOST pointers; blocking.  Uses a process-wide context on the
  * current HIP device (created on first use, guarded by a mutex); copies the

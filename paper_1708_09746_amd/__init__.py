@@ -86,6 +86,7 @@ def lib():
             "gf2x_out_words": (sz, [u64, u64]),
             "gf2x_fft_log2": (i32, [u64, u64]),
             "gf2x_workspace_bytes": (sz, [u64, u64]),
+            "gf2x_workspace_bytes_w": (sz, [u64, u64, i32]),
             "gf2x_mul": (i32, [vp, u64, vp, u64, vp]),
             "gf2x_mul_dev": (i32, [vp, vp, u64, vp, u64, vp, vp]),
             "gf2x_forward_dev": (i32, [vp, vp, u64, i32, vp, vp]),
@@ -143,8 +144,11 @@ def fft_log2(na_bits: int, nb_bits: int) -> int:
     return int(lib().gf2x_fft_log2(na_bits, nb_bits))
 
 
-def workspace_bytes(na_bits: int, nb_bits: int) -> int:
-    return int(lib().gf2x_workspace_bytes(na_bits, nb_bits))
+def workspace_bytes(na_bits: int, nb_bits: int, w: int = 64) -> int:
+    """Device workspace of one product with Split into w-bit words (64 or 128)."""
+    if w == 64:
+        return int(lib().gf2x_workspace_bytes(na_bits, nb_bits))
+    return int(lib().gf2x_workspace_bytes_w(na_bits, nb_bits, w))
 
 
 def strerror(code: int) -> str:

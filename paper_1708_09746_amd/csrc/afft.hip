@@ -1467,6 +1467,11 @@ size_t gf2x_workspace_bytes(uint64_t na_bits, uint64_t nb_bits) {
     return workspace_for(make_sizes(na_bits, nb_bits)).bytes;
 }
 
+size_t gf2x_workspace_bytes_w(uint64_t na_bits, uint64_t nb_bits, int w) {
+    if (!na_bits || !nb_bits || (w != 64 && w != 128)) return 0;
+    return workspace_for(make_sizes(na_bits, nb_bits, w)).bytes;
+}
+
 int gf2x_ctx_create(gf2x_ctx** out, int device) {
     if (!out) return GF2X_EINVAL;
     *out = nullptr;

@@ -43,6 +43,27 @@ def test_workspace_grows_with_size():
     assert 0 < small < big
 
 
+def test_workspace_by_word_width():
+    """Workspace = converted words + two spectra, each 256-byte aligned; for
+    w = 128 the words are 16 bytes and a spectrum is two planes of 16-byte
+    halves (the same bytes as w = 64 for large balanced products)."""
+    def al(x):
+        return (x + 255) // 256 * 256
+
+    def expect(na, nb, w):
+        ka, kb = (na + w - 1) // w, (nb + w - 1) // w
+        ma, mb = (ka - 1).bit_length(), (kb - 1).bit_length()
+        m = max(1, (ka + kb - 2).bit_length())
+        return al((w // 8) << ma) + al((w // 8) << mb) + 2 * al((16 * w // 64) << m)
+
+    for na, nb in [(1, 1), (64, 64), (65, 64), (128, 129), (1000, 7), (1 << 20, 1 << 19), (1 << 28, 1 << 28)]:
+        assert P.workspace_bytes(na, nb) == expect(na, nb, 64), (na, nb)
+        assert P.workspace_bytes(na, nb, 128) == expect(na, nb, 128), (na, nb)
+    assert P.workspace_bytes(1 << 28, 1 << 28, 128) == P.workspace_bytes(1 << 28, 1 << 28)
+    assert P.lib().gf2x_workspace_bytes_w(100, 100, 96) == 0
+    assert P.lib().gf2x_workspace_bytes_w(0, 100, 128) == 0
+
+
 def test_status_names():
     for code in (0, -1, -2, -3, -4):
         assert P.strerror(code)
