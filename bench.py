@@ -341,8 +341,9 @@ def bench_serving(ctx, nreq=10000, fracs=(0.1, 0.25, 0.5, 0.75, 0.9), arena_gib=
 def bench_sizes(P, ctx, runs=50):
     """Single products at the other configured sizes, operands resident: the
     latency of one call (2^16 and 2^20 bits: launch- and on-chip-bound; median
-    and p99 of `runs` calls, each timed by events on its stream) and the time
-    per product at 2^29 bits."""
+    and p99 of `runs` calls, each timed by events on its stream), also as a
+    reusable one-job batch replayed as a graph, and the time per product at
+    2^29 bits."""
     import numpy as np
     import torch
 
@@ -371,6 +372,26 @@ def bench_sizes(P, ctx, runs=50):
         out[name] = {"workload": desc, "runs": reps, "median_ms": round(ts[len(ts) // 2], 4),
                      "p99_ms": round(ts[min(len(ts) - 1, int(0.99 * len(ts)))], 4),
                      "fft_points": 1 << P.fft_log2(n, n)}
+        if name != "c3b":
+            # the same product as a reusable one-job batch: its launches replay
+            # as one hipGraph
+            B = ctx.batch([(a, n, b, n, c)])
+            for _ in range(3):
+                B.run(stream)
+            torch.cuda.synchronize()
+            gs = []
+            for _ in range(reps):
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+                B.run(stream)
+                e1.record(stream)
+                e1.synchronize()
+                gs.append(e0.elapsed_time(e1))
+            B.check()
+            B.close()
+            gs.sort()
+            out[name]["graph_median_ms"] = round(gs[len(gs) // 2], 4)
+            out[name]["graph_p99_ms"] = round(gs[min(len(gs) - 1, int(0.99 * len(gs)))], 4)
         if name in PAPER_MS:
             out[name]["paper_ms"] = PAPER_MS[name]
         del a, b, c
