@@ -826,7 +826,7 @@ int run_ops(gf2x_ctx* ctx, const std::vector<Op>& ops, hipStream_t st) {
                                    (const uint8_t*)ctx->d_mt, (const uint32_t*)ctx->d_ctab);
                 break;
             case OpKind::BcClass: {
-                const bool small = (uint64_t)op.bcc.q_rows << op.bcc.log_w <=
+                const bool small = (uint64_t)op.bcc.q_rows * op.bcc.w <=
                                    (1ull << ((op.bcc.wide ? kBcTileLog128 : kBcTileLog64) - kBcSmallShift));
                 const dim3 g(grid_for(bc_class_tiles(op.bcc), (small ? 4 : 2) * ncu));
                 if (small && op.bcc.wide)

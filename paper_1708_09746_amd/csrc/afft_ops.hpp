@@ -195,19 +195,26 @@ AFFT_HD void bc_tile(int tid, int nt, uint64_t tile, const BcTileOp& B, T* lds) 
 // mod P = 2^K - 1.  Writing t = q P + r, a tile holds the positions
 // x = r 2^log_u + c in [x0, x0 + W) of every row q (Q rows cover the block);
 // the layer becomes  row[q - 2^j] ^= row[q]  for the rows whose t has
-// t mod 2D in the layer's source range.
+// t mod 2D in the layer's source range.  Q is always just above a power of
+// two (2^m / P = 2^(m-K) (1 + 2^-K + ...)), so W is not restricted to powers
+// of two: the tile holds Q W elements, close to its capacity; element e of
+// the tile is row e / W (exact as (e ceil(2^32 / W)) >> 32 for e < 2^14).
 struct BcClassOp {
     void* data;
     uint64_t nelem;
     uint32_t m, K, log_u;
-    uint32_t log_w;   // W = 2^log_w positions per tile
+    uint32_t w;       // W positions per tile
     uint32_t q_rows;  // Q = ceil(2^m / P)
     uint32_t wide, inverse, pad;
+    uint64_t w_magic;  // ceil(2^32 / W)
 };
+
+static_assert(kBcTileLog64 < 14, "class tile rows come from a multiply-shift that is exact below 2^14 elements");
+AFFT_HD uint32_t bc_class_row(const BcClassOp& C, uint32_t e) { return (uint32_t)((e * C.w_magic) >> 32); }
 
 AFFT_HD uint64_t bc_class_tiles_per_block(const BcClassOp& C) {
     uint64_t X = ((1ull << C.K) - 1) << C.log_u;
-    return (X + (1ull << C.log_w) - 1) >> C.log_w;
+    return (X + C.w - 1) / C.w;
 }
 AFFT_HD uint64_t bc_class_tiles(const BcClassOp& C) {
     return (C.nelem >> (C.m + C.log_u)) * bc_class_tiles_per_block(C);
@@ -225,13 +232,14 @@ struct BcClassGeom {
 AFFT_HD BcClassGeom bc_class_geom(const BcClassOp& C, uint64_t tile) {
     const uint64_t tpb = bc_class_tiles_per_block(C);
     const uint64_t blk = tile / tpb;
-    return BcClassGeom{blk << (C.m + C.log_u), (tile - blk * tpb) << C.log_w, C.q_rows << C.log_w};
+    return BcClassGeom{blk << (C.m + C.log_u), (tile - blk * tpb) * C.w, C.q_rows * C.w};
 }
 
 // Offset of element e in its block, or ~0 if it is absent.
 AFFT_HD uint64_t bc_class_off(const BcClassOp& C, const BcClassGeom& G, uint32_t e) {
     const uint64_t P = (1ull << C.K) - 1, X = P << C.log_u;
-    const uint64_t q = e >> C.log_w, x = G.x0 + (e & ((1u << C.log_w) - 1));
+    const uint32_t qe = bc_class_row(C, e);
+    const uint64_t q = qe, x = G.x0 + (e - qe * C.w);
     if (x >= X || q * P + (x >> C.log_u) >= (1ull << C.m)) return ~0ull;
     return q * X + x;
 }
@@ -240,7 +248,6 @@ template <typename T>
 AFFT_HD void bc_class_layers(int tid, int nt, const BcClassOp& C, const BcClassGeom& G, T* lds) {
     const uint64_t P = (1ull << C.K) - 1;
     const uint64_t X = P << C.log_u;
-    const uint32_t lw = C.log_w, wm = (1u << lw) - 1;
     const uint64_t nunits = 1ull << C.m;
     const uint32_t ne = G.ne;
     const int nl = (int)(C.m - C.K);
@@ -254,11 +261,12 @@ AFFT_HD void bc_class_layers(int tid, int nt, const BcClassOp& C, const BcClassG
     for (int li = 0; li < nl; ++li) {
         const int j = C.inverse ? li : nl - 1 - li;
         const uint64_t D = 1ull << (C.K + j), k = 1ull << j;
-        const uint32_t rs = (uint32_t)k << lw;  // k rows
+        const uint32_t rs = (uint32_t)k * C.w;  // k rows
         for (uint32_t e = tid; e < ne; e += nt) {
-            const uint64_t x = G.x0 + (e & wm);
+            const uint32_t qe = bc_class_row(C, e);
+            const uint64_t x = G.x0 + (e - qe * C.w);
             if (x >= X) continue;
-            const uint64_t t = (uint64_t)(e >> lw) * P + (x >> C.log_u);
+            const uint64_t t = (uint64_t)qe * P + (x >> C.log_u);
             if (t >= nunits) continue;
             const uint64_t pos = t & (2 * D - 1);
             if (pos >= 2 * D - k) {

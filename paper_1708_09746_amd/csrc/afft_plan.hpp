@@ -194,8 +194,7 @@ struct BcPlanner {
         uint64_t P = (1ull << K) - 1;
         uint64_t Q = ((1ull << m) + P - 1) / P;
         if (Q <= (1ull << cap_log)) {
-            int log_w = 0;
-            while ((Q << (log_w + 1)) <= (1ull << cap_log) && (1ull << (log_w + 1)) <= (P << log_u)) ++log_w;
+            const uint64_t W = std::max<uint64_t>(1, std::min<uint64_t>((1ull << cap_log) / Q, P << log_u));
             Op op{};
             op.kind = OpKind::BcClass;
             op.bcc.data = data;
@@ -203,7 +202,8 @@ struct BcPlanner {
             op.bcc.m = (uint32_t)m;
             op.bcc.K = (uint32_t)K;
             op.bcc.log_u = (uint32_t)log_u;
-            op.bcc.log_w = (uint32_t)log_w;
+            op.bcc.w = (uint32_t)W;
+            op.bcc.w_magic = ((1ull << 32) + W - 1) / W;
             op.bcc.q_rows = (uint32_t)Q;
             op.bcc.wide = (uint32_t)wide;
             ops.push_back(op);
