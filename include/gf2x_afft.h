@@ -3,7 +3,8 @@
  * (gfx950) with the additive FFT over a tower field.
  *
  * Method: Chen, Cheng, Kuo, Li, Yang, "Faster Multiplication for Long Binary
- * Polynomials" (arXiv:1708.09746), Alg. 5 with w = 64 over TGF(2^128):
+ * Polynomials" (arXiv:1708.09746), Alg. 5 with w = 64 over TGF(2^128)
+ * (w = 128 over TGF(2^256) as a per-context setting, gf2x_set_word_bits):
  * Split -> BasisCvt (Alg. 3) -> changeRepr -> FFT_LCH (Alg. 1) -> pointmul ->
  * iFFT_LCH -> iBasisCvt -> changeRepr back -> InterleavedCombine.
  *
@@ -19,7 +20,8 @@
  *     at and above na+nb-1 in the last word are written as zero.
  *   - An operand of 0 bits is the zero polynomial: the product has 0 words,
  *     nothing is written and the call returns GF2X_OK.
- *   - Spectra are arrays of TGF(2^128) elements, 16 bytes each: bit j of an
+ *   - Spectra (of the stage entry points, always w = 64) are arrays of
+ *     TGF(2^128) elements, 16 bytes each: bit j of an
  *     element is the coefficient of the tower basis element v_j (Sec. 3.2,
  *     definition of (v_k)).  Spectrum entry j holds f(j̄), the value at the
  *     element whose tower representation is the integer j, of
@@ -61,8 +63,10 @@ typedef struct gf2x_ctx gf2x_ctx;
 
 /* Create a context on HIP device `device`: builds the constant tables (GF(256)
  * product table, butterfly multiplier basis lambda[i][t] = s_i(v_t) of
- * Sec. 4.4, the changeRepr tables of Sec. 4.3) on the host and uploads them.
- * The context owns them and a growable device workspace. */
+ * Sec. 4.4, the changeRepr tables of Sec. 4.3 for both word widths, the
+ * constant-multiple tables of the pointwise tower product of Sec. 4.1) on the
+ * host and uploads them.  The context owns them and a growable device
+ * workspace; its word width starts at 64. */
 int gf2x_ctx_create(gf2x_ctx **ctx, int device);
 
 /* Release a context (synchronizes its device first). NULL is ignored. */
