@@ -9,6 +9,8 @@ Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
   words and residues mod x^64 + q(x) for sampled checks at large sizes.
 * ``tower.py``: the paper's stage definitions (tower field, s_i, novel basis,
   Alg. 1/2/3/5, changeRepr) for small inputs.
+* ``simple.py``: the simple variant (Alg. 4): GF(2^128) in the polynomial
+  basis of Sec. 3.1, Cantor-basis points, for small inputs.
 
 Nothing here is shared with, or imported by, the GPU library.
 """
