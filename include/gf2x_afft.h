@@ -123,6 +123,33 @@ int gf2x_inverse_dev(gf2x_ctx *ctx, void *spec, int log2n, uint64_t *c, uint64_t
  * whole words, so it acts on each of the 64 bit positions independently. */
 int gf2x_basiscvt_dev(gf2x_ctx *ctx, uint64_t *words, int log2n, int inverse, void *stream);
 
+/* ---- the simple variant (Alg. 4) ----
+ * The same product by the paper's simple method: the working field stays
+ * GF(2^128) = GF(2)[x]/(x^128 + x^7 + x^2 + x + 1) in its polynomial basis
+ * (Sec. 3.1), FFT_LCH evaluates at the points phi(j) of a Cantor basis
+ * (Sec. 3.3: beta_0 = 1, beta_i^2 + beta_i = beta_{i-1}, each beta_i taken
+ * as the root without an x^0 term; phi(j) = sum of beta_t over the set bits t
+ * of j), and every butterfly and pointwise product is a full GF(2^128)
+ * product.  A second, independent route to the product, for cross-checks:
+ * it shares BasisCvt (Alg. 3) with the tower method and nothing else.
+ *
+ * gf2x_simple_mul_dev: c = a * b with DEVICE pointers, enqueued on `stream`;
+ * the same sizes, output, aliasing rules and status codes as gf2x_mul_dev, and
+ * the same product bits.  64-bit words and all N points always: the context's
+ * word-width and truncation settings do not apply.  Uses the context's
+ * workspace (gf2x_workspace_bytes(na_bits, nb_bits) bytes).
+ *
+ * gf2x_simple_forward_dev: spec[j] = f(phi(j)) for j < 2^log2n, where
+ * f(y) = sum_k a_k y^k and the 64-bit word a_k is the field element of degree
+ * < 64 with the same bits.  spec is DEVICE memory of 16 * 2^log2n bytes, an
+ * element stored as two little-endian 64-bit halves (bit e of the 128 is the
+ * coefficient of x^e), written entirely.  Requires
+ * 2^log2n >= 2^ceil(log2(ceil(na_bits/64))) and log2n <= 32. */
+int gf2x_simple_mul_dev(gf2x_ctx *ctx, const uint64_t *a, uint64_t na_bits, const uint64_t *b, uint64_t nb_bits,
+                        uint64_t *c, void *stream);
+int gf2x_simple_forward_dev(gf2x_ctx *ctx, const uint64_t *a, uint64_t na_bits, int log2n, void *spec,
+                            void *stream);
+
 /* One job of a batch: DEVICE pointers, same conventions as gf2x_mul_dev. */
 typedef struct {
     const uint64_t *a;

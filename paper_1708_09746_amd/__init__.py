@@ -93,6 +93,8 @@ def lib():
             "gf2x_pointmul_dev": (i32, [vp, vp, vp, vp, u64, vp]),
             "gf2x_inverse_dev": (i32, [vp, vp, i32, vp, u64, vp]),
             "gf2x_basiscvt_dev": (i32, [vp, vp, i32, i32, vp]),
+            "gf2x_simple_mul_dev": (i32, [vp, vp, u64, vp, u64, vp, vp]),
+            "gf2x_simple_forward_dev": (i32, [vp, vp, u64, i32, vp, vp]),
             "gf2x_mul_batch": (i32, [vp, ctypes.POINTER(Job), sz, vp]),
             "gf2x_batch_create": (i32, [vp, ctypes.POINTER(Job), sz, i32, ctypes.POINTER(vp)]),
             "gf2x_batch_check": (i32, [vp]),
@@ -210,6 +212,30 @@ class Context:
         ow = out_words(na_bits, nb_bits)
         c = torch.empty(max(ow, 1), dtype=torch.int64, device=a.device)[:ow]
         return self.mul_into(a, na_bits, b, nb_bits, c, stream)
+
+    def simple_mul_into(self, a, na_bits: int, b, nb_bits: int, c, stream=None):
+        """The same product by the simple variant (Alg. 4)."""
+        rc = lib().gf2x_simple_mul_dev(self._h, _ptr(a), na_bits, _ptr(b), nb_bits, _ptr(c), _stream_handle(stream))
+        self._check(rc, "gf2x_simple_mul_dev")
+        return c
+
+    def simple_mul(self, a, na_bits: int, b, nb_bits: int, stream=None):
+        import torch
+
+        ow = out_words(na_bits, nb_bits)
+        c = torch.empty(max(ow, 1), dtype=torch.int64, device=a.device)[:ow]
+        return self.simple_mul_into(a, na_bits, b, nb_bits, c, stream)
+
+    def simple_forward(self, a, na_bits: int, log2n: int, spec=None, stream=None):
+        """Values of the operand's word polynomial at the Cantor points phi(j),
+        j < 2^log2n, in the polynomial-basis GF(2^128) (Alg. 4)."""
+        import torch
+
+        if spec is None:
+            spec = torch.empty((1 << log2n, 2), dtype=torch.int64, device=a.device)
+        rc = lib().gf2x_simple_forward_dev(self._h, _ptr(a), na_bits, log2n, _ptr(spec), _stream_handle(stream))
+        self._check(rc, "gf2x_simple_forward_dev")
+        return spec
 
     def mul_batch(self, jobs, stream=None):
         """jobs: list of (a, na_bits, b, nb_bits, c) with device tensors."""

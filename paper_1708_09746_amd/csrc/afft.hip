@@ -16,6 +16,7 @@
 #include "../../include/gf2x_afft.h"
 #include "afft_plan.hpp"
 #include "arena.hpp"
+#include "simple.hpp"
 #include "tower_host.hpp"
 
 using namespace gf2x;
@@ -175,6 +176,67 @@ __global__ __launch_bounds__(kThreads) void k_psi(PsiOp P, const uint4* g_psi) {
 // per thread (a linear congruential sequence each), every address masked to
 // the table.
 constexpr int kLookupIters = 2000;
+// ---- the simple variant (Alg. 4): polynomial-basis GF(2^128), Cantor points
+
+__global__ __launch_bounds__(kSfThreads) void k_sfft_tab(SfftPass P, const uint4* g_cantor) {
+    __shared__ uint4 tab[((1 << kSfTabL) - 1) * kSfTabStride];
+    __shared__ uint4 dat[1 << kSfTabPtsLog];
+    const uint32_t npts = 1u << (P.L + P.c), ntab = (1u << P.L) - 1;
+    const uint64_t ngroups = sf_tab_groups(P);
+    for (uint64_t g = blockIdx.x; g < ngroups; g += gridDim.x) {
+        for (uint32_t e = threadIdx.x; e < npts; e += blockDim.x) dat[e] = sfft_load(P, sf_tab_point(P, g, e));
+        for (uint32_t t = threadIdx.x; t < ntab; t += blockDim.x) sf_tab_table(P, g, t, g_cantor, tab);
+        __syncthreads();
+        for (int s = 0; s < P.L; ++s) {
+            for (uint32_t q = threadIdx.x; q < npts / 2; q += blockDim.x) sf_tab_bfly(P, s, q, dat, tab);
+            __syncthreads();
+        }
+        for (uint32_t e = threadIdx.x; e < npts; e += blockDim.x) P.x[sf_tab_point(P, g, e)] = dat[e];
+        __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(kSfLaneThreads) void k_sfft_lane(SfftPass P, const uint4* g_cantor) {
+    __shared__ uint4 ltab[kSfLaneThreads * kSfTabStride];
+    __shared__ uint4 dat[1 << kSfLaneC];
+    __shared__ uint4 phit[1 << kSfLaneC];
+    __shared__ uint4 lam[kSfLaneC];
+    const uint32_t npts = 1u << P.c;
+    const uint64_t nchunks = P.n >> P.c;
+    uint4* T = ltab + threadIdx.x * kSfTabStride;
+    for (uint32_t u = threadIdx.x; u < npts; u += blockDim.x) phit[u] = g_cantor[kCantorBeta + u];
+    for (uint64_t g = blockIdx.x; g < nchunks; g += gridDim.x) {
+        const uint64_t J0 = g << P.c;
+        for (uint32_t e = threadIdx.x; e < npts; e += blockDim.x) dat[e] = sfft_load(P, J0 | e);
+        if ((int)threadIdx.x < P.L) lam[threadIdx.x] = phi_cantor(J0 >> threadIdx.x, g_cantor);
+        __syncthreads();
+        for (int s = 0; s < P.L; ++s) {
+            for (uint32_t q = threadIdx.x; q < npts / 2; q += blockDim.x) sf_lane_bfly(P, s, q, dat, lam, phit, T);
+            __syncthreads();
+        }
+        for (uint32_t e = threadIdx.x; e < npts; e += blockDim.x) P.x[J0 | e] = dat[e];
+        __syncthreads();
+    }
+}
+
+// pointmul of Alg. 4: sc[j] = sa[j] * sb[j] in GF(2^128)
+__global__ __launch_bounds__(kSfLaneThreads) void k_spmul(const uint4* sa, const uint4* sb, uint4* sc, uint64_t n) {
+    __shared__ uint4 ltab[kSfLaneThreads * kSfTabStride];
+    uint4* T = ltab + threadIdx.x * kSfTabStride;
+    for (uint64_t j = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n; j += (uint64_t)gridDim.x * blockDim.x) {
+        const uint4 a = sa[j], b = sb[j];
+        gcm_build_tab(a, T);
+        sc[j] = gcm_mul_tab(T, b);
+    }
+}
+
+__global__ __launch_bounds__(kSfThreads) void k_scombine(const uint4* F, uint64_t n, uint64_t* c, uint64_t nwords,
+                                                         uint64_t nc_bits) {
+    for (uint64_t k = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; k < nwords;
+         k += (uint64_t)gridDim.x * blockDim.x)
+        c[k] = sf_combine_word(F, n, k, nwords, nc_bits);
+}
+
 __global__ __launch_bounds__(kThreads) void k_lookup_rate(const uint8_t* g_mt, uint32_t* out) {
     __shared__ __align__(16) uint8_t mt[65536];
     copy_words(threadIdx.x, blockDim.x, (uint32_t*)mt, (const uint32_t*)g_mt, 16384);
@@ -546,6 +608,7 @@ struct gf2x_ctx {
     uint4* d_phi = nullptr;
     uint4* d_psi = nullptr;
     uint32_t* d_ctab = nullptr;  // constant-multiple tables of the generic product
+    uint4* d_cantor = nullptr;   // simple variant: Cantor basis and phi table
     char* ws = nullptr;
     size_t ws_bytes = 0;
     char* io = nullptr;  // operand/product staging for the host-pointer entry point
@@ -1440,6 +1503,64 @@ PlanParams single_params(const gf2x_ctx* ctx) {
     return pp;
 }
 
+// ------------------------------------------------ the simple variant (Alg. 4)
+
+int launch_sfft(gf2x_ctx* ctx, const std::vector<SfftPass>& passes, hipStream_t st) {
+    for (const SfftPass& p : passes) {
+        if (p.lo == 0) {
+            const uint64_t chunks = p.n >> p.c;
+            hipLaunchKernelGGL(k_sfft_lane, dim3(grid_for(chunks, 12ull * ctx->ncu)), dim3(kSfLaneThreads), 0, st, p,
+                               (const uint4*)ctx->d_cantor);
+        } else {
+            const uint64_t groups = p.n >> (p.L + p.c);
+            hipLaunchKernelGGL(k_sfft_tab, dim3(grid_for(groups, 12ull * ctx->ncu)), dim3(kSfThreads), 0, st, p,
+                               (const uint4*)ctx->d_cantor);
+        }
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return hip_fail(ctx, e, "simple-variant FFT launch");
+    }
+    return GF2X_OK;
+}
+
+// Split, BasisCvt on 64-bit words, FFT_LCH at the Cantor points (Alg. 4).
+int simple_forward(gf2x_ctx* ctx, const uint64_t* src, uint64_t nbits, uint64_t* words, int m_op, uint4* spec, int m,
+                   hipStream_t st) {
+    std::vector<Op> ops;
+    emit_pack(ops, src, nbits, words, 1ull << m_op);
+    emit_bc(ops, ctx->pool, words, 0, m_op, 0, single_params(ctx).bc_small);
+    int rc = run_ops(ctx, ops, st);
+    if (rc) return rc;
+    return launch_sfft(ctx, sfft_passes(spec, words, m_op, m, false), st);
+}
+
+int simple_mul(gf2x_ctx* ctx, const uint64_t* a, uint64_t na_bits, const uint64_t* b, uint64_t nb_bits, uint64_t* c,
+               hipStream_t st) {
+    const Sizes s = make_sizes(na_bits, nb_bits, 64);
+    const Workspace w = workspace_for(s);
+    int rc = ensure_ws(ctx, w.bytes, st);
+    if (rc) return rc;
+    uint64_t* wa = (uint64_t*)(ctx->ws + w.off_wa);
+    uint64_t* wb = (uint64_t*)(ctx->ws + w.off_wb);
+    uint4* sa = (uint4*)(ctx->ws + w.off_sa);
+    uint4* sb = (uint4*)(ctx->ws + w.off_sb);
+    const uint64_t N = 1ull << s.m;
+    if ((rc = simple_forward(ctx, a, na_bits, wa, s.m_a, sa, s.m, st))) return rc;
+    if ((rc = simple_forward(ctx, b, nb_bits, wb, s.m_b, sb, s.m, st))) return rc;
+    hipLaunchKernelGGL(k_spmul, dim3(grid_for((N + kSfLaneThreads - 1) / kSfLaneThreads, 16ull * ctx->ncu)),
+                       dim3(kSfLaneThreads), 0, st, (const uint4*)sa, (const uint4*)sb, sb, N);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(ctx, e, "simple-variant pointmul launch");
+    if ((rc = launch_sfft(ctx, sfft_passes(sb, nullptr, s.m, s.m, true), st))) return rc;
+    std::vector<Op> ops;
+    emit_bc(ops, ctx->pool, sb, 1, s.m, 1, single_params(ctx).bc_small);
+    if ((rc = run_ops(ctx, ops, st))) return rc;
+    hipLaunchKernelGGL(k_scombine, dim3(grid_for((s.out_words + kSfThreads - 1) / kSfThreads, 8ull * ctx->ncu)),
+                       dim3(kSfThreads), 0, st, (const uint4*)sb, N, c, s.out_words, s.nc_bits);
+    e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(ctx, e, "simple-variant combine launch");
+    return GF2X_OK;
+}
+
 extern "C" {
 
 const char* gf2x_strerror(int status) {
@@ -1521,6 +1642,16 @@ int gf2x_ctx_create(gf2x_ctx** out, int device) {
     if (e == hipSuccess) e = hipMemcpy(ctx->d_lam, lam, sizeof(lam), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(ctx->d_phi, phi.data(), phi.size() * sizeof(uint4), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(ctx->d_psi, psi.data(), psi.size() * sizeof(uint4), hipMemcpyHostToDevice);
+    std::vector<gcm_u128> cantor;
+    if (!build_cantor_table(cantor)) {
+        gf2x_ctx_destroy(ctx);
+        return GF2X_EINVAL;
+    }
+    std::vector<uint4> cantor4(cantor.size());
+    for (size_t i = 0; i < cantor.size(); ++i) cantor4[i] = to_u4((u128)cantor[i]);
+    if (e == hipSuccess) e = hipMalloc((void**)&ctx->d_cantor, cantor4.size() * sizeof(uint4));
+    if (e == hipSuccess)
+        e = hipMemcpy(ctx->d_cantor, cantor4.data(), cantor4.size() * sizeof(uint4), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMalloc((void**)&ctx->d_layers, ctx->pool.host.size() * sizeof(BcLayer));
     if (e == hipSuccess)
         e = hipMemcpy(ctx->d_layers, ctx->pool.host.data(), ctx->pool.host.size() * sizeof(BcLayer), hipMemcpyHostToDevice);
@@ -1544,6 +1675,7 @@ void gf2x_ctx_destroy(gf2x_ctx* ctx) {
     if (ctx->d_phi) (void)hipFree(ctx->d_phi);
     if (ctx->d_psi) (void)hipFree(ctx->d_psi);
     if (ctx->d_ctab) (void)hipFree(ctx->d_ctab);
+    if (ctx->d_cantor) (void)hipFree(ctx->d_cantor);
     if (ctx->d_layers) (void)hipFree(ctx->d_layers);
     if (ctx->transient) batch_free(ctx->transient);
     if (ctx->ws) (void)hipFree(ctx->ws);
@@ -1651,6 +1783,35 @@ int gf2x_basiscvt_dev(gf2x_ctx* ctx, uint64_t* words, int log2n, int inverse, vo
     std::vector<Op> ops;
     emit_bc(ops, ctx->pool, words, 0, log2n, inverse ? 1 : 0, 1);
     return run_ops(ctx, ops, (hipStream_t)stream);
+}
+
+int gf2x_simple_mul_dev(gf2x_ctx* ctx, const uint64_t* a, uint64_t na_bits, const uint64_t* b, uint64_t nb_bits,
+                        uint64_t* c, void* stream) {
+    if (check_ctx(ctx)) return GF2X_EINVAL;
+    ctx->err.clear();
+    const Sizes s = make_sizes(na_bits, nb_bits, 64);
+    if (!s.out_words) return GF2X_OK;
+    if (!a || !b || !c) return fail(ctx, GF2X_EINVAL, "NULL operand or product pointer");
+    if (s.m > kMaxLog2N) return fail(ctx, GF2X_ERANGE, "transform length above 2^32");
+    if (ranges_overlap(c, 8 * s.out_words, a, 8 * s.n_a) || ranges_overlap(c, 8 * s.out_words, b, 8 * s.n_b))
+        return fail(ctx, GF2X_EINVAL, "product overlaps an operand");
+    DeviceGuard g(ctx->device);
+    return simple_mul(ctx, a, na_bits, b, nb_bits, c, (hipStream_t)stream);
+}
+
+int gf2x_simple_forward_dev(gf2x_ctx* ctx, const uint64_t* a, uint64_t na_bits, int log2n, void* spec,
+                            void* stream) {
+    if (check_ctx(ctx)) return GF2X_EINVAL;
+    ctx->err.clear();
+    if (!a || !spec || na_bits == 0) return fail(ctx, GF2X_EINVAL, "NULL pointer or empty operand");
+    if (log2n < 0 || log2n > kMaxLog2N) return fail(ctx, GF2X_ERANGE, "log2n out of range");
+    const int m_a = ceil_log2((na_bits + 63) / 64);
+    if (m_a > log2n) return fail(ctx, GF2X_EINVAL, "spectrum shorter than the operand");
+    DeviceGuard g(ctx->device);
+    hipStream_t st = (hipStream_t)stream;
+    int rc = ensure_ws(ctx, align256(8ull << m_a), st);
+    if (rc) return rc;
+    return simple_forward(ctx, a, na_bits, (uint64_t*)ctx->ws, m_a, (uint4*)spec, log2n, st);
 }
 
 int gf2x_mul_batch(gf2x_ctx* ctx, const gf2x_job* jobs, size_t njobs, void* stream) {

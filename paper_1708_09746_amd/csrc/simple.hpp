@@ -1,0 +1,321 @@
+// The simple variant of the multiplier (Alg. 4): the working field stays
+// GF(2^128) = GF(2)[x]/(x^128 + x^7 + x^2 + x + 1) in its polynomial basis
+// (Sec. 3.1), the LCH FFT (Alg. 1) evaluates at the points phi(j) of a Cantor
+// basis (Sec. 3.3), and every butterfly product is a full GF(2^128) product.
+//
+// The multipliers of a layer-k butterfly block at offset o are
+// s_k(phi(o)) = phi(o >> k) (Sec. 3.3: s_k shifts Cantor coordinates), mapped
+// into the field through a table of the basis.  BasisCvt is shared with the
+// tower variant (the s_i are the same GF(2) polynomials for both bases), and
+// InterleavedCombine needs no change of representation: a 64-bit word is the
+// field element of degree < 64 with the same bits, and a product of two of
+// them has degree < 127, so it is never reduced.
+//
+// Products by a field element v use a table of the 16 multiples v * n(x),
+// deg n < 4: v * w is the sum over the 32 nibbles of w of table entries times
+// x^(4p), accumulated unreduced in 256 bits and reduced once.  A strided FFT
+// pass builds one table per distinct multiplier of its group (shared by all
+// butterflies of that block); the contiguous bottom pass, where blocks hold
+// one or two butterflies, builds the table of the butterfly's operand instead.
+#pragma once
+
+#include <stdint.h>
+
+#include <vector>
+
+#include "afft_device.hpp"
+
+namespace gf2x {
+
+constexpr int kSfThreads = 256;       // strided-pass workgroup
+constexpr int kSfLaneThreads = 128;   // bottom-pass and pointmul workgroups
+constexpr int kSfTabL = 7;            // layers of one strided pass, at most
+constexpr int kSfTabPtsLog = 10;      // points of one strided-pass workgroup, at most 2^10
+constexpr int kSfTabStride = 17;      // uint4 per table: 16 entries and one pad (spreads LDS banks)
+constexpr int kSfLaneC = 9;           // bottom pass: contiguous chunks of 2^9 points, layers 0..8
+constexpr int kCantorBeta = 64;       // beta_0 .. beta_63 in the device table
+constexpr int kCantorTotal = kCantorBeta + (1 << kSfLaneC);  // then phi(u) for u < 2^9
+
+struct SfftPass {
+    uint4* x;               // N points, 16 bytes each, read and written in place
+    const uint64_t* words;  // non-null: the pass reads word j & wmask as the point j instead of x
+    uint64_t wmask;
+    uint64_t n;             // N
+    int lo, L, c, inverse;  // layers [lo, lo + L); 2^c consecutive low indices per group
+};
+
+// ------------------------------------------ bodies (kernels and host checks)
+
+
+AFFT_HD uint32_t word_of(const uint4& v, int q) {
+    return q == 0 ? v.x : q == 1 ? v.y : q == 2 ? v.z : v.w;
+}
+
+// v * x mod x^128 + x^7 + x^2 + x + 1
+AFFT_HD uint4 gcm_mulx(uint4 v) {
+    const uint32_t top = v.w >> 31;
+    uint4 r;
+    r.w = (v.w << 1) | (v.z >> 31);
+    r.z = (v.z << 1) | (v.y >> 31);
+    r.y = (v.y << 1) | (v.x >> 31);
+    r.x = (v.x << 1) ^ (0x87u & (0u - top));
+    return r;
+}
+
+// T[n] = v * n(x) for the 16 polynomials n of degree < 4 (bit i of n is the
+// coefficient of x^i), walked in Gray-code order so that each entry is the
+// previous one plus a single v * x^i.
+AFFT_HD void gcm_build_tab(uint4 v, uint4* T) {
+    uint4 b[4];
+    b[0] = v;
+    b[1] = gcm_mulx(b[0]);
+    b[2] = gcm_mulx(b[1]);
+    b[3] = gcm_mulx(b[2]);
+    uint4 cur = make_uint4(0, 0, 0, 0);
+    T[0] = cur;
+#pragma unroll
+    for (int i = 1; i < 16; ++i) {
+        const int flip = __builtin_ctz(i);  // Gray code i ^ (i >> 1) changes this bit
+        cur = xor4(cur, b[flip]);
+        T[i ^ (i >> 1)] = cur;
+    }
+}
+
+// The 256-bit polynomial a[0..7] modulo x^128 + x^7 + x^2 + x + 1: the high
+// half H enters as H (x^7 + x^2 + x + 1); the up to 7 bits that this pushes
+// past x^127 are folded in the same way once more.
+AFFT_HD uint4 gcm_reduce(const uint32_t (&a)[8]) {
+    const uint32_t h0 = a[4], h1 = a[5], h2 = a[6], h3 = a[7];
+    uint4 r;
+    r.x = a[0] ^ h0 ^ (h0 << 1) ^ (h0 << 2) ^ (h0 << 7);
+    r.y = a[1] ^ h1 ^ ((h1 << 1) | (h0 >> 31)) ^ ((h1 << 2) | (h0 >> 30)) ^ ((h1 << 7) | (h0 >> 25));
+    r.z = a[2] ^ h2 ^ ((h2 << 1) | (h1 >> 31)) ^ ((h2 << 2) | (h1 >> 30)) ^ ((h2 << 7) | (h1 >> 25));
+    r.w = a[3] ^ h3 ^ ((h3 << 1) | (h2 >> 31)) ^ ((h3 << 2) | (h2 >> 30)) ^ ((h3 << 7) | (h2 >> 25));
+    const uint32_t ov = (h3 >> 31) ^ (h3 >> 30) ^ (h3 >> 25);
+    r.x ^= ov ^ (ov << 1) ^ (ov << 2) ^ (ov << 7);
+    return r;
+}
+
+// v * w with T the table of v: sum over nibble positions p = 8q + r of
+// T[nibble] x^(32q) x^(4r), by Horner's rule in x^4 over r.
+AFFT_HD uint4 gcm_mul_tab(const uint4* T, uint4 w) {
+    uint32_t a[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+#pragma unroll
+    for (int r = 7; r >= 0; --r) {
+        if (r != 7) {
+#pragma unroll
+            for (int i = 7; i > 0; --i) a[i] = (a[i] << 4) | (a[i - 1] >> 28);
+            a[0] <<= 4;
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const uint4 t = T[(word_of(w, q) >> (4 * r)) & 15u];
+            a[q] ^= t.x;
+            a[q + 1] ^= t.y;
+            a[q + 2] ^= t.z;
+            a[q + 3] ^= t.w;
+        }
+    }
+    return gcm_reduce(a);
+}
+
+// phi(v) = sum of beta_t over the set bits t of v (v < 2^64)
+AFFT_HD uint4 phi_cantor(uint64_t v, const uint4* beta) {
+    uint4 r = make_uint4(0, 0, 0, 0);
+    while (v) {
+        r = xor4(r, beta[__builtin_ctzll(v)]);
+        v &= v - 1;
+    }
+    return r;
+}
+
+AFFT_HD uint4 sfft_load(const SfftPass& P, uint64_t j) {
+    if (P.words) {
+        const uint64_t w = P.words[j & P.wmask];
+        return make_uint4((uint32_t)w, (uint32_t)(w >> 32), 0u, 0u);
+    }
+    return P.x[j];
+}
+
+// A strided pass: layers [lo, lo + L) on groups of 2^L points 2^lo apart,
+// 2^c neighbouring groups per workgroup (c <= lo) so that loads and stores
+// run over 2^c consecutive points.  Group g = (hi, lowblk) holds the points
+// j = (hi << (lo + L)) | ((e >> c) << lo) | (lowblk << c) | (e mod 2^c),
+// e < 2^(L + c).  At relative layer r (layer k = lo + r) the block of e holds
+// the rho = L - 1 - r group bits above r, b = e >> (c + r + 1), and its
+// multiplier is phi(o >> k) = phi((hi << (rho + 1)) | (b << 1)), kept in
+// table 2^rho - 1 + b.
+AFFT_HD uint64_t sf_tab_groups(const SfftPass& P) { return P.n >> (P.L + P.c); }
+
+AFFT_HD uint64_t sf_tab_point(const SfftPass& P, uint64_t g, uint32_t e) {
+    const uint64_t hi = g >> (P.lo - P.c), lowblk = g & ((1ull << (P.lo - P.c)) - 1);
+    return (hi << (P.lo + P.L)) | ((uint64_t)(e >> P.c) << P.lo) | (lowblk << P.c) | (e & ((1u << P.c) - 1));
+}
+
+AFFT_HD void sf_tab_table(const SfftPass& P, uint64_t g, uint32_t t, const uint4* beta, uint4* tab) {
+    const uint64_t hi = g >> (P.lo - P.c);
+    const int rho = 31 - __builtin_clz(t + 1);
+    const uint64_t b = t + 1 - (1u << rho);
+    gcm_build_tab(phi_cantor((hi << (rho + 1)) | (b << 1), beta), tab + t * kSfTabStride);
+}
+
+// Butterfly q of step s (forward: layers top-down; inverse: bottom-up).
+AFFT_HD void sf_tab_bfly(const SfftPass& P, int s, uint32_t q, uint4* dat, const uint4* tab) {
+    const int r = P.inverse ? s : P.L - 1 - s;
+    const int sh = P.c + r;
+    const uint32_t e0 = ((q >> sh) << (sh + 1)) | (q & ((1u << sh) - 1));
+    const uint32_t e1 = e0 | (1u << sh);
+    const uint4* T = tab + (((1u << (P.L - 1 - r)) - 1) + (e0 >> (sh + 1))) * kSfTabStride;
+    uint4 u = dat[e0], w = dat[e1];
+    if (!P.inverse) {
+        u = xor4(u, gcm_mul_tab(T, w));
+        w = xor4(w, u);
+    } else {
+        w = xor4(w, u);
+        u = xor4(u, gcm_mul_tab(T, w));
+    }
+    dat[e0] = u;
+    dat[e1] = w;
+}
+
+// The contiguous bottom pass: layers [0, L) on chunks of 2^c consecutive
+// points (L <= c).  For the chunk at J0 the layer-k multiplier of the block
+// holding local index e is phi(J0 >> k) + phi((e >> (k + 1)) << 1): the first
+// term once per chunk and layer (lam[k]), the second from the phi table.
+// Each butterfly tabulates its own operand in T (multipliers are rarely
+// shared here).
+AFFT_HD void sf_lane_bfly(const SfftPass& P, int s, uint32_t q, uint4* dat, const uint4* lam, const uint4* phit,
+                          uint4* T) {
+    const int k = P.inverse ? s : P.L - 1 - s;
+    const uint32_t e0 = ((q >> k) << (k + 1)) | (q & ((1u << k) - 1));
+    const uint32_t e1 = e0 | (1u << k);
+    const uint4 m = xor4(lam[k], phit[(e0 >> (k + 1)) << 1]);
+    uint4 u = dat[e0], w = dat[e1];
+    if (!P.inverse) {
+        gcm_build_tab(w, T);
+        u = xor4(u, gcm_mul_tab(T, m));
+        w = xor4(w, u);
+    } else {
+        w = xor4(w, u);
+        gcm_build_tab(w, T);
+        u = xor4(u, gcm_mul_tab(T, m));
+    }
+    dat[e0] = u;
+    dat[e1] = w;
+}
+
+// InterleavedCombine, word k: the low half of coefficient k plus the high
+// half of coefficient k - 1 (coefficients have degree < 127); the last word
+// keeps nc_bits mod 64 bits.
+AFFT_HD uint64_t sf_combine_word(const uint4* F, uint64_t n, uint64_t k, uint64_t nwords, uint64_t nc_bits) {
+    uint64_t v = 0;
+    if (k < n) v = (uint64_t)F[k].x | ((uint64_t)F[k].y << 32);
+    if (k >= 1 && k - 1 < n) v ^= (uint64_t)F[k - 1].z | ((uint64_t)F[k - 1].w << 32);
+    if (k == nwords - 1 && (nc_bits & 63)) v &= (1ull << (nc_bits & 63)) - 1;
+    return v;
+}
+
+// ------------------------------------------------------------------- host
+
+using gcm_u128 = unsigned __int128;
+
+inline gcm_u128 gcm_mul_host(gcm_u128 a, gcm_u128 b) {
+    gcm_u128 r = 0;
+    for (int i = 127; i >= 0; --i) {
+        const bool top = (r >> 127) & 1;
+        r <<= 1;
+        if (top) r ^= 0x87;
+        if ((b >> i) & 1) r ^= a;
+    }
+    return r;
+}
+
+// The Cantor basis beta_0 = 1, beta_i^2 + beta_i = beta_{i-1}, each beta_i the
+// root without an x^0 term.  y -> y^2 + y is GF(2)-linear with kernel {0, 1};
+// its images of x^1 .. x^127 are row-reduced once, then each equation is
+// solved by eliminating along the pivots.  False if some equation has no root.
+inline bool build_cantor(gcm_u128* beta, int count) {
+    struct Row {
+        int piv;
+        gcm_u128 img, pre;
+    };
+    std::vector<Row> rows;
+    for (int i = 1; i < 128; ++i) {
+        const gcm_u128 xi = (gcm_u128)1 << i;
+        gcm_u128 img = gcm_mul_host(xi, xi) ^ xi, pre = xi;
+        for (const Row& R : rows)
+            if ((img >> R.piv) & 1) {
+                img ^= R.img;
+                pre ^= R.pre;
+            }
+        if (!img) return false;
+        int piv = 127;
+        while (!((img >> piv) & 1)) --piv;
+        for (Row& R : rows)
+            if ((R.img >> piv) & 1) {
+                R.img ^= img;
+                R.pre ^= pre;
+            }
+        rows.push_back(Row{piv, img, pre});
+    }
+    beta[0] = 1;
+    for (int i = 1; i < count; ++i) {
+        gcm_u128 c = beta[i - 1], y = 0;
+        for (const Row& R : rows)
+            if ((c >> R.piv) & 1) {
+                c ^= R.img;
+                y ^= R.pre;
+            }
+        if (c) return false;
+        beta[i] = y;
+    }
+    return true;
+}
+
+// The device table: beta_0 .. beta_63, then phi(u) for u < 2^kSfLaneC.
+inline bool build_cantor_table(std::vector<gcm_u128>& out) {
+    out.assign(kCantorTotal, 0);
+    if (!build_cantor(out.data(), kCantorBeta)) return false;
+    for (uint32_t u = 0; u < (1u << kSfLaneC); ++u) {
+        gcm_u128 r = 0;
+        for (int t = 0; t < kSfLaneC; ++t)
+            if ((u >> t) & 1) r ^= out[t];
+        out[kCantorBeta + u] = r;
+    }
+    return true;
+}
+
+// The passes of one transform over N = 2^m points: layers [0, M) with
+// M = m_op forward (the layers above the operand's converted length 2^m_op
+// only copy it: its top half is zero) and M = m inverse.  Bottom pass first
+// (contiguous, layers [0, min(M, c)) with c = min(m, 9)), then strided passes
+// of at most 7 layers; the forward transform runs them in the reverse order,
+// its first pass reading the converted words.
+inline std::vector<SfftPass> sfft_passes(uint4* x, const uint64_t* words, int m_op, int m, bool inverse) {
+    std::vector<SfftPass> v;
+    const int M = inverse ? m : m_op;
+    const int C = m < kSfLaneC ? m : kSfLaneC;
+    const int Lb = M < C ? M : C;
+    v.push_back(SfftPass{x, nullptr, 0, 1ull << m, 0, Lb, C, inverse ? 1 : 0});
+    const int up = M - Lb;
+    if (up > 0) {
+        const int np = (up + kSfTabL - 1) / kSfTabL;
+        int lo = Lb;
+        for (int p = 0; p < np; ++p) {
+            const int L = up / np + (p < up % np ? 1 : 0);
+            int c = kSfTabPtsLog - L;
+            if (c > lo) c = lo;
+            v.push_back(SfftPass{x, nullptr, 0, 1ull << m, lo, L, c, inverse ? 1 : 0});
+            lo += L;
+        }
+    }
+    if (!inverse) {
+        std::vector<SfftPass> r(v.rbegin(), v.rend());
+        r[0].words = words;
+        r[0].wmask = (1ull << m_op) - 1;
+        return r;
+    }
+    return v;
+}
+
+}  // namespace gf2x

@@ -11,6 +11,7 @@
 #include <vector>
 
 #include "afft_plan.hpp"
+#include "simple.hpp"
 #include "tower_host.hpp"
 
 using namespace gf2x;
@@ -239,6 +240,95 @@ bool check_xcd_order(std::mt19937_64& g) {
     return true;
 }
 
+// ---- the simple variant (Alg. 4): the FFT passes, pointmul and combine run
+// here with the bodies the kernels run, workgroup by workgroup and phase by
+// phase (every thread of a phase before any of the next, as the barriers do)
+std::vector<uint4> CANTOR;
+
+void run_sfft(const std::vector<SfftPass>& passes) {
+    std::vector<uint4> tab(((1 << kSfTabL) - 1) * kSfTabStride), dat(1 << kSfTabPtsLog), T(kSfTabStride),
+        lam(kSfLaneC);
+    for (const SfftPass& P : passes) {
+        if (P.lo == 0) {
+            const uint32_t npts = 1u << P.c;
+            for (uint64_t g = 0; g < (P.n >> P.c); ++g) {
+                const uint64_t J0 = g << P.c;
+                for (uint32_t e = 0; e < npts; ++e) dat[e] = sfft_load(P, J0 | e);
+                for (int k = 0; k < P.L; ++k) lam[k] = phi_cantor(J0 >> k, CANTOR.data());
+                for (int s = 0; s < P.L; ++s)
+                    for (uint32_t q = 0; q < npts / 2; ++q)
+                        sf_lane_bfly(P, s, q, dat.data(), lam.data(), CANTOR.data() + kCantorBeta, T.data());
+                for (uint32_t e = 0; e < npts; ++e) P.x[J0 | e] = dat[e];
+            }
+        } else {
+            const uint32_t npts = 1u << (P.L + P.c), ntab = (1u << P.L) - 1;
+            for (uint64_t g = 0; g < sf_tab_groups(P); ++g) {
+                for (uint32_t e = 0; e < npts; ++e) dat[e] = sfft_load(P, sf_tab_point(P, g, e));
+                for (uint32_t t = 0; t < ntab; ++t) sf_tab_table(P, g, t, CANTOR.data(), tab.data());
+                for (int s = 0; s < P.L; ++s)
+                    for (uint32_t q = 0; q < npts / 2; ++q) sf_tab_bfly(P, s, q, dat.data(), tab.data());
+                for (uint32_t e = 0; e < npts; ++e) P.x[sf_tab_point(P, g, e)] = dat[e];
+            }
+        }
+    }
+}
+
+bool check_simple_tables() {
+    std::vector<gcm_u128> C;
+    if (!build_cantor_table(C)) return false;
+    CANTOR.resize(C.size());
+    for (size_t i = 0; i < C.size(); ++i) CANTOR[i] = to_u4(C[i]);
+    bool ok = C[0] == 1;
+    for (int i = 1; i < kCantorBeta; ++i) ok &= (gcm_mul_host(C[i], C[i]) ^ C[i]) == C[i - 1] && !(C[i] & 1);
+    // the table product against the shift-and-add product
+    std::mt19937_64 g(7);
+    std::vector<uint4> T(16);
+    for (int i = 0; i < 2000 && ok; ++i) {
+        const gcm_u128 a = ((gcm_u128)g() << 64) | g(), b = ((gcm_u128)g() << 64) | g();
+        gcm_build_tab(to_u4(a), T.data());
+        const uint4 r = gcm_mul_tab(T.data(), to_u4(b)), want = to_u4(gcm_mul_host(a, b));
+        ok &= r.x == want.x && r.y == want.y && r.z == want.z && r.w == want.w;
+    }
+    if (!ok) printf("simple-variant tables or table product wrong\n");
+    return ok;
+}
+
+bool check_simple_product(std::mt19937_64& g, uint64_t na, uint64_t nb) {
+    const Sizes s = make_sizes(na, nb, 64);
+    const Workspace w = workspace_for(s);
+    std::vector<char> ws(w.bytes, 0x5a);
+    auto a = rand_words(g, na), b = rand_words(g, nb);
+    std::vector<uint64_t> c(s.out_words + 1, 0xdead), r(s.out_words + 1, 0);
+    uint64_t* wa = (uint64_t*)(ws.data() + w.off_wa);
+    uint64_t* wb = (uint64_t*)(ws.data() + w.off_wb);
+    uint4* sa = (uint4*)(ws.data() + w.off_sa);
+    uint4* sb = (uint4*)(ws.data() + w.off_sb);
+    const uint64_t N = 1ull << s.m;
+    std::vector<Op> ops;
+    emit_pack(ops, a.data(), na, wa, 1ull << s.m_a);
+    emit_bc(ops, POOL, wa, 0, s.m_a, 0, 1);
+    emit_pack(ops, b.data(), nb, wb, 1ull << s.m_b);
+    emit_bc(ops, POOL, wb, 0, s.m_b, 0, 1);
+    run_ops(ops);
+    run_sfft(sfft_passes(sa, wa, s.m_a, s.m, false));
+    run_sfft(sfft_passes(sb, wb, s.m_b, s.m, false));
+    std::vector<uint4> T(16);
+    for (uint64_t j = 0; j < N; ++j) {
+        gcm_build_tab(sa[j], T.data());
+        sb[j] = gcm_mul_tab(T.data(), sb[j]);
+    }
+    run_sfft(sfft_passes(sb, nullptr, s.m, s.m, true));
+    ops.clear();
+    emit_bc(ops, POOL, sb, 1, s.m, 1, 1);
+    run_ops(ops);
+    for (uint64_t k = 0; k < s.out_words; ++k) c[k] = sf_combine_word(sb, N, k, s.out_words, s.nc_bits);
+    oracle_mul(a.data(), na, b.data(), nb, r.data(), 4);
+    const bool ok = memcmp(c.data(), r.data(), 8 * s.out_words) == 0 && c[s.out_words] == 0xdead;
+    if (!ok)
+        printf("SIMPLE MISMATCH %llu x %llu bits (N = 2^%d)\n", (unsigned long long)na, (unsigned long long)nb, s.m);
+    return ok;
+}
+
 }  // namespace
 
 int main(int argc, char** argv) {
@@ -286,6 +376,18 @@ int main(int argc, char** argv) {
         for (int i = 0; i < 40; ++i) bad += !check_product(g, 1 + g() % (1ull << (1 + g() % 18)), 1 + g() % (1ull << (1 + g() % 18)));
         bad += !check_batch(g, 30);
         PP.word_bits = 64;
+    }
+    if (what == "all" || what == "simple") {
+        // Alg. 4: bottom pass only (N <= 2^9), one and two strided passes
+        // above it, operands far shorter than N, single words
+        bad += !check_simple_tables();
+        const uint64_t fixed[][2] = {{1, 1},      {64, 64},     {65, 64},         {1, 700},     {1000, 999},
+                                     {5000, 70},  {64, 1 << 16}, {1 << 16, 1 << 16}, {100000, 3}, {1 << 19, 1 << 18},
+                                     {64 * 4096 + 1, 64 * 4095}, {1 << 20, 1 << 20}, {1 << 22, 1 << 22},
+                                     {(1 << 23) - 5, 1000}};
+        for (auto& p : fixed) bad += !check_simple_product(g, p[0], p[1]);
+        for (int i = 0; i < 30; ++i)
+            bad += !check_simple_product(g, 1 + g() % (1ull << (1 + g() % 18)), 1 + g() % (1ull << (1 + g() % 18)));
     }
     if (what == "all" || what == "xcd") bad += !check_xcd_order(g);
     if (what == "all" || what == "basiscvt") {
