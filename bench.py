@@ -434,6 +434,36 @@ def bench_w128(P, a, b, n, ref, steps, warmup, tune):
             "equal_to_w64": equal}
 
 
+def bench_simple(P, a, b, n, ref, steps, warmup):
+    """Alg. 4 (polynomial-basis GF(2^128), Cantor points) on the same operands:
+    timed like the headline product (operands resident), checked equal to the
+    tower product `ref`; also the rate of full GF(2^128) products it sustains
+    (butterflies of the three transforms plus the pointwise products)."""
+    import torch
+
+    ctx = P.Context(0)
+    c = torch.empty_like(ref)
+    for _ in range(warmup):
+        ctx.simple_mul_into(a, n, b, n, c)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        ctx.simple_mul_into(a, n, b, n, c)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    equal = bool(torch.equal(c, ref))
+    ctx.close()
+    assert equal, "the simple-variant product differs from the tower one"
+    k = (n + 63) // 64
+    m = max(1, (2 * k - 2).bit_length())
+    m_op = (k - 1).bit_length()
+    N = 1 << m
+    prods = (N // 2) * (2 * m_op + m) + N
+    return {"field": "GF(2^128) polynomial basis, Cantor points", "ms_per_product": round(ms, 4), "fft_points": N,
+            "field_products": prods, "field_products_per_s": round(prods / (ms * 1e-3), 1),
+            "equal_to_tower": equal}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -447,6 +477,7 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=10000)
     ap.add_argument("--no-tune", action="store_true", help="keep the default FFT pass schedules")
     ap.add_argument("--no-w128", action="store_true", help="skip the 128-bit-word (TGF(2^256)) variant")
+    ap.add_argument("--no-simple", action="store_true", help="skip the simple variant (Alg. 4)")
     ap.add_argument("--no-sizes", action="store_true", help="skip the single products at 2^16, 2^20, 2^29 bits")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="first run a plain device copy of this many MiB (counter calibration)")
@@ -580,6 +611,9 @@ def main():
     if not args.no_w128:
         log("bench: the same product with 128-bit words over TGF(2^256)")
         out["w128"] = bench_w128(P, a, b, n, c, args.steps, args.warmup, not args.no_tune)
+    if not args.no_simple:
+        log("bench: the same product by the simple variant (polynomial basis, Cantor points)")
+        out["simple"] = bench_simple(P, a, b, n, c, args.steps, args.warmup)
     if not args.no_batch:
         log(f"bench: batched products ({args.batch_jobs} jobs)")
         out["batched"] = bench_batched(ctx, args.batch_jobs)

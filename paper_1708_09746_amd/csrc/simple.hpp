@@ -32,7 +32,8 @@ constexpr int kSfLaneThreads = 128;   // bottom-pass and pointmul workgroups
 constexpr int kSfTabL = 7;            // layers of one strided pass, at most
 constexpr int kSfTabPtsLog = 10;      // points of one strided-pass workgroup, at most 2^10
 constexpr int kSfTabStride = 17;      // uint4 per table: 16 entries and one pad (spreads LDS banks)
-constexpr int kSfLaneC = 9;           // bottom pass: contiguous chunks of 2^9 points, layers 0..8
+constexpr int kSfLaneC = 9;           // bottom pass: contiguous chunks of 2^9 points
+constexpr int kSfLaneL = 4;           // bottom pass: layers 0..3 (multipliers shared by at most 8 butterflies)
 constexpr int kCantorBeta = 64;       // beta_0 .. beta_63 in the device table
 constexpr int kCantorTotal = kCantorBeta + (1 << kSfLaneC);  // then phi(u) for u < 2^9
 
@@ -288,14 +289,14 @@ inline bool build_cantor_table(std::vector<gcm_u128>& out) {
 // The passes of one transform over N = 2^m points: layers [0, M) with
 // M = m_op forward (the layers above the operand's converted length 2^m_op
 // only copy it: its top half is zero) and M = m inverse.  Bottom pass first
-// (contiguous, layers [0, min(M, c)) with c = min(m, 9)), then strided passes
-// of at most 7 layers; the forward transform runs them in the reverse order,
-// its first pass reading the converted words.
+// (contiguous chunks of 2^min(m, 9) points, layers [0, min(M, 4))), then
+// strided passes of at most 7 layers; the forward transform runs them in the
+// reverse order, its first pass reading the converted words.
 inline std::vector<SfftPass> sfft_passes(uint4* x, const uint64_t* words, int m_op, int m, bool inverse) {
     std::vector<SfftPass> v;
     const int M = inverse ? m : m_op;
     const int C = m < kSfLaneC ? m : kSfLaneC;
-    const int Lb = M < C ? M : C;
+    const int Lb = M < kSfLaneL ? M : kSfLaneL;
     v.push_back(SfftPass{x, nullptr, 0, 1ull << m, 0, Lb, C, inverse ? 1 : 0});
     const int up = M - Lb;
     if (up > 0) {
