@@ -452,8 +452,38 @@ def bench_simple(P, a, b, n, ref, steps, warmup):
     torch.cuda.synchronize()
     ms = (time.perf_counter() - t0) * 1e3 / steps
     equal = bool(torch.equal(c, ref))
-    ctx.close()
     assert equal, "the simple-variant product differs from the tower one"
+    # the other configured sizes: one call's latency (median of `reps`,
+    # events on the stream), product checked against the tower method's
+    import numpy as np
+
+    from paper_1708_09746_amd import inputs
+
+    sizes = {}
+    stream = torch.cuda.current_stream()
+    for name, reps in (("c1", 30), ("c2", 30), ("c3b", 5)):
+        n2, desc = WORKLOADS[name]
+        s1, s2 = inputs.SEEDS[name]
+        a2 = torch.from_numpy(inputs.random_poly(s1, n2).view(np.int64).copy()).cuda()
+        b2 = torch.from_numpy(inputs.random_poly(s2, n2).view(np.int64).copy()).cuda()
+        c2 = torch.empty(P.out_words(n2, n2), dtype=torch.int64, device="cuda")
+        for _ in range(2):
+            ctx.simple_mul_into(a2, n2, b2, n2, c2, stream)
+        ts = []
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            ctx.simple_mul_into(a2, n2, b2, n2, c2, stream)
+            e1.record(stream)
+            e1.synchronize()
+            ts.append(e0.elapsed_time(e1))
+        ts.sort()
+        same = bool(torch.equal(c2, ctx.mul(a2, n2, b2, n2, stream)))
+        assert same, f"the simple-variant product differs from the tower one at {desc}"
+        sizes[name] = {"workload": desc, "runs": reps, "median_ms": round(ts[len(ts) // 2], 4),
+                       "equal_to_tower": same}
+        del a2, b2, c2
+    ctx.close()
     k = (n + 63) // 64
     m = max(1, (2 * k - 2).bit_length())
     m_op = (k - 1).bit_length()
@@ -461,7 +491,7 @@ def bench_simple(P, a, b, n, ref, steps, warmup):
     prods = (N // 2) * (2 * m_op + m) + N
     return {"field": "GF(2^128) polynomial basis, Cantor points", "ms_per_product": round(ms, 4), "fft_points": N,
             "field_products": prods, "field_products_per_s": round(prods / (ms * 1e-3), 1),
-            "equal_to_tower": equal}
+            "equal_to_tower": equal, "sizes": sizes}
 
 
 def main():
