@@ -93,7 +93,10 @@ size_t gf2x_workspace_bytes_w(uint64_t na_bits, uint64_t nb_bits, int w);
 int gf2x_mul(const uint64_t *a, uint64_t na_bits, const uint64_t *b, uint64_t nb_bits, uint64_t *c);
 
 /* c = a * b with DEVICE pointers, enqueued on `stream` (Alg. 5).  a and b may
- * alias each other (squaring); c must not overlap either. */
+ * alias each other (squaring); c must not overlap either.  For transforms of
+ * 2^13 to 2^19 points the forward transform of b runs on a second stream
+ * owned by the context, forked from `stream` and joined back to it by events:
+ * the call stays ordered on `stream` like any other. */
 int gf2x_mul_dev(gf2x_ctx *ctx, const uint64_t *a, uint64_t na_bits, const uint64_t *b, uint64_t nb_bits,
                  uint64_t *c, void *stream);
 

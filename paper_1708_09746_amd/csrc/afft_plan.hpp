@@ -530,9 +530,11 @@ inline void plan_mul128(std::vector<Op>& ops, const LayerPool& pool, const PlanP
     ops.push_back(ps);
 }
 
-// The whole product c = a * b with the workspace at `ws`.
+// The whole product c = a * b with the workspace at `ws`.  If `split` is
+// given (w = 64), split[0] and split[1] receive the ends of the forward
+// transform of a (ops [0, split[0])) and of b (ops [split[0], split[1])).
 inline void plan_mul(std::vector<Op>& ops, const LayerPool& pool, const PlanParams& pp, const Sizes& s, const uint64_t* a,
-                     const uint64_t* b, uint64_t* c, char* ws) {
+                     const uint64_t* b, uint64_t* c, char* ws, size_t* split = nullptr) {
     if (s.w == 128) {
         plan_mul128(ops, pool, pp, s, a, b, c, ws);
         return;
@@ -552,6 +554,10 @@ inline void plan_mul(std::vector<Op>& ops, const LayerPool& pool, const PlanPara
     for (size_t i = a0; i < b0; ++i) ops[i].level = (uint32_t)(i - a0);
     for (size_t i = b0; i < p0; ++i) ops[i].level = (uint32_t)(i - b0);
     const uint32_t lp = (uint32_t)std::max(b0 - a0, p0 - b0);
+    if (split && a0 == 0) {
+        split[0] = b0;
+        split[1] = p0;
+    }
     emit_pmul(ops, sa, sb, sb, M, 1ull << s.m);
     emit_inverse(ops, pool, pp, sb, s.m, M, c, s.nc_bits);
     for (size_t i = p0; i < ops.size(); ++i) ops[i].level = lp + (uint32_t)(i - p0);
