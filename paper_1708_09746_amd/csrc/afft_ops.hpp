@@ -33,6 +33,9 @@ constexpr int kMuEntries = kMuHiCur + kMuHiN;
 constexpr int kBcTileLog64 = 13;  // BasisCvt tile on 64-bit words: 64 KiB
 constexpr int kBcTileLog128 = 12; // BasisCvt tile on 128-bit elements: 64 KiB
 constexpr int kBcSmallShift = 1;  // a small tile holds half the elements
+// single products of at most 2^kBcTinyMaxLog elements: tiles of 1/2^kBcTinyShift
+// (more blocks for arrays that fill only a few 32 KiB tiles)
+constexpr int kBcTinyShift = 3, kBcTinyMaxLog = 17;
 constexpr int kBcThreadsSmall = 512;
 constexpr int kPmulTile = 1024;
 constexpr int kPsiTile = 1024;

@@ -215,23 +215,30 @@ struct BcPlanner {
     }
 };
 
-// Emit BasisCvt (or its inverse) of 2^m elements at `data`: the forward op
-// list, reversed (each op running its layers backwards) for the inverse.
-inline void emit_bc(std::vector<Op>& ops, const LayerPool& pool, void* data, int wide, int m, int inverse,
-                    int small = 0) {
-    BcPlanner P{data, wide, 1ull << m, (wide ? kBcTileLog128 : kBcTileLog64) - (small ? kBcSmallShift : 0), &pool, {}};
-    P.cvt(m, 0);
+// Append a planned BasisCvt op list, or its inverse: the list reversed, each
+// tile and class op running its layers backwards.  A layer too tall for any
+// tile is two global ops (its two parts, each an XOR involution); reversing
+// the list already runs them in the opposite order, which is their inverse.
+inline void append_bc(std::vector<Op>& ops, const std::vector<Op>& fwd, int inverse) {
     if (!inverse) {
-        for (auto& op : P.ops) ops.push_back(op);
+        for (const Op& op : fwd) ops.push_back(op);
         return;
     }
-    for (size_t i = P.ops.size(); i-- > 0;) {
-        Op op = P.ops[i];
+    for (size_t i = fwd.size(); i-- > 0;) {
+        Op op = fwd[i];
         if (op.kind == OpKind::BcTile) op.bct.inverse = 1;
         if (op.kind == OpKind::BcClass) op.bcc.inverse = 1;
-        if (op.kind == OpKind::BcLayer) op.bcl.which = 1 - op.bcl.which;
         ops.push_back(op);
     }
+}
+
+// Emit BasisCvt (or its inverse) of 2^m elements at `data`.
+inline void emit_bc(std::vector<Op>& ops, const LayerPool& pool, void* data, int wide, int m, int inverse,
+                    int small = 0) {
+    const int shift = !small ? 0 : m <= kBcTinyMaxLog ? kBcTinyShift : kBcSmallShift;
+    BcPlanner P{data, wide, 1ull << m, (wide ? kBcTileLog128 : kBcTileLog64) - shift, &pool, {}};
+    P.cvt(m, 0);
+    append_bc(ops, P.ops, inverse);
 }
 
 // Layer ranges of the FFT passes: a contiguous bottom pass of up to 2^b

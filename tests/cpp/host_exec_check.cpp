@@ -201,6 +201,41 @@ bool check_basiscvt(int m, int small) {
     return ok;
 }
 
+// BasisCvt planned on tiles of 2^cap_log elements, so small that some layers
+// fit no class tile and run as global layer ops: forward against the flat
+// layer list, then the inverse back to the input.
+template <typename T>
+bool check_basiscvt_cap(int m, int cap_log) {
+    std::mt19937_64 g(2000 + m);
+    const uint64_t n = 1ull << m;
+    std::vector<T> a(n), flat, orig;
+    for (auto& x : a) x = rnd_elem<T>(g);
+    flat = a;
+    orig = a;
+    const int wide = sizeof(T) == 16;
+    BcPlanner P{a.data(), wide, n, cap_log, &POOL, {}};
+    P.cvt(m, 0);
+    bool global = false;
+    for (const Op& op : P.ops) global |= op.kind == OpKind::BcLayer;
+    std::vector<Op> ops;
+    append_bc(ops, P.ops, 0);
+    run_ops(ops);
+    std::vector<BcLayer> L;
+    bc_layer_list(m, 0, L);
+    for (const BcLayer& l : L)
+        for (int part = 0; part < 2; ++part) bc_part<T>(0, 1, flat.data(), n, l, part);
+    bool ok = global;
+    for (uint64_t i = 0; i < n && ok; ++i) ok = same(a[i], flat[i]);
+    std::vector<Op> inv;
+    append_bc(inv, P.ops, 1);
+    run_ops(inv);
+    for (uint64_t i = 0; i < n && ok; ++i) ok = same(a[i], orig[i]);
+    if (!ok)
+        printf("BasisCvt with global layers MISMATCH m = %d, tiles of 2^%d, %s (global layers planned: %d)\n", m,
+               cap_log, wide ? "128-bit" : "64-bit", (int)global);
+    return ok;
+}
+
 // The XCD-aware block-to-tile order of the block-strided kernels visits every
 // tile exactly once, for grids that are and are not multiples of 8 and tile
 // counts with and without a partial last round.
@@ -397,6 +432,17 @@ int main(int argc, char** argv) {
             for (int m : {0, 1, 2, 5, 12, 13, 14, 16, 17, 20, 22}) bad += !check_basiscvt<uint64_t>(m, small);
             for (int m : {11, 12, 13, 16, 19, 23}) bad += !check_basiscvt<uint4>(m, small);
         }
+        // every size on the tiles of single products (the smallest tiles up to
+        // 2^kBcTinyMaxLog elements, then the 32 KiB ones)
+        for (int m = 0; m <= kBcTinyMaxLog + 1; ++m) {
+            bad += !check_basiscvt<uint64_t>(m, 1);
+            bad += !check_basiscvt<uint4>(m, 1);
+        }
+        // layers too tall for any class tile (as for 2^29 words on 32 KiB
+        // tiles) on small stand-in tiles
+        bad += !check_basiscvt_cap<uint64_t>(16, 8);
+        bad += !check_basiscvt_cap<uint4>(17, 8);
+        bad += !check_basiscvt_cap<uint64_t>(16, 7);
     }
     printf(bad ? "host exec: %d failures\n" : "host exec ok\n", bad);
     return bad ? 1 : 0;

@@ -169,6 +169,26 @@ def test_basiscvt_mixed_schedule_matches_alg3(ctx, m):
     assert [int(x) for x in host(d)] == T.basis_cvt([int(x) for x in w])
 
 
+def test_basiscvt_global_layers_roundtrip(ctx):
+    """2^29 words (4 GiB): the top VarSubs layers fit no class tile and run as
+    global layer ops; iBasisCvt must undo BasisCvt (it once ran the two parts
+    of such a layer in the forward order)."""
+    m = 29
+    g = torch.Generator(device="cuda")
+    g.manual_seed(0x29)
+    x = torch.empty(1 << m, dtype=torch.int64, device="cuda").random_(generator=g)
+    y = x.clone()
+    say(f"case basiscvt roundtrip with global layers m={m}")
+    ctx.basiscvt(y, m)
+    torch.cuda.synchronize()
+    assert not torch.equal(x, y)
+    ctx.basiscvt(y, m, inverse=True)
+    torch.cuda.synchronize()
+    assert torch.equal(x, y)
+    del x, y
+    torch.cuda.empty_cache()
+
+
 @pytest.mark.parametrize("m", [20, 22, 23])
 def test_basiscvt_large_roundtrip_and_linearity(ctx, m):
     """iBasisCvt undoes BasisCvt and the map is GF(2)-linear; a single nonzero
