@@ -434,7 +434,7 @@ def bench_w128(P, a, b, n, ref, steps, warmup, tune):
             "equal_to_w64": equal}
 
 
-def bench_simple(P, a, b, n, ref, steps, warmup):
+def bench_simple(P, a, b, n, ref, steps, warmup, other_sizes=True):
     """Alg. 4 (polynomial-basis GF(2^128), Cantor points) on the same operands:
     timed like the headline product (operands resident), checked equal to the
     tower product `ref`; also the rate of full GF(2^128) products it sustains
@@ -461,7 +461,7 @@ def bench_simple(P, a, b, n, ref, steps, warmup):
 
     sizes = {}
     stream = torch.cuda.current_stream()
-    for name, reps in (("c1", 30), ("c2", 30), ("c3b", 5)):
+    for name, reps in (("c1", 30), ("c2", 30), ("c3b", 5)) if other_sizes else ():
         n2, desc = WORKLOADS[name]
         s1, s2 = inputs.SEEDS[name]
         a2 = torch.from_numpy(inputs.random_poly(s1, n2).view(np.int64).copy()).cuda()
@@ -643,7 +643,7 @@ def main():
         out["w128"] = bench_w128(P, a, b, n, c, args.steps, args.warmup, not args.no_tune)
     if not args.no_simple:
         log("bench: the same product by the simple variant (polynomial basis, Cantor points)")
-        out["simple"] = bench_simple(P, a, b, n, c, args.steps, args.warmup)
+        out["simple"] = bench_simple(P, a, b, n, c, args.steps, args.warmup, not args.no_sizes)
     if not args.no_batch:
         log(f"bench: batched products ({args.batch_jobs} jobs)")
         out["batched"] = bench_batched(ctx, args.batch_jobs)
