@@ -95,6 +95,16 @@ AFFT_HD uint32_t perm32(uint32_t hi, uint32_t lo, uint32_t sel) {
 }
 
 // Table index (k << 8) | e with k = byte kb of kw and e = byte eb of ew.
+// a ^ b ^ c in one instruction (gfx950's three-input bit operation, truth
+// table 0x96: the parity of the three inputs)
+AFFT_HD uint32_t xor3(uint32_t a, uint32_t b, uint32_t c) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96);
+#else
+    return a ^ b ^ c;
+#endif
+}
+
 #define AFFT_IX(kw, kb, ew, eb) perm32((kw), (ew), 0x0c0c0000u | ((4u + (kb)) << 8) | (eb))
 
 // word times lambda; mode 0: lambda in GF(256), 1: TGF(2^16), 2: TGF(2^32),
@@ -120,7 +130,7 @@ AFFT_HD uint32_t mul_word_k(const uint8_t* mt, const uint4& m, uint32_t a, int m
     if (mode == 1) {
         const uint32_t t1b = mt[AFFT_IX(m.x, 0, a, 2)], t2b = mt[AFFT_IX(m.x, 1, a, 3)];
         const uint32_t t3b = mt[AFFT_IX(m.x, 2, dd, 2)];
-        return perm32(t1b, t1a, 0x04040000u) ^ perm32(t2b, t2a, 0x0c040c00u) ^ perm32(t3b, t3a, 0x040c000cu);
+        return xor3(perm32(t1b, t1a, 0x04040000u), perm32(t2b, t2a, 0x0c040c00u), perm32(t3b, t3a, 0x040c000cu));
     }
     const uint32_t sw = a ^ (a >> 16);   // low half: a0 + a1
     const uint32_t sd = sw ^ (sw >> 8);  // byte 0: its two bytes summed
@@ -129,8 +139,8 @@ AFFT_HD uint32_t mul_word_k(const uint8_t* mt, const uint4& m, uint32_t a, int m
     const uint32_t t3b = mt[AFFT_IX(m.y, 2, dd, 2)];
     const uint32_t t1c = mt[AFFT_IX(m.z, 0, sw, 0)], t2c = mt[AFFT_IX(m.z, 1, sw, 1)];
     const uint32_t t3c = mt[AFFT_IX(m.z, 2, sd, 0)];
-    return perm32(t1a, t1a, 0x00000000u) ^ perm32(t3a, t2a, 0x04000400u) ^ perm32(t1c, t1b, 0x04040000u) ^
-           perm32(t3b, t2b, 0x0c0c0400u) ^ perm32(t3c, t2c, 0x04000c0cu);
+    return xor3(xor3(perm32(t1a, t1a, 0x00000000u), perm32(t3a, t2a, 0x04000400u), perm32(t1c, t1b, 0x04040000u)),
+                perm32(t3b, t2b, 0x0c0c0400u), perm32(t3c, t2c, 0x04000c0cu));
 }
 
 AFFT_HD uint4 mul_sub_k(const uint8_t* mt, const uint4& m, const uint4& v, int mode) {

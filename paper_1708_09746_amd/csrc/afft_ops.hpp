@@ -354,17 +354,25 @@ constexpr int kPhiNib = 512;
 constexpr int kPhinTotal = 256 + 2 * 512;
 AFFT_HD int phin_off(uint32_t mode) { return mode <= kPhi64 ? 0 : 256 + 512 * (int)(mode - kPhi128Lo); }
 AFFT_HD int phin_len(uint32_t mode) { return mode <= kPhi64 ? 256 : 512; }
+// r + a + b componentwise, by three-input XORs
+AFFT_HD uint4 xor3_4(const uint4& r, const uint4& a, const uint4& b) {
+    return make_uint4(xor3(r.x, a.x, b.x), xor3(r.y, a.y, b.y), xor3(r.z, a.z, b.z), xor3(r.w, a.w, b.w));
+}
+
 AFFT_HD uint4 phi_word(const uint4* phin, uint64_t w) {
     uint4 r = make_uint4(0, 0, 0, 0);
 #pragma unroll
-    for (int k = 0; k < 16; ++k) r = r ^ phin[k * 16 + ((w >> (4 * k)) & 15u)];
+    for (int k = 0; k < 16; k += 2)
+        r = xor3_4(r, phin[k * 16 + ((w >> (4 * k)) & 15u)], phin[(k + 1) * 16 + ((w >> (4 * k + 4)) & 15u)]);
     return r;
 }
 AFFT_HD uint4 phi_word128(const uint4* phin, const uint4& w) {
     const uint32_t ws[4] = {w.x, w.y, w.z, w.w};
     uint4 r = make_uint4(0, 0, 0, 0);
 #pragma unroll
-    for (int k = 0; k < 32; ++k) r = r ^ phin[k * 16 + ((ws[k >> 3] >> (4 * (k & 7))) & 15u)];
+    for (int k = 0; k < 32; k += 2)
+        r = xor3_4(r, phin[k * 16 + ((ws[k >> 3] >> (4 * (k & 7))) & 15u)],
+                   phin[(k + 1) * 16 + ((ws[(k + 1) >> 3] >> (4 * ((k + 1) & 7))) & 15u)]);
     return r;
 }
 
@@ -390,8 +398,8 @@ AFFT_HD void build_mt3(int tid, int nt, const uint8_t* mt, uint2* mt3) {
 }
 
 AFFT_HD uint32_t mul_word8_t(const uint2& t0, const uint2& t1, uint32_t t2, uint32_t a) {
-    return perm32(t0.y, t0.x, a & 0x07070707u) ^ perm32(t1.y, t1.x, (a >> 3) & 0x07070707u) ^
-           perm32(0u, t2, (a >> 6) & 0x03030303u);
+    return xor3(perm32(t0.y, t0.x, a & 0x07070707u), perm32(t1.y, t1.x, (a >> 3) & 0x07070707u),
+                perm32(0u, t2, (a >> 6) & 0x03030303u));
 }
 
 AFFT_HD uint4 mul_sub8_t(const uint2* mt3, uint32_t lam8, const uint4& v) {
@@ -709,7 +717,9 @@ AFFT_HD uint4 psi_half(const uint4* tab, const uint4& c0, const uint4& c1) {
     const uint32_t w[8] = {c0.x, c0.y, c0.z, c0.w, c1.x, c1.y, c1.z, c1.w};
     uint4 r = make_uint4(0, 0, 0, 0);
 #pragma unroll
-    for (int k = 0; k < 64; ++k) r = r ^ tab[k * 16 + ((w[k >> 3] >> (4 * (k & 7))) & 15u)];
+    for (int k = 0; k < 64; k += 2)
+        r = xor3_4(r, tab[k * 16 + ((w[k >> 3] >> (4 * (k & 7))) & 15u)],
+                   tab[(k + 1) * 16 + ((w[(k + 1) >> 3] >> (4 * ((k + 1) & 7))) & 15u)]);
     return r;
 }
 
@@ -720,10 +730,11 @@ AFFT_HD uint64_t psi_half64(const uint4* psi_tab, const uint4& e, int half) {
     uint32_t lo = 0, hi = 0;
     const uint32_t w[4] = {e.x, e.y, e.z, e.w};
 #pragma unroll
-    for (int k = 0; k < 16; ++k) {
+    for (int k = 0; k < 16; k += 2) {
         const uint2 v = t2[2 * (k * 256 + ((w[k >> 2] >> (8 * (k & 3))) & 255u)) + half];
-        lo ^= v.x;
-        hi ^= v.y;
+        const uint2 u = t2[2 * ((k + 1) * 256 + ((w[(k + 1) >> 2] >> (8 * ((k + 1) & 3))) & 255u)) + half];
+        lo = xor3(lo, v.x, u.x);
+        hi = xor3(hi, v.y, u.y);
     }
     return (uint64_t)lo | ((uint64_t)hi << 32);
 }

@@ -48,10 +48,6 @@ struct SfftPass {
 // ------------------------------------------ bodies (kernels and host checks)
 
 
-AFFT_HD uint32_t word_of(const uint4& v, int q) {
-    return q == 0 ? v.x : q == 1 ? v.y : q == 2 ? v.z : v.w;
-}
-
 // v * x mod x^128 + x^7 + x^2 + x + 1
 AFFT_HD uint4 gcm_mulx(uint4 v) {
     const uint32_t top = v.w >> 31;
@@ -88,17 +84,19 @@ AFFT_HD void gcm_build_tab(uint4 v, uint4* T) {
 AFFT_HD uint4 gcm_reduce(const uint32_t (&a)[8]) {
     const uint32_t h0 = a[4], h1 = a[5], h2 = a[6], h3 = a[7];
     uint4 r;
-    r.x = a[0] ^ h0 ^ (h0 << 1) ^ (h0 << 2) ^ (h0 << 7);
-    r.y = a[1] ^ h1 ^ ((h1 << 1) | (h0 >> 31)) ^ ((h1 << 2) | (h0 >> 30)) ^ ((h1 << 7) | (h0 >> 25));
-    r.z = a[2] ^ h2 ^ ((h2 << 1) | (h1 >> 31)) ^ ((h2 << 2) | (h1 >> 30)) ^ ((h2 << 7) | (h1 >> 25));
-    r.w = a[3] ^ h3 ^ ((h3 << 1) | (h2 >> 31)) ^ ((h3 << 2) | (h2 >> 30)) ^ ((h3 << 7) | (h2 >> 25));
-    const uint32_t ov = (h3 >> 31) ^ (h3 >> 30) ^ (h3 >> 25);
-    r.x ^= ov ^ (ov << 1) ^ (ov << 2) ^ (ov << 7);
+    r.x = xor3(xor3(a[0], h0, h0 << 1), h0 << 2, h0 << 7);
+    r.y = xor3(xor3(a[1], h1, (h1 << 1) | (h0 >> 31)), (h1 << 2) | (h0 >> 30), (h1 << 7) | (h0 >> 25));
+    r.z = xor3(xor3(a[2], h2, (h2 << 1) | (h1 >> 31)), (h2 << 2) | (h1 >> 30), (h2 << 7) | (h1 >> 25));
+    r.w = xor3(xor3(a[3], h3, (h3 << 1) | (h2 >> 31)), (h3 << 2) | (h2 >> 30), (h3 << 7) | (h2 >> 25));
+    const uint32_t ov = xor3(h3 >> 31, h3 >> 30, h3 >> 25);
+    r.x = xor3(xor3(r.x, ov, ov << 1), ov << 2, ov << 7);
     return r;
 }
 
 // v * w with T the table of v: sum over nibble positions p = 8q + r of
-// T[nibble] x^(32q) x^(4r), by Horner's rule in x^4 over r.
+// T[nibble] x^(32q) x^(4r), by Horner's rule in x^4 over r.  The four
+// lookups of one r land on words q .. q + 3 of the accumulator; each word
+// takes its (up to four) terms through three-input XORs.
 AFFT_HD uint4 gcm_mul_tab(const uint4* T, uint4 w) {
     uint32_t a[8] = {0, 0, 0, 0, 0, 0, 0, 0};
 #pragma unroll
@@ -108,14 +106,15 @@ AFFT_HD uint4 gcm_mul_tab(const uint4* T, uint4 w) {
             for (int i = 7; i > 0; --i) a[i] = (a[i] << 4) | (a[i - 1] >> 28);
             a[0] <<= 4;
         }
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const uint4 t = T[(word_of(w, q) >> (4 * r)) & 15u];
-            a[q] ^= t.x;
-            a[q + 1] ^= t.y;
-            a[q + 2] ^= t.z;
-            a[q + 3] ^= t.w;
-        }
+        const uint4 t0 = T[(w.x >> (4 * r)) & 15u], t1 = T[(w.y >> (4 * r)) & 15u];
+        const uint4 t2 = T[(w.z >> (4 * r)) & 15u], t3 = T[(w.w >> (4 * r)) & 15u];
+        a[0] ^= t0.x;
+        a[1] = xor3(a[1], t0.y, t1.x);
+        a[2] = xor3(a[2], t0.z, t1.y) ^ t2.x;
+        a[3] = xor3(xor3(a[3], t0.w, t1.z), t2.y, t3.x);
+        a[4] = xor3(a[4], t1.w, t2.z) ^ t3.y;
+        a[5] = xor3(a[5], t2.w, t3.z);
+        a[6] ^= t3.w;
     }
     return gcm_reduce(a);
 }
