@@ -138,6 +138,28 @@ def test_results_do_not_depend_on_the_stream(ctx):
     assert np.array_equal(host(c2), oracle.mul(a, na, b, nb))
 
 
+def test_back_to_back_products_across_the_fork_sizes(ctx):
+    """Products enqueued on one stream with no synchronisation in between,
+    sizes ascending (the workspace grows between them) and on both sides of
+    the range whose forward transforms run on a second stream: each result
+    is checked after a single synchronisation."""
+    cases = [((1 << 16) - 9, 1 << 16, False), (1 << 19, (1 << 17) + 3, False), ((1 << 20) + 5, 0, True),
+             ((1 << 20) + 64, 1 << 12, False), (1 << 25, 0, True)]
+    ops = []
+    for i, (na, nb, square) in enumerate(cases):
+        a = inputs.random_poly(0x900 + i, na)
+        b = None if square else inputs.random_poly(0x950 + i, nb)
+        da = dev(a)
+        ops.append((a, na, b, na if square else nb, da, da if square else dev(b)))
+    torch.cuda.synchronize()
+    say("case back-to-back products across the fork sizes")
+    jobs = [(a, na, b, nb, ctx.mul(da, na, db, nb)) for a, na, b, nb, da, db in ops]
+    torch.cuda.synchronize()
+    for a, na, b, nb, c in jobs:
+        want = spread_words(a, na) if b is None else oracle.mul(a, na, b, nb)
+        assert np.array_equal(host(c), want), (na, nb)
+
+
 # ------------------------------------------------------------- stages
 
 
