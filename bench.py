@@ -513,7 +513,7 @@ def main():
                     help="first run a plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build measures one GPU; --gpus {args.gpus} is not supported "
+        print(f"bench.py: the benchmark runs on one GPU; --gpus {args.gpus} is not supported "
               "(independent products shard across GPUs without communication)", file=sys.stderr)
         sys.exit(2)
 
