@@ -11,6 +11,8 @@ Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
   Alg. 1/2/3/5, changeRepr) for small inputs.
 * ``simple.py``: the simple variant (Alg. 4): GF(2^128) in the polynomial
   basis of Sec. 3.1, Cantor-basis points, for small inputs.
+* ``frobenius.py``: the Frobenius-partition variant (App. C): values at
+  beta_{m+64} + V_m, the seven-layer encoding, for small inputs.
 
 Nothing here is shared with, or imported by, the GPU library.
 """
