@@ -94,9 +94,10 @@ int gf2x_mul(const uint64_t *a, uint64_t na_bits, const uint64_t *b, uint64_t nb
 
 /* c = a * b with DEVICE pointers, enqueued on `stream` (Alg. 5).  a and b may
  * alias each other (squaring); c must not overlap either.  For transforms of
- * 2^13 to 2^19 points the forward transform of b runs on a second stream
- * owned by the context, forked from `stream` and joined back to it by events:
- * the call stays ordered on `stream` like any other. */
+ * 2^13 points or more, part of the forward transform of b runs on a second
+ * stream owned by the context, forked from `stream` and joined back to it by
+ * events: up to 2^19 points the whole transform, above only its pack and
+ * BasisCvt.  The call stays ordered on `stream` like any other. */
 int gf2x_mul_dev(gf2x_ctx *ctx, const uint64_t *a, uint64_t na_bits, const uint64_t *b, uint64_t nb_bits,
                  uint64_t *c, void *stream);
 

@@ -1746,11 +1746,25 @@ int gf2x_mul_dev(gf2x_ctx* ctx, const uint64_t* a, uint64_t na_bits, const uint6
     std::vector<Op> ops;
     size_t split[2] = {0, 0};
     plan_mul(ops, ctx->pool, single_params(ctx), s, a, b, c, ctx->ws, split);
-    if (s.m < kForkMinLog || s.m > kForkMaxLog || !split[1]) return run_ops(ctx, ops, st);
-    // the two forward transforms are independent: b's runs on the second
-    // stream, between a fork event recorded here and a join event the rest waits for
-    const std::vector<Op> fa(ops.begin(), ops.begin() + split[0]), fb(ops.begin() + split[0], ops.begin() + split[1]),
+    if (s.m < kForkMinLog || !split[1]) return run_ops(ctx, ops, st);
+    // The two forward transforms are independent: b's runs on the second
+    // stream, between a fork event recorded here and a join event that a's
+    // continuation waits for.  Up to 2^kForkMaxLog points the whole transforms
+    // overlap; above, only their pack and BasisCvt launches do (each FFT pass
+    // fills the device, and its launches stay alone).
+    std::vector<Op> fa(ops.begin(), ops.begin() + split[0]), fb(ops.begin() + split[0], ops.begin() + split[1]),
         rest(ops.begin() + split[1], ops.end());
+    std::vector<Op> fa_fft, fb_fft;
+    if (s.m > kForkMaxLog) {
+        auto cut = [](std::vector<Op>& v, std::vector<Op>& tail) {
+            size_t i = 0;
+            while (i < v.size() && v[i].kind != OpKind::Fft && v[i].kind != OpKind::Spine) ++i;
+            tail.assign(v.begin() + i, v.end());
+            v.resize(i);
+        };
+        cut(fa, fa_fft);
+        cut(fb, fb_fft);
+    }
     hipError_t e = hipEventRecord(ctx->ev_fork, st);
     if (e == hipSuccess) e = hipStreamWaitEvent(ctx->aux_stream, ctx->ev_fork, 0);
     if (e != hipSuccess) return hip_fail(ctx, e, "fork");
@@ -1762,6 +1776,8 @@ int gf2x_mul_dev(gf2x_ctx* ctx, const uint64_t* a, uint64_t na_bits, const uint6
     if (rc) return rc;
     e = hipStreamWaitEvent(st, ctx->ev_join, 0);
     if (e != hipSuccess) return hip_fail(ctx, e, "join");
+    if ((rc = run_ops(ctx, fa_fft, st))) return rc;
+    if ((rc = run_ops(ctx, fb_fft, st))) return rc;
     return run_ops(ctx, rest, st);
 }
 
