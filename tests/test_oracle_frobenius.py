@@ -5,7 +5,8 @@ encoding equals the first seven layers of the full FFT_LCH over 128 n points
 (the truncated transform of App. C); the map is a bijection (the Frobenius
 orbits of the n points are disjoint, of size 128 each, and the encoding
 products are independent); interpolation inverts evaluation; products equal
-the bitwise product.  Planted mistakes in the oracle are caught."""
+the bitwise product; BasisCvt over bits factors through 64-bit words.
+Planted mistakes in the oracle are caught."""
 import random
 
 import pytest
@@ -78,7 +79,42 @@ def check_products():
         assert F.binpolymul_frobenius(a, na, b, nb) == T.clmul_int(a, b), (na, nb)
 
 
+def _polydivmod(a: int, b: int):
+    q = 0
+    db = b.bit_length() - 1
+    while a and a.bit_length() - 1 >= db:
+        sh = a.bit_length() - 1 - db
+        q ^= 1 << sh
+        a ^= b << sh
+    return q, a
+
+
+def check_bit_basiscvt_factors_through_words():
+    """BasisCvt over GF(2) coefficients factors through 64-bit words: with
+    z = s_6(x), X_{64q+r}(x) = X_r(x) X_q(z) (s_{6+j} = s_j o s_6), so the
+    bit-level conversion is the z-adic expansion a = sum_q H_q(x) z^q
+    (deg H_q < 64), then BasisCvt of the word sequence H_q, then the 64-bit
+    conversion inside each word."""
+    z = T.s_poly(6)
+    assert z == (1 << 64) | (1 << 16) | (1 << 4) | (1 << 1)
+    rng = random.Random(15)
+    for M in (7, 8, 10):
+        n = 1 << M
+        a = rng.getrandbits(n)
+        direct = T.basis_cvt([(a >> k) & 1 for k in range(n)])
+        digits, r = [], a
+        for _ in range(n // 64):
+            r, h = _polydivmod(r, z)
+            digits.append(h)
+        assert r == 0
+        out = []
+        for gq in T.basis_cvt(digits):
+            out.extend(T.basis_cvt([(gq >> i) & 1 for i in range(64)]))
+        assert out == direct, M
+
+
 CHECKS = [
+    check_bit_basiscvt_factors_through_words,
     check_values_are_evaluations,
     check_encoding_is_the_truncated_fft,
     check_bijection,
