@@ -486,7 +486,7 @@ inline void emit_inverse(std::vector<Op>& ops, const LayerPool& pool, const Plan
 // on whole coefficients, so on 128-bit words, and on each plane alone.  Ops
 // of the two planes are independent and share levels.
 inline void plan_mul128(std::vector<Op>& ops, const LayerPool& pool, const PlanParams& pp, const Sizes& s,
-                        const uint64_t* a, const uint64_t* b, uint64_t* c, char* ws) {
+                        const uint64_t* a, const uint64_t* b, uint64_t* c, char* ws, size_t* split = nullptr) {
     const Workspace w = workspace_for(s);
     const uint64_t N = 1ull << s.m;
     uint4* wa = (uint4*)(ws + w.off_wa);
@@ -513,7 +513,15 @@ inline void plan_mul128(std::vector<Op>& ops, const LayerPool& pool, const PlanP
             }
         return l + (uint32_t)pl[0].size();
     };
-    const uint32_t lp = std::max(forward(a, s.na_bits, wa, s.m_a, sa), forward(b, s.nb_bits, wb, s.m_b, sb));
+    const size_t a0 = ops.size();
+    const uint32_t la = forward(a, s.na_bits, wa, s.m_a, sa);
+    const size_t b0 = ops.size();
+    const uint32_t lb = forward(b, s.nb_bits, wb, s.m_b, sb);
+    if (split && a0 == 0) {
+        split[0] = b0;
+        split[1] = ops.size();
+    }
+    const uint32_t lp = std::max(la, lb);
     Op pm{};
     pm.kind = OpKind::Pmul;
     pm.pmul = PmulOp{sa, sb, sb, N, N, sa + N, sb + N, sb + N};
@@ -538,12 +546,12 @@ inline void plan_mul128(std::vector<Op>& ops, const LayerPool& pool, const PlanP
 }
 
 // The whole product c = a * b with the workspace at `ws`.  If `split` is
-// given (w = 64), split[0] and split[1] receive the ends of the forward
-// transform of a (ops [0, split[0])) and of b (ops [split[0], split[1])).
+// given, split[0] and split[1] receive the ends of the forward transform of a
+// (ops [0, split[0])) and of b (ops [split[0], split[1])).
 inline void plan_mul(std::vector<Op>& ops, const LayerPool& pool, const PlanParams& pp, const Sizes& s, const uint64_t* a,
                      const uint64_t* b, uint64_t* c, char* ws, size_t* split = nullptr) {
     if (s.w == 128) {
-        plan_mul128(ops, pool, pp, s, a, b, c, ws);
+        plan_mul128(ops, pool, pp, s, a, b, c, ws, split);
         return;
     }
     Workspace w = workspace_for(s);
