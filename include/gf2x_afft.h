@@ -33,9 +33,14 @@
  *     (spectra) and come from hipMalloc (or torch on ROCm).
  *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
  *     *_dev calls only enqueue work and return; completion is observed on the
- *     stream.  A context's scratch is reused by its next call, so calls on one
- *     context must be issued from one host thread and on one stream (or the
- *     caller serializes them).
+ *     stream.  Calls on one context must be issued from one host thread.  A
+ *     context's workspace is reused by its next call; a call that uses it
+ *     (gf2x_mul_dev, gf2x_forward_dev, gf2x_simple_mul_dev,
+ *     gf2x_simple_forward_dev) on a stream other than the previous such
+ *     call's first makes its stream wait for everything that call enqueued
+ *     (an event recorded at its end), so calls on mixed streams run one after
+ *     the other.  Calls made while `stream` is being captured into a graph
+ *     take no part in this ordering (the caller orders them).
  *
  * Status codes: every function returns GF2X_OK or a negative code and never
  * aborts.  gf2x_strerror() names a code; gf2x_last_error() gives the message
@@ -365,12 +370,17 @@ uint64_t gf2x_now_ns(void);
 int gf2x_server_create(gf2x_ctx *ctx, const gf2x_server_cfg *cfg, gf2x_server **server);
 
 /* Queues c = a * b (device pointers, sizes in bits as for gf2x_mul_dev).
+ * `stream` is the caller's stream that produced a and b (and last used c):
+ * an event is recorded on it now, and the request's first work on the
+ * server's own stream waits for it, so the request reads its operands and
+ * writes c only after everything enqueued on `stream` before this call.
+ * Work the caller enqueues later may read c once poll reports the request.
  * Returns at once: EINVAL for NULL pointers with nonzero sizes or overlap of
  * c with a or b, ERANGE for N > 2^32, ENOMEM if the request's footprint
  * exceeds the whole arena (it could never be admitted); the request is then
  * not queued.  An empty product is complete at once (nothing is written). */
 int gf2x_server_submit(gf2x_server *server, const uint64_t *a, uint64_t na_bits, const uint64_t *b, uint64_t nb_bits,
-                       uint64_t *c, uint64_t tag);
+                       uint64_t *c, uint64_t tag, void *stream);
 
 /* Runs the engine until gf2x_now_ns() >= until_ns or there is nothing left
  * to do: records completions, admits queued requests, builds and launches

@@ -112,7 +112,7 @@ def lib():
             "gf2x_lookup_rate": (i32, [vp, ctypes.POINTER(ctypes.c_double)]),
             "gf2x_now_ns": (u64, []),
             "gf2x_server_create": (i32, [vp, ctypes.POINTER(ServerCfg), ctypes.POINTER(vp)]),
-            "gf2x_server_submit": (i32, [vp, vp, u64, vp, u64, vp, u64]),
+            "gf2x_server_submit": (i32, [vp, vp, u64, vp, u64, vp, u64, vp]),
             "gf2x_server_step": (i32, [vp, u64]),
             "gf2x_server_poll": (sz, [vp, ctypes.POINTER(Done), sz]),
             "gf2x_server_info": (i32, [vp, ctypes.POINTER(ServerStats)]),
@@ -416,8 +416,11 @@ class Server:
         self._h = h
         self._buf = (Done * 4096)()
 
-    def submit(self, a, na_bits: int, b, nb_bits: int, c, tag: int):
-        rc = lib().gf2x_server_submit(self._h, _ptr(a), na_bits, _ptr(b), nb_bits, _ptr(c), tag)
+    def submit(self, a, na_bits: int, b, nb_bits: int, c, tag: int, stream=None):
+        """Queue c = a * b; the request starts after the work already enqueued
+        on `stream` (default: the current stream), which produced a and b."""
+        rc = lib().gf2x_server_submit(self._h, _ptr(a), na_bits, _ptr(b), nb_bits, _ptr(c), tag,
+                                      _stream_handle(stream))
         self.ctx._check(rc, "gf2x_server_submit")
 
     def step(self, until_ns: int = 0):

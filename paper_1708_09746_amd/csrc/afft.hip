@@ -618,6 +618,11 @@ struct gf2x_ctx {
     // enough to leave most CUs idle; fork and join events
     hipStream_t aux_stream = nullptr;
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+    // calls that use the workspace on a stream other than the previous such
+    // call's wait for ev_last, recorded at the end of that call
+    hipEvent_t ev_last = nullptr;
+    hipStream_t last_st = nullptr;
+    bool has_last = false;
     std::string err;
     gf2x_batch* transient = nullptr;  // the last gf2x_mul_batch call's plan
     hipStream_t transient_stream = nullptr;
@@ -665,6 +670,8 @@ struct gf2x_server {
         uint64_t* c = nullptr;
         uint64_t na = 0, nb = 0, tag = 0, t_submit = 0, t_admit = 0;
         int w = 64;  // word width when submitted (its footprint is for that width)
+        hipStream_t src = nullptr;  // the caller's stream at submit, and an event recorded on it then
+        hipEvent_t ready = nullptr;
         size_t off = 0, bytes = 0;
         std::vector<gf2x::Op> ops;
         std::vector<uint64_t> level_tiles;  // tiles of each dependency level
@@ -695,6 +702,8 @@ struct gf2x_server {
     std::vector<gf2x::BatchGroup> it_groups;
     std::vector<gf2x::LaunchGroup> it_launch;
     std::vector<char> it_host;
+    // events recorded on callers' streams at submit, reused
+    std::vector<hipEvent_t> free_events, all_events;
 };
 
 
@@ -734,6 +743,40 @@ bool ranges_overlap(const void* p, size_t pn, const void* q, size_t qn) {
     if (!p || !q || !pn || !qn) return false;
     auto a = (uintptr_t)p, b = (uintptr_t)q;
     return a < b + qn && b < a + pn;
+}
+
+// Calls on one context share its workspace.  A call on a stream other than
+// the previous workspace call's waits for everything that call enqueued (an
+// event recorded at its end), so calls on mixed streams run one after the
+// other instead of racing.  Calls under stream capture take no part (an event
+// recorded outside a capture cannot be waited on inside it).
+bool stream_capturing(hipStream_t st) {
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(st, &cs) != hipSuccess) {
+        (void)hipGetLastError();
+        return false;
+    }
+    return cs != hipStreamCaptureStatusNone;
+}
+
+int ws_enter(gf2x_ctx* ctx, hipStream_t st, bool capturing) {
+    if (capturing || !ctx->has_last || st == ctx->last_st) return GF2X_OK;
+    hipError_t e = hipStreamWaitEvent(st, ctx->ev_last, 0);
+    if (e != hipSuccess) return hip_fail(ctx, e, "hipStreamWaitEvent (stream order)");
+    return GF2X_OK;
+}
+
+int ws_leave(gf2x_ctx* ctx, hipStream_t st, bool capturing, int rc) {
+    if (rc) return rc;
+    if (capturing) {
+        ctx->has_last = false;
+        return GF2X_OK;
+    }
+    hipError_t e = hipEventRecord(ctx->ev_last, st);
+    if (e != hipSuccess) return hip_fail(ctx, e, "hipEventRecord (stream order)");
+    ctx->last_st = st;
+    ctx->has_last = true;
+    return GF2X_OK;
 }
 
 int ensure_ws(gf2x_ctx* ctx, size_t bytes, hipStream_t st) {
@@ -1240,6 +1283,7 @@ void server_free(gf2x_server* S) {
     }
     if (S->arena) (void)hipFree(S->arena);
     if (S->st) (void)hipStreamDestroy(S->st);
+    for (hipEvent_t ev : S->all_events) (void)hipEventDestroy(ev);
     delete S;
 }
 
@@ -1258,6 +1302,8 @@ void server_fail_all(gf2x_server* S, int status) {
         S->slots[i].fin.clear();
     }
     auto finish = [&](gf2x_server::Req& r) {
+        if (r.ready) S->free_events.push_back(r.ready);
+        r.ready = nullptr;
         S->done.push_back(gf2x_done{r.tag, status, r.iters, r.t_submit, r.t_admit, t});
         ++S->stats.completed;
     };
@@ -1367,6 +1413,23 @@ int server_iterate(gf2x_server* S, bool& launched) {
     }
     S->it_ops.clear();
     S->it_rank.clear();
+    // requests starting in this iteration: their operands are ready once the
+    // work enqueued on the submitter's stream before the submit is done (one
+    // wait per distinct stream, on its newest event: submits are admitted in
+    // order)
+    std::vector<std::pair<hipStream_t, hipEvent_t>> waits;
+    for (auto& r : S->active) {
+        if (r.next != 0 || !r.ready) continue;
+        bool found = false;
+        for (auto& w : waits)
+            if (w.first == r.src) {
+                S->free_events.push_back(w.second);
+                w.second = r.ready;
+                found = true;
+            }
+        if (!found) waits.push_back({r.src, r.ready});
+        r.ready = nullptr;
+    }
     std::vector<gf2x_server::Req> keep;
     keep.reserve(S->active.size());
     for (auto& r : S->active) {
@@ -1411,6 +1474,11 @@ int server_iterate(gf2x_server* S, bool& launched) {
     *(uint32_t*)(sl.host + sl.abort_off) = 0;
     hipStream_t st = S->st;
     hipError_t e = hipSuccess;
+    for (auto& w : waits) {
+        if (e == hipSuccess) e = hipStreamWaitEvent(st, w.second, 0);
+        S->free_events.push_back(w.second);
+    }
+    if (e != hipSuccess) return hip_fail(S->ctx, e, "serving: wait for the submitters' streams");
     if (image) e = hipMemcpyAsync(sl.dev, sl.host, image, hipMemcpyHostToDevice, st);
     if (e != hipSuccess) return hip_fail(S->ctx, e, "serving descriptor upload");
     if (pers) {
@@ -1671,6 +1739,7 @@ int gf2x_ctx_create(gf2x_ctx** out, int device) {
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&ctx->aux_stream, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&ctx->ev_fork, hipEventDisableTiming);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&ctx->ev_join, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&ctx->ev_last, hipEventDisableTiming);
     if (e != hipSuccess) {
         (void)hipGetLastError();
         gf2x_ctx_destroy(ctx);
@@ -1698,6 +1767,7 @@ void gf2x_ctx_destroy(gf2x_ctx* ctx) {
     if (ctx->aux_stream) (void)hipStreamDestroy(ctx->aux_stream);
     if (ctx->ev_fork) (void)hipEventDestroy(ctx->ev_fork);
     if (ctx->ev_join) (void)hipEventDestroy(ctx->ev_join);
+    if (ctx->ev_last) (void)hipEventDestroy(ctx->ev_last);
     delete ctx;
 }
 
@@ -1728,24 +1798,23 @@ int64_t gf2x_trace_read(gf2x_ctx* ctx, gf2x_trace_rec* out, size_t max) {
     return rc ? rc : n;
 }
 
-int gf2x_mul_dev(gf2x_ctx* ctx, const uint64_t* a, uint64_t na_bits, const uint64_t* b, uint64_t nb_bits,
-                 uint64_t* c, void* stream) {
-    if (check_ctx(ctx)) return GF2X_EINVAL;
-    ctx->err.clear();
-    Sizes s = make_sizes(na_bits, nb_bits, ctx->params.word_bits);
-    if (!s.out_words) return GF2X_OK;
+}  // extern "C"
+
+// Checks of a product's arguments shared by the product entry points.
+int check_product(gf2x_ctx* ctx, const Sizes& s, const uint64_t* a, const uint64_t* b, const uint64_t* c) {
     if (!a || !b || !c) return fail(ctx, GF2X_EINVAL, "NULL operand or product pointer");
     if (s.m > kMaxLog2N) return fail(ctx, GF2X_ERANGE, "transform length above 2^32");
     if (ranges_overlap(c, 8 * s.out_words, a, 8 * s.n_a) || ranges_overlap(c, 8 * s.out_words, b, 8 * s.n_b))
         return fail(ctx, GF2X_EINVAL, "product overlaps an operand");
-    DeviceGuard g(ctx->device);
-    hipStream_t st = (hipStream_t)stream;
-    Workspace w = workspace_for(s);
-    int rc = ensure_ws(ctx, w.bytes, st);
-    if (rc) return rc;
+    return GF2X_OK;
+}
+
+// The product's ops on stream st with the workspace at ws (Alg. 5).
+int mul_on(gf2x_ctx* ctx, const Sizes& s, const uint64_t* a, const uint64_t* b, uint64_t* c, char* ws,
+           hipStream_t st) {
     std::vector<Op> ops;
     size_t split[2] = {0, 0};
-    plan_mul(ops, ctx->pool, single_params(ctx), s, a, b, c, ctx->ws, split);
+    plan_mul(ops, ctx->pool, single_params(ctx), s, a, b, c, ws, split);
     if (s.m < kForkMinLog || !split[1]) return run_ops(ctx, ops, st);
     // The two forward transforms are independent: b's runs on the second
     // stream, between a fork event recorded here and a join event that a's
@@ -1768,7 +1837,7 @@ int gf2x_mul_dev(gf2x_ctx* ctx, const uint64_t* a, uint64_t na_bits, const uint6
     hipError_t e = hipEventRecord(ctx->ev_fork, st);
     if (e == hipSuccess) e = hipStreamWaitEvent(ctx->aux_stream, ctx->ev_fork, 0);
     if (e != hipSuccess) return hip_fail(ctx, e, "fork");
-    rc = run_ops(ctx, fb, ctx->aux_stream);
+    int rc = run_ops(ctx, fb, ctx->aux_stream);
     if (rc) return rc;
     e = hipEventRecord(ctx->ev_join, ctx->aux_stream);
     if (e != hipSuccess) return hip_fail(ctx, e, "join");
@@ -1781,6 +1850,24 @@ int gf2x_mul_dev(gf2x_ctx* ctx, const uint64_t* a, uint64_t na_bits, const uint6
     return run_ops(ctx, rest, st);
 }
 
+extern "C" {
+
+int gf2x_mul_dev(gf2x_ctx* ctx, const uint64_t* a, uint64_t na_bits, const uint64_t* b, uint64_t nb_bits,
+                 uint64_t* c, void* stream) {
+    if (check_ctx(ctx)) return GF2X_EINVAL;
+    ctx->err.clear();
+    Sizes s = make_sizes(na_bits, nb_bits, ctx->params.word_bits);
+    if (!s.out_words) return GF2X_OK;
+    int rc = check_product(ctx, s, a, b, c);
+    if (rc) return rc;
+    DeviceGuard g(ctx->device);
+    hipStream_t st = (hipStream_t)stream;
+    const bool cap = stream_capturing(st);
+    if ((rc = ws_enter(ctx, st, cap))) return rc;
+    if ((rc = ensure_ws(ctx, workspace_for(s).bytes, st))) return rc;
+    return ws_leave(ctx, st, cap, mul_on(ctx, s, a, b, c, ctx->ws, st));
+}
+
 int gf2x_forward_dev(gf2x_ctx* ctx, const uint64_t* a, uint64_t na_bits, int log2n, void* spec, void* stream) {
     if (check_ctx(ctx)) return GF2X_EINVAL;
     ctx->err.clear();
@@ -1791,12 +1878,14 @@ int gf2x_forward_dev(gf2x_ctx* ctx, const uint64_t* a, uint64_t na_bits, int log
     if (m_a > log2n) return fail(ctx, GF2X_EINVAL, "spectrum shorter than the operand");
     DeviceGuard g(ctx->device);
     hipStream_t st = (hipStream_t)stream;
-    int rc = ensure_ws(ctx, align256(8ull << m_a), st);
+    const bool cap = stream_capturing(st);
+    int rc = ws_enter(ctx, st, cap);
     if (rc) return rc;
+    if ((rc = ensure_ws(ctx, align256(8ull << m_a), st))) return rc;
     std::vector<Op> ops;
     emit_forward(ops, ctx->pool, single_params(ctx), a, na_bits, (uint64_t*)ctx->ws, m_a, (uint4*)spec, log2n,
                  1ull << log2n);
-    return run_ops(ctx, ops, st);
+    return ws_leave(ctx, st, cap, run_ops(ctx, ops, st));
 }
 
 int gf2x_pointmul_dev(gf2x_ctx* ctx, const void* sa, const void* sb, void* sc, uint64_t n, void* stream) {
@@ -1841,12 +1930,13 @@ int gf2x_simple_mul_dev(gf2x_ctx* ctx, const uint64_t* a, uint64_t na_bits, cons
     ctx->err.clear();
     const Sizes s = make_sizes(na_bits, nb_bits, 64);
     if (!s.out_words) return GF2X_OK;
-    if (!a || !b || !c) return fail(ctx, GF2X_EINVAL, "NULL operand or product pointer");
-    if (s.m > kMaxLog2N) return fail(ctx, GF2X_ERANGE, "transform length above 2^32");
-    if (ranges_overlap(c, 8 * s.out_words, a, 8 * s.n_a) || ranges_overlap(c, 8 * s.out_words, b, 8 * s.n_b))
-        return fail(ctx, GF2X_EINVAL, "product overlaps an operand");
+    int rc = check_product(ctx, s, a, b, c);
+    if (rc) return rc;
     DeviceGuard g(ctx->device);
-    return simple_mul(ctx, a, na_bits, b, nb_bits, c, (hipStream_t)stream);
+    hipStream_t st = (hipStream_t)stream;
+    const bool cap = stream_capturing(st);
+    if ((rc = ws_enter(ctx, st, cap))) return rc;
+    return ws_leave(ctx, st, cap, simple_mul(ctx, a, na_bits, b, nb_bits, c, st));
 }
 
 int gf2x_simple_forward_dev(gf2x_ctx* ctx, const uint64_t* a, uint64_t na_bits, int log2n, void* spec,
@@ -1859,9 +1949,11 @@ int gf2x_simple_forward_dev(gf2x_ctx* ctx, const uint64_t* a, uint64_t na_bits, 
     if (m_a > log2n) return fail(ctx, GF2X_EINVAL, "spectrum shorter than the operand");
     DeviceGuard g(ctx->device);
     hipStream_t st = (hipStream_t)stream;
-    int rc = ensure_ws(ctx, align256(8ull << m_a), st);
+    const bool cap = stream_capturing(st);
+    int rc = ws_enter(ctx, st, cap);
     if (rc) return rc;
-    return simple_forward(ctx, a, na_bits, (uint64_t*)ctx->ws, m_a, (uint4*)spec, log2n, st);
+    if ((rc = ensure_ws(ctx, align256(8ull << m_a), st))) return rc;
+    return ws_leave(ctx, st, cap, simple_forward(ctx, a, na_bits, (uint64_t*)ctx->ws, m_a, (uint4*)spec, log2n, st));
 }
 
 int gf2x_mul_batch(gf2x_ctx* ctx, const gf2x_job* jobs, size_t njobs, void* stream) {
@@ -2064,7 +2156,7 @@ int gf2x_server_create(gf2x_ctx* ctx, const gf2x_server_cfg* cfg, gf2x_server** 
 }
 
 int gf2x_server_submit(gf2x_server* S, const uint64_t* a, uint64_t na_bits, const uint64_t* b, uint64_t nb_bits,
-                       uint64_t* c, uint64_t tag) {
+                       uint64_t* c, uint64_t tag, void* stream) {
     if (!S) return GF2X_EINVAL;
     gf2x_ctx* ctx = S->ctx;
     ctx->err.clear();
@@ -2092,6 +2184,19 @@ int gf2x_server_submit(gf2x_server* S, const uint64_t* a, uint64_t na_bits, cons
     r.bytes = workspace_for(s).bytes;
     if (Arena::round(r.bytes) > S->alloc.capacity())
         return fail(ctx, GF2X_ENOMEM, "request footprint exceeds the server arena");
+    DeviceGuard g(ctx->device);
+    if (S->free_events.empty()) {
+        hipEvent_t ev = nullptr;
+        hipError_t e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+        if (e != hipSuccess) return hip_fail(ctx, e, "serving: submit event");
+        S->all_events.push_back(ev);
+        S->free_events.push_back(ev);
+    }
+    r.src = (hipStream_t)stream;
+    r.ready = S->free_events.back();
+    hipError_t e = hipEventRecord(r.ready, r.src);
+    if (e != hipSuccess) return hip_fail(ctx, e, "serving: record on the submitter's stream");
+    S->free_events.pop_back();
     S->queue.push_back(std::move(r));
     ++S->stats.submitted;
     return GF2X_OK;

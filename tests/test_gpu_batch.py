@@ -1,7 +1,9 @@
 """Batches on the GPU: every job of a batch equals the oracle and the single
 gf2x_mul_dev call, on the one-shot entry point and on a reusable batch whose
 hipGraph is replayed several times with eager work in between."""
+import os
 import sys
+from concurrent.futures import ThreadPoolExecutor
 
 import numpy as np
 import pytest
@@ -143,3 +145,41 @@ def test_large_persistent_batch_headline_like(ctx):
         (da, na, db, nb, c), (a, b) = jobs[k], ref[k]
         assert np.array_equal(host(c)[: P.out_words(na, nb)], oracle.mul(a, na, b, nb))
     B.close()
+
+
+def oracle_all(ref, spec, threads=16):
+    """The oracle's product of every job, computed by a pool of threads (one
+    job per call, so the pool runs independent products side by side)."""
+    with ThreadPoolExecutor(min(threads, os.cpu_count() or 1)) as ex:
+        return list(ex.map(lambda x: oracle.mul(x[0][0], x[1][0], x[0][1], x[1][1]), zip(ref, spec)))
+
+
+def test_configured_batch_every_job_both_modes_tuned():
+    """The configured batch: 4096 jobs with operand lengths floor(2^u),
+    u ~ U[12, 20] bits for a and b independently, planned after the
+    autotuner picked the FFT schedules; staged and persistent, each run on
+    outputs filled with a sentinel, every job compared with the oracle."""
+    ctx = P.Context(0)
+    try:
+        spec = inputs.batch_workload(4096, 12, 20)
+        jobs, ref = make_jobs(spec)
+        say("case configured batch: oracle products of 4096 jobs")
+        want = oracle_all(ref, spec)
+        say("case configured batch: autotune 2^6..2^20")
+        tuned = ctx.autotune(6, 20, reps=2)
+        assert len(tuned) == 15
+        for persistent in (False, True):
+            for j in jobs:
+                j[4].fill_(-1)
+            say(f"case configured batch: 4096 jobs, persistent={persistent}")
+            B = ctx.batch(jobs, persistent=persistent)
+            B.run()
+            B.run()  # the graph replay, on the first run's results
+            torch.cuda.synchronize()
+            B.check()
+            B.close()
+            for k, ((da, na, db, nb, c), w) in enumerate(zip(jobs, want)):
+                assert np.array_equal(host(c)[: P.out_words(na, nb)], w), (k, na, nb, persistent)
+    finally:
+        torch.cuda.synchronize()
+        ctx.close()

@@ -160,6 +160,32 @@ def test_back_to_back_products_across_the_fork_sizes(ctx):
         assert np.array_equal(host(c), want), (na, nb)
 
 
+def test_calls_on_mixed_streams_are_serialised(ctx):
+    """Products on two streams in turn, with no synchronisation and no event
+    from the caller between them, sizes ascending so the shared workspace
+    grows: each call on a stream other than the previous call's waits for
+    that call's work (the header's stream rule), so every result is exact."""
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    sizes = [(1 << 14, 1 << 14), (1 << 18, (1 << 18) - 7), (1 << 16, 1 << 16), ((1 << 21) + 3, 1 << 20),
+             (1 << 12, 999), ((1 << 22) + 64, (1 << 22) - 1)]
+    ops = []
+    for i, (na, nb) in enumerate(sizes):
+        a = inputs.random_poly(0xA00 + i, na)
+        b = inputs.random_poly(0xA50 + i, nb)
+        ops.append((a, na, b, nb, dev(a), dev(b)))
+    cs = [torch.full((P.out_words(na, nb),), -1, dtype=torch.int64, device="cuda") for _, na, _, nb, _, _ in ops]
+    torch.cuda.synchronize()
+    say("case products on alternating streams")
+    outs = []
+    for i, (a, na, b, nb, da, db) in enumerate(ops):
+        st = s1 if i % 2 == 0 else s2
+        outs.append((a, na, b, nb, ctx.mul_into(da, na, db, nb, cs[i], stream=st)))
+    s1.synchronize()
+    s2.synchronize()
+    for a, na, b, nb, c in outs:
+        assert np.array_equal(host(c), oracle.mul(a, na, b, nb, threads=8)), (na, nb)
+
+
 # ------------------------------------------------------------- stages
 
 
@@ -394,8 +420,8 @@ def test_headline_product(ctx, name):
         q = rng.getrandbits(64)
         assert oracle.mulmod(oracle.mod(a, n, q), oracle.mod(b, n, q), q) == oracle.mod(got, 2 * n - 1, q)
     g = _golden(name)
-    if g is not None:
-        assert hashlib.sha256(got.tobytes()).hexdigest() == g[6]
+    assert g is not None, f"tests/golden/product_sha256.txt has no line for {name}"
+    assert hashlib.sha256(got.tobytes()).hexdigest() == g[6]
 
 
 def test_product_2p30_widest_multipliers(ctx):
@@ -465,5 +491,11 @@ def test_error_paths(ctx):
     assert L.gf2x_forward_dev(ctx.handle, P._ptr(a), 640, 2, P._ptr(spec), nul) == P.GF2X_EINVAL
     assert L.gf2x_ctx_create(ctypes.byref(ctypes.c_void_p()), 1 << 20) == P.GF2X_EDEVICE
     assert L.gf2x_mul_batch(ctx.handle, None, 3, nul) == P.GF2X_EINVAL
-    assert "product" in L.gf2x_last_error(ctx.handle).decode() or True
+    assert L.gf2x_last_error(ctx.handle).decode() == "NULL job array"
+    # the message names the failing call's cause, and a later success clears it
+    assert L.gf2x_mul_dev(ctx.handle, P._ptr(a), 640, P._ptr(a), 640, P._ptr(a), nul) == P.GF2X_EINVAL
+    assert L.gf2x_last_error(ctx.handle).decode() == "product overlaps an operand"
+    c = torch.zeros(P.out_words(640, 640), dtype=torch.int64, device="cuda")
+    assert L.gf2x_mul_dev(ctx.handle, P._ptr(a), 640, P._ptr(a), 640, P._ptr(c), nul) == P.GF2X_OK
+    assert L.gf2x_last_error(ctx.handle).decode() == ""
     torch.cuda.synchronize()

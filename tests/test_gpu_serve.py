@@ -2,7 +2,9 @@
 bit-identical to the same product computed alone, under staggered arrivals,
 admission limited by arena space and slots, both execution modes and several
 iteration lengths; errors are reported per request without stopping the rest."""
+import os
 import sys
+from concurrent.futures import ThreadPoolExecutor
 
 import numpy as np
 import pytest
@@ -160,3 +162,29 @@ def test_serving_workload_sizes(ctx):
     ref = alone(ctx, reqs)
     for i, r in enumerate(reqs):
         assert np.array_equal(host(r["c"])[: P.out_words(r["na"], r["nb"])], ref[i]), i
+
+
+def test_serving_full_length_range_against_oracle(ctx):
+    """Requests over the whole configured length range 2^10..2^24 bits per
+    operand (24 drawn by the serving workload's generator, plus two with both
+    operands of 2^24 bits), submitted in waves to the adaptive engine; every
+    result compared with the oracle."""
+    reqs = make_requests(24, 10, 24, rate_index=3)
+    for k in range(2):
+        n = 1 << 24
+        a, b = inputs.random_poly(0x5F00 + 2 * k, n), inputs.random_poly(0x5F01 + 2 * k, n)
+        c = torch.full((P.out_words(n, n),), -1, dtype=torch.int64, device="cuda")
+        reqs.append(dict(na=n, nb=n, a=a, b=b, da=dev(a), db=dev(b), c=c))
+    assert max(max(r["na"], r["nb"]) for r in reqs) == 1 << 24
+    say("case serve 2^10..2^24 bits, 26 requests, adaptive engine")
+    srv = ctx.server(1 << 31, max_active=32, levels_per_iter=2, persistent="adaptive")
+    done = run_staggered(srv, reqs, waves=3)
+    srv.close()
+    assert sorted(d["tag"] for d in done) == list(range(len(reqs)))
+    assert all(d["status"] == 0 for d in done)
+    torch.cuda.synchronize()
+    say("case serve 2^10..2^24 bits: oracle products")
+    with ThreadPoolExecutor(min(16, os.cpu_count() or 1)) as ex:
+        want = list(ex.map(lambda r: oracle.mul(r["a"], r["na"], r["b"], r["nb"]), reqs))
+    for i, (r, w) in enumerate(zip(reqs, want)):
+        assert np.array_equal(host(r["c"])[: P.out_words(r["na"], r["nb"])], w), (i, r["na"], r["nb"])
