@@ -106,6 +106,26 @@ int gf2x_mul(const uint64_t *a, uint64_t na_bits, const uint64_t *b, uint64_t nb
 int gf2x_mul_dev(gf2x_ctx *ctx, const uint64_t *a, uint64_t na_bits, const uint64_t *b, uint64_t nb_bits,
                  uint64_t *c, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): c = a * b as
+ * gf2x_mul_dev computes it (same result, same word width and truncation
+ * settings of ctx), with the whole workspace in a fixed device buffer of
+ * GF2X_STATIC_SCRATCH_BYTES that the library holds on each GPU it runs on
+ * until the process ends (its address is looked up when a context is created
+ * on that GPU).  The call allocates nothing on the device and creates no
+ * stream or event: every kernel runs on `stream`, and it is never traced.
+ * A product whose workspace (gf2x_workspace_bytes_w at ctx's word width)
+ * exceeds the buffer returns GF2X_ENOMEM with the sizes in gf2x_last_error;
+ * with w = 64 that admits every product of at most 2^20 points, i.e.
+ * operands of up to 2^25 bits each.  Every call on one GPU, from any
+ * context, shares that GPU's buffer, so calls that overlap in time (other
+ * streams, other host threads) race: the caller orders them, e.g. on one
+ * stream.  The buffer keeps the last call's contents; no call needs it to
+ * start zeroed.  Arguments, aliasing and errors otherwise as gf2x_mul_dev. */
+#define GF2X_STATIC_SCRATCH_BYTES (64u << 20)
+int gf2x_mul_dev_static(gf2x_ctx *ctx, const uint64_t *a, uint64_t na_bits, const uint64_t *b, uint64_t nb_bits,
+                        uint64_t *c, void *stream);
+
 /* Forward transform of one operand (Split, BasisCvt of Alg. 3 on 64-bit words,
  * changeRepr, FFT_LCH of Alg. 1 at alpha = 0): spec[j] = f(j̄) for
  * j < 2^log2n (see the spectrum convention above).  Requires

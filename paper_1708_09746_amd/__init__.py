@@ -20,6 +20,7 @@ LIB_PATH = os.path.join(_HERE, "libgf2x_afft.so")
 HEADER_PATH = os.path.join(os.path.dirname(_HERE), "include", "gf2x_afft.h")
 
 GF2X_OK, GF2X_EINVAL, GF2X_ERANGE, GF2X_ENOMEM, GF2X_EDEVICE = 0, -1, -2, -3, -4
+STATIC_SCRATCH_BYTES = 64 << 20  # GF2X_STATIC_SCRATCH_BYTES: the fixed buffer of gf2x_mul_dev_static
 
 _lib = None
 
@@ -89,6 +90,7 @@ def lib():
             "gf2x_workspace_bytes_w": (sz, [u64, u64, i32]),
             "gf2x_mul": (i32, [vp, u64, vp, u64, vp]),
             "gf2x_mul_dev": (i32, [vp, vp, u64, vp, u64, vp, vp]),
+            "gf2x_mul_dev_static": (i32, [vp, vp, u64, vp, u64, vp, vp]),
             "gf2x_forward_dev": (i32, [vp, vp, u64, i32, vp, vp]),
             "gf2x_pointmul_dev": (i32, [vp, vp, vp, vp, u64, vp]),
             "gf2x_inverse_dev": (i32, [vp, vp, i32, vp, u64, vp]),
@@ -204,6 +206,13 @@ class Context:
     def mul_into(self, a, na_bits: int, b, nb_bits: int, c, stream=None):
         rc = lib().gf2x_mul_dev(self._h, _ptr(a), na_bits, _ptr(b), nb_bits, _ptr(c), _stream_handle(stream))
         self._check(rc, "gf2x_mul_dev")
+        return c
+
+    def mul_static_into(self, a, na_bits: int, b, nb_bits: int, c, stream=None):
+        """The same product with the workspace in the library's fixed device
+        buffer (gf2x_mul_dev_static: no device allocation in the call)."""
+        rc = lib().gf2x_mul_dev_static(self._h, _ptr(a), na_bits, _ptr(b), nb_bits, _ptr(c), _stream_handle(stream))
+        self._check(rc, "gf2x_mul_dev_static")
         return c
 
     def mul(self, a, na_bits: int, b, nb_bits: int, stream=None):

@@ -598,6 +598,37 @@ __global__ __launch_bounds__(kThreads) void k_persistent(PersistArgs P, const ui
     }
 }
 
+// ------------------------------------------------------- the static buffer
+
+// Workspace of gf2x_mul_dev_static: a fixed array in device memory, one copy
+// per GPU, held until the process ends.  In host code `scratch` names a host
+// stand-in, not the device copy: host code only ever uses the address that
+// hipGetSymbolAddress returns for the current device (scratch_address).
+static __device__ __align__(256) char scratch[GF2X_STATIC_SCRATCH_BYTES];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+char* g_scratch_ptr[kMaxDevices] = {};
+
+// This device's copy of `scratch`, looked up once per device with that
+// device current (gf2x_ctx_create makes it current).
+hipError_t scratch_address(int device, char** out) {
+    *out = nullptr;
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[device]) {
+        void* p = nullptr;
+        hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!p) return hipErrorInvalidSymbol;
+        g_scratch_ptr[device] = (char*)p;
+    }
+    *out = g_scratch_ptr[device];
+    return hipSuccess;
+}
+}  // namespace
+
 // ------------------------------------------------------------------ context
 
 struct gf2x_ctx {
@@ -623,6 +654,8 @@ struct gf2x_ctx {
     hipEvent_t ev_last = nullptr;
     hipStream_t last_st = nullptr;
     bool has_last = false;
+    // this device's copy of the static product buffer (gf2x_mul_dev_static)
+    char* scratch = nullptr;
     std::string err;
     gf2x_batch* transient = nullptr;  // the last gf2x_mul_batch call's plan
     hipStream_t transient_stream = nullptr;
@@ -883,11 +916,13 @@ void op_traffic(const Op& op, gf2x_trace_rec& r) {
     } while (0)
 #define GF2X_LAUNCH(K, GRID, ...) GF2X_LAUNCH_N(K, GRID, kThreads, __VA_ARGS__)
 
-int run_ops(gf2x_ctx* ctx, const std::vector<Op>& ops, hipStream_t st) {
+// `may_trace` false: no launch is traced whatever the trace mask says (tracing
+// creates events, and some callers must not have anything created for them).
+int run_ops(gf2x_ctx* ctx, const std::vector<Op>& ops, hipStream_t st, bool may_trace = true) {
     const uint64_t ncu = (uint64_t)ctx->ncu;
     for (const Op& op : ops) {
         gf2x_ctx::Pending pend{};
-        const bool traced = (ctx->trace_mask >> (int)op.kind) & 1u;
+        const bool traced = may_trace && ((ctx->trace_mask >> (int)op.kind) & 1u);
         if (traced) {
             op_traffic(op, pend.rec);
             hipError_t e = hipEventCreate(&pend.start);
@@ -1740,6 +1775,7 @@ int gf2x_ctx_create(gf2x_ctx** out, int device) {
     if (e == hipSuccess) e = hipEventCreateWithFlags(&ctx->ev_fork, hipEventDisableTiming);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&ctx->ev_join, hipEventDisableTiming);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&ctx->ev_last, hipEventDisableTiming);
+    if (e == hipSuccess) e = scratch_address(device, &ctx->scratch);
     if (e != hipSuccess) {
         (void)hipGetLastError();
         gf2x_ctx_destroy(ctx);
@@ -1866,6 +1902,28 @@ int gf2x_mul_dev(gf2x_ctx* ctx, const uint64_t* a, uint64_t na_bits, const uint6
     if ((rc = ws_enter(ctx, st, cap))) return rc;
     if ((rc = ensure_ws(ctx, workspace_for(s).bytes, st))) return rc;
     return ws_leave(ctx, st, cap, mul_on(ctx, s, a, b, c, ctx->ws, st));
+}
+
+int gf2x_mul_dev_static(gf2x_ctx* ctx, const uint64_t* a, uint64_t na_bits, const uint64_t* b, uint64_t nb_bits,
+                        uint64_t* c, void* stream) {
+    if (check_ctx(ctx)) return GF2X_EINVAL;
+    ctx->err.clear();
+    Sizes s = make_sizes(na_bits, nb_bits, ctx->params.word_bits);
+    if (!s.out_words) return GF2X_OK;
+    int rc = check_product(ctx, s, a, b, c);
+    if (rc) return rc;
+    const size_t need = workspace_for(s).bytes;
+    if (need > (size_t)GF2X_STATIC_SCRATCH_BYTES)
+        return fail(ctx, GF2X_ENOMEM, "product needs " + std::to_string(need) + " bytes of workspace; the static buffer holds " +
+                                          std::to_string((size_t)GF2X_STATIC_SCRATCH_BYTES));
+    if (!ctx->scratch) return fail(ctx, GF2X_EDEVICE, "no address for the static buffer on this device");
+    DeviceGuard g(ctx->device);
+    // every op on the caller's stream (no second stream, no events, no trace):
+    // the ops write each workspace byte before they read it, so nothing in the
+    // buffer has to start at zero
+    std::vector<Op> ops;
+    plan_mul(ops, ctx->pool, single_params(ctx), s, a, b, c, ctx->scratch);
+    return run_ops(ctx, ops, (hipStream_t)stream, false);
 }
 
 int gf2x_forward_dev(gf2x_ctx* ctx, const uint64_t* a, uint64_t na_bits, int log2n, void* spec, void* stream) {

@@ -68,3 +68,19 @@ def test_status_names():
     for code in (0, -1, -2, -3, -4):
         assert P.strerror(code)
     assert P.strerror(-99) == "unknown status"
+
+
+def test_static_buffer_size_matches_header():
+    """The binding's size of gf2x_mul_dev_static's fixed buffer is the
+    header's GF2X_STATIC_SCRATCH_BYTES, and that buffer holds the workspace of
+    every product of up to 2^20 points (operands of 2^25 bits each) and none
+    beyond."""
+    import re
+
+    with open(P.HEADER_PATH) as f:
+        m = re.search(r"#define\s+GF2X_STATIC_SCRATCH_BYTES\s+\((\d+)u\s*<<\s*(\d+)\)", f.read())
+    assert m and int(m.group(1)) << int(m.group(2)) == P.STATIC_SCRATCH_BYTES
+    assert P.workspace_bytes(1 << 25, 1 << 25) <= P.STATIC_SCRATCH_BYTES
+    assert P.workspace_bytes(64 << 20, 64) <= P.STATIC_SCRATCH_BYTES  # 2^20 words: 2^20 points
+    assert P.fft_log2((1 << 25) + 65, 1 << 25) == 21
+    assert P.workspace_bytes((1 << 25) + 65, 1 << 25) > P.STATIC_SCRATCH_BYTES
