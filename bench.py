@@ -570,25 +570,34 @@ def bench_w128(P, a, b, n, ref, steps, warmup, tune):
             "equal_to_w64": equal}
 
 
-def bench_simple(P, a, b, n, ref, steps, warmup, other_sizes=True):
-    """Alg. 4 (polynomial-basis GF(2^128), Cantor points) on the same operands:
-    timed like the headline product (operands resident), checked equal to the
-    tower product `ref`; also the rate of full GF(2^128) products it sustains
-    (butterflies of the three transforms plus the pointwise products)."""
+VARIANTS = {
+    "simple": ("simple_mul_into", "GF(2^128) polynomial basis, Cantor points"),
+    "frobenius": ("frobenius_mul_into", "GF(2^128) polynomial basis, Frobenius partition: points beta_{m+64} + V_m"),
+}
+
+
+def bench_variant(P, name, a, b, n, ref, steps, warmup, other_sizes=True):
+    """Alg. 4 (polynomial-basis GF(2^128), Cantor points) or the
+    Frobenius-partition variant (App. C) on the same operands: timed like the
+    headline product (operands resident), checked equal to the tower product
+    `ref`; also the rate of full GF(2^128) products it sustains (butterflies
+    of the three transforms plus the pointwise products)."""
     import torch
 
+    meth, field = VARIANTS[name]
     ctx = P.Context(0)
+    mul_into = getattr(ctx, meth)
     c = torch.empty_like(ref)
     for _ in range(warmup):
-        ctx.simple_mul_into(a, n, b, n, c)
+        mul_into(a, n, b, n, c)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(steps):
-        ctx.simple_mul_into(a, n, b, n, c)
+        mul_into(a, n, b, n, c)
     torch.cuda.synchronize()
     ms = (time.perf_counter() - t0) * 1e3 / steps
     equal = bool(torch.equal(c, ref))
-    assert equal, "the simple-variant product differs from the tower one"
+    assert equal, f"the {name} variant's product differs from the tower one"
     # the other configured sizes: one call's latency (median of `reps`,
     # events on the stream), product checked against the tower method's
     import numpy as np
@@ -597,35 +606,39 @@ def bench_simple(P, a, b, n, ref, steps, warmup, other_sizes=True):
 
     sizes = {}
     stream = torch.cuda.current_stream()
-    for name, reps in (("c1", 30), ("c2", 30), ("c3b", 5)) if other_sizes else ():
-        n2, desc = WORKLOADS[name]
-        s1, s2 = inputs.SEEDS[name]
+    for wl, reps in (("c1", 30), ("c2", 30), ("c3b", 5)) if other_sizes else ():
+        n2, desc = WORKLOADS[wl]
+        s1, s2 = inputs.SEEDS[wl]
         a2 = torch.from_numpy(inputs.random_poly(s1, n2).view(np.int64).copy()).cuda()
         b2 = torch.from_numpy(inputs.random_poly(s2, n2).view(np.int64).copy()).cuda()
         c2 = torch.empty(P.out_words(n2, n2), dtype=torch.int64, device="cuda")
         for _ in range(2):
-            ctx.simple_mul_into(a2, n2, b2, n2, c2, stream)
+            mul_into(a2, n2, b2, n2, c2, stream)
         ts = []
         for _ in range(reps):
             e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
             e0.record(stream)
-            ctx.simple_mul_into(a2, n2, b2, n2, c2, stream)
+            mul_into(a2, n2, b2, n2, c2, stream)
             e1.record(stream)
             e1.synchronize()
             ts.append(e0.elapsed_time(e1))
         ts.sort()
         same = bool(torch.equal(c2, ctx.mul(a2, n2, b2, n2, stream)))
-        assert same, f"the simple-variant product differs from the tower one at {desc}"
-        sizes[name] = {"workload": desc, "runs": reps, "median_ms": round(ts[len(ts) // 2], 4),
-                       "equal_to_tower": same}
+        assert same, f"the {name} variant's product differs from the tower one at {desc}"
+        sizes[wl] = {"workload": desc, "runs": reps, "median_ms": round(ts[len(ts) // 2], 4), "equal_to_tower": same}
         del a2, b2, c2
     ctx.close()
     k = (n + 63) // 64
-    m = max(1, (2 * k - 2).bit_length())
-    m_op = (k - 1).bit_length()
-    N = 1 << m
-    prods = (N // 2) * (2 * m_op + m) + N
-    return {"field": "GF(2^128) polynomial basis, Cantor points", "ms_per_product": round(ms, 4), "fft_points": N,
+    if name == "simple":
+        m = max(1, (2 * k - 2).bit_length())
+        m_op = (k - 1).bit_length()
+        N = 1 << m
+        prods = (N // 2) * (2 * m_op + m) + N
+    else:
+        m = P.frobenius_log2n(n, n)
+        N = 1 << m
+        prods = (N // 2) * 3 * m + N
+    return {"field": field, "ms_per_product": round(ms, 4), "fft_points": N,
             "field_products": prods, "field_products_per_s": round(prods / (ms * 1e-3), 1),
             "equal_to_tower": equal, "sizes": sizes}
 
@@ -645,6 +658,7 @@ def main():
                     help="let the autotuner pick the headline product's FFT pass schedules instead of the pinned ones")
     ap.add_argument("--no-w128", action="store_true", help="skip the 128-bit-word (TGF(2^256)) variant")
     ap.add_argument("--no-simple", action="store_true", help="skip the simple variant (Alg. 4)")
+    ap.add_argument("--no-frobenius", action="store_true", help="skip the Frobenius-partition variant (App. C)")
     ap.add_argument("--no-sizes", action="store_true", help="skip the single products at 2^16, 2^20, 2^29 bits")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="first run a plain device copy of this many MiB (counter calibration)")
@@ -832,7 +846,10 @@ def main():
         out["w128"] = bench_w128(P, a, b, n, c, args.steps, args.warmup, args.tune)
     if not args.no_simple:
         log("bench: the same product by the simple variant (polynomial basis, Cantor points)")
-        out["simple"] = bench_simple(P, a, b, n, c, args.steps, args.warmup, not args.no_sizes)
+        out["simple"] = bench_variant(P, "simple", a, b, n, c, args.steps, args.warmup, not args.no_sizes)
+    if not args.no_frobenius:
+        log("bench: the same product by the Frobenius partition (App. C)")
+        out["frobenius"] = bench_variant(P, "frobenius", a, b, n, c, args.steps, args.warmup, not args.no_sizes)
     if not args.no_batch:
         log(f"bench: batched products ({args.batch_jobs} jobs)")
         out["batched"] = bench_batched(ctx, args.batch_jobs)

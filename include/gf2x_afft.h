@@ -195,6 +195,52 @@ typedef struct {
  * its next gf2x_mul_batch call (which first waits for it). */
 int gf2x_mul_batch(gf2x_ctx *ctx, const gf2x_job *jobs, size_t njobs, void *stream);
 
+/* ---- the Frobenius-partition variant (App. C) ----
+ * The same product with no Kronecker segmentation: a polynomial of fewer than
+ * 128 n bits (n = 2^m) is represented by its values at the n points
+ * beta_{m+64} + V_m of GF(2^128) (the field and Cantor basis of the simple
+ * variant above; V_m = span(beta_0 .. beta_{m-1})), a bijection because the
+ * Frobenius orbits of these points are disjoint and hold 128 points each
+ * (App. C, the partition of the evaluation points).  The values are computed
+ * as App. C's truncated FFT: BasisCvt (Alg. 3) over the bits, the "encoding"
+ * (its first seven layers: value-vector element i = sum over j < 128 of bit
+ * j n + i times P_j, P_j the product of beta_{64-t} over the set bits t of j,
+ * since s_{m+t}(beta_{m+64}) = beta_{64-t}), then FFT_LCH (Alg. 1) at
+ * alpha = beta_{m+64} over the n elements.  A product takes n = 2^m points
+ * with m the least such that 128 n >= na + nb - 1, about half the points of
+ * Alg. 4 with w = 64. */
+
+/* m for the product of an na-bit and an nb-bit operand (-1 if either is 0). */
+int gf2x_frobenius_log2n(uint64_t na_bits, uint64_t nb_bits);
+
+/* Device workspace bytes of gf2x_frobenius_mul_dev for these sizes (0 if
+ * either is 0): the operands' words and two n-point value vectors. */
+size_t gf2x_frobenius_workspace_bytes(uint64_t na_bits, uint64_t nb_bits);
+
+/* c = a * b with DEVICE pointers on `stream`, by the Frobenius partition:
+ * the values of a and b at the n points, their pointwise products in
+ * GF(2^128), then the inverse (iFFT_LCH at alpha, the inverse of the
+ * encoding, iBasisCvt over the bits).  Conventions, aliasing, ordering and
+ * errors as gf2x_mul_dev (ERANGE above 2^32 points); the context's word width
+ * and truncation settings do not apply. */
+int gf2x_frobenius_mul_dev(gf2x_ctx *ctx, const uint64_t *a, uint64_t na_bits, const uint64_t *b, uint64_t nb_bits,
+                           uint64_t *c, void *stream);
+
+/* The values of a (na_bits bits, na_bits <= 128 * 2^log2n, log2n <= 32) at
+ * the 2^log2n points: spec[j] = a(beta_{m+64} + phi(j)), m = log2n, with
+ * phi(j) the sum of beta_t over the set bits t of j; each element 16 bytes,
+ * bit e the coefficient of x^e (as the simple variant's spectra).  spec is
+ * DEVICE memory of 16 * 2^log2n bytes, written entirely. */
+int gf2x_frobenius_forward_dev(gf2x_ctx *ctx, const uint64_t *a, uint64_t na_bits, int log2n, void *spec,
+                               void *stream);
+
+/* The inverse: given the values at the 2^log2n points of a polynomial of
+ * fewer than 128 * 2^log2n bits, writes its first ceil(nc_bits/64) words to c
+ * (nc_bits <= 128 * 2^log2n; bits at and above nc_bits of the polynomial are
+ * dropped, those below kept).  spec is overwritten (used as scratch); c must
+ * not overlap it. */
+int gf2x_frobenius_inverse_dev(gf2x_ctx *ctx, void *spec, int log2n, uint64_t *c, uint64_t nc_bits, void *stream);
+
 /* ---- tracing: per-kernel timing with HIP events (Sec. "Results" profiles the
  * same stages per component).  While a mask is set, every launch of a kernel
  * kind whose bit is in the mask carries two hipEvents in its own dispatch

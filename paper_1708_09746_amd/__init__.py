@@ -97,6 +97,11 @@ def lib():
             "gf2x_basiscvt_dev": (i32, [vp, vp, i32, i32, vp]),
             "gf2x_simple_mul_dev": (i32, [vp, vp, u64, vp, u64, vp, vp]),
             "gf2x_simple_forward_dev": (i32, [vp, vp, u64, i32, vp, vp]),
+            "gf2x_frobenius_log2n": (i32, [u64, u64]),
+            "gf2x_frobenius_workspace_bytes": (sz, [u64, u64]),
+            "gf2x_frobenius_mul_dev": (i32, [vp, vp, u64, vp, u64, vp, vp]),
+            "gf2x_frobenius_forward_dev": (i32, [vp, vp, u64, i32, vp, vp]),
+            "gf2x_frobenius_inverse_dev": (i32, [vp, vp, i32, vp, u64, vp]),
             "gf2x_mul_batch": (i32, [vp, ctypes.POINTER(Job), sz, vp]),
             "gf2x_batch_create": (i32, [vp, ctypes.POINTER(Job), sz, i32, ctypes.POINTER(vp)]),
             "gf2x_batch_check": (i32, [vp]),
@@ -146,6 +151,10 @@ def out_words(na_bits: int, nb_bits: int) -> int:
 
 def fft_log2(na_bits: int, nb_bits: int) -> int:
     return int(lib().gf2x_fft_log2(na_bits, nb_bits))
+
+
+def frobenius_log2n(na_bits: int, nb_bits: int) -> int:
+    return int(lib().gf2x_frobenius_log2n(na_bits, nb_bits))
 
 
 def workspace_bytes(na_bits: int, nb_bits: int, w: int = 64) -> int:
@@ -245,6 +254,42 @@ class Context:
         rc = lib().gf2x_simple_forward_dev(self._h, _ptr(a), na_bits, log2n, _ptr(spec), _stream_handle(stream))
         self._check(rc, "gf2x_simple_forward_dev")
         return spec
+
+    def frobenius_mul_into(self, a, na_bits: int, b, nb_bits: int, c, stream=None):
+        """The same product by the Frobenius partition (App. C)."""
+        rc = lib().gf2x_frobenius_mul_dev(self._h, _ptr(a), na_bits, _ptr(b), nb_bits, _ptr(c),
+                                          _stream_handle(stream))
+        self._check(rc, "gf2x_frobenius_mul_dev")
+        return c
+
+    def frobenius_mul(self, a, na_bits: int, b, nb_bits: int, stream=None):
+        import torch
+
+        ow = out_words(na_bits, nb_bits)
+        c = torch.empty(max(ow, 1), dtype=torch.int64, device=a.device)[:ow]
+        return self.frobenius_mul_into(a, na_bits, b, nb_bits, c, stream)
+
+    def frobenius_forward(self, a, na_bits: int, log2n: int, spec=None, stream=None):
+        """Values of the operand at the 2^log2n points beta_{m+64} + phi(j)
+        (App. C), elements of the polynomial-basis GF(2^128)."""
+        import torch
+
+        if spec is None:
+            spec = torch.empty((1 << log2n, 2), dtype=torch.int64, device=a.device)
+        rc = lib().gf2x_frobenius_forward_dev(self._h, _ptr(a), na_bits, log2n, _ptr(spec), _stream_handle(stream))
+        self._check(rc, "gf2x_frobenius_forward_dev")
+        return spec
+
+    def frobenius_inverse(self, spec, log2n: int, nc_bits: int, c=None, stream=None):
+        """The polynomial (first nc_bits bits) with these values; spec is overwritten."""
+        import torch
+
+        if c is None:
+            ow = (nc_bits + 63) // 64
+            c = torch.empty(max(ow, 1), dtype=torch.int64, device=spec.device)[:ow]
+        rc = lib().gf2x_frobenius_inverse_dev(self._h, _ptr(spec), log2n, _ptr(c), nc_bits, _stream_handle(stream))
+        self._check(rc, "gf2x_frobenius_inverse_dev")
+        return c
 
     def mul_batch(self, jobs, stream=None):
         """jobs: list of (a, na_bits, b, nb_bits, c) with device tensors."""

@@ -16,6 +16,7 @@
 #include "../../include/gf2x_afft.h"
 #include "afft_plan.hpp"
 #include "arena.hpp"
+#include "frobenius.hpp"
 #include "simple.hpp"
 #include "tower_host.hpp"
 
@@ -208,7 +209,7 @@ __global__ __launch_bounds__(kSfLaneThreads) void k_sfft_lane(SfftPass P, const 
     for (uint64_t g = blockIdx.x; g < nchunks; g += gridDim.x) {
         const uint64_t J0 = g << P.c;
         for (uint32_t e = threadIdx.x; e < npts; e += blockDim.x) dat[e] = sfft_load(P, J0 | e);
-        if ((int)threadIdx.x < P.L) lam[threadIdx.x] = phi_cantor(J0 >> threadIdx.x, g_cantor);
+        if ((int)threadIdx.x < P.L) lam[threadIdx.x] = sf_lane_lam(P, J0, (int)threadIdx.x, g_cantor);
         __syncthreads();
         for (int s = 0; s < P.L; ++s) {
             for (uint32_t q = threadIdx.x; q < npts / 2; q += blockDim.x) sf_lane_bfly(P, s, q, dat, lam, phit, T);
@@ -235,6 +236,42 @@ __global__ __launch_bounds__(kSfThreads) void k_scombine(const uint4* F, uint64_
     for (uint64_t k = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; k < nwords;
          k += (uint64_t)gridDim.x * blockDim.x)
         c[k] = sf_combine_word(F, n, k, nwords, nc_bits);
+}
+
+// ---- the Frobenius-partition variant (App. C)
+
+// z-adic expansion or recomposition: the levels of one pass, tile by tile
+__global__ __launch_bounds__(kZThreads) void k_zadic(ZadicPass Z) {
+    __shared__ uint64_t lds[1 << kZTileLog];
+    const uint64_t nt = zadic_tiles(Z);
+    for (uint64_t t = blockIdx.x; t < nt; t += gridDim.x)
+        zadic_tile(threadIdx.x, blockDim.x, xcd_tile(t, gridDim.x, nt), Z, lds);
+}
+
+// per-word conversion, bit transpose and encoding map: the n elements
+__global__ __launch_bounds__(kFeThreads) void k_fencode(FrobEncode F, const uint4* g_tab) {
+    __shared__ uint4 etab[kElemTab];
+    __shared__ uint64_t wtab[kWordTab];
+    __shared__ uint64_t lds[128 * kFeRowPad];
+    const uint64_t* gw = (const uint64_t*)(g_tab + kFrobWordOff);
+    for (uint32_t i = threadIdx.x; i < kElemTab; i += blockDim.x) etab[i] = g_tab[kFrobEncOff + i];
+    for (uint32_t i = threadIdx.x; i < kWordTab; i += blockDim.x) wtab[i] = gw[i];
+    __syncthreads();
+    const uint64_t nt = frob_tiles(F.m);
+    for (uint64_t t = blockIdx.x; t < nt; t += gridDim.x) frob_encode_tile(threadIdx.x, blockDim.x, t, F, etab, wtab, lds);
+}
+
+// inverse encoding map, bit transpose back, inverse per-word conversion
+__global__ __launch_bounds__(kFeThreads) void k_fdecode(FrobDecode F, const uint4* g_tab) {
+    __shared__ uint4 dtab[kElemTab];
+    __shared__ uint64_t wtab[kWordTab];
+    __shared__ uint64_t lds[2 << (6 + kFeGroupsLog)];
+    const uint64_t* gw = (const uint64_t*)(g_tab + kFrobWordOff) + kWordTab;
+    for (uint32_t i = threadIdx.x; i < kElemTab; i += blockDim.x) dtab[i] = g_tab[kFrobDecOff + i];
+    for (uint32_t i = threadIdx.x; i < kWordTab; i += blockDim.x) wtab[i] = gw[i];
+    __syncthreads();
+    const uint64_t nt = frob_tiles(F.m);
+    for (uint64_t t = blockIdx.x; t < nt; t += gridDim.x) frob_decode_tile(threadIdx.x, blockDim.x, t, F, dtab, wtab, lds);
 }
 
 __global__ __launch_bounds__(kThreads) void k_lookup_rate(const uint8_t* g_mt, uint32_t* out) {
@@ -640,6 +677,7 @@ struct gf2x_ctx {
     uint4* d_psi = nullptr;
     uint32_t* d_ctab = nullptr;  // constant-multiple tables of the generic product
     uint4* d_cantor = nullptr;   // simple variant: Cantor basis and phi table
+    uint4* d_frob = nullptr;     // Frobenius variant: encoding maps and per-word conversions
     char* ws = nullptr;
     size_t ws_bytes = 0;
     char* io = nullptr;  // operand/product staging for the host-pointer entry point
@@ -1675,6 +1713,75 @@ int simple_mul(gf2x_ctx* ctx, const uint64_t* a, uint64_t na_bits, const uint64_
     return GF2X_OK;
 }
 
+// ------------------------------ the Frobenius-partition variant (App. C)
+
+int launch_zadic(gf2x_ctx* ctx, const std::vector<ZadicPass>& passes, hipStream_t st) {
+    for (const ZadicPass& z : passes) {
+        hipLaunchKernelGGL(k_zadic, dim3(grid_for(zadic_tiles(z), 4ull * ctx->ncu)), dim3(kZThreads), 0, st, z);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return hip_fail(ctx, e, "z-adic pass launch");
+    }
+    return GF2X_OK;
+}
+
+// E(a): Split into 2^W words, BasisCvt over the bits (z-adic expansion, the
+// word-level conversion; the per-word map runs inside the encoding), the
+// encoding, FFT_LCH at beta_{m+64} over the 2^m elements.
+int frob_forward(gf2x_ctx* ctx, const uint64_t* src, uint64_t nbits, uint64_t* words, int W, uint4* spec, int m,
+                 hipStream_t st) {
+    std::vector<Op> ops;
+    emit_pack(ops, src, nbits, words, 1ull << W);
+    int rc = run_ops(ctx, ops, st);
+    if (rc) return rc;
+    if ((rc = launch_zadic(ctx, zadic_passes(words, W, false), st))) return rc;
+    ops.clear();
+    emit_bc(ops, ctx->pool, words, 0, W, 0, single_params(ctx).bc_small);
+    if ((rc = run_ops(ctx, ops, st))) return rc;
+    const FrobEncode F{words, spec, (uint32_t)W, (uint32_t)m};
+    hipLaunchKernelGGL(k_fencode, dim3(grid_for(frob_tiles((uint32_t)m), 4ull * ctx->ncu)), dim3(kFeThreads), 0, st, F,
+                       (const uint4*)ctx->d_frob);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(ctx, e, "encoding launch");
+    return launch_sfft(ctx, sfft_passes(spec, nullptr, m, m, false, m + 64), st);
+}
+
+// The inverse: iFFT_LCH at beta_{m+64}, the inverse encoding and per-word
+// map into 2^(m+1) words, iBasisCvt of the words, the z-adic recomposition;
+// the first ceil(nc_bits/64) words of the polynomial go to c.  spec is
+// overwritten.
+int frob_inverse(gf2x_ctx* ctx, uint4* spec, int m, uint64_t* words, uint64_t* c, uint64_t nc_bits, hipStream_t st) {
+    int rc = launch_sfft(ctx, sfft_passes(spec, nullptr, m, m, true, m + 64), st);
+    if (rc) return rc;
+    const FrobDecode F{spec, words, (uint32_t)m};
+    hipLaunchKernelGGL(k_fdecode, dim3(grid_for(frob_tiles((uint32_t)m), 4ull * ctx->ncu)), dim3(kFeThreads), 0, st, F,
+                       (const uint4*)ctx->d_frob);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(ctx, e, "decoding launch");
+    std::vector<Op> ops;
+    emit_bc(ops, ctx->pool, words, 0, m + 1, 1, single_params(ctx).bc_small);
+    if ((rc = run_ops(ctx, ops, st))) return rc;
+    return launch_zadic(ctx, zadic_passes(words, m + 1, true, c, (nc_bits + 63) / 64), st);
+}
+
+int frob_mul(gf2x_ctx* ctx, const FrobSizes& s, const uint64_t* a, const uint64_t* b, uint64_t* c, hipStream_t st) {
+    const FrobWorkspace w = frob_workspace(s);
+    int rc = ensure_ws(ctx, w.bytes, st);
+    if (rc) return rc;
+    uint64_t* wa = (uint64_t*)(ctx->ws + w.off_wa);
+    uint64_t* wb = (uint64_t*)(ctx->ws + w.off_wb);
+    uint4* sa = (uint4*)(ctx->ws + w.off_sa);
+    uint4* sb = (uint4*)(ctx->ws + w.off_sb);
+    const uint64_t n = 1ull << s.m;
+    if ((rc = frob_forward(ctx, a, s.na_bits, wa, s.w_a, sa, s.m, st))) return rc;
+    if ((rc = frob_forward(ctx, b, s.nb_bits, wb, s.w_b, sb, s.m, st))) return rc;
+    hipLaunchKernelGGL(k_spmul, dim3(grid_for((n + kSfLaneThreads - 1) / kSfLaneThreads, 16ull * ctx->ncu)),
+                       dim3(kSfLaneThreads), 0, st, (const uint4*)sa, (const uint4*)sb, sb, n);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(ctx, e, "Frobenius-variant pointmul launch");
+    // the decoded words overwrite sa (2^(m+1) words = 16 n bytes)
+    return frob_inverse(ctx, sb, s.m, (uint64_t*)sa, c, s.nc_bits, st);
+}
+
 extern "C" {
 
 const char* gf2x_strerror(int status) {
@@ -1766,6 +1873,21 @@ int gf2x_ctx_create(gf2x_ctx** out, int device) {
     if (e == hipSuccess) e = hipMalloc((void**)&ctx->d_cantor, cantor4.size() * sizeof(uint4));
     if (e == hipSuccess)
         e = hipMemcpy(ctx->d_cantor, cantor4.data(), cantor4.size() * sizeof(uint4), hipMemcpyHostToDevice);
+    std::vector<gcm_u128> fenc, fdec;
+    std::vector<uint64_t> fwf, fwi;
+    if (!build_frob_tables(cantor.data(), fenc, fdec, fwf, fwi)) {
+        gf2x_ctx_destroy(ctx);
+        return GF2X_EINVAL;
+    }
+    std::vector<uint4> frob(kFrobTabU4);
+    for (int i = 0; i < kElemTab; ++i) {
+        frob[kFrobEncOff + i] = to_u4((u128)fenc[i]);
+        frob[kFrobDecOff + i] = to_u4((u128)fdec[i]);
+    }
+    memcpy(frob.data() + kFrobWordOff, fwf.data(), 8 * kWordTab);
+    memcpy((char*)(frob.data() + kFrobWordOff) + 8 * kWordTab, fwi.data(), 8 * kWordTab);
+    if (e == hipSuccess) e = hipMalloc((void**)&ctx->d_frob, frob.size() * sizeof(uint4));
+    if (e == hipSuccess) e = hipMemcpy(ctx->d_frob, frob.data(), frob.size() * sizeof(uint4), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMalloc((void**)&ctx->d_layers, ctx->pool.host.size() * sizeof(BcLayer));
     if (e == hipSuccess)
         e = hipMemcpy(ctx->d_layers, ctx->pool.host.data(), ctx->pool.host.size() * sizeof(BcLayer), hipMemcpyHostToDevice);
@@ -1795,6 +1917,7 @@ void gf2x_ctx_destroy(gf2x_ctx* ctx) {
     if (ctx->d_psi) (void)hipFree(ctx->d_psi);
     if (ctx->d_ctab) (void)hipFree(ctx->d_ctab);
     if (ctx->d_cantor) (void)hipFree(ctx->d_cantor);
+    if (ctx->d_frob) (void)hipFree(ctx->d_frob);
     if (ctx->d_layers) (void)hipFree(ctx->d_layers);
     if (ctx->transient) batch_free(ctx->transient);
     if (ctx->ws) (void)hipFree(ctx->ws);
@@ -2012,6 +2135,70 @@ int gf2x_simple_forward_dev(gf2x_ctx* ctx, const uint64_t* a, uint64_t na_bits, 
     if (rc) return rc;
     if ((rc = ensure_ws(ctx, align256(8ull << m_a), st))) return rc;
     return ws_leave(ctx, st, cap, simple_forward(ctx, a, na_bits, (uint64_t*)ctx->ws, m_a, (uint4*)spec, log2n, st));
+}
+
+int gf2x_frobenius_log2n(uint64_t na_bits, uint64_t nb_bits) {
+    if (!na_bits || !nb_bits) return -1;
+    return frob_sizes(na_bits, nb_bits).m;
+}
+
+size_t gf2x_frobenius_workspace_bytes(uint64_t na_bits, uint64_t nb_bits) {
+    if (!na_bits || !nb_bits) return 0;
+    return frob_workspace(frob_sizes(na_bits, nb_bits)).bytes;
+}
+
+int gf2x_frobenius_mul_dev(gf2x_ctx* ctx, const uint64_t* a, uint64_t na_bits, const uint64_t* b, uint64_t nb_bits,
+                           uint64_t* c, void* stream) {
+    if (check_ctx(ctx)) return GF2X_EINVAL;
+    ctx->err.clear();
+    const FrobSizes s = frob_sizes(na_bits, nb_bits);
+    if (!s.out_words) return GF2X_OK;
+    if (!a || !b || !c) return fail(ctx, GF2X_EINVAL, "NULL operand or product pointer");
+    if (s.m > kMaxLog2N) return fail(ctx, GF2X_ERANGE, "more than 2^32 points");
+    if (ranges_overlap(c, 8 * s.out_words, a, 8 * ((na_bits + 63) / 64)) ||
+        ranges_overlap(c, 8 * s.out_words, b, 8 * ((nb_bits + 63) / 64)))
+        return fail(ctx, GF2X_EINVAL, "product overlaps an operand");
+    DeviceGuard g(ctx->device);
+    hipStream_t st = (hipStream_t)stream;
+    const bool cap = stream_capturing(st);
+    int rc = ws_enter(ctx, st, cap);
+    if (rc) return rc;
+    return ws_leave(ctx, st, cap, frob_mul(ctx, s, a, b, c, st));
+}
+
+int gf2x_frobenius_forward_dev(gf2x_ctx* ctx, const uint64_t* a, uint64_t na_bits, int log2n, void* spec,
+                               void* stream) {
+    if (check_ctx(ctx)) return GF2X_EINVAL;
+    ctx->err.clear();
+    if (!a || !spec || na_bits == 0) return fail(ctx, GF2X_EINVAL, "NULL pointer or empty operand");
+    if (log2n < 0 || log2n > kMaxLog2N) return fail(ctx, GF2X_ERANGE, "log2n out of range");
+    if (na_bits > (128ull << log2n)) return fail(ctx, GF2X_EINVAL, "operand longer than 128 bits per point");
+    const int W = frob_ceil_log2((na_bits + 63) / 64);
+    DeviceGuard g(ctx->device);
+    hipStream_t st = (hipStream_t)stream;
+    const bool cap = stream_capturing(st);
+    int rc = ws_enter(ctx, st, cap);
+    if (rc) return rc;
+    if ((rc = ensure_ws(ctx, align256(8ull << W), st))) return rc;
+    return ws_leave(ctx, st, cap, frob_forward(ctx, a, na_bits, (uint64_t*)ctx->ws, W, (uint4*)spec, log2n, st));
+}
+
+int gf2x_frobenius_inverse_dev(gf2x_ctx* ctx, void* spec, int log2n, uint64_t* c, uint64_t nc_bits, void* stream) {
+    if (check_ctx(ctx)) return GF2X_EINVAL;
+    ctx->err.clear();
+    if (nc_bits == 0) return GF2X_OK;
+    if (!spec || !c) return fail(ctx, GF2X_EINVAL, "NULL pointer");
+    if (log2n < 0 || log2n > kMaxLog2N) return fail(ctx, GF2X_ERANGE, "log2n out of range");
+    if (nc_bits > (128ull << log2n)) return fail(ctx, GF2X_EINVAL, "more than 128 bits per point requested");
+    if (ranges_overlap(c, 8 * ((nc_bits + 63) / 64), spec, 16ull << log2n))
+        return fail(ctx, GF2X_EINVAL, "output overlaps the values");
+    DeviceGuard g(ctx->device);
+    hipStream_t st = (hipStream_t)stream;
+    const bool cap = stream_capturing(st);
+    int rc = ws_enter(ctx, st, cap);
+    if (rc) return rc;
+    if ((rc = ensure_ws(ctx, align256(16ull << log2n), st))) return rc;
+    return ws_leave(ctx, st, cap, frob_inverse(ctx, (uint4*)spec, log2n, (uint64_t*)ctx->ws, c, nc_bits, st));
 }
 
 int gf2x_mul_batch(gf2x_ctx* ctx, const gf2x_job* jobs, size_t njobs, void* stream) {

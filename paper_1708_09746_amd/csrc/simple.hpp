@@ -34,7 +34,7 @@ constexpr int kSfTabPtsLog = 10;      // points of one strided-pass workgroup, a
 constexpr int kSfTabStride = 17;      // uint4 per table: 16 entries and one pad (spreads LDS banks)
 constexpr int kSfLaneC = 9;           // bottom pass: contiguous chunks of 2^9 points
 constexpr int kSfLaneL = 4;           // bottom pass: layers 0..3 (multipliers shared by at most 8 butterflies)
-constexpr int kCantorBeta = 64;       // beta_0 .. beta_63 in the device table
+constexpr int kCantorBeta = 128;      // beta_0 .. beta_127 in the device table (the whole Cantor basis)
 constexpr int kCantorTotal = kCantorBeta + (1 << kSfLaneC);  // then phi(u) for u < 2^9
 
 struct SfftPass {
@@ -43,6 +43,7 @@ struct SfftPass {
     uint64_t wmask;
     uint64_t n;             // N
     int lo, L, c, inverse;  // layers [lo, lo + L); 2^c consecutive low indices per group
+    int alpha;              // >= 0: the transform is at alpha = beta_alpha (its points alpha + phi(j)); -1: at 0
 };
 
 // ------------------------------------------ bodies (kernels and host checks)
@@ -129,6 +130,19 @@ AFFT_HD uint4 phi_cantor(uint64_t v, const uint4* beta) {
     return r;
 }
 
+// The constant part of a layer-k multiplier of a transform at
+// alpha = beta_A: s_k(alpha) = beta_{A-k} (Sec. 3.3: s_k shifts Cantor
+// coordinates down by k); zero for a transform at 0.
+AFFT_HD uint4 sf_alpha_term(const SfftPass& P, int k, const uint4* beta) {
+    return P.alpha >= 0 ? beta[P.alpha - k] : make_uint4(0u, 0u, 0u, 0u);
+}
+
+// The chunk part of a bottom-pass multiplier: s_k(alpha + phi(J0)) for the
+// chunk at J0 (the block part phi((e >> (k + 1)) << 1) is added per butterfly).
+AFFT_HD uint4 sf_lane_lam(const SfftPass& P, uint64_t J0, int k, const uint4* beta) {
+    return xor4(phi_cantor(J0 >> k, beta), sf_alpha_term(P, k, beta));
+}
+
 AFFT_HD uint4 sfft_load(const SfftPass& P, uint64_t j) {
     if (P.words) {
         const uint64_t w = P.words[j & P.wmask];
@@ -156,7 +170,9 @@ AFFT_HD void sf_tab_table(const SfftPass& P, uint64_t g, uint32_t t, const uint4
     const uint64_t hi = g >> (P.lo - P.c);
     const int rho = 31 - __builtin_clz(t + 1);
     const uint64_t b = t + 1 - (1u << rho);
-    gcm_build_tab(phi_cantor((hi << (rho + 1)) | (b << 1), beta), tab + t * kSfTabStride);
+    const int k = P.lo + P.L - 1 - rho;
+    gcm_build_tab(xor4(phi_cantor((hi << (rho + 1)) | (b << 1), beta), sf_alpha_term(P, k, beta)),
+                  tab + t * kSfTabStride);
 }
 
 // Butterfly q of step s (forward: layers top-down; inverse: bottom-up).
@@ -291,12 +307,13 @@ inline bool build_cantor_table(std::vector<gcm_u128>& out) {
 // (contiguous chunks of 2^min(m, 9) points, layers [0, min(M, 4))), then
 // strided passes of at most 7 layers; the forward transform runs them in the
 // reverse order, its first pass reading the converted words.
-inline std::vector<SfftPass> sfft_passes(uint4* x, const uint64_t* words, int m_op, int m, bool inverse) {
+inline std::vector<SfftPass> sfft_passes(uint4* x, const uint64_t* words, int m_op, int m, bool inverse,
+                                         int alpha = -1) {
     std::vector<SfftPass> v;
     const int M = inverse ? m : m_op;
     const int C = m < kSfLaneC ? m : kSfLaneC;
     const int Lb = M < kSfLaneL ? M : kSfLaneL;
-    v.push_back(SfftPass{x, nullptr, 0, 1ull << m, 0, Lb, C, inverse ? 1 : 0});
+    v.push_back(SfftPass{x, nullptr, 0, 1ull << m, 0, Lb, C, inverse ? 1 : 0, alpha});
     const int up = M - Lb;
     if (up > 0) {
         const int np = (up + kSfTabL - 1) / kSfTabL;
@@ -305,7 +322,7 @@ inline std::vector<SfftPass> sfft_passes(uint4* x, const uint64_t* words, int m_
             const int L = up / np + (p < up % np ? 1 : 0);
             int c = kSfTabPtsLog - L;
             if (c > lo) c = lo;
-            v.push_back(SfftPass{x, nullptr, 0, 1ull << m, lo, L, c, inverse ? 1 : 0});
+            v.push_back(SfftPass{x, nullptr, 0, 1ull << m, lo, L, c, inverse ? 1 : 0, alpha});
             lo += L;
         }
     }

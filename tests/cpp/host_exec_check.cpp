@@ -11,6 +11,7 @@
 #include <vector>
 
 #include "afft_plan.hpp"
+#include "frobenius.hpp"
 #include "simple.hpp"
 #include "tower_host.hpp"
 
@@ -289,7 +290,7 @@ void run_sfft(const std::vector<SfftPass>& passes) {
             for (uint64_t g = 0; g < (P.n >> P.c); ++g) {
                 const uint64_t J0 = g << P.c;
                 for (uint32_t e = 0; e < npts; ++e) dat[e] = sfft_load(P, J0 | e);
-                for (int k = 0; k < P.L; ++k) lam[k] = phi_cantor(J0 >> k, CANTOR.data());
+                for (int k = 0; k < P.L; ++k) lam[k] = sf_lane_lam(P, J0, k, CANTOR.data());
                 for (int s = 0; s < P.L; ++s)
                     for (uint32_t q = 0; q < npts / 2; ++q)
                         sf_lane_bfly(P, s, q, dat.data(), lam.data(), CANTOR.data() + kCantorBeta, T.data());
@@ -364,6 +365,111 @@ bool check_simple_product(std::mt19937_64& g, uint64_t na, uint64_t nb) {
     return ok;
 }
 
+// ---- the Frobenius-partition variant (App. C): z-adic passes, the word
+// BasisCvt, encoding, the simple variant's passes at alpha = beta_{m+64},
+// pointmul, and the inverse chain, run here with the kernels' bodies
+std::vector<uint4> FROB;
+
+void run_zadic(const std::vector<ZadicPass>& passes) {
+    std::vector<uint64_t> lds(1 << kZTileLog);
+    for (const ZadicPass& z : passes)
+        for (uint64_t t = 0; t < zadic_tiles(z); ++t) zadic_tile(0, 1, t, z, lds.data());
+}
+
+bool init_frob() {
+    if (CANTOR.empty() && !check_simple_tables()) return false;
+    std::vector<gcm_u128> C, enc, dec;
+    std::vector<uint64_t> wf, wi;
+    if (!build_cantor_table(C) || !build_frob_tables(C.data(), enc, dec, wf, wi)) return false;
+    FROB.assign(kFrobTabU4, make_uint4(0, 0, 0, 0));
+    for (int i = 0; i < kElemTab; ++i) {
+        FROB[kFrobEncOff + i] = to_u4((u128)enc[i]);
+        FROB[kFrobDecOff + i] = to_u4((u128)dec[i]);
+    }
+    memcpy(FROB.data() + kFrobWordOff, wf.data(), 8 * kWordTab);
+    memcpy((char*)(FROB.data() + kFrobWordOff) + 8 * kWordTab, wi.data(), 8 * kWordTab);
+    return true;
+}
+
+void frob_forward_host(const uint64_t* src, uint64_t nbits, uint64_t* words, int W, uint4* spec, int m) {
+    std::vector<Op> ops;
+    emit_pack(ops, src, nbits, words, 1ull << W);
+    run_ops(ops);
+    run_zadic(zadic_passes(words, W, false));
+    ops.clear();
+    emit_bc(ops, POOL, words, 0, W, 0, 1);
+    run_ops(ops);
+    const FrobEncode F{words, spec, (uint32_t)W, (uint32_t)m};
+    std::vector<uint64_t> lds(128 * kFeRowPad);
+    const uint64_t* wt = (const uint64_t*)(FROB.data() + kFrobWordOff);
+    for (uint64_t t = 0; t < frob_tiles((uint32_t)m); ++t)
+        frob_encode_tile(0, 1, t, F, FROB.data() + kFrobEncOff, wt, lds.data());
+    run_sfft(sfft_passes(spec, nullptr, m, m, false, m + 64));
+}
+
+bool check_frob_product(std::mt19937_64& g, uint64_t na, uint64_t nb) {
+    const FrobSizes s = frob_sizes(na, nb);
+    const FrobWorkspace w = frob_workspace(s);
+    std::vector<char> ws(w.bytes, 0x5a);
+    auto a = rand_words(g, na), b = rand_words(g, nb);
+    std::vector<uint64_t> c(s.out_words + 1, 0xdead), r(s.out_words + 1, 0);
+    uint64_t* wa = (uint64_t*)(ws.data() + w.off_wa);
+    uint64_t* wb = (uint64_t*)(ws.data() + w.off_wb);
+    uint4* sa = (uint4*)(ws.data() + w.off_sa);
+    uint4* sb = (uint4*)(ws.data() + w.off_sb);
+    const uint64_t n = 1ull << s.m;
+    frob_forward_host(a.data(), na, wa, s.w_a, sa, s.m);
+    frob_forward_host(b.data(), nb, wb, s.w_b, sb, s.m);
+    std::vector<uint4> T(16);
+    for (uint64_t j = 0; j < n; ++j) {
+        gcm_build_tab(sa[j], T.data());
+        sb[j] = gcm_mul_tab(T.data(), sb[j]);
+    }
+    run_sfft(sfft_passes(sb, nullptr, s.m, s.m, true, s.m + 64));
+    uint64_t* words = (uint64_t*)sa;
+    const FrobDecode F{sb, words, (uint32_t)s.m};
+    std::vector<uint64_t> lds(2 << (6 + kFeGroupsLog));
+    const uint64_t* wt = (const uint64_t*)(FROB.data() + kFrobWordOff) + kWordTab;
+    for (uint64_t t = 0; t < frob_tiles((uint32_t)s.m); ++t)
+        frob_decode_tile(0, 1, t, F, FROB.data() + kFrobDecOff, wt, lds.data());
+    std::vector<Op> ops;
+    emit_bc(ops, POOL, words, 0, s.m + 1, 1, 1);
+    run_ops(ops);
+    run_zadic(zadic_passes(words, s.m + 1, true, c.data(), s.out_words));
+    oracle_mul(a.data(), na, b.data(), nb, r.data(), 4);
+    const bool ok = memcmp(c.data(), r.data(), 8 * s.out_words) == 0 && c[s.out_words] == 0xdead;
+    if (!ok) {
+        uint64_t k = 0;
+        while (k < s.out_words && c[k] == r[k]) ++k;
+        printf("FROBENIUS MISMATCH %llu x %llu bits (n = 2^%d), first bad word %llu of %llu\n",
+               (unsigned long long)na, (unsigned long long)nb, s.m, (unsigned long long)k,
+               (unsigned long long)s.out_words);
+    }
+    return ok;
+}
+
+// the z-adic expansion alone: recomposition inverts it, and the digits of a
+// polynomial below x^64 (one word) are the polynomial itself
+bool check_zadic(std::mt19937_64& g) {
+    bool ok = true;
+    for (int W = 0; W <= 17 && ok; ++W) {
+        std::vector<uint64_t> x(1ull << W), y;
+        for (auto& v : x) v = g();
+        y = x;
+        run_zadic(zadic_passes(y.data(), W, false));
+        std::vector<uint64_t> z(1ull << W, 0);
+        run_zadic(zadic_passes(y.data(), W, true, z.data(), z.size()));
+        ok &= z == x;
+        std::vector<uint64_t> one(1ull << W, 0);
+        one[0] = x[0];
+        run_zadic(zadic_passes(one.data(), W, false));
+        ok &= one[0] == x[0];
+        for (size_t k = 1; k < one.size(); ++k) ok &= one[k] == 0;
+        if (!ok) printf("z-adic round trip or single-word digits wrong at W = %d\n", W);
+    }
+    return ok;
+}
+
 }  // namespace
 
 int main(int argc, char** argv) {
@@ -423,6 +529,23 @@ int main(int argc, char** argv) {
         for (auto& p : fixed) bad += !check_simple_product(g, p[0], p[1]);
         for (int i = 0; i < 30; ++i)
             bad += !check_simple_product(g, 1 + g() % (1ull << (1 + g() % 18)), 1 + g() % (1ull << (1 + g() % 18)));
+    }
+    if (what == "all" || what == "frobenius") {
+        if (!init_frob()) {
+            printf("Frobenius tables failed\n");
+            return 2;
+        }
+        bad += !check_zadic(g);
+        // n = 1 .. 2^13 points: the small-encoding path (n < 64), one and
+        // several encoding tiles, one and several z-adic passes
+        const uint64_t fixed[][2] = {{1, 1},       {64, 64},        {65, 64},       {1, 700},         {128, 1},
+                                     {129, 1},     {100, 29},       {1000, 999},    {5000, 70},       {4096, 4097},
+                                     {1 << 13, 1 << 13}, {(1 << 13) + 1, 1 << 13}, {64, 1 << 16}, {1 << 16, 1 << 16},
+                                     {100000, 3},  {1 << 19, 1 << 18}, {(1 << 19) + 77, (1 << 19) - 5},
+                                     {1 << 20, 1 << 20}};
+        for (auto& p : fixed) bad += !check_frob_product(g, p[0], p[1]);
+        for (int i = 0; i < 30; ++i)
+            bad += !check_frob_product(g, 1 + g() % (1ull << (1 + g() % 18)), 1 + g() % (1ull << (1 + g() % 18)));
     }
     if (what == "all" || what == "xcd") bad += !check_xcd_order(g);
     if (what == "all" || what == "basiscvt") {
