@@ -252,7 +252,7 @@ __global__ __launch_bounds__(kZThreads) void k_zadic(ZadicPass Z) {
 __global__ __launch_bounds__(kFeThreads) void k_fencode(FrobEncode F, const uint4* g_tab) {
     __shared__ uint4 etab[kElemTab];
     __shared__ uint64_t wtab[kWordTab];
-    __shared__ uint64_t lds[128 * kFeRowPad];
+    __shared__ uint64_t lds[kFeStage];
     const uint64_t* gw = (const uint64_t*)(g_tab + kFrobWordOff);
     for (uint32_t i = threadIdx.x; i < kElemTab; i += blockDim.x) etab[i] = g_tab[kFrobEncOff + i];
     for (uint32_t i = threadIdx.x; i < kWordTab; i += blockDim.x) wtab[i] = gw[i];
@@ -265,7 +265,7 @@ __global__ __launch_bounds__(kFeThreads) void k_fencode(FrobEncode F, const uint
 __global__ __launch_bounds__(kFeThreads) void k_fdecode(FrobDecode F, const uint4* g_tab) {
     __shared__ uint4 dtab[kElemTab];
     __shared__ uint64_t wtab[kWordTab];
-    __shared__ uint64_t lds[2 << (6 + kFeGroupsLog)];
+    __shared__ uint64_t lds[kFeStage];
     const uint64_t* gw = (const uint64_t*)(g_tab + kFrobWordOff) + kWordTab;
     for (uint32_t i = threadIdx.x; i < kElemTab; i += blockDim.x) dtab[i] = g_tab[kFrobDecOff + i];
     for (uint32_t i = threadIdx.x; i < kWordTab; i += blockDim.x) wtab[i] = gw[i];

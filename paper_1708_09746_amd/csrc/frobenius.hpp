@@ -35,6 +35,7 @@
 #include <vector>
 
 #include "afft_device.hpp"
+#include "afft_ops.hpp"
 #include "simple.hpp"
 
 namespace gf2x {
@@ -134,9 +135,10 @@ AFFT_HD void zadic_word_level(uint32_t tid, uint32_t nt, const ZadicPass& Z, int
 }
 
 // Level j < 6 of the contiguous pass (rows are words): halves of hw = 2^j
-// words, shifts of d = 2^j bits.  The high step changes only the words that
-// hold bits below 16d (the first max(1, hw/4)) and reads words holding bits
-// at or above 48d, which it never changes.
+// words, shifts of d = 2^j bits, inside blocks of at most 64 words.  The high
+// step changes only the words that hold bits below 16d (the first
+// max(1, hw/4)) and reads words holding bits at or above 48d, which it never
+// changes; the low step writes the low half and reads the high half.
 AFFT_HD void zadic_bit_level(uint32_t tid, uint32_t nt, const ZadicPass& Z, int j, uint64_t* lds, bool inv) {
     const int64_t hw = 1ll << j, d = 1ll << j;
     const uint32_t nblk = 1u << (Z.log_rows - j - 1);
@@ -256,20 +258,24 @@ AFFT_HD uint64_t word_map(const uint64_t* tab, uint64_t v) {
 // ------------------------------------------------------ encoding, decoding
 // Element i of the encoding takes bit j n + i of the converted bits for every
 // j < 128: the 128 x n bit matrix (row j = bits j n .. j n + n - 1) read by
-// columns.  For n >= 64 a row is 2^(m-6) words and a tile is 2^kFeGroupsLog
-// groups of 64 columns, staged through LDS as 128 rows of that many words; for
-// n < 64 one tile holds the whole array (at most 64 words).  The 128 bits of a
-// column enter the 128 x 128 map E(b) = sum_j b_j P_j through 32 tables of 16
-// elements (one per nibble of the column); decoding applies the inverse map the
-// same way and writes the bits back by rows.
-constexpr int kFeGroupsLog = 3;  // groups of 64 elements per tile: 8 (512 elements)
-constexpr int kFeThreads = 512;
+// columns.  For n >= 64 a row is 2^(m-6) words; a tile covers G consecutive
+// groups of 64 columns (G words of every row, staged through LDS so that
+// global loads and stores run along rows), and one wave turns the 128 words
+// of a group into the 64 columns by two 64 x 64 bit transposes done with
+// lane exchanges (six stages each).  The 128 bits of a column enter the
+// 128 x 128 map E(b) = sum_j b_j P_j through 32 tables of 16 elements (one per
+// nibble of the column); decoding applies the inverse map the same way, then
+// the transposes back.  For n < 64 one tile holds the whole array (at most 64
+// words) and each column is gathered bit by bit.
+constexpr int kFeGroupsLog = 4;  // groups of 64 elements per tile: 16 (1024 elements)
+constexpr int kFeThreads = 1024;
 constexpr int kFeRowPad = (1 << kFeGroupsLog) + 1;  // words per staged row
 constexpr int kElemTab = 32 * 16;                    // entries of an element-map table (uint4)
 // device table image of the variant, in uint4 units: the encoding map, its
 // inverse, then the per-word forward and inverse conversions (64-bit entries)
 constexpr int kFrobEncOff = 0, kFrobDecOff = kElemTab, kFrobWordOff = 2 * kElemTab;
 constexpr int kFrobTabU4 = 2 * kElemTab + kWordTab;  // two word tables = kWordTab uint4
+constexpr int kFeStage = 128 * kFeRowPad;            // staged words of a tile
 
 struct FrobEncode {
     const uint64_t* words;  // 2^log_words words of the word-level conversion (before the per-word map)
@@ -284,18 +290,75 @@ struct FrobDecode {
 };
 
 AFFT_HD uint64_t frob_tiles(uint32_t m) { return m >= 6 + kFeGroupsLog ? 1ull << (m - 6 - kFeGroupsLog) : 1ull; }
+AFFT_HD uint32_t frob_groups(uint32_t m) { return m >= 6 + kFeGroupsLog ? 1u << kFeGroupsLog : 1u << (m - 6); }
 
 AFFT_HD uint4 elem_map(const uint4* tab, uint64_t lo, uint64_t hi) {
     uint4 r = make_uint4(0, 0, 0, 0);
 #pragma unroll
-    for (int q = 0; q < 16; ++q) r = xor4(r, tab[(q << 4) | ((lo >> (4 * q)) & 15u)]);
+    for (int q = 0; q < 16; q += 2)
+        r = xor3_4(r, tab[(q << 4) | ((lo >> (4 * q)) & 15u)], tab[((q + 1) << 4) | ((lo >> (4 * q + 4)) & 15u)]);
 #pragma unroll
-    for (int q = 0; q < 16; ++q) r = xor4(r, tab[((16 + q) << 4) | ((hi >> (4 * q)) & 15u)]);
+    for (int q = 0; q < 16; q += 2)
+        r = xor3_4(r, tab[((16 + q) << 4) | ((hi >> (4 * q)) & 15u)],
+                   tab[((17 + q) << 4) | ((hi >> (4 * q + 4)) & 15u)]);
     return r;
 }
 
-// the encoding of one tile; lds holds the staged rows (128 * kFeRowPad words,
-// or the whole array of at most 64 words when n < 64)
+// The 64 x 64 bit transpose of a matrix whose row r is the word v[r]: on
+// return v[c] holds column c (bit r of v[c] = bit c of the old v[r]).  Stage
+// s pairs rows r and r + s (bit s of r clear) and swaps the s x s blocks off
+// the diagonal: row r keeps its bits i with bit s of i clear and takes those
+// of row r + s, moved up by s; row r + s keeps the others and takes row r's,
+// moved down by s.
+AFFT_HD uint64_t tr_mask(int s) {
+    return s == 32 ? 0x00000000FFFFFFFFull
+         : s == 16 ? 0x0000FFFF0000FFFFull
+         : s == 8  ? 0x00FF00FF00FF00FFull
+         : s == 4  ? 0x0F0F0F0F0F0F0F0Full
+         : s == 2  ? 0x3333333333333333ull
+                   : 0x5555555555555555ull;
+}
+
+AFFT_HD void transpose64_host(uint64_t* v) {
+    for (int s = 32; s >= 1; s >>= 1) {
+        const uint64_t M = tr_mask(s);
+        for (int r = 0; r < 64; ++r) {
+            if (r & s) continue;
+            const uint64_t a = v[r], b = v[r + s];
+            v[r] = (a & M) | ((b & M) << s);
+            v[r + s] = (b & ~M) | ((a >> s) & M);
+        }
+    }
+}
+
+#if defined(__HIP_DEVICE_COMPILE__)
+// The same transpose across the lanes of a wave: lane r holds row r on
+// entry and column r on return.  A lane needs half of its partner's bits per
+// stage; for s = 32 that half is one 32-bit word, otherwise two.
+__device__ __forceinline__ uint64_t transpose64_wave(uint64_t v) {
+    const uint32_t lane = threadIdx.x & 63u;
+#pragma unroll
+    for (int s = 32; s >= 1; s >>= 1) {
+        const uint64_t M = tr_mask(s);
+        const bool up = (lane & (uint32_t)s) != 0;
+        // what the partner needs from this lane, in the place it goes
+        const uint64_t send = up ? (v & M) : ((v >> s) & M);
+        uint64_t got;
+        if (s == 32) {
+            got = (uint64_t)(uint32_t)__shfl_xor((int)(uint32_t)send, 32);
+        } else {
+            const uint32_t lo = (uint32_t)__shfl_xor((int)(uint32_t)send, s);
+            const uint32_t hi = (uint32_t)__shfl_xor((int)(uint32_t)(send >> 32), s);
+            got = ((uint64_t)hi << 32) | lo;
+        }
+        v = up ? ((v & ~M) | got) : ((v & M) | (got << s));
+    }
+    return v;
+}
+#endif
+
+// the encoding of one tile; lds holds the staged rows (128 rows of
+// kFeRowPad words, or the whole array of at most 64 words when n < 64)
 AFFT_HD void frob_encode_tile(uint32_t tid, uint32_t nt, uint64_t tile, const FrobEncode& F, const uint4* etab,
                               const uint64_t* wtab, uint64_t* lds) {
     const uint64_t nw = 1ull << F.log_words;
@@ -318,27 +381,41 @@ AFFT_HD void frob_encode_tile(uint32_t tid, uint32_t nt, uint64_t tile, const Fr
         AFFT_SYNC();
         return;
     }
-    const uint32_t G = F.m >= 6 + kFeGroupsLog ? 1u << kFeGroupsLog : 1u << (F.m - 6);
+    const uint32_t G = frob_groups(F.m);
     const uint64_t rw = 1ull << (F.m - 6);  // words per row
     const uint64_t w0 = tile * G;
+    // rows in, along the rows: the per-word map on the way
     for (uint32_t it = tid; it < 128 * G; it += nt) {
-        const uint32_t j = it / G, w = it % G;
-        const uint64_t k = j * rw + w0 + w;
-        lds[j * kFeRowPad + w] = k < nw ? word_map(wtab, F.words[k]) : 0;
+        const uint32_t j = it / G, c = it % G;
+        const uint64_t k = j * rw + w0 + c;
+        lds[j * kFeRowPad + c] = k < nw ? word_map(wtab, F.words[k]) : 0;
     }
     AFFT_SYNC();
-    for (uint32_t e = tid; e < 64 * G; e += nt) {
-        const uint32_t w = e >> 6, l = e & 63;
-        uint64_t lo = 0, hi = 0;
-        for (uint32_t j = 0; j < 64; ++j) lo |= ((lds[j * kFeRowPad + w] >> l) & 1) << j;
-        for (uint32_t j = 0; j < 64; ++j) hi |= ((lds[(64 + j) * kFeRowPad + w] >> l) & 1) << j;
-        F.spec[(w0 << 6) + e] = elem_map(etab, lo, hi);
+#if defined(__HIP_DEVICE_COMPILE__)
+    {
+        const uint32_t lane = tid & 63u, wave = tid >> 6, nwaves = nt >> 6;
+        for (uint32_t c = wave; c < G; c += nwaves) {
+            const uint64_t lo = transpose64_wave(lds[lane * kFeRowPad + c]);
+            const uint64_t hi = transpose64_wave(lds[(64 + lane) * kFeRowPad + c]);
+            F.spec[((w0 + c) << 6) + lane] = elem_map(etab, lo, hi);
+        }
     }
+#else
+    for (uint32_t c = 0; c < G; ++c) {
+        uint64_t lo[64], hi[64];
+        for (int r = 0; r < 64; ++r) {
+            lo[r] = lds[r * kFeRowPad + c];
+            hi[r] = lds[(64 + r) * kFeRowPad + c];
+        }
+        transpose64_host(lo);
+        transpose64_host(hi);
+        for (int l = 0; l < 64; ++l) F.spec[((w0 + c) << 6) + l] = elem_map(etab, lo[l], hi[l]);
+    }
+#endif
     AFFT_SYNC();
 }
 
-// the decoding of one tile; lds holds the tile's decoded columns (two words
-// per element: rows 0..63 and 64..127)
+// the decoding of one tile; lds stages the tile's rows (as the encoding)
 AFFT_HD void frob_decode_tile(uint32_t tid, uint32_t nt, uint64_t tile, const FrobDecode& F, const uint4* dtab,
                               const uint64_t* wtab, uint64_t* lds) {
     if (F.m < 6) {
@@ -361,22 +438,44 @@ AFFT_HD void frob_decode_tile(uint32_t tid, uint32_t nt, uint64_t tile, const Fr
         AFFT_SYNC();
         return;
     }
-    const uint32_t G = F.m >= 6 + kFeGroupsLog ? 1u << kFeGroupsLog : 1u << (F.m - 6);
+    const uint32_t G = frob_groups(F.m);
     const uint64_t rw = 1ull << (F.m - 6);
     const uint64_t w0 = tile * G;
-    for (uint32_t e = tid; e < 64 * G; e += nt) {
-        const uint4 x = F.spec[(w0 << 6) + e];
-        const uint4 b = elem_map(dtab, (uint64_t)x.x | ((uint64_t)x.y << 32), (uint64_t)x.z | ((uint64_t)x.w << 32));
-        lds[2 * e] = (uint64_t)b.x | ((uint64_t)b.y << 32);
-        lds[2 * e + 1] = (uint64_t)b.z | ((uint64_t)b.w << 32);
+#if defined(__HIP_DEVICE_COMPILE__)
+    {
+        const uint32_t lane = tid & 63u, wave = tid >> 6, nwaves = nt >> 6;
+        for (uint32_t c = wave; c < G; c += nwaves) {
+            const uint4 x = F.spec[((w0 + c) << 6) + lane];
+            const uint4 b =
+                elem_map(dtab, (uint64_t)x.x | ((uint64_t)x.y << 32), (uint64_t)x.z | ((uint64_t)x.w << 32));
+            const uint64_t lo = transpose64_wave((uint64_t)b.x | ((uint64_t)b.y << 32));
+            const uint64_t hi = transpose64_wave((uint64_t)b.z | ((uint64_t)b.w << 32));
+            lds[lane * kFeRowPad + c] = word_map(wtab, lo);
+            lds[(64 + lane) * kFeRowPad + c] = word_map(wtab, hi);
+        }
     }
+#else
+    for (uint32_t c = 0; c < G; ++c) {
+        uint64_t lo[64], hi[64];
+        for (int l = 0; l < 64; ++l) {
+            const uint4 x = F.spec[((w0 + c) << 6) + l];
+            const uint4 b =
+                elem_map(dtab, (uint64_t)x.x | ((uint64_t)x.y << 32), (uint64_t)x.z | ((uint64_t)x.w << 32));
+            lo[l] = (uint64_t)b.x | ((uint64_t)b.y << 32);
+            hi[l] = (uint64_t)b.z | ((uint64_t)b.w << 32);
+        }
+        transpose64_host(lo);
+        transpose64_host(hi);
+        for (int r = 0; r < 64; ++r) {
+            lds[r * kFeRowPad + c] = word_map(wtab, lo[r]);
+            lds[(64 + r) * kFeRowPad + c] = word_map(wtab, hi[r]);
+        }
+    }
+#endif
     AFFT_SYNC();
     for (uint32_t it = tid; it < 128 * G; it += nt) {
-        const uint32_t j = it / G, w = it % G;
-        const uint32_t half = j >> 6, bit = j & 63;
-        uint64_t v = 0;
-        for (uint32_t l = 0; l < 64; ++l) v |= ((lds[2 * ((w << 6) + l) + half] >> bit) & 1) << l;
-        F.words[j * rw + w0 + w] = word_map(wtab, v);
+        const uint32_t j = it / G, c = it % G;
+        F.words[j * rw + w0 + c] = lds[j * kFeRowPad + c];
     }
     AFFT_SYNC();
 }

@@ -400,7 +400,7 @@ void frob_forward_host(const uint64_t* src, uint64_t nbits, uint64_t* words, int
     emit_bc(ops, POOL, words, 0, W, 0, 1);
     run_ops(ops);
     const FrobEncode F{words, spec, (uint32_t)W, (uint32_t)m};
-    std::vector<uint64_t> lds(128 * kFeRowPad);
+    std::vector<uint64_t> lds(kFeStage);
     const uint64_t* wt = (const uint64_t*)(FROB.data() + kFrobWordOff);
     for (uint64_t t = 0; t < frob_tiles((uint32_t)m); ++t)
         frob_encode_tile(0, 1, t, F, FROB.data() + kFrobEncOff, wt, lds.data());
@@ -428,7 +428,7 @@ bool check_frob_product(std::mt19937_64& g, uint64_t na, uint64_t nb) {
     run_sfft(sfft_passes(sb, nullptr, s.m, s.m, true, s.m + 64));
     uint64_t* words = (uint64_t*)sa;
     const FrobDecode F{sb, words, (uint32_t)s.m};
-    std::vector<uint64_t> lds(2 << (6 + kFeGroupsLog));
+    std::vector<uint64_t> lds(kFeStage);
     const uint64_t* wt = (const uint64_t*)(FROB.data() + kFrobWordOff) + kWordTab;
     for (uint64_t t = 0; t < frob_tiles((uint32_t)s.m); ++t)
         frob_decode_tile(0, 1, t, F, FROB.data() + kFrobDecOff, wt, lds.data());
