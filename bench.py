@@ -508,6 +508,39 @@ def bench_sizes(P, ctx, runs=50):
         out[name] = {"workload": desc, "runs": reps, "median_ms": round(ts[len(ts) // 2], 4),
                      "p99_ms": round(ts[min(len(ts) - 1, int(0.99 * len(ts)))], 4),
                      "fft_points": 1 << P.fft_log2(n, n)}
+        # the kernels one call launches (the library's trace), and its product
+        # against the oracle's recorded SHA-256
+        ctx.trace_begin(0x1FF)
+        c.fill_(-1)
+        ctx.mul_into(a, n, b, n, c, stream)
+        recs = ctx.trace_end()
+        import hashlib
+
+        out[name]["sha256_equals_oracle_record"] = (
+            hashlib.sha256(c.cpu().numpy().tobytes()).hexdigest() == golden_sha(name))
+        out[name]["launches"] = len(recs)
+        out[name]["kernels"] = sorted(set(r["kernel"] for r in recs))
+        if name == "c1":
+            # the same call as one launch: a single block runs every stage
+            ctx.set_single_launch(12)
+            c.fill_(-1)
+            ctx.trace_begin(0x1FF)
+            ctx.mul_into(a, n, b, n, c, stream)
+            one = ctx.trace_end()
+            same = hashlib.sha256(c.cpu().numpy().tobytes()).hexdigest() == golden_sha(name)
+            ms = []
+            for _ in range(reps):
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+                ctx.mul_into(a, n, b, n, c, stream)
+                e1.record(stream)
+                e1.synchronize()
+                ms.append(e0.elapsed_time(e1))
+            ctx.set_single_launch(-1)
+            ms.sort()
+            out[name]["single_launch"] = {"median_ms": round(ms[len(ms) // 2], 4), "launches": len(one),
+                                          "kernels": sorted(set(r["kernel"] for r in one)),
+                                          "sha256_equals_oracle_record": same}
         if name != "c3b":
             # the same product as a reusable one-job batch: its launches replay
             # as one hipGraph

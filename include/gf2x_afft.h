@@ -98,13 +98,22 @@ size_t gf2x_workspace_bytes_w(uint64_t na_bits, uint64_t nb_bits, int w);
 int gf2x_mul(const uint64_t *a, uint64_t na_bits, const uint64_t *b, uint64_t nb_bits, uint64_t *c);
 
 /* c = a * b with DEVICE pointers, enqueued on `stream` (Alg. 5).  a and b may
- * alias each other (squaring); c must not overlap either.  For transforms of
- * 2^13 points or more, part of the forward transform of b runs on a second
- * stream owned by the context, forked from `stream` and joined back to it by
- * events: up to 2^19 points the whole transform, above only its pack and
- * BasisCvt.  The call stays ordered on `stream` like any other. */
+ * alias each other (squaring); c must not overlap either.  A small product
+ * can be one kernel launch (gf2x_set_single_launch).  For transforms of 2^13
+ * points or more, part of the forward
+ * transform of b runs on a second stream owned by the context, forked from
+ * `stream` and joined back to it by events: up to 2^19 points the whole
+ * transform, above only its pack and BasisCvt.  The call stays ordered on
+ * `stream` like any other. */
 int gf2x_mul_dev(gf2x_ctx *ctx, const uint64_t *a, uint64_t na_bits, const uint64_t *b, uint64_t nb_bits,
                  uint64_t *c, void *stream);
+
+/* The largest transform, 2^max_log2n points, that gf2x_mul_dev runs as one
+ * launch (a single block running every stage of Alg. 5 in order, the ops in
+ * the kernel arguments); -1 (the default) never does.  At most 12 (EINVAL
+ * otherwise).  Results are the same either way; one launch saves the launch
+ * gaps but runs every stage on one compute unit. */
+int gf2x_set_single_launch(gf2x_ctx *ctx, int max_log2n);
 
 /* For callers that cannot allocate device memory (code under HIP graph
  * capture, tight serving loops, harnesses that forbid hipMalloc): c = a * b as
@@ -247,7 +256,8 @@ int gf2x_frobenius_inverse_dev(gf2x_ctx *ctx, void *spec, int log2n, uint64_t *c
  * (hipExtLaunchKernelGGL), so their interval is the kernel's execution time;
  * gf2x_trace_read() waits for them and returns one record per launch.  Kinds (bit = 1 << kind): 0 pack, 1 BasisCvt tile, 2 BasisCvt global
  * layer, 3 FFT pass, 4 pointmul, 5 changeRepr back + combine, 6 BasisCvt
- * VarSubs class pass, 7 truncated-transform step. */
+ * VarSubs class pass, 7 truncated-transform step, 8 a whole product in one
+ * launch (gf2x_set_single_launch: one block runs all its stages in order). */
 typedef struct {
     int kind;            /* one of the kinds above */
     uint64_t elements;   /* elements (words or 16-byte field elements) the launch covers */

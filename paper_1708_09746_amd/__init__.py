@@ -37,8 +37,9 @@ class TraceRec(ctypes.Structure):
 
 
 KIND_NAMES = ["pack", "basiscvt_tile", "basiscvt_layer", "fft_pass", "pointmul", "psi_combine", "basiscvt_class",
-              "spine"]
-KERNEL_OF_KIND = ["k_pack", "k_bc_tile", "k_bc_layer", "k_fft", "k_pmul", "k_psi", "k_bc_class", "k_spine"]
+              "spine", "whole_product"]
+KERNEL_OF_KIND = ["k_pack", "k_bc_tile", "k_bc_layer", "k_fft", "k_pmul", "k_psi", "k_bc_class", "k_spine",
+                  "k_single"]
 
 
 class BatchStats(ctypes.Structure):
@@ -91,6 +92,7 @@ def lib():
             "gf2x_mul": (i32, [vp, u64, vp, u64, vp]),
             "gf2x_mul_dev": (i32, [vp, vp, u64, vp, u64, vp, vp]),
             "gf2x_mul_dev_static": (i32, [vp, vp, u64, vp, u64, vp, vp]),
+            "gf2x_set_single_launch": (i32, [vp, i32]),
             "gf2x_forward_dev": (i32, [vp, vp, u64, i32, vp, vp]),
             "gf2x_pointmul_dev": (i32, [vp, vp, vp, vp, u64, vp]),
             "gf2x_inverse_dev": (i32, [vp, vp, i32, vp, u64, vp]),
@@ -216,6 +218,10 @@ class Context:
         rc = lib().gf2x_mul_dev(self._h, _ptr(a), na_bits, _ptr(b), nb_bits, _ptr(c), _stream_handle(stream))
         self._check(rc, "gf2x_mul_dev")
         return c
+
+    def set_single_launch(self, max_log2n: int):
+        """Products of at most 2^max_log2n points in one launch (-1: never)."""
+        self._check(lib().gf2x_set_single_launch(self._h, int(max_log2n)), "gf2x_set_single_launch")
 
     def mul_static_into(self, a, na_bits: int, b, nb_bits: int, c, stream=None):
         """The same product with the workspace in the library's fixed device
@@ -345,7 +351,7 @@ class Context:
                  for k, _ in TuneRec._fields_} for r in out]
 
     # ---- tracing
-    def trace_begin(self, kind_mask: int = 0xFF):
+    def trace_begin(self, kind_mask: int = 0x1FF):
         self._check(lib().gf2x_trace_begin(self._h, kind_mask), "gf2x_trace_begin")
 
     def trace_end(self):

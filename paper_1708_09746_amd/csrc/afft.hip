@@ -495,12 +495,110 @@ __global__ __launch_bounds__(kThreads) void k_zero_u32(uint32_t* p, uint64_t n) 
 
 static_assert(kConstTabWords <= 4 * ((1 << kFftTileLog) + kMuEntries), "the pointmul tables fit the work area");
 
+// One block's state for running items (op, tile) of any kind: the LDS tables
+// of the kernels above and what the shared work area currently holds (0
+// nothing reusable, 1 the FFT local mu-sets of (cur_lo, cur_hi), 2 the w = 64
+// Psi table, 3 the w = 128 one, 4 the constant-multiple tables of pointmul);
+// phin holds the changeRepr table of mode cur_phi.  Used by the persistent
+// kernel and the single-block product kernel.
+struct ItemBlock {
+    uint8_t* mt;
+    uint32_t* lam;
+    uint4* work;  // FFT tile + mu-set tables, a BasisCvt tile, or the Psi table
+    uint4* mu_tile;
+    uint2* mt3;
+    uint4* phin;
+    const uint4* g_phi;
+    const uint4* g_psi;
+    const uint32_t* g_ctab;
+    int held;
+    uint32_t cur_lo, cur_hi, cur_phi;
+};
+
+__device__ void block_need_phin(int tid, int nt, ItemBlock& S, uint32_t mode) {
+    if (mode == kPhiNone || mode == S.cur_phi) return;
+    copy_words(tid, nt, (uint32_t*)S.phin, (const uint32_t*)(S.g_phi + phin_off(mode)), 4 * phin_len(mode));
+    __syncthreads();
+    S.cur_phi = mode;
+}
+
+// Tile t of op D, by the whole block.  Every body ends with a barrier, so the
+// next item may reuse the LDS at once.
+__device__ void run_item(int tid, int nt, ItemBlock& S, const DevOp& D, uint64_t t) {
+    uint4* tl = S.work;
+    uint4* mu = S.work + (1 << kFftTileLog);
+    switch ((OpKind)D.kind) {
+        case OpKind::Pack: pack_tile(tid, nt, t, D.pack); break;
+        case OpKind::BcTile:
+            if (D.wide)
+                bc_tile<uint4>(tid, nt, t, D.bct, S.work);
+            else
+                bc_tile<uint64_t>(tid, nt, t, D.bct, (uint64_t*)S.work);
+            S.held = 0;
+            break;
+        case OpKind::BcClass:
+            if (D.wide)
+                bc_class_tile<uint4>(tid, nt, t, D.bcc, S.work);
+            else
+                bc_class_tile<uint64_t>(tid, nt, t, D.bcc, (uint64_t*)S.work);
+            S.held = 0;
+            break;
+        case OpKind::BcLayer: {
+            // one item covers one global layer part (only very long jobs)
+            const BcLayerOp L = D.bcl;
+            if (L.wide)
+                bc_part<uint4>(tid, nt, (uint4*)L.data, L.nelem, L.layer, (int)L.which);
+            else
+                bc_part<uint64_t>(tid, nt, (uint64_t*)L.data, L.nelem, L.layer, (int)L.which);
+            __syncthreads();
+            break;
+        }
+        case OpKind::Fft: {
+            const FftPass A = D.fft;
+            block_need_phin(tid, nt, S, A.phi_in);
+            if (S.held != 1 || A.lo != S.cur_lo || A.hi != S.cur_hi) {
+                fft_local_mu(tid, nt, A, S.mt, S.lam, mu);
+                S.held = 1;
+                S.cur_lo = A.lo;
+                S.cur_hi = A.hi;
+            }
+            fft_tile<kFftRL>(tid, nt, t, A, S.mt, S.mt3, S.lam, S.phin, tl, mu, S.mu_tile);
+            break;
+        }
+        case OpKind::Pmul:
+            if (S.held != 4) {
+                copy_words(tid, nt, (uint32_t*)S.work, S.g_ctab, kConstTabWords);
+                __syncthreads();
+                S.held = 4;
+            }
+            pmul_tile(tid, nt, t, D.pmul, S.mt, (const uint32_t*)S.work);
+            __syncthreads();
+            break;
+        case OpKind::Psi: {
+            const int want = D.psi.spech ? 3 : 2;
+            if (S.held != want) {
+                copy_words(tid, nt, S.work, S.g_psi + psi_tab_off(D.psi), psi_tab_len(D.psi));
+                __syncthreads();
+                S.held = want;
+            }
+            psi_tile(tid, nt, t, D.psi, S.work);
+            __syncthreads();
+            break;
+        }
+        case OpKind::Spine:
+            block_need_phin(tid, nt, S, kPhi64);
+            spine_tile(tid, nt, t, D.spn, S.mt, S.phin);
+            __syncthreads();
+            break;
+    }
+}
+
 __global__ __launch_bounds__(kThreads) void k_persistent(PersistArgs P, const uint8_t* g_mt, const uint32_t* g_lam,
                                                          const uint4* g_phi, const uint4* g_psi,
                                                          const uint32_t* g_ctab) {
     __shared__ __align__(16) uint8_t mt[65536];
     __shared__ uint32_t lam[1024];
-    __shared__ uint4 work[(1 << kFftTileLog) + kMuEntries];  // FFT tile + mu-set tables, a BasisCvt tile, or the Psi table
+    __shared__ uint4 work[(1 << kFftTileLog) + kMuEntries];
     __shared__ uint4 mu_tile[32];
     __shared__ uint2 mt3[768];
     __shared__ uint4 phin[kPhiNib];
@@ -511,20 +609,7 @@ __global__ __launch_bounds__(kThreads) void k_persistent(PersistArgs P, const ui
     copy_words(tid, nt, lam, g_lam, 1024);
     __syncthreads();
     build_mt3(tid, nt, mt, mt3);  // visible after the item loop's first barrier
-    uint4* tl = work;
-    uint4* mu = work + (1 << kFftTileLog);
-    // what `work` holds: 0 nothing reusable, 1 FFT local mu-sets of (cur_lo,
-    // cur_hi), 2 the w = 64 Psi table, 3 the w = 128 one, 4 the constant-
-    // multiple tables of pointmul; phin holds the changeRepr table of mode
-    // cur_phi
-    int held = 0;
-    uint32_t cur_lo = ~0u, cur_hi = ~0u, cur_phi = kPhiNone;
-    auto need_phin = [&](uint32_t mode) {
-        if (mode == kPhiNone || mode == cur_phi) return;
-        copy_words(tid, nt, (uint32_t*)phin, (const uint32_t*)(g_phi + phin_off(mode)), 4 * phin_len(mode));
-        __syncthreads();
-        cur_phi = mode;
-    };
+    ItemBlock S{mt, lam, work, mu_tile, mt3, phin, g_phi, g_psi, g_ctab, 0, ~0u, ~0u, kPhiNone};
     int o = -1;
     for (int r = 0; r < P.nranks; ++r) {
         const uint64_t end = P.rank_first[r + 1];
@@ -540,68 +625,7 @@ __global__ __launch_bounds__(kThreads) void k_persistent(PersistArgs P, const ui
             const uint64_t item = s_item;
             if (item >= end) break;
             o = op_of_tile(P.prefix, P.nops, item, -1);
-            const DevOp& D = P.ops[o];
-            const uint64_t t = item - P.prefix[o];
-            switch ((OpKind)D.kind) {
-                case OpKind::Pack: pack_tile(tid, nt, t, D.pack); break;
-                case OpKind::BcTile:
-                    if (D.wide)
-                        bc_tile<uint4>(tid, nt, t, D.bct, work);
-                    else
-                        bc_tile<uint64_t>(tid, nt, t, D.bct, (uint64_t*)work);
-                    held = 0;
-                    break;
-                case OpKind::BcClass:
-                    if (D.wide)
-                        bc_class_tile<uint4>(tid, nt, t, D.bcc, work);
-                    else
-                        bc_class_tile<uint64_t>(tid, nt, t, D.bcc, (uint64_t*)work);
-                    held = 0;
-                    break;
-                case OpKind::BcLayer: {
-                    // one item covers one global layer part (only very long jobs)
-                    const BcLayerOp L = D.bcl;
-                    if (L.wide)
-                        bc_part<uint4>(tid, nt, (uint4*)L.data, L.nelem, L.layer, (int)L.which);
-                    else
-                        bc_part<uint64_t>(tid, nt, (uint64_t*)L.data, L.nelem, L.layer, (int)L.which);
-                    break;
-                }
-                case OpKind::Fft: {
-                    const FftPass A = D.fft;
-                    need_phin(A.phi_in);
-                    if (held != 1 || A.lo != cur_lo || A.hi != cur_hi) {
-                        fft_local_mu(tid, nt, A, mt, lam, mu);
-                        held = 1;
-                        cur_lo = A.lo;
-                        cur_hi = A.hi;
-                    }
-                    fft_tile<kFftRL>(tid, nt, t, A, mt, mt3, lam, phin, tl, mu, mu_tile);
-                    break;
-                }
-                case OpKind::Pmul:
-                    if (held != 4) {
-                        copy_words(tid, nt, (uint32_t*)work, g_ctab, kConstTabWords);
-                        __syncthreads();
-                        held = 4;
-                    }
-                    pmul_tile(tid, nt, t, D.pmul, mt, (const uint32_t*)work);
-                    break;
-                case OpKind::Psi: {
-                    const int want = D.psi.spech ? 3 : 2;
-                    if (held != want) {
-                        copy_words(tid, nt, work, g_psi + psi_tab_off(D.psi), psi_tab_len(D.psi));
-                        __syncthreads();
-                        held = want;
-                    }
-                    psi_tile(tid, nt, t, D.psi, work);
-                    break;
-                }
-                case OpKind::Spine:
-                    need_phin(kPhi64);
-                    spine_tile(tid, nt, t, D.spn, mt, phin);
-                    break;
-            }
+            run_item(tid, nt, S, P.ops[o], item - P.prefix[o]);
         }
         // grid barrier between ranks.  After the workgroup barrier every store
         // of this block has completed; one thread releases them at agent
@@ -632,6 +656,41 @@ __global__ __launch_bounds__(kThreads) void k_persistent(PersistArgs P, const ui
         }
         __syncthreads();
         if (s_stop) break;
+    }
+}
+
+// ------------------------------------------------ whole product in one launch
+// A small product's ops, carried in the kernel arguments, run one after the
+// other by a single block: every tile of an op, then a barrier (op k + 1
+// reads what op k wrote, through the block's own cache), then the next op.
+// One dispatch per product; the spectra stay in that CU's cache hierarchy.
+constexpr int kSingleMaxOps = 32;
+constexpr int kSingleMaxLog = 12;  // transforms of at most 2^12 points take this path
+struct SingleArgs {
+    DevOp ops[kSingleMaxOps];
+    int nops;
+};
+static_assert(sizeof(SingleArgs) <= 4096, "the op list fits the kernel arguments");
+
+__global__ __launch_bounds__(kThreads) void k_single(SingleArgs P, const uint8_t* g_mt, const uint32_t* g_lam,
+                                                     const uint4* g_phi, const uint4* g_psi, const uint32_t* g_ctab) {
+    __shared__ __align__(16) uint8_t mt[65536];
+    __shared__ uint32_t lam[1024];
+    __shared__ uint4 work[(1 << kFftTileLog) + kMuEntries];
+    __shared__ uint4 mu_tile[32];
+    __shared__ uint2 mt3[768];
+    __shared__ uint4 phin[kPhiNib];
+    const int tid = threadIdx.x, nt = blockDim.x;
+    copy_words(tid, nt, (uint32_t*)mt, (const uint32_t*)g_mt, 16384);
+    copy_words(tid, nt, lam, g_lam, 1024);
+    __syncthreads();
+    build_mt3(tid, nt, mt, mt3);
+    __syncthreads();
+    ItemBlock S{mt, lam, work, mu_tile, mt3, phin, g_phi, g_psi, g_ctab, 0, ~0u, ~0u, kPhiNone};
+    for (int o = 0; o < P.nops; ++o) {
+        const DevOp D = P.ops[o];
+        for (uint64_t t = 0; t < D.tiles; ++t) run_item(tid, nt, S, D, t);
+        __syncthreads();
     }
 }
 
@@ -694,6 +753,10 @@ struct gf2x_ctx {
     bool has_last = false;
     // this device's copy of the static product buffer (gf2x_mul_dev_static)
     char* scratch = nullptr;
+    // products of at most 2^single_max_log points run in one dispatch (-1:
+    // never, the default: one block running every stage measured slower than
+    // the op-by-op launches, which spread each stage's tiles over the device)
+    int single_max_log = -1;
     std::string err;
     gf2x_batch* transient = nullptr;  // the last gf2x_mul_batch call's plan
     hipStream_t transient_stream = nullptr;
@@ -1166,6 +1229,26 @@ int batch_upload(gf2x_batch* B) {
 
 int batch_launch_groups(gf2x_batch* B, hipStream_t st) { return launch_groups(B->ctx, B->groups, B->desc, st); }
 
+// The device form of an op (its record and tile count).
+DevOp make_devop(const Op& op) {
+    DevOp d;
+    memset(&d, 0, sizeof(d));
+    d.kind = (int)op.kind;
+    d.wide = op_wide(op);
+    d.tiles = (uint32_t)(op.kind == OpKind::BcLayer ? 1 : op_tiles(op));
+    switch (op.kind) {
+        case OpKind::Pack: d.pack = op.pack; break;
+        case OpKind::BcTile: d.bct = op.bct; break;
+        case OpKind::BcLayer: d.bcl = op.bcl; break;
+        case OpKind::Fft: d.fft = op.fft; break;
+        case OpKind::Pmul: d.pmul = op.pmul; break;
+        case OpKind::Psi: d.psi = op.psi; break;
+        case OpKind::BcClass: d.bcc = op.bcc; break;
+        case OpKind::Spine: d.spn = op.spn; break;
+    }
+    return d;
+}
+
 // Persistent descriptor image: one array of DevOp in item order (group after
 // group, so rank by rank), the op and rank item prefixes, then the scheduler
 // words (abort flag, per-rank arrive counters, per-rank 64-bit item counters).
@@ -1183,21 +1266,7 @@ void pack_persistent(const std::vector<Op>& ops, const std::vector<uint32_t>& ra
                 cur_rank = rank_of[i];
                 rank_first.push_back(prefix.back());
             }
-            DevOp d;
-            memset(&d, 0, sizeof(d));
-            d.kind = (int)op.kind;
-            d.wide = op_wide(op);
-            d.tiles = (uint32_t)(op.kind == OpKind::BcLayer ? 1 : op_tiles(op));
-            switch (op.kind) {
-                case OpKind::Pack: d.pack = op.pack; break;
-                case OpKind::BcTile: d.bct = op.bct; break;
-                case OpKind::BcLayer: d.bcl = op.bcl; break;
-                case OpKind::Fft: d.fft = op.fft; break;
-                case OpKind::Pmul: d.pmul = op.pmul; break;
-                case OpKind::Psi: d.psi = op.psi; break;
-                case OpKind::BcClass: d.bcc = op.bcc; break;
-                case OpKind::Spine: d.spn = op.spn; break;
-            }
+            const DevOp d = make_devop(op);
             dops.push_back(d);
             prefix.push_back(prefix.back() + d.tiles);
         }
@@ -1968,9 +2037,52 @@ int check_product(gf2x_ctx* ctx, const Sizes& s, const uint64_t* a, const uint64
     return GF2X_OK;
 }
 
-// The product's ops on stream st with the workspace at ws (Alg. 5).
+// The whole product in one dispatch (k_single): its ops, planned with the
+// tiles of the batch kernels (1024-thread blocks), go in the kernel
+// arguments.  Returns 1, having done nothing, if the plan has more ops than
+// the arguments hold.
+constexpr int kTraceSingle = 8;  // trace kind of a whole-product launch
+int mul_single(gf2x_ctx* ctx, const Sizes& s, const uint64_t* a, const uint64_t* b, uint64_t* c, char* ws,
+               hipStream_t st) {
+    std::vector<Op> ops;
+    plan_mul(ops, ctx->pool, ctx->params, s, a, b, c, ws);
+    if (ops.size() > (size_t)kSingleMaxOps) return 1;
+    SingleArgs A;
+    memset(&A, 0, sizeof(A));
+    for (size_t i = 0; i < ops.size(); ++i) A.ops[i] = make_devop(ops[i]);
+    A.nops = (int)ops.size();
+    gf2x_ctx::Pending pend{};
+    const bool traced = (ctx->trace_mask >> kTraceSingle) & 1u;
+    if (traced) {
+        pend.rec.kind = kTraceSingle;
+        pend.rec.elements = 1ull << s.m;
+        pend.rec.bytes_read = 8 * (s.n_a + s.n_b);
+        pend.rec.bytes_written = 8 * s.out_words;
+        hipError_t e = hipEventCreate(&pend.start);
+        if (e == hipSuccess) e = hipEventCreate(&pend.stop);
+        if (e != hipSuccess) return hip_fail(ctx, e, "trace event");
+        hipExtLaunchKernelGGL(k_single, dim3(1), dim3(kThreads), 0, st, pend.start, pend.stop, 0, A,
+                              (const uint8_t*)ctx->d_mt, (const uint32_t*)ctx->d_lam, (const uint4*)ctx->d_phi,
+                              (const uint4*)ctx->d_psi, (const uint32_t*)ctx->d_ctab);
+    } else {
+        hipLaunchKernelGGL(k_single, dim3(1), dim3(kThreads), 0, st, A, (const uint8_t*)ctx->d_mt,
+                           (const uint32_t*)ctx->d_lam, (const uint4*)ctx->d_phi, (const uint4*)ctx->d_psi,
+                           (const uint32_t*)ctx->d_ctab);
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(ctx, e, "single-block product launch");
+    if (traced) ctx->trace.push_back(pend);
+    return GF2X_OK;
+}
+
+// The product's ops on stream st with the workspace at ws (Alg. 5): small
+// products in one dispatch, the others op by op.
 int mul_on(gf2x_ctx* ctx, const Sizes& s, const uint64_t* a, const uint64_t* b, uint64_t* c, char* ws,
            hipStream_t st) {
+    if (s.m <= ctx->single_max_log) {
+        const int rc = mul_single(ctx, s, a, b, c, ws, st);
+        if (rc != 1) return rc;
+    }
     std::vector<Op> ops;
     size_t split[2] = {0, 0};
     plan_mul(ops, ctx->pool, single_params(ctx), s, a, b, c, ws, split);
@@ -2135,6 +2247,13 @@ int gf2x_simple_forward_dev(gf2x_ctx* ctx, const uint64_t* a, uint64_t na_bits, 
     if (rc) return rc;
     if ((rc = ensure_ws(ctx, align256(8ull << m_a), st))) return rc;
     return ws_leave(ctx, st, cap, simple_forward(ctx, a, na_bits, (uint64_t*)ctx->ws, m_a, (uint4*)spec, log2n, st));
+}
+
+int gf2x_set_single_launch(gf2x_ctx* ctx, int max_log2n) {
+    if (check_ctx(ctx)) return GF2X_EINVAL;
+    if (max_log2n < -1 || max_log2n > kSingleMaxLog) return fail(ctx, GF2X_EINVAL, "single-launch bound out of range");
+    ctx->single_max_log = max_log2n;
+    return GF2X_OK;
 }
 
 int gf2x_frobenius_log2n(uint64_t na_bits, uint64_t nb_bits) {
