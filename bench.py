@@ -251,7 +251,10 @@ def bench_batched(ctx, njobs=4096, reps=5):
             st = B.stats()
             out[f"{name}{tag}"] = t
             res[f"{name}{tag}_products_per_s"] = round(njobs / t, 1)
-            res[f"{name}_launches"] = st["launches"]
+            if not tag.startswith("_trunc"):
+                res[f"{name}_launches"] = st["launches"]
+            else:
+                res[f"{name}{tag}_launches"] = st["launches"]
             B.close()
 
     batches("_default_schedule")
@@ -260,6 +263,21 @@ def bench_batched(ctx, njobs=4096, reps=5):
     tuned = ctx.autotune(6, 20, reps=3)
     res["schedule"] = {str(r["m"]): [r["bottom_log"], r["col_rows_log"]] for r in tuned}
     batches("")
+    # truncated transforms: each product evaluated at n_c rounded up to a
+    # multiple of 2^(m - levels) points instead of all N (the tuned schedules)
+    res["truncation"] = {}
+    for levels, min_log in ((2, 8), (3, 8), (3, 11)):
+        ctx.set_truncation(levels, min_log)
+        tag = f"_trunc_{levels}_{min_log}"
+        batches(tag)
+        res["truncation"][f"levels={levels},min_log2n={min_log}"] = {
+            "staged_graph_products_per_s": res.pop(f"staged_graph{tag}_products_per_s"),
+            "staged_graph_launches": res.pop(f"staged_graph{tag}_launches"),
+            "persistent_graph_products_per_s": res.pop(f"persistent_graph{tag}_products_per_s")}
+        res.pop(f"persistent_graph{tag}_launches")
+        out.pop(f"staged_graph{tag}")
+        out.pop(f"persistent_graph{tag}")
+    ctx.set_truncation(0, 22)
     best = min(out, key=out.get)
     res["best"] = best
     res["speedup_vs_loop"] = round(t_loop / out[best], 2)
@@ -392,6 +410,14 @@ def bench_serving(ctx, nreq=10000, fracs=(0.1, 0.25, 0.5, 0.75, 0.9, 0.9, 0.9, 1
         tune[key] = round(rate, 1)
         log(f"bench: serving saturation {key}: {rate:.0f} products/s, {st['iterations']} iterations")
     res["saturation_products_per_s"] = tune
+    # the same with truncated transforms (evaluation at n_c rounded up to a
+    # multiple of 2^(m - 3) points, transforms of 2^8 points and more)
+    ctx.set_truncation(3, 8)
+    rate, st = saturate(2, "adaptive")
+    ctx.set_truncation(0, 22)
+    res["saturation_truncated_products_per_s"] = {"adaptive_L2": round(rate, 1),
+                                                  "setting": "levels=3, min_log2n=8"}
+    log(f"bench: serving saturation adaptive_L2 with truncation: {rate:.0f} products/s")
     sat = max(tune.values())
     # the open-loop streams run on the adaptive engine (persistent iterations
     # under load, staged ones when idle or backlogged), at fractions of the

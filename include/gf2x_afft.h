@@ -302,7 +302,11 @@ typedef struct {
  * PERSISTENT runs the whole batch in one launch of a persistent kernel (one
  * block per CU) whose blocks take (op, tile) items of a rank from a counter
  * and meet at a grid barrier between ranks (bounded wait: on timeout the run
- * stops early and gf2x_batch_check reports GF2X_EDEVICE). */
+ * stops early and gf2x_batch_check reports GF2X_EDEVICE).  The context checks
+ * at creation that a CU can hold a block of that kernel (the occupancy
+ * query); if none can, a persistent run fails with GF2X_EDEVICE before it
+ * launches.  All blocks are then resident unless other work shares the
+ * device, which the bounded wait turns into that error. */
 enum { GF2X_BATCH_STAGED = 0, GF2X_BATCH_PERSISTENT = 1 };
 
 int gf2x_batch_create(gf2x_ctx *ctx, const gf2x_job *jobs, size_t njobs, int mode, gf2x_batch **batch);
@@ -422,7 +426,10 @@ typedef struct {
  * launch while at least GF2X_SERVER_ADAPTIVE_ACTIVE requests are admitted and
  * fewer than GF2X_SERVER_ADAPTIVE_BACKLOG wait in the queue (no launch tails:
  * the lowest latency under load), and staged otherwise (few requests: the
- * lowest latency alone; a long queue: the highest throughput). */
+ * lowest latency alone; a long queue: the highest throughput).  Under light
+ * load (nothing queued, at most two requests admitted) an iteration runs every
+ * remaining level of the admitted requests; a lone request then runs as a
+ * plain call does, one launch per op, with no descriptor upload. */
 enum { GF2X_SERVER_ADAPTIVE = 2, GF2X_SERVER_ADAPTIVE_ACTIVE = 8, GF2X_SERVER_ADAPTIVE_BACKLOG = 1024 };
 
 typedef struct {

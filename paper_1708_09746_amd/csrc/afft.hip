@@ -515,16 +515,17 @@ struct ItemBlock {
     uint32_t cur_lo, cur_hi, cur_phi;
 };
 
-__device__ void block_need_phin(int tid, int nt, ItemBlock& S, uint32_t mode) {
+__device__ __forceinline__ void block_need_phin(int tid, int nt, ItemBlock& S, uint32_t mode) {
     if (mode == kPhiNone || mode == S.cur_phi) return;
     copy_words(tid, nt, (uint32_t*)S.phin, (const uint32_t*)(S.g_phi + phin_off(mode)), 4 * phin_len(mode));
     __syncthreads();
     S.cur_phi = mode;
 }
 
-// Tile t of op D, by the whole block.  Every body ends with a barrier, so the
-// next item may reuse the LDS at once.
-__device__ void run_item(int tid, int nt, ItemBlock& S, const DevOp& D, uint64_t t) {
+// Tile t of op D, by the whole block (inlined into each kernel, so that the
+// LDS pointers keep their address space).  The tile bodies that use the LDS
+// as a work area end with a barrier; the others only read their tables.
+__device__ __forceinline__ void run_item(int tid, int nt, ItemBlock& S, const DevOp& D, uint64_t t) {
     uint4* tl = S.work;
     uint4* mu = S.work + (1 << kFftTileLog);
     switch ((OpKind)D.kind) {
@@ -550,7 +551,6 @@ __device__ void run_item(int tid, int nt, ItemBlock& S, const DevOp& D, uint64_t
                 bc_part<uint4>(tid, nt, (uint4*)L.data, L.nelem, L.layer, (int)L.which);
             else
                 bc_part<uint64_t>(tid, nt, (uint64_t*)L.data, L.nelem, L.layer, (int)L.which);
-            __syncthreads();
             break;
         }
         case OpKind::Fft: {
@@ -572,7 +572,6 @@ __device__ void run_item(int tid, int nt, ItemBlock& S, const DevOp& D, uint64_t
                 S.held = 4;
             }
             pmul_tile(tid, nt, t, D.pmul, S.mt, (const uint32_t*)S.work);
-            __syncthreads();
             break;
         case OpKind::Psi: {
             const int want = D.psi.spech ? 3 : 2;
@@ -582,13 +581,11 @@ __device__ void run_item(int tid, int nt, ItemBlock& S, const DevOp& D, uint64_t
                 S.held = want;
             }
             psi_tile(tid, nt, t, D.psi, S.work);
-            __syncthreads();
             break;
         }
         case OpKind::Spine:
             block_need_phin(tid, nt, S, kPhi64);
             spine_tile(tid, nt, t, D.spn, S.mt, S.phin);
-            __syncthreads();
             break;
     }
 }
@@ -753,6 +750,10 @@ struct gf2x_ctx {
     bool has_last = false;
     // this device's copy of the static product buffer (gf2x_mul_dev_static)
     char* scratch = nullptr;
+    // blocks of the persistent kernel one CU holds at once (its launch needs
+    // at least one: the grid is one block per CU and its blocks wait for
+    // each other)
+    int persist_per_cu = 0;
     // products of at most 2^single_max_log points run in one dispatch (-1:
     // never, the default: one block running every stage measured slower than
     // the op-by-op launches, which spread each stage's tiles over the device)
@@ -1317,6 +1318,8 @@ PersistArgs persist_args(const char* dev, const PersistLayout& L, uint32_t spin_
 // graph), then launches one persistent block per CU.
 int launch_persistent(gf2x_ctx* ctx, char* dev, const PersistLayout& L, uint32_t spin_limit, hipStream_t st) {
     if (!L.items) return GF2X_OK;
+    if (ctx->persist_per_cu < 1)
+        return fail(ctx, GF2X_EDEVICE, "the persistent kernel does not fit a compute unit (occupancy 0)");
     PersistArgs a = persist_args(dev, L, spin_limit);
     hipLaunchKernelGGL(k_zero_u32, dim3(grid_for((L.state_words + kThreads - 1) / kThreads, 64)), dim3(kThreads), 0, st,
                        (uint32_t*)(dev + L.state_off), (uint64_t)L.state_words);
@@ -1539,7 +1542,14 @@ int server_iterate(gf2x_server* S, bool& launched) {
     const int si = S->free_slots.back();
     gf2x_server::Slot& sl = S->slots[si];
     uint32_t L = S->cfg.levels_per_iter;
-    if (S->cfg.iter_tiles) {
+    // adaptive mode, light load (nothing queued, at most kLightActive
+    // requests admitted): they run all their remaining levels in this
+    // iteration, as plain calls would (too few to gain from sharing launches)
+    constexpr size_t kLightActive = 2;
+    const bool idle = S->cfg.mode == GF2X_SERVER_ADAPTIVE && S->queue.empty() && S->active.size() <= kLightActive;
+    if (idle) {
+        for (const auto& r : S->active) L = std::max<uint32_t>(L, r.levels - r.next);
+    } else if (S->cfg.iter_tiles) {
         // as many levels as fit the work bound (at least one)
         uint64_t acc = 0;
         uint32_t l = 0;
@@ -1553,6 +1563,17 @@ int server_iterate(gf2x_server* S, bool& launched) {
         }
         L = std::max<uint32_t>(l, 1);
     }
+    // a lone request starting on a lightly loaded engine runs as a plain call
+    // does: replanned with the single-product tiles, one launch per op, no
+    // descriptor upload (its arena region fits either plan)
+    const bool direct = idle && S->active.size() == 1 && S->active[0].next == 0;
+    std::vector<Op> direct_ops;
+    if (direct) {
+        const gf2x_server::Req& r = S->active[0];
+        PlanParams pp = S->ctx->params;
+        pp.bc_small = 1;
+        plan_mul(direct_ops, S->ctx->pool, pp, make_sizes(r.na, r.nb, r.w), r.a, r.b, r.c, S->arena + r.off);
+    }
     S->it_ops.clear();
     S->it_rank.clear();
     // requests starting in this iteration: their operands are ready once the
@@ -1562,6 +1583,13 @@ int server_iterate(gf2x_server* S, bool& launched) {
     std::vector<std::pair<hipStream_t, hipEvent_t>> waits;
     for (auto& r : S->active) {
         if (r.next != 0 || !r.ready) continue;
+        if (hipEventQuery(r.ready) == hipSuccess) {
+            // the submitter's work is already done: nothing to wait for
+            S->free_events.push_back(r.ready);
+            r.ready = nullptr;
+            continue;
+        }
+        (void)hipGetLastError();
         bool found = false;
         for (auto& w : waits)
             if (w.first == r.src) {
@@ -1590,6 +1618,25 @@ int server_iterate(gf2x_server* S, bool& launched) {
         }
     }
     S->active.swap(keep);
+    if (direct) {
+        S->free_slots.pop_back();
+        S->inflight.push_back(si);
+        sl.persistent = false;
+        hipStream_t st = S->st;
+        hipError_t e = hipSuccess;
+        for (auto& w : waits) {
+            if (e == hipSuccess) e = hipStreamWaitEvent(st, w.second, 0);
+            S->free_events.push_back(w.second);
+        }
+        if (e != hipSuccess) return hip_fail(S->ctx, e, "serving: wait for the submitters' streams");
+        int rc = run_ops(S->ctx, direct_ops, st);
+        if (rc) return rc;
+        S->stats.launches += direct_ops.size();
+        e = hipEventRecord(sl.ev, st);
+        if (e != hipSuccess) return hip_fail(S->ctx, e, "serving event");
+        ++S->stats.iterations;
+        return GF2X_OK;
+    }
     S->it_groups.clear();
     group_by_rank(S->it_ops, S->it_rank, 0, L, S->it_groups);
     S->it_host.clear();
@@ -1967,6 +2014,7 @@ int gf2x_ctx_create(gf2x_ctx** out, int device) {
     if (e == hipSuccess) e = hipEventCreateWithFlags(&ctx->ev_join, hipEventDisableTiming);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&ctx->ev_last, hipEventDisableTiming);
     if (e == hipSuccess) e = scratch_address(device, &ctx->scratch);
+    if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&ctx->persist_per_cu, k_persistent, kThreads, 0);
     if (e != hipSuccess) {
         (void)hipGetLastError();
         gf2x_ctx_destroy(ctx);
