@@ -22,6 +22,22 @@
 #endif
 #define AFFT_HD __host__ __device__ __forceinline__
 
+// Ordering among the lanes of one wave only: the LDS writes of this wave are
+// complete and visible to its own later LDS reads (a wave's LDS operations are
+// executed in order; the fence keeps the compiler from moving accesses across
+// it).  For phases whose LDS data each wave owns alone.
+#if defined(__HIP_DEVICE_COMPILE__)
+#define AFFT_WAVE_SYNC()                                     \
+    do {                                                     \
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront"); \
+        __builtin_amdgcn_wave_barrier();                     \
+    } while (0)
+#else
+#define AFFT_WAVE_SYNC() \
+    do {                 \
+    } while (0)
+#endif
+
 namespace gf2x {
 
 struct BcLayer {

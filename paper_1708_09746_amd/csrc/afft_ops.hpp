@@ -553,6 +553,18 @@ AFFT_HD void fft_tile_layers(int tid, int nt, const FftPass& A, const FftTileGeo
         if (li < rlog && y < (1 << (nb > 6 ? nb - 6 : 0))) mu[kMuHiCur + E] = xor4(mu[kMuHiBase + E], mu_tile[li]);
     }
     AFFT_SYNC();
+    // A step of R layers from local layer h0 gives thread g the rows of group
+    // g; with contiguous rows (log_tc = 0), one group per thread and
+    // h0 <= 6, the 64 threads of a wave then own exactly the 64 2^R rows from
+    // 64 2^R w on, so between two such steps of equal R the exchange stays
+    // inside each wave: a wave-level sync replaces the workgroup barrier.
+    const uint32_t nel = 1u << (A.hi - A.lo + A.log_tc);
+    auto wave_owned = [&](int d, int& Rd) {
+        const int r = rlog - d;
+        Rd = r >= RL ? RL : r;
+        const int i0 = A.inverse ? (int)A.lo + d : (int)A.hi - d - Rd;
+        return A.log_tc == 0 && (nel >> Rd) <= (uint32_t)nt && i0 - (int)A.lo <= 6;
+    };
     int done = 0;
     while (done < rlog) {
         int r = rlog - done;
@@ -573,8 +585,13 @@ AFFT_HD void fft_tile_layers(int tid, int nt, const FftPass& A, const FftTileGeo
             else
                 fft_step<1, false>(tid, nt, A, i0, mt, mt3, tl, mu);
         }
-        AFFT_SYNC();
+        int Rc = 0, Rn = 0;
+        const bool here = wave_owned(done, Rc);
         done += R;
+        if (done < rlog && here && wave_owned(done, Rn) && Rn == Rc)
+            AFFT_WAVE_SYNC();
+        else
+            AFFT_SYNC();
     }
 }
 
