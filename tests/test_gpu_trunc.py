@@ -117,3 +117,81 @@ def test_truncation_range_and_stage_calls(ctx):
     again = host(ctx.forward(dev(a), na, 12))
     ctx.set_truncation(3, 22)
     assert np.array_equal(full, again)
+
+
+def _oracle_all(pairs):
+    import os
+    from concurrent.futures import ThreadPoolExecutor
+
+    with ThreadPoolExecutor(min(16, os.cpu_count() or 1)) as ex:
+        return list(ex.map(lambda p: oracle.mul(*p), pairs))
+
+
+@pytest.mark.parametrize("levels", [2, 3])
+def test_truncated_batch_at_configured_lengths(levels):
+    """Jobs drawn like the configured batch (operands floor(2^u) bits,
+    u ~ U[12, 20]), truncated to multiples of N / 2^levels from 2^8 points up;
+    staged and persistent, every job against the oracle."""
+    c_ = P.Context(0)
+    try:
+        c_.set_truncation(levels, 8)
+        spec = inputs.batch_workload(256, 12, 20)
+        host_ops, jobs = [], []
+        for na, nb, sa, sb in spec:
+            a, b = inputs.random_poly(sa, na), inputs.random_poly(sb, nb)
+            host_ops.append((a, na, b, nb))
+            jobs.append((dev(a), na, dev(b), nb, torch.full((P.out_words(na, nb),), -1, dtype=torch.int64,
+                                                             device="cuda")))
+        assert sum(c_.eval_points(na, nb) < (1 << P.fft_log2(na, nb)) for na, nb, _, _ in spec) > 100
+        want = _oracle_all(host_ops)
+        for persistent in (False, True):
+            for j in jobs:
+                j[4].fill_(-1)
+            say(f"case truncated batch at configured lengths, levels {levels}, persistent={persistent}")
+            B = c_.batch(jobs, persistent=persistent)
+            B.run()
+            B.run()
+            torch.cuda.synchronize()
+            B.check()
+            B.close()
+            for k, ((_a, na, _b, nb, c), w) in enumerate(zip(jobs, want)):
+                assert np.array_equal(host(c), w), (levels, persistent, k, na, nb)
+    finally:
+        torch.cuda.synchronize()
+        c_.close()
+
+
+def test_truncated_server_at_configured_lengths():
+    """Served requests with operands floor(2^u) bits, u ~ U[10, 22], on a
+    context that truncates transforms of 2^8 points and more (levels 3), in
+    waves on the adaptive engine; every result against the oracle."""
+    c_ = P.Context(0)
+    try:
+        c_.set_truncation(3, 8)
+        reqs = []
+        for na, nb, sa, sb, _u in inputs.serve_workload(40, 2, 10, 22):
+            a, b = inputs.random_poly(sa, na), inputs.random_poly(sb, nb)
+            reqs.append((a, na, b, nb, dev(a), dev(b),
+                         torch.full((P.out_words(na, nb),), -1, dtype=torch.int64, device="cuda")))
+        assert sum(c_.eval_points(r[1], r[3]) < (1 << P.fft_log2(r[1], r[3])) for r in reqs) > 10
+        torch.cuda.synchronize()
+        srv = c_.server(1 << 30, max_active=16, levels_per_iter=2, persistent="adaptive")
+        say("case truncated server, 40 requests")
+        done = []
+        for w in range(4):
+            for i in range(10 * w, 10 * w + 10):
+                a, na, b, nb, da, db, c = reqs[i]
+                srv.submit(da, na, db, nb, c, i)
+            srv.step(P.now_ns() + 200_000)
+            done.extend(srv.poll())
+        done.extend(srv.drain())
+        srv.close()
+        assert sorted(d["tag"] for d in done) == list(range(len(reqs)))
+        assert all(d["status"] == 0 for d in done)
+        torch.cuda.synchronize()
+        want = _oracle_all([(r[0], r[1], r[2], r[3]) for r in reqs])
+        for i, (r, w) in enumerate(zip(reqs, want)):
+            assert np.array_equal(host(r[6]), w), (i, r[1], r[3])
+    finally:
+        torch.cuda.synchronize()
+        c_.close()
