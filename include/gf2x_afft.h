@@ -121,8 +121,10 @@ int gf2x_set_single_launch(gf2x_ctx *ctx, int max_log2n);
  * settings of ctx), with the whole workspace in a fixed device buffer of
  * GF2X_STATIC_SCRATCH_BYTES that the library holds on each GPU it runs on
  * until the process ends (its address is looked up when a context is created
- * on that GPU).  The call allocates nothing on the device and creates no
- * stream or event: every kernel runs on `stream`, and it is never traced.
+ * on that GPU).  The call allocates no device memory (no hipMalloc, hipFree
+ * or other device-allocating routine) and creates no stream or event: every
+ * kernel runs on `stream`, and it is never traced.  (Its host-side planning
+ * builds a few small std::vector op lists on the host heap.)
  * A product whose workspace (gf2x_workspace_bytes_w at ctx's word width)
  * exceeds the buffer returns GF2X_ENOMEM with the sizes in gf2x_last_error;
  * with w = 64 that admits every product of at most 2^20 points, i.e.
