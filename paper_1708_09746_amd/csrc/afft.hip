@@ -376,7 +376,7 @@ __global__ __launch_bounds__(kThreads) void k_fft_multi(const FftPass* ops, cons
     uint64_t g0, g1;
     block_chunk(total, g0, g1);
     int o = -1;
-    uint32_t cur_lo = ~0u, cur_hi = ~0u, cur_phi = kPhiNone;
+    uint32_t cur_lo = ~0u, cur_hi = ~0u, cur_pack = ~0u, cur_phi = kPhiNone;
     for (uint64_t g = g0; g < g1; ++g) {
         o = op_of_tile(prefix, nops, g, o);
         const FftPass A = ops[o];
@@ -386,11 +386,12 @@ __global__ __launch_bounds__(kThreads) void k_fft_multi(const FftPass* ops, cons
             __syncthreads();
             cur_phi = A.phi_in;
         }
-        if (A.lo != cur_lo || A.hi != cur_hi) {
-            // the local mu-sets depend only on the layer range of the pass
+        if (A.lo != cur_lo || A.hi != cur_hi || A.pack != cur_pack) {
+            // the local mu-sets depend only on the layer range and row bits of the pass
             fft_local_mu(tid, nt, A, mt, lam, mu);
             cur_lo = A.lo;
             cur_hi = A.hi;
+            cur_pack = A.pack;
         }
         fft_tile<kFftRL>(tid, nt, g - prefix[o], A, mt, mt3, lam, phin, tl, mu, mu_tile);
     }
@@ -512,7 +513,7 @@ struct ItemBlock {
     const uint4* g_psi;
     const uint32_t* g_ctab;
     int held;
-    uint32_t cur_lo, cur_hi, cur_phi;
+    uint32_t cur_lo, cur_hi, cur_phi, cur_pack;
 };
 
 __device__ __forceinline__ void block_need_phin(int tid, int nt, ItemBlock& S, uint32_t mode) {
@@ -556,11 +557,12 @@ __device__ __forceinline__ void run_item(int tid, int nt, ItemBlock& S, const De
         case OpKind::Fft: {
             const FftPass A = D.fft;
             block_need_phin(tid, nt, S, A.phi_in);
-            if (S.held != 1 || A.lo != S.cur_lo || A.hi != S.cur_hi) {
+            if (S.held != 1 || A.lo != S.cur_lo || A.hi != S.cur_hi || A.pack != S.cur_pack) {
                 fft_local_mu(tid, nt, A, S.mt, S.lam, mu);
                 S.held = 1;
                 S.cur_lo = A.lo;
                 S.cur_hi = A.hi;
+                S.cur_pack = A.pack;
             }
             fft_tile<kFftRL>(tid, nt, t, A, S.mt, S.mt3, S.lam, S.phin, tl, mu, S.mu_tile);
             break;
@@ -606,7 +608,7 @@ __global__ __launch_bounds__(kThreads) void k_persistent(PersistArgs P, const ui
     copy_words(tid, nt, lam, g_lam, 1024);
     __syncthreads();
     build_mt3(tid, nt, mt, mt3);  // visible after the item loop's first barrier
-    ItemBlock S{mt, lam, work, mu_tile, mt3, phin, g_phi, g_psi, g_ctab, 0, ~0u, ~0u, kPhiNone};
+    ItemBlock S{mt, lam, work, mu_tile, mt3, phin, g_phi, g_psi, g_ctab, 0, ~0u, ~0u, kPhiNone, ~0u};
     int o = -1;
     for (int r = 0; r < P.nranks; ++r) {
         const uint64_t end = P.rank_first[r + 1];
@@ -683,7 +685,7 @@ __global__ __launch_bounds__(kThreads) void k_single(SingleArgs P, const uint8_t
     __syncthreads();
     build_mt3(tid, nt, mt, mt3);
     __syncthreads();
-    ItemBlock S{mt, lam, work, mu_tile, mt3, phin, g_phi, g_psi, g_ctab, 0, ~0u, ~0u, kPhiNone};
+    ItemBlock S{mt, lam, work, mu_tile, mt3, phin, g_phi, g_psi, g_ctab, 0, ~0u, ~0u, kPhiNone, ~0u};
     for (int o = 0; o < P.nops; ++o) {
         const DevOp D = P.ops[o];
         for (uint64_t t = 0; t < D.tiles; ++t) run_item(tid, nt, S, D, t);
@@ -1572,6 +1574,7 @@ int server_iterate(gf2x_server* S, bool& launched) {
         const gf2x_server::Req& r = S->active[0];
         PlanParams pp = S->ctx->params;
         pp.bc_small = 1;
+        pp.fft_pack_min_tiles = (uint32_t)S->ctx->ncu;
         plan_mul(direct_ops, S->ctx->pool, pp, make_sizes(r.na, r.nb, r.w), r.a, r.b, r.c, S->arena + r.off);
     }
     S->it_ops.clear();
@@ -1768,6 +1771,7 @@ int tune_time(gf2x_ctx* ctx, TuneBuffers& T, const PlanParams& pp, int M, int co
 PlanParams single_params(const gf2x_ctx* ctx) {
     PlanParams pp = ctx->params;
     pp.bc_small = 1;
+    pp.fft_pack_min_tiles = (uint32_t)ctx->ncu;
     return pp;
 }
 

@@ -332,12 +332,19 @@ struct FftPass {
     uint4* dst;       // the whole transform; blocks are at (coset0 + c) << log_m
     uint32_t log_m, lo, hi, log_tc;
     uint32_t ncosets, coset0, inverse, phi_in;
-    uint32_t log_total, pad0, pad1, pad2;  // log_total: log2 of the whole transform's length
+    uint32_t log_total;  // log2 of the whole transform's length
+    uint32_t pack;       // a one-pass transform (lo = 0, hi = log_m): 2^pack cosets per tile
+    uint32_t pad1, pad2;
 };
 
 AFFT_HD uint64_t fft_tiles(const FftPass& A) {
-    return (uint64_t)A.ncosets << ((A.log_m - A.hi) + (A.lo - A.log_tc));
+    return (uint64_t)(A.ncosets >> A.pack) << ((A.log_m - A.hi) + (A.lo - A.log_tc));
 }
+
+// Row bits of a tile: the layer range, and for a one-pass transform of
+// cosets packed 2^pack to a tile, the coset bits above it (the multipliers
+// of those rows differ only by their global index, which the row bits carry).
+AFFT_HD int fft_row_bits(const FftPass& A) { return (int)(A.hi - A.lo + A.pack); }
 
 // Multiplication mode of a multiplier of at most w bits: 0 GF(256), 1
 // TGF(2^16), 3 TGF(2^32) with a high TGF(2^16) half in GF(256) (w <= 24), 2
@@ -420,7 +427,7 @@ AFFT_HD uint4 fft_mu(const uint4* mu, int li, uint32_t b) {
 template <int RL, bool INV>
 AFFT_HD void fft_step(int tid, int nt, const FftPass& A, int i0, const uint8_t* mt, const uint2* mt3, uint4* tl,
                       const uint4* mu) {
-    const uint32_t nel = 1u << (A.hi - A.lo + A.log_tc);
+    const uint32_t nel = 1u << (A.hi - A.lo + A.pack + A.log_tc);
     const uint32_t groups = nel >> RL;
     const uint32_t tcm = (1u << A.log_tc) - 1;
     const int h0 = i0 - (int)A.lo;
@@ -470,14 +477,14 @@ AFFT_HD void fft_step(int tid, int nt, const FftPass& A, int i0, const uint8_t* 
 // the same for every tile of the pass (written here), and each tile adds its
 // own tile part (fft_tile_layers).  li = i - lo is the local layer.
 AFFT_HD void fft_local_mu(int tid, int nt, const FftPass& A, const uint8_t* mt, const uint32_t* lam, uint4* mu) {
-    const int rlog = (int)(A.hi - A.lo);
+    const int nlay = (int)(A.hi - A.lo), rlog = fft_row_bits(A);
     for (int E = tid; E < kMuLoN + kMuHiN; E += nt) {
         const bool hi = E >= kMuLoN;
         const int F = hi ? E - kMuLoN : E;
         int li = 0;
         while (li + 1 < kFftTileLog && (hi ? mu_hi_off(li + 1) : mu_lo_off(li + 1)) <= F) ++li;
         const uint32_t x = (uint32_t)(F - (hi ? mu_hi_off(li) : mu_lo_off(li)));
-        if (li >= rlog) continue;
+        if (li >= nlay) continue;
         const int nb = rlog - li - 1;
         const int lob = nb < 6 ? nb : 6;
         if (x >= (1u << (hi ? nb - lob : lob))) continue;
@@ -499,12 +506,12 @@ AFFT_HD FftTileGeom fft_geom(const FftPass& A, uint64_t tile) {
     const uint64_t cb = tile & (ncb - 1);
     const uint64_t rest = tile >> (A.lo - A.log_tc);
     const uint64_t outer = rest & (nouter - 1);
-    const uint64_t coset = rest >> (A.log_m - A.hi);
+    const uint64_t coset = (rest >> (A.log_m - A.hi)) << A.pack;
     FftTileGeom G;
     G.base_p = (outer << A.hi) | (cb << A.log_tc);
     G.gbase = ((uint64_t)A.coset0 + coset) << A.log_m;
     G.s_hi = G.gbase | (outer << A.hi);
-    G.nel = 1u << (A.hi - A.lo + A.log_tc);
+    G.nel = 1u << (A.hi - A.lo + A.pack + A.log_tc);
     return G;
 }
 
@@ -516,10 +523,10 @@ AFFT_HD uint64_t fft_elem_index(const FftPass& A, const FftTileGeom& G, uint32_t
 // of its converted word (fft_word, fft_word128), else the element of the
 // spectrum (fft_spec).  phin is the table of the pass's mode.
 AFFT_HD uint64_t fft_word(const FftPass& A, const FftTileGeom& G, uint32_t e) {
-    return ((const uint64_t*)A.src)[fft_elem_index(A, G, e)];
+    return ((const uint64_t*)A.src)[fft_elem_index(A, G, e) & ((1ull << A.log_m) - 1)];
 }
 AFFT_HD uint4 fft_word128(const FftPass& A, const FftTileGeom& G, uint32_t e) {
-    return ((const uint4*)A.src)[fft_elem_index(A, G, e)];
+    return ((const uint4*)A.src)[fft_elem_index(A, G, e) & ((1ull << A.log_m) - 1)];
 }
 AFFT_HD uint4 fft_spec(const FftPass& A, const FftTileGeom& G, uint32_t e) {
     return A.dst[G.gbase | fft_elem_index(A, G, e)];
@@ -537,7 +544,7 @@ AFFT_HD uint4 fft_load(const FftPass& A, const uint4* phin, const FftTileGeom& G
 template <int RL>
 AFFT_HD void fft_tile_layers(int tid, int nt, const FftPass& A, const FftTileGeom& G, const uint8_t* mt,
                              const uint2* mt3, const uint32_t* lam, uint4* tl, uint4* mu, uint4* mu_tile) {
-    const int rlog = (int)(A.hi - A.lo);
+    const int rlog = (int)(A.hi - A.lo), rbits = fft_row_bits(A);
     for (int li = tid; li < rlog; li += nt) {
         int i = (int)A.lo + li;
         uint32_t lv = 0;
@@ -549,7 +556,7 @@ AFFT_HD void fft_tile_layers(int tid, int nt, const FftPass& A, const FftTileGeo
     for (int E = tid; E < kMuHiN; E += nt) {
         int li = 0;
         while (li + 1 < kFftTileLog && mu_hi_off(li + 1) <= E) ++li;
-        const int y = E - mu_hi_off(li), nb = rlog - li - 1;
+        const int y = E - mu_hi_off(li), nb = rbits - li - 1;
         if (li < rlog && y < (1 << (nb > 6 ? nb - 6 : 0))) mu[kMuHiCur + E] = xor4(mu[kMuHiBase + E], mu_tile[li]);
     }
     AFFT_SYNC();
@@ -558,7 +565,7 @@ AFFT_HD void fft_tile_layers(int tid, int nt, const FftPass& A, const FftTileGeo
     // h0 <= 6, the 64 threads of a wave then own exactly the 64 2^R rows from
     // 64 2^R w on, so between two such steps of equal R the exchange stays
     // inside each wave: a wave-level sync replaces the workgroup barrier.
-    const uint32_t nel = 1u << (A.hi - A.lo + A.log_tc);
+    const uint32_t nel = 1u << (A.hi - A.lo + A.pack + A.log_tc);
     auto wave_owned = [&](int d, int& Rd) {
         const int r = rlog - d;
         Rd = r >= RL ? RL : r;

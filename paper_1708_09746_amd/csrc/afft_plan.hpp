@@ -126,6 +126,11 @@ struct PlanParams {
     int word_bits = 64;
     // 1: BasisCvt on 32 KiB tiles (single products; see kBcSmallShift)
     int bc_small = 0;
+    // a one-pass transform's cosets are packed into tiles only while at
+    // least this many tiles remain (0: as many to a tile as fit; batches and
+    // the server, whose launches hold the tiles of many products; single
+    // products keep one tile per CU at least)
+    uint32_t fft_pack_min_tiles = 0;
     const uint32_t* lam = nullptr;
     const uint8_t* mt = nullptr;
     PlanParams() {
@@ -294,6 +299,16 @@ inline void emit_fft_block(std::vector<Op>& ops, const PlanParams& pp, const voi
         A.coset0 = coset0;
         A.inverse = inverse ? 1u : 0u;
         A.log_total = (uint32_t)log_total;
+        // a transform done in one pass that fills less than a tile: as many
+        // cosets to a tile as fit (an aligned run of them: the tile's row bits
+        // then carry the cosets' global index bits)
+        if (nr == 1 && log_m < kFftTileLog) {
+            uint32_t pk = 0;
+            while (log_m + (int)pk < kFftTileLog && ((ncosets | coset0) & ((2u << pk) - 1)) == 0 &&
+                   (ncosets >> (pk + 1)) >= pp.fft_pack_min_tiles)
+                ++pk;
+            A.pack = pk;
+        }
         ops.push_back(op);
     }
 }
