@@ -115,6 +115,23 @@ int gf2x_mul_dev(gf2x_ctx *ctx, const uint64_t *a, uint64_t na_bits, const uint6
  * gaps but runs every stage on one compute unit. */
 int gf2x_set_single_launch(gf2x_ctx *ctx, int max_log2n);
 
+/* Which BasisCvt sub-conversions run inside FFT passes (Alg. 3's recursion:
+ * the conversion of the index bits [q, q + mb) commutes with the FFT layers
+ * above them, with changeRepr and with the conversions of other bits, so a
+ * pass whose tile rows hold those bits can run it before its layers, or, in
+ * an inverse transform, its inverse after them).  Bits of mask: 1 in forward
+ * transforms, 2 in inverse transforms, 4 split a transform's strided passes at
+ * BasisCvt's top level when that keeps their number; only transforms of at
+ * most 2^max_log2n points fuse, and truncated ones never do.  Default: mask 0
+ * (every conversion its own pass), bound 20.  A fused conversion's layer
+ * sweeps cost the FFT kernel about what the conversion's own pass costs (both
+ * are bound by LDS, not by the HBM round trip that fusion saves): products of
+ * 2^28 and 2^29 bits run 0.5-1.5 % slower with mask 6 at any bound, batches
+ * and served requests within 2 % either way, so it stays off.  Results are the
+ * same for every setting; EINVAL for a mask outside 0..7 or a bound outside
+ * 0..32. */
+int gf2x_set_fusion(gf2x_ctx *ctx, int mask, int max_log2n);
+
 /* For callers that cannot allocate device memory (code under HIP graph
  * capture, tight serving loops, harnesses that forbid hipMalloc): c = a * b as
  * gf2x_mul_dev computes it (same result, same word width and truncation

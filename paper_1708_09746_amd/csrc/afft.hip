@@ -2308,6 +2308,15 @@ int gf2x_set_single_launch(gf2x_ctx* ctx, int max_log2n) {
     return GF2X_OK;
 }
 
+int gf2x_set_fusion(gf2x_ctx* ctx, int mask, int max_log2n) {
+    if (check_ctx(ctx)) return GF2X_EINVAL;
+    if (mask < 0 || mask > 7) return fail(ctx, GF2X_EINVAL, "fusion mask outside 0..7");
+    if (max_log2n < 0 || max_log2n > PlanParams::kMaxM) return fail(ctx, GF2X_EINVAL, "fusion size bound outside 0..32");
+    ctx->params.fuse_bc = mask;
+    ctx->params.fuse_max_log = max_log2n;
+    return GF2X_OK;
+}
+
 int gf2x_frobenius_log2n(uint64_t na_bits, uint64_t nb_bits) {
     if (!na_bits || !nb_bits) return -1;
     return frob_sizes(na_bits, nb_bits).m;

@@ -53,19 +53,37 @@ struct PackOp {
 
 AFFT_HD uint64_t pack_tiles(const PackOp& P) { return (P.ndst + kPackTile - 1) / kPackTile; }
 
+// Word k of an operand of nbits bits: its bits at and above nbits cleared,
+// zero past its last word.
+AFFT_HD uint64_t operand_word(const uint64_t* src, uint64_t nbits, uint64_t k) {
+    const uint64_t nw = (nbits + 63) / 64;
+    if (k >= nw) return 0;
+    uint64_t w = src[k];
+    if (k == nw - 1 && (nbits % 64)) w &= ~0ull >> (64 - nbits % 64);
+    return w;
+}
+
 AFFT_HD void pack_tile(int tid, int nt, uint64_t tile, const PackOp& P) {
-    uint64_t nw = (P.nbits + 63) / 64;
-    uint64_t mask = (P.nbits % 64) ? (~0ull >> (64 - P.nbits % 64)) : ~0ull;
     for (int e = tid; e < kPackTile; e += nt) {
         uint64_t k = tile * kPackTile + e;
         if (k >= P.ndst) break;
-        uint64_t w = 0;
-        if (k < nw) {
-            w = P.src[k];
-            if (k == nw - 1) w &= mask;
-        }
-        P.dst[k] = w;
+        P.dst[k] = operand_word(P.src, P.nbits, k);
     }
+}
+
+// Element e of a split operand read in place of its packed copy: the word
+// (w = 64) or the two words 2e, 2e + 1 (w = 128).
+template <typename T>
+AFFT_HD T operand_elem(const void* src, uint64_t nbits, uint64_t e);
+template <>
+AFFT_HD uint64_t operand_elem<uint64_t>(const void* src, uint64_t nbits, uint64_t e) {
+    return operand_word((const uint64_t*)src, nbits, e);
+}
+template <>
+AFFT_HD uint4 operand_elem<uint4>(const void* src, uint64_t nbits, uint64_t e) {
+    const uint64_t lo = operand_word((const uint64_t*)src, nbits, 2 * e);
+    const uint64_t hi = operand_word((const uint64_t*)src, nbits, 2 * e + 1);
+    return make_uint4((uint32_t)lo, (uint32_t)(lo >> 32), (uint32_t)hi, (uint32_t)(hi >> 32));
 }
 
 // --------------------------------------------------------------- BasisCvt
@@ -73,7 +91,9 @@ AFFT_HD void pack_tile(int tid, int nt, uint64_t tile, const PackOp& P) {
 // in LDS (BcTileOp, contiguous or strided "column" tiles), the VarSubs layers
 // of a large block run as one class pass (BcClassOp).  A layer that fits
 // neither runs as two global passes (BcLayerOp, which = 0 then 1; reversed for
-// the inverse).
+// the inverse).  The first tile op of a forward conversion may read the
+// operand itself (src, src_bits; see operand_elem) in place of its packed
+// copy, and writes the converted elements to data.
 
 template <typename T>
 AFFT_HD T zero_elem();
@@ -137,6 +157,8 @@ struct BcTileOp {
     uint32_t inverse;  // run the layers (and their two parts) in reverse
     uint32_t nlayers;
     const BcLayer* layers;  // nlayers entries (device memory shared by all ops)
+    const void* src;        // non-null: gather from the operand (src_bits bits)
+    uint64_t src_bits;
 };
 
 struct BcLayerOp {
@@ -185,7 +207,10 @@ template <typename T>
 AFFT_HD void bc_tile(int tid, int nt, uint64_t tile, const BcTileOp& B, T* lds) {
     const BcTileGeom G = bc_tile_geom(B, tile);
     T* g = (T*)B.data + G.base;
-    for (uint32_t e = tid; e < G.ne; e += nt) lds[e] = g[bc_tile_off(B, e)];
+    if (B.src)
+        for (uint32_t e = tid; e < G.ne; e += nt) lds[e] = operand_elem<T>(B.src, B.src_bits, G.base + bc_tile_off(B, e));
+    else
+        for (uint32_t e = tid; e < G.ne; e += nt) lds[e] = g[bc_tile_off(B, e)];
     AFFT_SYNC();
     bc_tile_layers<T>(tid, nt, B, G.ne, lds);
     for (uint32_t e = tid; e < G.ne; e += nt) g[bc_tile_off(B, e)] = lds[e];
@@ -326,6 +351,16 @@ AFFT_HD void bc_class_tile(int tid, int nt, uint64_t tile, const BcClassOp& C, T
 // changeRepr into TGF(2^128); 2 / 3 it reads 128-bit words and keeps the low /
 // high TGF(2^128) half of their changeRepr into TGF(2^256) (w = 128: the
 // spectrum is two planes of halves, each transformed alone, Prop. 2).
+//
+// A pass may also run a BasisCvt sub-conversion on its tile (bc_n layers in
+// tile-element units): the conversion of 2^mb units of 2^q elements (Alg. 3
+// on index bits [q, q + mb), the same map for every value of the other
+// bits) commutes with every FFT layer at or above q + mb (such a layer acts
+// on a higher bit, with a multiplier that depends only on still higher bits),
+// with changeRepr (GF(2)-linear on each element), and with the BasisCvt ops
+// on disjoint bits that follow it in Alg. 3's recursion.  A forward pass whose
+// rows hold those bits runs it on its tile before its layers, an inverse pass
+// (its inverse) after them.
 enum : uint32_t { kPhiNone = 0, kPhi64 = 1, kPhi128Lo = 2, kPhi128Hi = 3 };
 struct FftPass {
     const void* src;  // phi_in: the words (2^log_m of them); else == dst
@@ -334,7 +369,9 @@ struct FftPass {
     uint32_t ncosets, coset0, inverse, phi_in;
     uint32_t log_total;  // log2 of the whole transform's length
     uint32_t pack;       // a one-pass transform (lo = 0, hi = log_m): 2^pack cosets per tile
-    uint32_t pad1, pad2;
+    uint32_t bc_n, pad;
+    const BcLayer* bc_layers;
+    uint64_t src_bits;   // phi_in with src_bits > 0: src is the operand itself (operand_elem)
 };
 
 AFFT_HD uint64_t fft_tiles(const FftPass& A) {
@@ -523,10 +560,12 @@ AFFT_HD uint64_t fft_elem_index(const FftPass& A, const FftTileGeom& G, uint32_t
 // of its converted word (fft_word, fft_word128), else the element of the
 // spectrum (fft_spec).  phin is the table of the pass's mode.
 AFFT_HD uint64_t fft_word(const FftPass& A, const FftTileGeom& G, uint32_t e) {
-    return ((const uint64_t*)A.src)[fft_elem_index(A, G, e) & ((1ull << A.log_m) - 1)];
+    const uint64_t k = fft_elem_index(A, G, e) & ((1ull << A.log_m) - 1);
+    return A.src_bits ? operand_elem<uint64_t>(A.src, A.src_bits, k) : ((const uint64_t*)A.src)[k];
 }
 AFFT_HD uint4 fft_word128(const FftPass& A, const FftTileGeom& G, uint32_t e) {
-    return ((const uint4*)A.src)[fft_elem_index(A, G, e) & ((1ull << A.log_m) - 1)];
+    const uint64_t k = fft_elem_index(A, G, e) & ((1ull << A.log_m) - 1);
+    return A.src_bits ? operand_elem<uint4>(A.src, A.src_bits, k) : ((const uint4*)A.src)[k];
 }
 AFFT_HD uint4 fft_spec(const FftPass& A, const FftTileGeom& G, uint32_t e) {
     return A.dst[G.gbase | fft_elem_index(A, G, e)];
@@ -537,10 +576,24 @@ AFFT_HD uint4 fft_load(const FftPass& A, const uint4* phin, const FftTileGeom& G
     return fft_spec(A, G, e);
 }
 
+// The BasisCvt layers fused into a pass, on its tile (nel elements), in the
+// direction of the pass; every thread's tile writes are visible at the end.
+AFFT_HD void fft_tile_bc(int tid, int nt, const FftPass& A, uint32_t nel, uint4* tl) {
+    const int n = (int)A.bc_n;
+    for (int li = 0; li < n; ++li) {
+        const BcLayer L = A.bc_layers[A.inverse ? n - 1 - li : li];
+        for (int part = 0; part < 2; ++part) {
+            bc_part_lds<uint4>(tid, nt, tl, nel, L, A.inverse ? 1 - part : part);
+            AFFT_SYNC();
+        }
+    }
+}
+
 // Layers [lo, hi) of one tile already in LDS (tl); mu holds the pass's local
 // mu-set tables (fft_local_mu), completed here with the tile part of every
 // layer (mu_tile, up to 32 entries).  RL: layers kept in registers per LDS
-// round trip.
+// round trip.  A fused BasisCvt (bc_n > 0) runs first (forward) or last
+// (inverse).
 template <int RL>
 AFFT_HD void fft_tile_layers(int tid, int nt, const FftPass& A, const FftTileGeom& G, const uint8_t* mt,
                              const uint2* mt3, const uint32_t* lam, uint4* tl, uint4* mu, uint4* mu_tile) {
@@ -560,12 +613,13 @@ AFFT_HD void fft_tile_layers(int tid, int nt, const FftPass& A, const FftTileGeo
         if (li < rlog && y < (1 << (nb > 6 ? nb - 6 : 0))) mu[kMuHiCur + E] = xor4(mu[kMuHiBase + E], mu_tile[li]);
     }
     AFFT_SYNC();
+    const uint32_t nel = 1u << (A.hi - A.lo + A.pack + A.log_tc);
+    if (A.bc_n && !A.inverse) fft_tile_bc(tid, nt, A, nel, tl);
     // A step of R layers from local layer h0 gives thread g the rows of group
     // g; with contiguous rows (log_tc = 0), one group per thread and
     // h0 <= 6, the 64 threads of a wave then own exactly the 64 2^R rows from
     // 64 2^R w on, so between two such steps of equal R the exchange stays
     // inside each wave: a wave-level sync replaces the workgroup barrier.
-    const uint32_t nel = 1u << (A.hi - A.lo + A.pack + A.log_tc);
     auto wave_owned = [&](int d, int& Rd) {
         const int r = rlog - d;
         Rd = r >= RL ? RL : r;
@@ -600,6 +654,7 @@ AFFT_HD void fft_tile_layers(int tid, int nt, const FftPass& A, const FftTileGeo
         else
             AFFT_SYNC();
     }
+    if (A.bc_n && A.inverse) fft_tile_bc(tid, nt, A, nel, tl);
 }
 
 // One whole tile: load, layers, store (the sequential form; the GPU kernel

@@ -131,6 +131,18 @@ struct PlanParams {
     // the server, whose launches hold the tiles of many products; single
     // products keep one tile per CU at least)
     uint32_t fft_pack_min_tiles = 0;
+    // BasisCvt sub-conversions inside the FFT passes whose rows hold their
+    // index bits (FftPass): kFuseForward in forward transforms, kFuseInverse
+    // in inverse ones, kFuseAlign splits the strided passes of a transform at
+    // BasisCvt's top level when that keeps their number
+    // (transforms of at most 2^fuse_max_log points only).  Off by default:
+    // BasisCvt's layer sweeps are bound by LDS and barriers, as the FFT
+    // layers are by LDS lookups, so a fused conversion costs the FFT kernel
+    // about what its own pass costs, and the HBM round trip it saves was
+    // already overlapped
+    enum : int { kFuseForward = 1, kFuseInverse = 2, kFuseAlign = 4 };
+    int fuse_bc = 0;
+    int fuse_max_log = 20;
     const uint32_t* lam = nullptr;
     const uint8_t* mt = nullptr;
     PlanParams() {
@@ -143,6 +155,14 @@ struct PlanParams {
     int rows(int M) const { return fft_col_rows_log[std::min(std::max(M, 0), kMaxM)]; }
 };
 
+// An FFT pass (once per plane) that can run one BasisCvt sub-conversion on
+// its tile: its rows are index bits [lo, hi), at tile-element bit log_tc.
+struct BcSlot {
+    std::vector<FftPass*> passes;
+    int lo, hi, log_tc, nel_log;
+    bool used;
+};
+
 struct BcPlanner {
     void* data;
     int wide;
@@ -150,6 +170,80 @@ struct BcPlanner {
     int cap_log;        // LDS capacity of a tile, log2 elements
     const LayerPool* pool;
     std::vector<Op> ops;
+    std::vector<BcSlot>* slots = nullptr;
+    struct Fused {
+        int m, log_u, slot;
+    };
+    std::vector<Fused> fused;  // conversions assigned to slots (assign_slots)
+
+    // a conversion of 2^m units of 2^log_u elements that one tile op runs
+    bool tileable(int m, int log_u) const {
+        return m + log_u <= cap_log || (log_u > 0 && m + std::min(log_u, 3) <= cap_log);
+    }
+    static int top_k(int m) {
+        int K = 1;
+        while (2 * K < m) K *= 2;
+        return K;
+    }
+
+    // Which conversions run inside FFT passes: the nodes cvt() can reach (the
+    // split ones and the tile-sized ones below them) whose bits [log_u,
+    // log_u + m) lie in a slot's rows, one per slot, the largest first, never
+    // a node together with one inside it.
+    void assign_slots(int m_root) {
+        if (!slots) return;
+        struct Node {
+            int m, log_u, parent;
+            bool taken, below;  // assigned; some node inside it assigned
+        };
+        std::vector<Node> nodes;
+        auto collect = [&](auto&& self, int m, int log_u, int parent) -> void {
+            if (m <= 1) return;
+            const int id = (int)nodes.size();
+            nodes.push_back(Node{m, log_u, parent, false, false});
+            if (tileable(m, log_u)) return;
+            const int K = top_k(m);
+            self(self, m - K, log_u + K, id);
+            self(self, K, log_u, id);
+        };
+        collect(collect, m_root, 0, -1);
+        std::vector<int> order(nodes.size());
+        for (size_t i = 0; i < order.size(); ++i) order[i] = (int)i;
+        std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return nodes[x].m > nodes[y].m; });
+        for (int id : order) {
+            Node& nd = nodes[id];
+            if (nd.below) continue;
+            bool above = false;
+            for (int p = nd.parent; p >= 0; p = nodes[p].parent) above = above || nodes[p].taken;
+            if (above) continue;
+            for (size_t k = 0; k < slots->size(); ++k) {
+                BcSlot& sl = (*slots)[k];
+                if (sl.used || nd.log_u < sl.lo || nd.log_u + nd.m > sl.hi) continue;
+                sl.used = true;
+                nd.taken = true;
+                for (int p = nd.parent; p >= 0; p = nodes[p].parent) nodes[p].below = true;
+                fused.push_back(Fused{nd.m, nd.log_u, (int)k});
+                break;
+            }
+        }
+    }
+
+    // run the conversion inside its pass if assign_slots gave it one
+    bool fuse(int m, int log_u) {
+        for (const Fused& f : fused) {
+            if (f.m != m || f.log_u != log_u) continue;
+            const BcSlot& sl = (*slots)[f.slot];
+            const int u = log_u - sl.lo + sl.log_tc;
+            uint32_t nl = 0;
+            const BcLayer* L = pool->get(m, u, nl);
+            for (FftPass* A : sl.passes) {
+                A->bc_layers = L;
+                A->bc_n = nl;
+            }
+            return true;
+        }
+        return false;
+    }
 
     // the layers of BasisCvt on 2^m units of 2^log_u LDS elements, on tiles
     void tile_pass(int log_rows, int log_stride, int log_tc, int m, int log_u) {
@@ -181,6 +275,7 @@ struct BcPlanner {
     // BasisCvt on every aligned block of 2^m units of 2^log_u elements.
     void cvt(int m, int log_u) {
         if (m <= 1) return;
+        if (fuse(m, log_u)) return;
         const int blk_log = m + log_u;
         if (blk_log <= cap_log) {
             // whole blocks fit: a contiguous tile holds 2^(T - blk_log) of them
@@ -194,8 +289,7 @@ struct BcPlanner {
             tile_pass(m, log_u, log_tc, m, log_tc);  // row units scaled to LDS elements
             return;
         }
-        int K = 1;
-        while (2 * K < m) K *= 2;
+        const int K = top_k(m);
         uint64_t P = (1ull << K) - 1;
         uint64_t Q = ((1ull << m) + P - 1) / P;
         if (Q <= (1ull << cap_log)) {
@@ -255,12 +349,26 @@ inline std::vector<std::pair<int, int>> fft_pass_ranges(int M, const PlanParams&
     int rem = M - bottom;
     int rows = std::max(1, std::min(pp.rows(M), kFftTileLog));
     int ncol = (rem + rows - 1) / rows;
+    // BasisCvt's top level (Alg. 3: K the largest power of two below M)
+    // converts index bits [K, M); a top pass of exactly those rows runs it
+    // (FftPass), if that keeps the number of passes and leaves the top pass
+    // at least 16 columns
+    int K = 1;
+    while (2 * K < M) K *= 2;
+    int top = 0;
+    if ((pp.fuse_bc & PlanParams::kFuseAlign) && M <= pp.fuse_max_log && ncol >= 2 && K > bottom && M - K <= kFftTileLog - 4 && K - bottom >= ncol - 1 &&
+        (K - bottom + ncol - 2) / (ncol - 1) <= kFftTileLog) {
+        top = M - K;
+        rem -= top;
+        --ncol;
+    }
     int lo = bottom;
     for (int c = 0; c < ncol; ++c) {
         int sz = rem / ncol + (c < rem % ncol ? 1 : 0);
         col.push_back({lo, lo + sz});
         lo += sz;
     }
+    if (top) col.push_back({K, M});
     std::vector<std::pair<int, int>> r;
     r.push_back({0, bottom});
     for (auto& p : col) r.push_back(p);
@@ -419,6 +527,69 @@ inline void emit_pack(std::vector<Op>& ops, const uint64_t* src, uint64_t nbits,
     ops.push_back(op);
 }
 
+// Slots of the FFT passes in `ffts` (the same pass list once per plane).
+inline std::vector<BcSlot> bc_slots(const std::vector<std::vector<Op>*>& ffts) {
+    std::vector<BcSlot> sl;
+    if (ffts.empty()) return sl;
+    const std::vector<Op>& f0 = *ffts[0];
+    for (size_t k = 0; k < f0.size(); ++k) {
+        if (f0[k].kind != OpKind::Fft) continue;
+        const FftPass& A = f0[k].fft;
+        BcSlot b{{}, (int)A.lo, (int)A.hi, (int)A.log_tc, (int)(A.hi - A.lo + A.pack + A.log_tc), false};
+        for (std::vector<Op>* v : ffts) b.passes.push_back(&(*v)[k].fft);
+        sl.push_back(b);
+    }
+    return sl;
+}
+
+// BasisCvt of 2^m elements at `data` planned around FFT passes (BcSlot):
+// the sub-conversions whose bits lie in a pass's rows run in that pass, the
+// rest are returned as ops, in forward order.
+// (dir: PlanParams::kFuseForward or kFuseInverse, the direction of the
+// transforms)
+inline std::vector<Op> plan_bc_around(const LayerPool& pool, const PlanParams& pp, void* data, int wide, int m,
+                                      const std::vector<std::vector<Op>*>& ffts, int dir) {
+    const int shift = !pp.bc_small ? 0 : m <= kBcTinyMaxLog ? kBcTinyShift : kBcSmallShift;
+    BcPlanner P{data, wide, 1ull << m, (wide ? kBcTileLog128 : kBcTileLog64) - shift, &pool, {}};
+    std::vector<BcSlot> sl;
+    int log_total = 0;
+    for (const std::vector<Op>* v : ffts)
+        for (const Op& op : *v)
+            if (op.kind == OpKind::Fft) log_total = std::max(log_total, (int)op.fft.log_total);
+    if ((pp.fuse_bc & dir) && log_total <= pp.fuse_max_log) {
+        sl = bc_slots(ffts);
+        P.slots = &sl;
+        P.assign_slots(m);
+    }
+    P.cvt(m, 0);
+    return P.ops;
+}
+
+// How the operand (nbits bits at src) enters its forward transform, the
+// words at `words` (nwords 64-bit words) being its converted copy: a first
+// BasisCvt op on contiguous tiles reads it in place of a packed copy, and with
+// no BasisCvt op left the changeRepr passes read it; otherwise a pack op
+// copies it (a class pass gathers rows far apart, where reading the operand
+// itself, with its bounds and mask per word, measured slower than the copy).
+// Appends the pack op (if any) and the BasisCvt ops.
+inline void emit_operand_bc(std::vector<Op>& ops, std::vector<Op>& bc, const std::vector<std::vector<Op>*>& ffts,
+                            const uint64_t* src, uint64_t nbits, uint64_t* words, uint64_t nwords) {
+    if (nbits && !bc.empty() && bc[0].kind == OpKind::BcTile && bc[0].bct.log_stride == 0) {
+        bc[0].bct.src = src;
+        bc[0].bct.src_bits = nbits;
+    } else if (nbits && bc.empty()) {
+        for (std::vector<Op>* v : ffts)
+            for (Op& op : *v)
+                if (op.kind == OpKind::Fft && op.fft.phi_in != kPhiNone) {
+                    op.fft.src = src;
+                    op.fft.src_bits = nbits;
+                }
+    } else {
+        emit_pack(ops, src, nbits, words, nwords);
+    }
+    ops.insert(ops.end(), bc.begin(), bc.end());
+}
+
 inline void emit_pmul(std::vector<Op>& ops, const uint4* a, const uint4* b, uint4* c, uint64_t n,
                       uint64_t n_out = 0) {
     Op op{};
@@ -464,12 +635,18 @@ inline Workspace workspace_for(const Sizes& s) {
 // entirely below M are full transforms, the one holding M is truncated.
 inline void emit_forward(std::vector<Op>& ops, const LayerPool& pool, const PlanParams& pp, const uint64_t* src,
                          uint64_t nbits, uint64_t* words, int m_op, uint4* spec, int m, uint64_t M) {
-    emit_pack(ops, src, nbits, words, 1ull << m_op);
-    emit_bc(ops, pool, words, 0, m_op, 0, pp.bc_small);
     if (M == (1ull << m)) {
-        emit_fft_forward(ops, pp, words, spec, m_op, m - m_op);
+        std::vector<Op> fft;
+        emit_fft_forward(fft, pp, words, spec, m_op, m - m_op);
+        std::vector<Op> bc = plan_bc_around(pool, pp, words, 0, m_op, {&fft}, PlanParams::kFuseForward);
+        emit_operand_bc(ops, bc, {&fft}, src, nbits, words, 1ull << m_op);
+        ops.insert(ops.end(), fft.begin(), fft.end());
         return;
     }
+    // a truncated transform mixes the top bits of the converted words before
+    // its FFT blocks (spine steps): BasisCvt runs whole, before it
+    emit_pack(ops, src, nbits, words, 1ull << m_op);
+    emit_bc(ops, pool, words, 0, m_op, 0, pp.bc_small);
     const uint64_t full = M >> m_op, rem = M - (full << m_op);
     if (full) emit_fft_block(ops, pp, words, spec, m_op, 0, (uint32_t)full, m, false);
     if (rem) {
@@ -485,11 +662,16 @@ inline void emit_forward(std::vector<Op>& ops, const LayerPool& pool, const Plan
 // there.
 inline void emit_inverse(std::vector<Op>& ops, const LayerPool& pool, const PlanParams& pp, uint4* spec, int m,
                          uint64_t M, uint64_t* out, uint64_t nc_bits) {
-    if (M == (1ull << m))
-        emit_fft_inverse(ops, pp, spec, m);
-    else
+    if (M == (1ull << m)) {
+        std::vector<Op> fft;
+        emit_fft_inverse(fft, pp, spec, m);
+        const std::vector<Op> bc = plan_bc_around(pool, pp, spec, 1, m, {&fft}, PlanParams::kFuseInverse);
+        ops.insert(ops.end(), fft.begin(), fft.end());
+        append_bc(ops, bc, 1);
+    } else {
         emit_inv_spine(ops, pp, spec, 0, m, M, m);  // pointmul wrote zeros at M and beyond
-    emit_bc(ops, pool, spec, 1, m, 1, pp.bc_small);
+        emit_bc(ops, pool, spec, 1, m, 1, pp.bc_small);
+    }
     emit_psi(ops, spec, 1ull << m, out, nc_bits);
 }
 
@@ -510,11 +692,11 @@ inline void plan_mul128(std::vector<Op>& ops, const LayerPool& pool, const PlanP
     uint4* sb = (uint4*)(ws + w.off_sb);
     auto forward = [&](const uint64_t* src, uint64_t nbits, uint4* words, int m_op, uint4* spec) {
         std::vector<Op> pre, pl[2];
-        emit_pack(pre, src, nbits, (uint64_t*)words, 2ull << m_op);
-        emit_bc(pre, pool, words, 1, m_op, 0, pp.bc_small);
         for (int h = 0; h < 2; ++h)
             emit_fft_block(pl[h], pp, words, spec + h * N, m_op, 0, 1u << (s.m - m_op), s.m, false,
                            h ? kPhi128Hi : kPhi128Lo);
+        std::vector<Op> bc = plan_bc_around(pool, pp, words, 1, m_op, {&pl[0], &pl[1]}, PlanParams::kFuseForward);
+        emit_operand_bc(pre, bc, {&pl[0], &pl[1]}, src, nbits, (uint64_t*)words, 2ull << m_op);
         uint32_t l = 0;
         for (Op op : pre) {
             op.level = l++;
@@ -545,7 +727,8 @@ inline void plan_mul128(std::vector<Op>& ops, const LayerPool& pool, const PlanP
     std::vector<Op> inv[2];
     for (int h = 0; h < 2; ++h) {
         emit_fft_inverse(inv[h], pp, sb + h * N, s.m);
-        emit_bc(inv[h], pool, sb + h * N, 1, s.m, 1, pp.bc_small);
+        const std::vector<Op> bc = plan_bc_around(pool, pp, sb + h * N, 1, s.m, {&inv[h]}, PlanParams::kFuseInverse);
+        append_bc(inv[h], bc, 1);
     }
     for (size_t q = 0; q < inv[0].size(); ++q)
         for (int h = 0; h < 2; ++h) {

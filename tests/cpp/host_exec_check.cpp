@@ -496,6 +496,31 @@ int main(int argc, char** argv) {
         bad += !check_product(g, 1 << 22, 1 << 22);
         bad += !check_product(g, (1 << 23) - 77, (1 << 22) + 5);
     }
+    if (what == "all" || what == "fusion") {
+        // BasisCvt sub-conversions inside FFT passes: every mask, products of
+        // one and several passes (single-product and batch tiles), the 128-bit
+        // words, a batch
+        PP.fuse_max_log = 32;
+        const uint64_t fixed[][2] = {{1, 1},     {65, 64},      {1000, 999},  {64 * 33, 64 * 31}, {1 << 16, 1 << 16},
+                                     {100000, 3}, {1 << 20, 1 << 20}, {1 << 21, 1 << 19}, {1 << 22, (1 << 22) - 3}};
+        for (int mask = 1; mask <= 7; ++mask) {
+            PP.fuse_bc = mask;
+            for (int small = 0; small < 2; ++small) {
+                PP.bc_small = small;
+                for (auto& p : fixed) bad += !check_product(g, p[0], p[1]);
+                for (int i = 0; i < 8; ++i)
+                    bad += !check_product(g, 1 + g() % (1ull << (1 + g() % 18)), 1 + g() % (1ull << (1 + g() % 18)));
+            }
+            PP.bc_small = 0;
+            PP.word_bits = 128;
+            for (int i = 0; i < 4; ++i)
+                bad += !check_product(g, 1 + g() % (1ull << (1 + g() % 18)), 1 + g() % (1ull << (1 + g() % 18)));
+            PP.word_bits = 64;
+            bad += !check_batch(g, 12);
+        }
+        PP.fuse_bc = 0;
+        PP.fuse_max_log = 20;
+    }
     if (what == "all" || what == "batch") bad += !check_batch(g, 60);
     if (what == "all" || what == "trunc") {
         PP.trunc_min_log = 1;

@@ -1,6 +1,7 @@
 """Host logic on the CPU: the planner's op lists (products, batches,
 truncated transforms, BasisCvt passes, products with 128-bit words over
-TGF(2^256), the simple variant of Alg. 4, the Frobenius-partition variant of App. C) executed sequentially with the same
+TGF(2^256), the simple variant of Alg. 4, the Frobenius-partition variant of
+App. C, BasisCvt sub-conversions run inside FFT passes) executed sequentially with the same
 tile bodies the kernels run, compared with the oracle; the kernels' block to
 tile order visits every tile once (no GPU)."""
 import os
@@ -33,7 +34,8 @@ def host_exec(tmp_path_factory):
     return str(exe)
 
 
-@pytest.mark.parametrize("what", ["products", "batch", "trunc", "basiscvt", "xcd", "w128", "simple", "frobenius"])
+@pytest.mark.parametrize("what", ["products", "batch", "trunc", "basiscvt", "xcd", "w128", "simple", "frobenius",
+                                  "fusion"])
 def test_host_execution_matches_oracle(host_exec, what):
     out = subprocess.run([host_exec, what], capture_output=True, text=True, timeout=600)
     assert out.returncode == 0, out.stdout + out.stderr
