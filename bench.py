@@ -277,7 +277,7 @@ def bench_batched(ctx, njobs=4096, reps=5):
         res.pop(f"persistent_graph{tag}_launches")
         out.pop(f"staged_graph{tag}")
         out.pop(f"persistent_graph{tag}")
-    ctx.set_truncation(0, 22)
+    ctx.set_truncation(3, 23, 2)  # the default
     best = min(out, key=out.get)
     res["best"] = best
     res["speedup_vs_loop"] = round(t_loop / out[best], 2)
@@ -414,7 +414,7 @@ def bench_serving(ctx, nreq=10000, fracs=(0.1, 0.25, 0.5, 0.75, 0.9, 0.9, 0.9, 1
     # multiple of 2^(m - 3) points, transforms of 2^8 points and more)
     ctx.set_truncation(3, 8)
     rate, st = saturate(2, "adaptive")
-    ctx.set_truncation(0, 22)
+    ctx.set_truncation(3, 23, 2)  # the default
     res["saturation_truncated_products_per_s"] = {"adaptive_L2": round(rate, 1),
                                                   "setting": "levels=3, min_log2n=8"}
     log(f"bench: serving saturation adaptive_L2 with truncation: {rate:.0f} products/s")

@@ -375,19 +375,25 @@ int gf2x_autotune(gf2x_ctx *ctx, int m_lo, int m_hi, int reps, gf2x_tune_rec *ou
  * A product of n_c = ceil(na/64) + ceil(nb/64) - 1 word coefficients needs
  * N = 2^m >= n_c evaluation points; with truncation the two forward
  * transforms evaluate only the first M points, n_c rounded up to a multiple
- * of 2^max(m - levels, 6), pointmul runs on M points, and the inverse
+ * of 2^g, g = max(m - levels, 6), and further to the next M whose count of
+ * 2^g blocks has at most max_terms set bits (each set bit is a full block of
+ * the recursion below; 0: any count), pointmul runs on M points, and the inverse
  * recovers the coefficients from those M values (the coefficients at M and
  * beyond are zero by the degree bound): the butterflies of Alg. 1 restricted
  * to the needed points, and their inverse run on the values below M and the
  * known coefficients above it.  Only transforms of at least 2^min_log2n
  * points are truncated: each step of the recursion is a pass of its own,
  * which smaller transforms do not repay.  levels = 0 turns truncation off
- * (M = N); the default is 3 levels from 2^22 points on.  The product bits
- * are the same either way. */
+ * (M = N).  The default, 3 levels from 2^23 points on with at most 2 terms,
+ * follows single-product timings on one MI355X: with n_c just above N/2,
+ * M = 5/8 N takes 10 % (2^23 points) to 16 % (2^25) less time than M = N;
+ * M = 3/4 N 5-11 % less; M = 7/8 N (three terms) 5-9 % more; at 2^22 points
+ * and below truncation gains nothing or loses.  The product bits are the same
+ * either way. */
 
 /* Truncation for products planned afterwards: levels in 0..16, min_log2n in
- * 1..32 (EINVAL outside). */
-int gf2x_set_truncation(gf2x_ctx *ctx, int levels, int min_log2n);
+ * 1..32, max_terms in 0..32 (EINVAL outside). */
+int gf2x_set_truncation(gf2x_ctx *ctx, int levels, int min_log2n, int max_terms);
 /* Points M a product of these sizes is evaluated at on ctx (0 if empty). */
 uint64_t gf2x_eval_points(gf2x_ctx *ctx, uint64_t na_bits, uint64_t nb_bits);
 

@@ -115,7 +115,7 @@ def lib():
             "gf2x_set_schedule": (i32, [vp, i32, i32, i32]),
             "gf2x_get_schedule": (i32, [vp, i32, ctypes.POINTER(i32), ctypes.POINTER(i32)]),
             "gf2x_autotune": (i32, [vp, i32, i32, i32, ctypes.POINTER(TuneRec)]),
-            "gf2x_set_truncation": (i32, [vp, i32, i32]),
+            "gf2x_set_truncation": (i32, [vp, i32, i32, i32]),
             "gf2x_eval_points": (u64, [vp, u64, u64]),
             "gf2x_set_word_bits": (i32, [vp, i32]),
             "gf2x_get_word_bits": (i32, [vp]),
@@ -326,10 +326,11 @@ class Context:
         return v.value
 
     # ---- truncated transforms
-    def set_truncation(self, levels: int, min_log2n: int = 22):
+    def set_truncation(self, levels: int, min_log2n: int = 23, max_terms: int = 2):
         """Evaluate products of at least 2^min_log2n points at n_c rounded up
-        to a multiple of 2^(m - levels) points (levels 0: all N)."""
-        self._check(lib().gf2x_set_truncation(self._h, levels, min_log2n), "gf2x_set_truncation")
+        to a multiple of 2^(m - levels) points, and further to at most
+        max_terms set bits in blocks (0: any; levels 0: all N)."""
+        self._check(lib().gf2x_set_truncation(self._h, levels, min_log2n, max_terms), "gf2x_set_truncation")
 
     def eval_points(self, na_bits: int, nb_bits: int) -> int:
         return int(lib().gf2x_eval_points(self._h, na_bits, nb_bits))

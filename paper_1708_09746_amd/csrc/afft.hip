@@ -2752,12 +2752,14 @@ int gf2x_autotune(gf2x_ctx* ctx, int m_lo, int m_hi, int reps, gf2x_tune_rec* ou
     return GF2X_OK;
 }
 
-int gf2x_set_truncation(gf2x_ctx* ctx, int levels, int min_log2n) {
+int gf2x_set_truncation(gf2x_ctx* ctx, int levels, int min_log2n, int max_terms) {
     if (check_ctx(ctx)) return GF2X_EINVAL;
     if (levels < 0 || levels > 16) return fail(ctx, GF2X_EINVAL, "truncation levels outside 0..16");
     if (min_log2n < 1 || min_log2n > 32) return fail(ctx, GF2X_EINVAL, "truncation size outside 1..32");
+    if (max_terms < 0 || max_terms > 32) return fail(ctx, GF2X_EINVAL, "truncation terms outside 0..32");
     ctx->params.trunc_levels = levels;
     ctx->params.trunc_min_log = min_log2n;
+    ctx->params.trunc_max_terms = max_terms;
     return GF2X_OK;
 }
 

@@ -110,8 +110,11 @@ struct PlanParams {
     int8_t fft_bottom_log[kMaxM + 1];
     int8_t fft_col_rows_log[kMaxM + 1];
     // Truncated transforms: a product of n_c = n_a + n_b - 1 word coefficients
-    // is evaluated at M points, n_c rounded up to a multiple of
-    // 2^max(m - trunc_levels, kTruncMinLog) (M = N when trunc_levels = 0 or
+    // is evaluated at M points, n_c rounded up to a multiple of 2^g,
+    // g = max(m - trunc_levels, kTruncMinLog), and further to the next M whose
+    // count of 2^g blocks has at most trunc_max_terms set bits (0: any): each
+    // set bit is a full block plus spine steps, and a third one (M = 7/8 N)
+    // measured slower than no truncation (M = N when trunc_levels = 0 or
     // m < trunc_min_log).
     // The spine steps need the multipliers on the host: the 32 x 32 table
     // lam[i][t] = s_i(v_t) and the GF(256) product table (both owned by the
@@ -121,7 +124,8 @@ struct PlanParams {
     // do not repay).
     static constexpr int kTruncMinLog = 6;
     int trunc_levels = 3;
-    int trunc_min_log = 22;
+    int trunc_min_log = 23;
+    int trunc_max_terms = 2;
     // word width of Split: 64 (TGF(2^128)) or 128 (TGF(2^256), never truncated)
     int word_bits = 64;
     // 1: BasisCvt on 32 KiB tiles (single products; see kBcSmallShift)
@@ -440,7 +444,10 @@ inline uint64_t eval_points(const Sizes& s, const PlanParams& pp) {
     const int g = std::max(s.m - pp.trunc_levels, PlanParams::kTruncMinLog);
     if (g >= s.m) return N;
     const uint64_t nc = s.n_a + s.n_b - 1;
-    return ((nc + (1ull << g) - 1) >> g) << g;
+    uint64_t q = (nc + (1ull << g) - 1) >> g;  // blocks of 2^g points, at most 2^(m - g)
+    if (pp.trunc_max_terms > 0)
+        while (__builtin_popcountll(q) > pp.trunc_max_terms) q += q & (~q + 1);
+    return q << g;
 }
 
 // lambda of layer i for the block starting at global index s (a multiple of 2^(i+1))

@@ -526,11 +526,14 @@ int main(int argc, char** argv) {
         PP.trunc_min_log = 1;
         for (int i = 0; i < 300; ++i) {
             PP.trunc_levels = i % 9;
+            PP.trunc_max_terms = (i / 9) % 4;  // any count, 1, 2, 3 terms
             bad += !check_product(g, 1 + g() % (1ull << (1 + g() % 17)), 1 + g() % (1ull << (1 + g() % 17)));
         }
         PP.trunc_levels = 3;
+        PP.trunc_max_terms = 0;
         bad += !check_batch(g, 40);
-        PP.trunc_min_log = 22;
+        PP.trunc_max_terms = 2;
+        PP.trunc_min_log = 23;
     }
     if (what == "all" || what == "w128") {
         // Split into 128-bit words, products over TGF(2^256)

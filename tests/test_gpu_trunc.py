@@ -53,7 +53,7 @@ SIZES = [
 
 @pytest.mark.parametrize("levels", [0, 1, 3, 8])
 def test_truncated_products(ctx, levels):
-    ctx.set_truncation(levels, 1)
+    ctx.set_truncation(levels, 1, 0)
     try:
         for na, nb in SIZES:
             a = inputs.random_poly(0x7A0 + na % 101, na)
@@ -71,11 +71,37 @@ def test_truncated_products(ctx, levels):
             got = host(ctx.mul(dev(a), na, dev(b), nb))
             assert np.array_equal(got, oracle.mul(a, na, b, nb)), (levels, na, nb, M, N)
     finally:
-        ctx.set_truncation(3, 22)
+        ctx.set_truncation(3, 23, 2)
+
+
+# M rounded up to at most two terms: 5/8 and 3/4 stay, 7/8 (and 15/16) go to N
+TERM_SIZES = [(64 * 1280, 64 * 1280), (64 * 1536, 64 * 1536 + 7), (64 * 1792, 64 * 1792),
+              (64 * 1920 + 3, 64 * 1900), (64 * 40000 + 3, 64 * 30000), ((1 << 20) + 64, (1 << 19) + 64)]
+
+
+def test_truncation_terms(ctx):
+    ctx.set_truncation(3, 1, 2)
+    try:
+        for na, nb in TERM_SIZES:
+            nc = words(na) + words(nb) - 1
+            N = 1 << max(1, (nc - 1).bit_length())
+            g = max((N.bit_length() - 1) - 3, 6)
+            q = -(-nc // (1 << g))
+            while bin(q).count("1") > 2:
+                q += q & -q
+            M = ctx.eval_points(na, nb)
+            assert M == q << g and nc <= M <= N, (na, nb, M)
+            a = inputs.random_poly(0x7B0 + na % 101, na)
+            b = inputs.random_poly(0x7B1 + nb % 103, nb)
+            say(f"case truncation terms: {na} x {nb} bits, N {N}, M {M}")
+            got = host(ctx.mul(dev(a), na, dev(b), nb))
+            assert np.array_equal(got, oracle.mul(a, na, b, nb)), (na, nb, M, N)
+    finally:
+        ctx.set_truncation(3, 23, 2)
 
 
 def test_truncated_batch_matches_single_calls(ctx):
-    ctx.set_truncation(3, 1)
+    ctx.set_truncation(3, 1, 0)
     spec = inputs.batch_workload(64, 10, 18)
     jobs, refs = [], []
     for na, nb, sa, sb in spec:
@@ -94,7 +120,7 @@ def test_truncated_batch_matches_single_calls(ctx):
         B.close()
         for (da, na, db, nb, c), ref in zip(jobs, refs):
             assert np.array_equal(host(c), ref), (persistent, na, nb)
-    ctx.set_truncation(3, 22)
+    ctx.set_truncation(3, 23, 2)
 
 
 def test_truncation_range_and_stage_calls(ctx):
@@ -105,9 +131,14 @@ def test_truncation_range_and_stage_calls(ctx):
     with pytest.raises(P.Gf2xError):
         ctx.set_truncation(3, 0)
     assert ctx.eval_points(0, 100) == 0
-    # by default only transforms of 2^22 points and more are truncated
+    with pytest.raises(P.Gf2xError):
+        ctx.set_truncation(3, 23, 33)
+    # by default only transforms of 2^23 points and more are truncated, to M
+    # of at most two terms
     assert ctx.eval_points(64 * 1280, 64 * 1280) == 4096
     assert ctx.eval_points(64 * 5 * 2**19, 64 * 5 * 2**19) == 5 * 2**20
+    assert ctx.eval_points(64 * 5 * 2**18, 64 * 5 * 2**18) == 2**22  # 2^22 points: not truncated
+    assert ctx.eval_points(64 * 7 * 2**19, 64 * 7 * 2**19) == 2**23  # 7/8: three terms, not truncated
     # the stage entry points always transform all 2^log2n points
     na = 64 * 1500
     a = inputs.random_poly(0x7A9, na)
@@ -115,7 +146,7 @@ def test_truncation_range_and_stage_calls(ctx):
     full = host(ctx.forward(dev(a), na, 12))
     ctx.set_truncation(0)
     again = host(ctx.forward(dev(a), na, 12))
-    ctx.set_truncation(3, 22)
+    ctx.set_truncation(3, 23, 2)
     assert np.array_equal(full, again)
 
 
@@ -134,7 +165,7 @@ def test_truncated_batch_at_configured_lengths(levels):
     staged and persistent, every job against the oracle."""
     c_ = P.Context(0)
     try:
-        c_.set_truncation(levels, 8)
+        c_.set_truncation(levels, 8, 0)
         spec = inputs.batch_workload(256, 12, 20)
         host_ops, jobs = [], []
         for na, nb, sa, sb in spec:
@@ -167,7 +198,7 @@ def test_truncated_server_at_configured_lengths():
     waves on the adaptive engine; every result against the oracle."""
     c_ = P.Context(0)
     try:
-        c_.set_truncation(3, 8)
+        c_.set_truncation(3, 8, 0)
         reqs = []
         for na, nb, sa, sb, _u in inputs.serve_workload(40, 2, 10, 22):
             a, b = inputs.random_poly(sa, na), inputs.random_poly(sb, nb)
