@@ -107,7 +107,9 @@ __global__ __launch_bounds__(kThreads) void k_fft(FftPass A, const uint8_t* g_mt
     FftTileGeom G = fft_geom(A, xcd_tile(t, gridDim.x, ntiles));
     // prefetch registers: the words of a changeRepr pass (PHI), else elements
     std::conditional_t<PHI == 1, uint64_t, uint4> pre[kFftPrefetch];
-    auto fetch = [&](const FftTileGeom& Gx) {
+    // (both lambdas inlined: called out of line, the prefetch registers go
+    // through scratch and the LDS tables through generic addresses)
+    auto fetch = [&](const FftTileGeom& Gx) __attribute__((always_inline)) {
 #pragma unroll
         for (int j = 0; j < kFftPrefetch; ++j) {
             const uint32_t e = min(tid + j * kThreads, Gx.nel - 1);
@@ -119,7 +121,7 @@ __global__ __launch_bounds__(kThreads) void k_fft(FftPass A, const uint8_t* g_mt
                 pre[j] = fft_spec(A, Gx, e);
         }
     };
-    auto fill = [&]() {
+    auto fill = [&]() __attribute__((always_inline)) {
 #pragma unroll
         for (int j = 0; j < kFftPrefetch; ++j) {
             if constexpr (PHI == 1)
