@@ -100,6 +100,34 @@ def test_truncation_terms(ctx):
         ctx.set_truncation(3, 23, 2)
 
 
+# the default setting at the sizes it acts on: 2^23 points with M = 5N/8 and
+# 3N/4, 2^24 points with M = 5N/8, and 7N/8 left untruncated
+@pytest.mark.parametrize("nc_words,want_frac", [(int(1.02 * 2**22), 5 / 8), (int(1.45 * 2**22), 3 / 4),
+                                                (int(1.03 * 2**23), 5 / 8), (int(1.6 * 2**22), 1)])
+def test_default_truncation_large(ctx, nc_words, want_frac):
+    import random
+    na = nb = 64 * ((nc_words + 1) // 2)
+    nc = words(na) + words(nb) - 1
+    N = 1 << (nc - 1).bit_length()
+    ctx.set_truncation(3, 23, 2)
+    M = ctx.eval_points(na, nb)
+    assert M == int(want_frac * N), (M, N)
+    a = inputs.random_poly(0x7C0 + nc_words % 97, na)
+    b = inputs.random_poly(0x7C1 + nc_words % 89, nb)
+    da, db = dev(a), dev(b)
+    say(f"case default truncation: {na} x {nb} bits, N {N}, M {M}")
+    got = host(ctx.mul(da, na, db, nb))
+    ctx.set_truncation(0, 23, 2)
+    try:
+        full = host(ctx.mul(da, na, db, nb))
+    finally:
+        ctx.set_truncation(3, 23, 2)
+    assert np.array_equal(got, full)
+    rng = random.Random(nc_words)
+    for k in [0, 1, got.size // 2, got.size - 1] + [rng.randrange(got.size) for _ in range(4)]:
+        assert int(got[k]) == oracle.word(a, na, b, nb, k), k
+
+
 def test_truncated_batch_matches_single_calls(ctx):
     ctx.set_truncation(3, 1, 0)
     spec = inputs.batch_workload(64, 10, 18)
