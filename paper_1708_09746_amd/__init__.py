@@ -224,7 +224,7 @@ class Context:
         """Products of at most 2^max_log2n points in one launch (-1: never)."""
         self._check(lib().gf2x_set_single_launch(self._h, int(max_log2n)), "gf2x_set_single_launch")
 
-    def set_fusion(self, mask: int, max_log2n: int = 20):
+    def set_fusion(self, mask: int, max_log2n: int = 11):
         """Which BasisCvt sub-conversions run inside FFT passes (bits: 1
         forward transforms, 2 inverse transforms, 4 pass split aligned to
         BasisCvt's top level), for transforms of at most 2^max_log2n points."""

@@ -139,14 +139,15 @@ struct PlanParams {
     // index bits (FftPass): kFuseForward in forward transforms, kFuseInverse
     // in inverse ones, kFuseAlign splits the strided passes of a transform at
     // BasisCvt's top level when that keeps their number
-    // (transforms of at most 2^fuse_max_log points only).  Off by default:
-    // BasisCvt's layer sweeps are bound by LDS and barriers, as the FFT
-    // layers are by LDS lookups, so a fused conversion costs the FFT kernel
-    // about what its own pass costs, and the HBM round trip it saves was
-    // already overlapped
+    // (transforms of at most 2^fuse_max_log points only).  By default only
+    // transforms of one small pass fuse (at most 2^11 points), where the
+    // launches saved dominate: above that BasisCvt's layer sweeps, bound by
+    // LDS and barriers as the FFT layers are by LDS lookups, cost the FFT
+    // kernel about what their own pass costs, and the HBM round trip saved
+    // was already overlapped
     enum : int { kFuseForward = 1, kFuseInverse = 2, kFuseAlign = 4 };
-    int fuse_bc = 0;
-    int fuse_max_log = 20;
+    int fuse_bc = kFuseForward | kFuseInverse | kFuseAlign;
+    int fuse_max_log = 11;
     const uint32_t* lam = nullptr;
     const uint8_t* mt = nullptr;
     PlanParams() {

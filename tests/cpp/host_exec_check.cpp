@@ -497,9 +497,10 @@ int main(int argc, char** argv) {
         bad += !check_product(g, (1 << 23) - 77, (1 << 22) + 5);
     }
     if (what == "all" || what == "fusion") {
-        // BasisCvt sub-conversions inside FFT passes: every mask, products of
-        // one and several passes (single-product and batch tiles), the 128-bit
-        // words, a batch
+        // BasisCvt sub-conversions inside FFT passes at every size (the default
+        // fuses transforms of at most 2^11 points only): every mask, products
+        // of one and several passes (single-product and batch tiles), the
+        // 128-bit words, a batch
         PP.fuse_max_log = 32;
         const uint64_t fixed[][2] = {{1, 1},     {65, 64},      {1000, 999},  {64 * 33, 64 * 31}, {1 << 16, 1 << 16},
                                      {100000, 3}, {1 << 20, 1 << 20}, {1 << 21, 1 << 19}, {1 << 22, (1 << 22) - 3}};
@@ -518,8 +519,8 @@ int main(int argc, char** argv) {
             PP.word_bits = 64;
             bad += !check_batch(g, 12);
         }
-        PP.fuse_bc = 0;
-        PP.fuse_max_log = 20;
+        PP.fuse_bc = 7;  // the default
+        PP.fuse_max_log = 11;
     }
     if (what == "all" || what == "batch") bad += !check_batch(g, 60);
     if (what == "all" || what == "trunc") {

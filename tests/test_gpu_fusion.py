@@ -1,5 +1,6 @@
 """BasisCvt sub-conversions run inside FFT passes (gf2x_set_fusion): for every
-mask, products at ragged sizes of one and several FFT passes bit-exact
+mask (0: none, also for the small products the default fuses) at every
+size, products at ragged sizes of one and several FFT passes bit-exact
 against the oracle, with 128-bit words too, a batch staged and persistent
 against the oracle job by job, the 2^28-bit product against its recorded
 SHA-256, and the setting's error paths."""
@@ -42,7 +43,7 @@ SIZES = [(1, 1), (65, 64), (1000, 999), (64 * 33, 64 * 31), (5000, 70), (1 << 16
          (64 * 2047 + 5, 64 * 2049 + 11), (1 << 20, 1 << 20), ((1 << 21) + 7, 1 << 19), ((1 << 22) - 9, 1 << 22)]
 
 
-@pytest.mark.parametrize("mask", [1, 2, 4, 6, 7])
+@pytest.mark.parametrize("mask", [0, 1, 2, 4, 6, 7])
 def test_fused_products(ctx, mask):
     ctx.set_fusion(mask, 32)
     try:
@@ -54,7 +55,7 @@ def test_fused_products(ctx, mask):
             ctx.mul_into(dev(a), na, dev(b), nb, c)
             assert np.array_equal(host(c), oracle.mul(a, na, b, nb, threads=8)), (mask, na, nb)
     finally:
-        ctx.set_fusion(0, 20)
+        ctx.set_fusion(7, 11)  # the default
 
 
 @pytest.mark.parametrize("mask", [3, 7])
@@ -71,7 +72,7 @@ def test_fused_products_128(ctx, mask):
             assert np.array_equal(host(c), oracle.mul(a, na, b, nb, threads=8)), (mask, na, nb)
     finally:
         ctx.set_word_bits(64)
-        ctx.set_fusion(0, 20)
+        ctx.set_fusion(7, 11)  # the default
 
 
 @pytest.mark.parametrize("persistent", [False, True])
@@ -98,7 +99,7 @@ def test_fused_batch(ctx, persistent):
         for k, (j, w) in enumerate(zip(jobs, want)):
             assert np.array_equal(host(j[4]), w), k
     finally:
-        ctx.set_fusion(0, 20)
+        ctx.set_fusion(7, 11)  # the default
 
 
 def test_fused_headline_product(ctx):
@@ -115,7 +116,7 @@ def test_fused_headline_product(ctx):
         ctx.mul_into(dev(a), n, dev(b), n, c)
         got = host(c)
     finally:
-        ctx.set_fusion(0, 20)
+        ctx.set_fusion(7, 11)  # the default
     assert hashlib.sha256(got.tobytes()).hexdigest() == g[0][6]
 
 
@@ -126,4 +127,4 @@ def test_fusion_setting_errors(ctx):
         ctx.set_fusion(-1, 20)
     with pytest.raises(P.Gf2xError):
         ctx.set_fusion(1, 33)
-    ctx.set_fusion(0, 20)
+    ctx.set_fusion(7, 11)  # the default
