@@ -82,17 +82,13 @@ static_assert(16 * ((1 << kFftTileLog) + kMuEntries) + 65536 + 4096 + 16 * 32 + 
               "FFT kernels fit in LDS");
 
 // PHI: 0 the pass reads the spectrum, 1 64-bit words (kPhi64), 2 128-bit
-// words (kPhi128Lo / kPhi128Hi)
+// words (kPhi128Lo / kPhi128Hi).  The body of one block of a pass launched
+// over nblk blocks (block bid of them); inlined into each kernel, so that the
+// LDS pointers keep their address space.
 template <int PHI>
-__global__ __launch_bounds__(kThreads) void k_fft(FftPass A, const uint8_t* g_mt, const uint32_t* g_lam,
-                                                  const uint4* g_phi) {
-    __shared__ __align__(16) uint8_t mt[65536];
-    __shared__ uint32_t lam[1024];
-    __shared__ uint4 tl[1 << kFftTileLog];
-    __shared__ uint4 mu[kMuEntries];
-    __shared__ uint4 mu_tile[32];
-    __shared__ uint2 mt3[768];
-    __shared__ uint4 phin[kPhiNib];
+__device__ __forceinline__ void fft_pass_block(const FftPass& A, uint32_t bid, uint32_t nblk, const uint8_t* g_mt,
+                                               const uint32_t* g_lam, const uint4* g_phi, uint8_t* mt, uint32_t* lam,
+                                               uint4* tl, uint4* mu, uint4* mu_tile, uint2* mt3, uint4* phin) {
     const uint32_t tid = threadIdx.x;
     const int nt = kThreads;  // the launch uses kThreads threads per block
     copy_words(tid, nt, (uint32_t*)mt, (const uint32_t*)g_mt, 16384);
@@ -102,9 +98,9 @@ __global__ __launch_bounds__(kThreads) void k_fft(FftPass A, const uint8_t* g_mt
     build_mt3(tid, nt, mt, mt3);
     fft_local_mu(tid, nt, A, mt, lam, mu);
     const uint64_t ntiles = fft_tiles(A);
-    uint64_t t = blockIdx.x;
+    uint64_t t = bid;
     if (t >= ntiles) return;
-    FftTileGeom G = fft_geom(A, xcd_tile(t, gridDim.x, ntiles));
+    FftTileGeom G = fft_geom(A, xcd_tile(t, nblk, ntiles));
     // prefetch registers: the words of a changeRepr pass (PHI), else elements
     std::conditional_t<PHI == 1, uint64_t, uint4> pre[kFftPrefetch];
     // (both lambdas inlined: called out of line, the prefetch registers go
@@ -138,9 +134,9 @@ __global__ __launch_bounds__(kThreads) void k_fft(FftPass A, const uint8_t* g_mt
         __syncthreads();
         // the next tile; the last one fetches its own tile again, unused, so
         // that every iteration issues the same loads
-        const uint64_t tn = t + gridDim.x;
+        const uint64_t tn = t + nblk;
         const bool more = tn < ntiles;
-        const FftTileGeom Gn = fft_geom(A, xcd_tile(more ? tn : t, gridDim.x, ntiles));
+        const FftTileGeom Gn = fft_geom(A, xcd_tile(more ? tn : t, nblk, ntiles));
         fetch(Gn);
         fft_tile_layers<kFftRL>(tid, nt, A, G, mt, mt3, lam, tl, mu, mu_tile);
 #pragma unroll
@@ -154,6 +150,36 @@ __global__ __launch_bounds__(kThreads) void k_fft(FftPass A, const uint8_t* g_mt
         t = tn;
         G = Gn;
     }
+}
+
+#define AFFT_FFT_LDS                          \
+    __shared__ __align__(16) uint8_t mt[65536]; \
+    __shared__ uint32_t lam[1024];            \
+    __shared__ uint4 tl[1 << kFftTileLog];    \
+    __shared__ uint4 mu[kMuEntries];          \
+    __shared__ uint4 mu_tile[32];             \
+    __shared__ uint2 mt3[768];                \
+    __shared__ uint4 phin[kPhiNib]
+
+template <int PHI>
+__global__ __launch_bounds__(kThreads) void k_fft(FftPass A, const uint8_t* g_mt, const uint32_t* g_lam,
+                                                  const uint4* g_phi) {
+    AFFT_FFT_LDS;
+    fft_pass_block<PHI>(A, blockIdx.x, gridDim.x, g_mt, g_lam, g_phi, mt, lam, tl, mu, mu_tile, mt3, phin);
+}
+
+// Two independent passes of the same kind in one launch (the two operands'
+// forward transforms of a small product, whose passes hold few tiles each):
+// blocks [0, nA) run A, the rest B.
+template <int PHI>
+__global__ __launch_bounds__(kThreads) void k_fft_pair(FftPass A, FftPass B, uint32_t nA, const uint8_t* g_mt,
+                                                       const uint32_t* g_lam, const uint4* g_phi) {
+    AFFT_FFT_LDS;
+    if (blockIdx.x < nA)
+        fft_pass_block<PHI>(A, blockIdx.x, nA, g_mt, g_lam, g_phi, mt, lam, tl, mu, mu_tile, mt3, phin);
+    else
+        fft_pass_block<PHI>(B, blockIdx.x - nA, gridDim.x - nA, g_mt, g_lam, g_phi, mt, lam, tl, mu, mu_tile, mt3,
+                            phin);
 }
 
 __global__ __launch_bounds__(kThreads) void k_pmul(PmulOp P, const uint8_t* g_mt, const uint32_t* g_ctab) {
@@ -1024,13 +1050,33 @@ void op_traffic(const Op& op, gf2x_trace_rec& r) {
 
 // `may_trace` false: no launch is traced whatever the trace mask says (tracing
 // creates events, and some callers must not have anything created for them).
-int run_ops(gf2x_ctx* ctx, const std::vector<Op>& ops, hipStream_t st, bool may_trace = true) {
+// `pair_levels`: the list's levels are dependency levels (plan_mul), and two
+// consecutive FFT passes of one level whose tiles fit one round of the grid
+// run in one launch (one trace record covers both).
+int run_ops(gf2x_ctx* ctx, const std::vector<Op>& ops, hipStream_t st, bool may_trace = true,
+            bool pair_levels = false) {
     const uint64_t ncu = (uint64_t)ctx->ncu;
-    for (const Op& op : ops) {
+    for (size_t oi = 0; oi < ops.size(); ++oi) {
+        const Op& op = ops[oi];
+        const Op* mate = nullptr;
+        if (pair_levels && op.kind == OpKind::Fft && oi + 1 < ops.size()) {
+            const Op& nx = ops[oi + 1];
+            if (nx.kind == OpKind::Fft && nx.level == op.level && nx.fft.phi_in == op.fft.phi_in &&
+                fft_tiles(op.fft) + fft_tiles(nx.fft) <= ncu)
+                mate = &nx;
+        }
         gf2x_ctx::Pending pend{};
         const bool traced = may_trace && ((ctx->trace_mask >> (int)op.kind) & 1u);
         if (traced) {
             op_traffic(op, pend.rec);
+            if (mate) {
+                gf2x_trace_rec r2{};
+                op_traffic(*mate, r2);
+                pend.rec.elements += r2.elements;
+                pend.rec.bytes_read += r2.bytes_read;
+                pend.rec.bytes_written += r2.bytes_written;
+                pend.rec.lookups += r2.lookups;
+            }
             hipError_t e = hipEventCreate(&pend.start);
             if (e == hipSuccess) e = hipEventCreate(&pend.stop);
             if (e != hipSuccess) return hip_fail(ctx, e, "trace event");
@@ -1063,7 +1109,19 @@ int run_ops(gf2x_ctx* ctx, const std::vector<Op>& ops, hipStream_t st, bool may_
                 break;
             }
             case OpKind::Fft:
-                if (op.fft.phi_in == kPhi64)
+                if (mate) {
+                    const uint32_t nA = (uint32_t)fft_tiles(op.fft);
+                    const dim3 g((unsigned)(nA + fft_tiles(mate->fft)));
+                    if (op.fft.phi_in == kPhi64)
+                        GF2X_LAUNCH(k_fft_pair<1>, g, op.fft, mate->fft, nA, (const uint8_t*)ctx->d_mt,
+                                    (const uint32_t*)ctx->d_lam, (const uint4*)ctx->d_phi);
+                    else if (op.fft.phi_in != kPhiNone)
+                        GF2X_LAUNCH(k_fft_pair<2>, g, op.fft, mate->fft, nA, (const uint8_t*)ctx->d_mt,
+                                    (const uint32_t*)ctx->d_lam, (const uint4*)ctx->d_phi);
+                    else
+                        GF2X_LAUNCH(k_fft_pair<0>, g, op.fft, mate->fft, nA, (const uint8_t*)ctx->d_mt,
+                                    (const uint32_t*)ctx->d_lam, (const uint4*)ctx->d_phi);
+                } else if (op.fft.phi_in == kPhi64)
                     GF2X_LAUNCH(k_fft<1>, dim3(grid_for(fft_tiles(op.fft), ncu)), op.fft,
                                 (const uint8_t*)ctx->d_mt, (const uint32_t*)ctx->d_lam, (const uint4*)ctx->d_phi);
                 else if (op.fft.phi_in != kPhiNone)
@@ -1103,6 +1161,7 @@ int run_ops(gf2x_ctx* ctx, const std::vector<Op>& ops, hipStream_t st, bool may_
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return hip_fail(ctx, e, "kernel launch");
         if (traced) ctx->trace.push_back(pend);
+        if (mate) ++oi;
     }
     return GF2X_OK;
 }
@@ -2140,7 +2199,22 @@ int mul_on(gf2x_ctx* ctx, const Sizes& s, const uint64_t* a, const uint64_t* b, 
     std::vector<Op> ops;
     size_t split[2] = {0, 0};
     plan_mul(ops, ctx->pool, single_params(ctx), s, a, b, c, ws, split);
-    if (s.m < kForkMinLog || !split[1]) return run_ops(ctx, ops, st);
+    if (!split[1]) return run_ops(ctx, ops, st);
+    if (s.m < kForkMinLog) {
+        // one stream: the two forward transforms interleaved level by level,
+        // so that their FFT passes of one level can share a launch
+        std::vector<Op> il;
+        il.reserve(ops.size());
+        size_t ia = 0, ib = split[0];
+        while (ia < split[0] || ib < split[1]) {
+            const uint32_t la = ia < split[0] ? ops[ia].level : ~0u, lb = ib < split[1] ? ops[ib].level : ~0u;
+            const uint32_t l = la < lb ? la : lb;
+            while (ia < split[0] && ops[ia].level == l) il.push_back(ops[ia++]);
+            while (ib < split[1] && ops[ib].level == l) il.push_back(ops[ib++]);
+        }
+        il.insert(il.end(), ops.begin() + split[1], ops.end());
+        return run_ops(ctx, il, st, true, true);
+    }
     // The two forward transforms are independent: b's runs on the second
     // stream, between a fork event recorded here and a join event that a's
     // continuation waits for.  Up to 2^kForkMaxLog points the whole transforms
