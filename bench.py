@@ -536,7 +536,7 @@ def bench_sizes(P, ctx, runs=50):
                      "fft_points": 1 << P.fft_log2(n, n)}
         # the kernels one call launches (the library's trace), and its product
         # against the oracle's recorded SHA-256
-        ctx.trace_begin(0x1FF)
+        ctx.trace_begin(0x3FF)
         c.fill_(-1)
         ctx.mul_into(a, n, b, n, c, stream)
         recs = ctx.trace_end()
@@ -550,7 +550,7 @@ def bench_sizes(P, ctx, runs=50):
             # the same call as one launch: a single block runs every stage
             ctx.set_single_launch(12)
             c.fill_(-1)
-            ctx.trace_begin(0x1FF)
+            ctx.trace_begin(0x3FF)
             ctx.mul_into(a, n, b, n, c, stream)
             one = ctx.trace_end()
             same = hashlib.sha256(c.cpu().numpy().tobytes()).hexdigest() == golden_sha(name)

@@ -278,7 +278,11 @@ int gf2x_frobenius_inverse_dev(gf2x_ctx *ctx, void *spec, int log2n, uint64_t *c
  * gf2x_trace_read() waits for them and returns one record per launch.  Kinds (bit = 1 << kind): 0 pack, 1 BasisCvt tile, 2 BasisCvt global
  * layer, 3 FFT pass, 4 pointmul, 5 changeRepr back + combine, 6 BasisCvt
  * VarSubs class pass, 7 truncated-transform step, 8 a whole product in one
- * launch (gf2x_set_single_launch: one block runs all its stages in order). */
+ * launch (gf2x_set_single_launch: one block runs all its stages in order), 9
+ * the last steps of a small product in one launch (pointmul, an inverse
+ * transform of one tile with its BasisCvt, changeRepr back and combine).
+ * Two FFT passes of one level of a small product (its two forward
+ * transforms) can share one launch and one record. */
 typedef struct {
     int kind;            /* one of the kinds above */
     uint64_t elements;   /* elements (words or 16-byte field elements) the launch covers */

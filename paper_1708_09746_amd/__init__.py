@@ -37,9 +37,9 @@ class TraceRec(ctypes.Structure):
 
 
 KIND_NAMES = ["pack", "basiscvt_tile", "basiscvt_layer", "fft_pass", "pointmul", "psi_combine", "basiscvt_class",
-              "spine", "whole_product"]
+              "spine", "whole_product", "product_tail"]
 KERNEL_OF_KIND = ["k_pack", "k_bc_tile", "k_bc_layer", "k_fft", "k_pmul", "k_psi", "k_bc_class", "k_spine",
-                  "k_single"]
+                  "k_single", "k_tail"]
 
 
 class BatchStats(ctypes.Structure):
@@ -359,7 +359,7 @@ class Context:
                  for k, _ in TuneRec._fields_} for r in out]
 
     # ---- tracing
-    def trace_begin(self, kind_mask: int = 0x1FF):
+    def trace_begin(self, kind_mask: int = 0x3FF):
         self._check(lib().gf2x_trace_begin(self._h, kind_mask), "gf2x_trace_begin")
 
     def trace_end(self):

@@ -44,7 +44,7 @@ def test_single_launch_products(ctx, na, nb):
     b = inputs.random_poly(0x51D + nb % 103, nb)
     da, db = dev(a), dev(b)
     say(f"case single launch {na}x{nb}")
-    ctx.trace_begin(0x1FF)
+    ctx.trace_begin(0x3FF)
     c = torch.full((P.out_words(na, nb),), -1, dtype=torch.int64, device="cuda")
     ctx.mul_into(da, na, db, nb, c)
     recs = ctx.trace_end()
@@ -67,7 +67,7 @@ def test_single_launch_boundary(ctx):
         a = inputs.random_poly(0x51E, na)
         da = dev(a)
         assert P.fft_log2(na, na) == m
-        ctx.trace_begin(0x1FF)
+        ctx.trace_begin(0x3FF)
         c = ctx.mul(da, na, da, na)
         recs = ctx.trace_end()
         assert (["k_single"] == [r["kernel"] for r in recs]) == single, recs
