@@ -927,6 +927,11 @@ struct gf2x_server {
 };
 
 
+// (defined below, with the single-product launchers; the serving engine's
+// light-load path uses it too)
+int run_product(gf2x_ctx* ctx, const std::vector<Op>& ops, const size_t* split, int m, hipStream_t st,
+                bool may_trace);
+
 namespace {
 
 struct DeviceGuard {
@@ -1686,12 +1691,16 @@ int server_iterate(gf2x_server* S, bool& launched) {
     // descriptor upload (its arena region fits either plan)
     const bool direct = idle && S->active.size() == 1 && S->active[0].next == 0;
     std::vector<Op> direct_ops;
+    size_t direct_split[2] = {0, 0};
+    int direct_m = 0;
     if (direct) {
         const gf2x_server::Req& r = S->active[0];
         PlanParams pp = S->ctx->params;
         pp.bc_small = 1;
         pp.fft_pack_min_tiles = (uint32_t)S->ctx->ncu;
-        plan_mul(direct_ops, S->ctx->pool, pp, make_sizes(r.na, r.nb, r.w), r.a, r.b, r.c, S->arena + r.off);
+        const Sizes sz = make_sizes(r.na, r.nb, r.w);
+        direct_m = sz.m;
+        plan_mul(direct_ops, S->ctx->pool, pp, sz, r.a, r.b, r.c, S->arena + r.off, direct_split);
     }
     S->it_ops.clear();
     S->it_rank.clear();
@@ -1748,9 +1757,9 @@ int server_iterate(gf2x_server* S, bool& launched) {
             S->free_events.push_back(w.second);
         }
         if (e != hipSuccess) return hip_fail(S->ctx, e, "serving: wait for the submitters' streams");
-        int rc = run_ops(S->ctx, direct_ops, st);
+        int rc = run_product(S->ctx, direct_ops, direct_split, direct_m, st, true);
         if (rc) return rc;
-        S->stats.launches += direct_ops.size();
+        S->stats.launches += direct_ops.size();  // ops (paired passes and a merged tail launch fewer)
         e = hipEventRecord(sl.ev, st);
         if (e != hipSuccess) return hip_fail(S->ctx, e, "serving event");
         ++S->stats.iterations;
@@ -2289,6 +2298,30 @@ int run_tail(gf2x_ctx* ctx, const std::vector<Op>& rest, hipStream_t st, bool ma
     return GF2X_OK;
 }
 
+// A product planned by plan_mul (split: the ends of the two forward
+// transforms) on one stream.  Below 2^kForkMinLog points the forward
+// transforms are interleaved level by level, so that their FFT passes of one
+// level share a launch (run_ops), and the last steps run as one launch when
+// they fit one block (run_tail); otherwise op by op.
+int run_product(gf2x_ctx* ctx, const std::vector<Op>& ops, const size_t* split, int m, hipStream_t st,
+                bool may_trace) {
+    if (!split[1] || m >= kForkMinLog) return run_ops(ctx, ops, st, may_trace);
+    std::vector<Op> il;
+    il.reserve(split[1]);
+    size_t ia = 0, ib = split[0];
+    while (ia < split[0] || ib < split[1]) {
+        const uint32_t la = ia < split[0] ? ops[ia].level : ~0u, lb = ib < split[1] ? ops[ib].level : ~0u;
+        const uint32_t l = la < lb ? la : lb;
+        while (ia < split[0] && ops[ia].level == l) il.push_back(ops[ia++]);
+        while (ib < split[1] && ops[ib].level == l) il.push_back(ops[ib++]);
+    }
+    int rc = run_ops(ctx, il, st, may_trace, true);
+    if (rc) return rc;
+    const std::vector<Op> rest(ops.begin() + split[1], ops.end());
+    rc = run_tail(ctx, rest, st, may_trace);
+    return rc == 1 ? run_ops(ctx, rest, st, may_trace, true) : rc;
+}
+
 // The product's ops on stream st with the workspace at ws (Alg. 5): small
 // products in one dispatch, the others op by op.
 int mul_on(gf2x_ctx* ctx, const Sizes& s, const uint64_t* a, const uint64_t* b, uint64_t* c, char* ws,
@@ -2300,25 +2333,7 @@ int mul_on(gf2x_ctx* ctx, const Sizes& s, const uint64_t* a, const uint64_t* b, 
     std::vector<Op> ops;
     size_t split[2] = {0, 0};
     plan_mul(ops, ctx->pool, single_params(ctx), s, a, b, c, ws, split);
-    if (!split[1]) return run_ops(ctx, ops, st);
-    if (s.m < kForkMinLog) {
-        // one stream: the two forward transforms interleaved level by level,
-        // so that their FFT passes of one level can share a launch
-        std::vector<Op> il;
-        il.reserve(ops.size());
-        size_t ia = 0, ib = split[0];
-        while (ia < split[0] || ib < split[1]) {
-            const uint32_t la = ia < split[0] ? ops[ia].level : ~0u, lb = ib < split[1] ? ops[ib].level : ~0u;
-            const uint32_t l = la < lb ? la : lb;
-            while (ia < split[0] && ops[ia].level == l) il.push_back(ops[ia++]);
-            while (ib < split[1] && ops[ib].level == l) il.push_back(ops[ib++]);
-        }
-        int rc = run_ops(ctx, il, st, true, true);
-        if (rc) return rc;
-        const std::vector<Op> rest(ops.begin() + split[1], ops.end());
-        rc = run_tail(ctx, rest, st, true);
-        return rc == 1 ? run_ops(ctx, rest, st, true, true) : rc;
-    }
+    if (!split[1] || s.m < kForkMinLog) return run_product(ctx, ops, split, s.m, st, true);
     // The two forward transforms are independent: b's runs on the second
     // stream, between a fork event recorded here and a join event that a's
     // continuation waits for.  Up to 2^kForkMaxLog points the whole transforms
@@ -2389,8 +2404,9 @@ int gf2x_mul_dev_static(gf2x_ctx* ctx, const uint64_t* a, uint64_t na_bits, cons
     // the ops write each workspace byte before they read it, so nothing in the
     // buffer has to start at zero
     std::vector<Op> ops;
-    plan_mul(ops, ctx->pool, single_params(ctx), s, a, b, c, ctx->scratch);
-    return run_ops(ctx, ops, (hipStream_t)stream, false);
+    size_t split[2] = {0, 0};
+    plan_mul(ops, ctx->pool, single_params(ctx), s, a, b, c, ctx->scratch, split);
+    return run_product(ctx, ops, split, s.m, (hipStream_t)stream, false);
 }
 
 int gf2x_forward_dev(gf2x_ctx* ctx, const uint64_t* a, uint64_t na_bits, int log2n, void* spec, void* stream) {
