@@ -121,18 +121,20 @@ int gf2x_set_single_launch(gf2x_ctx *ctx, int max_log2n);
  * pass whose tile rows hold those bits can run it before its layers, or, in
  * an inverse transform, its inverse after them).  Bits of mask: 1 in forward
  * transforms, 2 in inverse transforms, 4 split a transform's strided passes at
- * BasisCvt's top level when that keeps their number; only transforms of at
- * most 2^max_log2n points fuse, and truncated ones never do.  Default: mask 7
- * up to 2^11 points, where a product's transforms are one pass each and the
- * launches saved dominate (2^16-bit products 0.107 -> 0.100 ms, 10 -> 5
- * launches; batches +1 %).  Above that a fused conversion's layer sweeps cost
- * the FFT kernel about what the conversion's own pass costs (both are bound by
- * LDS, not by the HBM round trip that fusion saves): products of 2^28 and
- * 2^29 bits run 0.5-1.5 % slower with mask 6, batches and served requests
- * within 2 % either way.  Mask 0 runs every conversion as its own pass.
- * Results are the same for every setting; EINVAL for a mask outside 0..7 or a
- * bound outside 0..32. */
-int gf2x_set_fusion(gf2x_ctx *ctx, int mask, int max_log2n);
+ * BasisCvt's top level when that keeps their number.  Only transforms of at
+ * most 2^single_max_log2n points (single products: gf2x_mul_dev, the
+ * no-allocation entry point, requests an idle server runs alone) or
+ * 2^batch_max_log2n points (batches, serving iterations) fuse, and truncated
+ * ones never do.  Default: mask 7, bounds 13 and 11.  There the launches
+ * saved dominate (single products of 2^17 bits 0.13 -> 0.098 ms, 15 -> 4
+ * launches; 2^18 bits 0.17 -> 0.16 ms; batches +1 % at 2^11 points, -2 % at
+ * 2^12).  Above that a fused conversion's layer sweeps cost the FFT kernel
+ * about what the conversion's own pass costs (both are bound by LDS, not by
+ * the HBM round trip that fusion saves): products of 2^28 and 2^29 bits run
+ * 0.5-1.5 % slower with mask 6.  Mask 0 runs every conversion as its own
+ * pass.  Results are the same for every setting; EINVAL for a mask outside
+ * 0..7 or a bound outside 0..32. */
+int gf2x_set_fusion(gf2x_ctx *ctx, int mask, int single_max_log2n, int batch_max_log2n);
 
 /* For callers that cannot allocate device memory (code under HIP graph
  * capture, tight serving loops, harnesses that forbid hipMalloc): c = a * b as

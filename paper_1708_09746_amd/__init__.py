@@ -93,7 +93,7 @@ def lib():
             "gf2x_mul_dev": (i32, [vp, vp, u64, vp, u64, vp, vp]),
             "gf2x_mul_dev_static": (i32, [vp, vp, u64, vp, u64, vp, vp]),
             "gf2x_set_single_launch": (i32, [vp, i32]),
-            "gf2x_set_fusion": (i32, [vp, i32, i32]),
+            "gf2x_set_fusion": (i32, [vp, i32, i32, i32]),
             "gf2x_forward_dev": (i32, [vp, vp, u64, i32, vp, vp]),
             "gf2x_pointmul_dev": (i32, [vp, vp, vp, vp, u64, vp]),
             "gf2x_inverse_dev": (i32, [vp, vp, i32, vp, u64, vp]),
@@ -224,11 +224,14 @@ class Context:
         """Products of at most 2^max_log2n points in one launch (-1: never)."""
         self._check(lib().gf2x_set_single_launch(self._h, int(max_log2n)), "gf2x_set_single_launch")
 
-    def set_fusion(self, mask: int, max_log2n: int = 11):
+    def set_fusion(self, mask: int, single_max_log2n: int = 13, batch_max_log2n: int = 11):
         """Which BasisCvt sub-conversions run inside FFT passes (bits: 1
         forward transforms, 2 inverse transforms, 4 pass split aligned to
-        BasisCvt's top level), for transforms of at most 2^max_log2n points."""
-        self._check(lib().gf2x_set_fusion(self._h, int(mask), int(max_log2n)), "gf2x_set_fusion")
+        BasisCvt's top level), for transforms of at most 2^single_max_log2n
+        points in single products and 2^batch_max_log2n in batches and
+        serving iterations."""
+        self._check(lib().gf2x_set_fusion(self._h, int(mask), int(single_max_log2n), int(batch_max_log2n)),
+                    "gf2x_set_fusion")
 
     def mul_static_into(self, a, na_bits: int, b, nb_bits: int, c, stream=None):
         """The same product with the workspace in the library's fixed device

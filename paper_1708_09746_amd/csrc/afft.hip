@@ -843,6 +843,10 @@ struct gf2x_ctx {
     // never, the default: one block running every stage measured slower than
     // the op-by-op launches, which spread each stage's tiles over the device)
     int single_max_log = -1;
+    // BasisCvt inside FFT passes for single products (gf2x_mul_dev, the
+    // no-allocation entry, served requests on an idle engine) up to 2^13
+    // points; batches and serving iterations use params.fuse_max_log (2^11)
+    int fuse_single_max_log = 13;
     std::string err;
     gf2x_batch* transient = nullptr;  // the last gf2x_mul_batch call's plan
     hipStream_t transient_stream = nullptr;
@@ -931,6 +935,7 @@ struct gf2x_server {
 // light-load path uses it too)
 int run_product(gf2x_ctx* ctx, const std::vector<Op>& ops, const size_t* split, int m, hipStream_t st,
                 bool may_trace);
+PlanParams single_params(const gf2x_ctx* ctx);
 
 namespace {
 
@@ -1695,9 +1700,7 @@ int server_iterate(gf2x_server* S, bool& launched) {
     int direct_m = 0;
     if (direct) {
         const gf2x_server::Req& r = S->active[0];
-        PlanParams pp = S->ctx->params;
-        pp.bc_small = 1;
-        pp.fft_pack_min_tiles = (uint32_t)S->ctx->ncu;
+        const PlanParams pp = single_params(S->ctx);
         const Sizes sz = make_sizes(r.na, r.nb, r.w);
         direct_m = sz.m;
         plan_mul(direct_ops, S->ctx->pool, pp, sz, r.a, r.b, r.c, S->arena + r.off, direct_split);
@@ -1897,6 +1900,7 @@ PlanParams single_params(const gf2x_ctx* ctx) {
     PlanParams pp = ctx->params;
     pp.bc_small = 1;
     pp.fft_pack_min_tiles = (uint32_t)ctx->ncu;
+    pp.fuse_max_log = ctx->fuse_single_max_log;
     return pp;
 }
 
@@ -2504,12 +2508,15 @@ int gf2x_set_single_launch(gf2x_ctx* ctx, int max_log2n) {
     return GF2X_OK;
 }
 
-int gf2x_set_fusion(gf2x_ctx* ctx, int mask, int max_log2n) {
+int gf2x_set_fusion(gf2x_ctx* ctx, int mask, int single_max_log2n, int batch_max_log2n) {
     if (check_ctx(ctx)) return GF2X_EINVAL;
     if (mask < 0 || mask > 7) return fail(ctx, GF2X_EINVAL, "fusion mask outside 0..7");
-    if (max_log2n < 0 || max_log2n > PlanParams::kMaxM) return fail(ctx, GF2X_EINVAL, "fusion size bound outside 0..32");
+    if (single_max_log2n < 0 || single_max_log2n > PlanParams::kMaxM || batch_max_log2n < 0 ||
+        batch_max_log2n > PlanParams::kMaxM)
+        return fail(ctx, GF2X_EINVAL, "fusion size bound outside 0..32");
     ctx->params.fuse_bc = mask;
-    ctx->params.fuse_max_log = max_log2n;
+    ctx->params.fuse_max_log = batch_max_log2n;
+    ctx->fuse_single_max_log = single_max_log2n;
     return GF2X_OK;
 }
 

@@ -45,7 +45,7 @@ SIZES = [(1, 1), (65, 64), (1000, 999), (64 * 33, 64 * 31), (5000, 70), (1 << 16
 
 @pytest.mark.parametrize("mask", [0, 1, 2, 4, 6, 7])
 def test_fused_products(ctx, mask):
-    ctx.set_fusion(mask, 32)
+    ctx.set_fusion(mask, 32, 32)
     try:
         for na, nb in SIZES:
             a = inputs.random_poly(0xF5 + na % 97, na)
@@ -55,12 +55,12 @@ def test_fused_products(ctx, mask):
             ctx.mul_into(dev(a), na, dev(b), nb, c)
             assert np.array_equal(host(c), oracle.mul(a, na, b, nb, threads=8)), (mask, na, nb)
     finally:
-        ctx.set_fusion(7, 11)  # the default
+        ctx.set_fusion(7, 13, 11)  # the default
 
 
 @pytest.mark.parametrize("mask", [3, 7])
 def test_fused_products_128(ctx, mask):
-    ctx.set_fusion(mask, 32)
+    ctx.set_fusion(mask, 32, 32)
     ctx.set_word_bits(128)
     try:
         for na, nb in [(129, 128), (1000, 999), (1 << 16, 1 << 16), (100000, 3), ((1 << 20) + 3, 1 << 19)]:
@@ -72,12 +72,12 @@ def test_fused_products_128(ctx, mask):
             assert np.array_equal(host(c), oracle.mul(a, na, b, nb, threads=8)), (mask, na, nb)
     finally:
         ctx.set_word_bits(64)
-        ctx.set_fusion(7, 11)  # the default
+        ctx.set_fusion(7, 13, 11)  # the default
 
 
 @pytest.mark.parametrize("persistent", [False, True])
 def test_fused_batch(ctx, persistent):
-    ctx.set_fusion(7, 32)
+    ctx.set_fusion(7, 32, 32)
     try:
         rng = random.Random(77)
         jobs, want = [], []
@@ -99,7 +99,7 @@ def test_fused_batch(ctx, persistent):
         for k, (j, w) in enumerate(zip(jobs, want)):
             assert np.array_equal(host(j[4]), w), k
     finally:
-        ctx.set_fusion(7, 11)  # the default
+        ctx.set_fusion(7, 13, 11)  # the default
 
 
 def test_fused_headline_product(ctx):
@@ -109,22 +109,24 @@ def test_fused_headline_product(ctx):
     with open(GOLDEN) as f:
         g = [line.split() for line in f if line.startswith("c3a ")]
     assert g, "tests/golden/product_sha256.txt has no line for c3a"
-    ctx.set_fusion(7, 32)
+    ctx.set_fusion(7, 32, 32)
     try:
         say("case fusion mask 7: 2^28 x 2^28-bit product")
         c = torch.empty(P.out_words(n, n), dtype=torch.int64, device="cuda")
         ctx.mul_into(dev(a), n, dev(b), n, c)
         got = host(c)
     finally:
-        ctx.set_fusion(7, 11)  # the default
+        ctx.set_fusion(7, 13, 11)  # the default
     assert hashlib.sha256(got.tobytes()).hexdigest() == g[0][6]
 
 
 def test_fusion_setting_errors(ctx):
     with pytest.raises(P.Gf2xError):
-        ctx.set_fusion(8, 20)
+        ctx.set_fusion(8, 20, 20)
     with pytest.raises(P.Gf2xError):
-        ctx.set_fusion(-1, 20)
+        ctx.set_fusion(-1, 20, 20)
     with pytest.raises(P.Gf2xError):
-        ctx.set_fusion(1, 33)
-    ctx.set_fusion(7, 11)  # the default
+        ctx.set_fusion(1, 33, 11)
+    with pytest.raises(P.Gf2xError):
+        ctx.set_fusion(1, 13, 33)
+    ctx.set_fusion(7, 13, 11)  # the default
