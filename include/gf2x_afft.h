@@ -99,8 +99,10 @@ int gf2x_mul(const uint64_t *a, uint64_t na_bits, const uint64_t *b, uint64_t nb
 
 /* c = a * b with DEVICE pointers, enqueued on `stream` (Alg. 5).  a and b may
  * alias each other (squaring); c must not overlap either.  A small product
- * can be one kernel launch (gf2x_set_single_launch).  For transforms of 2^13
- * points or more, part of the forward
+ * can be one kernel launch (gf2x_set_single_launch).  Below 2^15 points the
+ * two forward transforms run interleaved on `stream`, their FFT passes of
+ * one level sharing launches; for transforms of 2^15 points or more, part of
+ * the forward
  * transform of b runs on a second stream owned by the context, forked from
  * `stream` and joined back to it by events: up to 2^19 points the whole
  * transform, above only its pack and BasisCvt.  The call stays ordered on

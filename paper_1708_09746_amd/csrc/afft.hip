@@ -1528,12 +1528,14 @@ int batch_build(gf2x_ctx* ctx, const gf2x_job* jobs, size_t njobs, int mode, gf2
 }
 
 constexpr int kMaxLog2N = 32;  // multipliers s_i(v_t) are tabulated for t < 32
-// Single products of 2^13 to 2^19 points overlap their two forward
-// transforms: below that the fork and join cost more than the overlap saves,
-// above it each transform fills the device on its own (the overlap still
-// saves about 2 % at 2^23 points, but then no kernel's time can be read on
-// its own).
-constexpr int kForkMinLog = 13, kForkMaxLog = 19;
+// Single products of 2^15 to 2^19 points overlap their two forward
+// transforms on two streams: below that the two transforms run interleaved on
+// one stream with their FFT passes paired (run_product), which beats the
+// fork and join (2^18-bit products 0.148 -> 0.131 ms, 2^19-bit 0.177 ->
+// 0.171); above it each transform fills the device on its own (the overlap
+// still saves about 2 % at 2^23 points, but then no kernel's time can be read
+// on its own).
+constexpr int kForkMinLog = 15, kForkMaxLog = 19;
 
 int check_ctx(gf2x_ctx* ctx) { return ctx ? GF2X_OK : GF2X_EINVAL; }
 
