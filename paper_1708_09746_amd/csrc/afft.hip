@@ -345,7 +345,10 @@ __global__ __launch_bounds__(kFeThreads) void k_fencode(FrobEncode F, const uint
 }
 
 // inverse encoding map, bit transpose back, inverse per-word conversion
-__global__ __launch_bounds__(kFeThreads) void k_fdecode(FrobDecode F, const uint4* g_tab) {
+// (512-thread blocks: the decoding body needs more than the 128 registers a
+// 1024-thread block leaves each lane, and spilled with them)
+constexpr int kFdThreads = 512;
+__global__ __launch_bounds__(kFdThreads) void k_fdecode(FrobDecode F, const uint4* g_tab) {
     __shared__ uint4 dtab[kElemTab];
     __shared__ uint64_t wtab[kWordTab];
     __shared__ uint64_t lds[kFeStage];
@@ -2004,7 +2007,7 @@ int frob_inverse(gf2x_ctx* ctx, uint4* spec, int m, uint64_t* words, uint64_t* c
     int rc = launch_sfft(ctx, sfft_passes(spec, nullptr, m, m, true, m + 64), st);
     if (rc) return rc;
     const FrobDecode F{spec, words, (uint32_t)m};
-    hipLaunchKernelGGL(k_fdecode, dim3(grid_for(frob_tiles((uint32_t)m), 4ull * ctx->ncu)), dim3(kFeThreads), 0, st, F,
+    hipLaunchKernelGGL(k_fdecode, dim3(grid_for(frob_tiles((uint32_t)m), 4ull * ctx->ncu)), dim3(kFdThreads), 0, st, F,
                        (const uint4*)ctx->d_frob);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(ctx, e, "decoding launch");
