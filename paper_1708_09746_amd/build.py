@@ -6,7 +6,6 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libgf2x_afft.so")
 SOURCES = [os.path.join(HERE, "csrc", "afft.hip")]
-HEADERS = [os.path.join(HERE, "csrc", f) for f in ("afft_device.hpp", "afft_ops.hpp", "afft_plan.hpp", "tower_host.hpp")]
 ARCH = os.environ.get("GF2X_OFFLOAD_ARCH", "gfx950")
 
 

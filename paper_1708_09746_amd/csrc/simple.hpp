@@ -94,11 +94,48 @@ AFFT_HD uint4 gcm_reduce(const uint32_t (&a)[8]) {
     return r;
 }
 
+// The entry of the LDS table T at byte offset (byte k of v); every byte of v
+// is a multiple of 16.  On the device the address is one VOP2 add that reads
+// byte k of its second operand (SDWA) in place of a shift, a mask and an add.
+AFFT_HD uint4 gcm_entry(const uint4* T, uint32_t v, int k) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    typedef const __attribute__((address_space(3))) uint4* lds_ptr;
+    const uint32_t base = (uint32_t)(uintptr_t)(lds_ptr)T;
+    uint32_t a;
+    switch (k) {
+        case 0:
+            asm("v_add_u32_sdwa %0, %1, %2 dst_sel:DWORD dst_unused:UNUSED_PAD src0_sel:DWORD src1_sel:BYTE_0"
+                : "=v"(a) : "v"(base), "v"(v));
+            break;
+        case 1:
+            asm("v_add_u32_sdwa %0, %1, %2 dst_sel:DWORD dst_unused:UNUSED_PAD src0_sel:DWORD src1_sel:BYTE_1"
+                : "=v"(a) : "v"(base), "v"(v));
+            break;
+        case 2:
+            asm("v_add_u32_sdwa %0, %1, %2 dst_sel:DWORD dst_unused:UNUSED_PAD src0_sel:DWORD src1_sel:BYTE_2"
+                : "=v"(a) : "v"(base), "v"(v));
+            break;
+        default:
+            asm("v_add_u32_sdwa %0, %1, %2 dst_sel:DWORD dst_unused:UNUSED_PAD src0_sel:DWORD src1_sel:BYTE_3"
+                : "=v"(a) : "v"(base), "v"(v));
+            break;
+    }
+    return *(lds_ptr)(uintptr_t)a;
+#else
+    return T[((v >> (8 * k)) & 255u) >> 4];
+#endif
+}
+
 // v * w with T the table of v: sum over nibble positions p = 8q + r of
 // T[nibble] x^(32q) x^(4r), by Horner's rule in x^4 over r.  The four
 // lookups of one r land on words q .. q + 3 of the accumulator; each word
-// takes its (up to four) terms through three-input XORs.
+// takes its (up to four) terms through three-input XORs.  The nibbles of
+// word q are spread once into the bytes of ev[q] (even r, times 16) and
+// od[q] (odd r, times 16): byte offsets of the entries.
 AFFT_HD uint4 gcm_mul_tab(const uint4* T, uint4 w) {
+    const uint32_t ev[4] = {(w.x << 4) & 0xF0F0F0F0u, (w.y << 4) & 0xF0F0F0F0u, (w.z << 4) & 0xF0F0F0F0u,
+                            (w.w << 4) & 0xF0F0F0F0u};
+    const uint32_t od[4] = {w.x & 0xF0F0F0F0u, w.y & 0xF0F0F0F0u, w.z & 0xF0F0F0F0u, w.w & 0xF0F0F0F0u};
     uint32_t a[8] = {0, 0, 0, 0, 0, 0, 0, 0};
 #pragma unroll
     for (int r = 7; r >= 0; --r) {
@@ -107,8 +144,9 @@ AFFT_HD uint4 gcm_mul_tab(const uint4* T, uint4 w) {
             for (int i = 7; i > 0; --i) a[i] = (a[i] << 4) | (a[i - 1] >> 28);
             a[0] <<= 4;
         }
-        const uint4 t0 = T[(w.x >> (4 * r)) & 15u], t1 = T[(w.y >> (4 * r)) & 15u];
-        const uint4 t2 = T[(w.z >> (4 * r)) & 15u], t3 = T[(w.w >> (4 * r)) & 15u];
+        const uint32_t* s = (r & 1) ? od : ev;
+        const uint4 t0 = gcm_entry(T, s[0], r >> 1), t1 = gcm_entry(T, s[1], r >> 1);
+        const uint4 t2 = gcm_entry(T, s[2], r >> 1), t3 = gcm_entry(T, s[3], r >> 1);
         a[0] ^= t0.x;
         a[1] = xor3(a[1], t0.y, t1.x);
         a[2] = xor3(a[2], t0.z, t1.y) ^ t2.x;
