@@ -280,26 +280,46 @@ __global__ __launch_bounds__(kSfThreads) void k_sfft_tab(SfftPass P, const uint4
     }
 }
 
-__global__ __launch_bounds__(kSfLaneThreads) void k_sfft_lane(SfftPass P, const uint4* g_cantor) {
-    __shared__ uint4 ltab[kSfLaneThreads * kSfTabStride];
-    __shared__ uint4 dat[1 << kSfLaneC];
-    __shared__ uint4 phit[1 << kSfLaneC];
-    __shared__ uint4 lam[kSfLaneC];
-    const uint32_t npts = 1u << P.c;
-    const uint64_t nchunks = P.n >> P.c;
-    uint4* T = ltab + threadIdx.x * kSfTabStride;
-    for (uint32_t u = threadIdx.x; u < npts; u += blockDim.x) phit[u] = g_cantor[kCantorBeta + u];
-    for (uint64_t g = blockIdx.x; g < nchunks; g += gridDim.x) {
-        const uint64_t J0 = g << P.c;
-        for (uint32_t e = threadIdx.x; e < npts; e += blockDim.x) dat[e] = sfft_load(P, J0 | e);
-        if ((int)threadIdx.x < P.L) lam[threadIdx.x] = sf_lane_lam(P, J0, (int)threadIdx.x, g_cantor);
-        __syncthreads();
-        for (int s = 0; s < P.L; ++s) {
-            for (uint32_t q = threadIdx.x; q < npts / 2; q += blockDim.x) sf_lane_bfly(P, s, q, dat, lam, phit, T);
-            __syncthreads();
+// The bottom pass: one wave per chunk of 64 groups of 2^kSfGroupLog
+// consecutive points, one group per thread.  A thread's table region
+// (kSfTabStride entries) also carries its group in and out: lane l loads
+// points 64 i + l of the chunk (coalesced) into the regions of their groups'
+// threads, and every thread then reads its own.  Each wave touches only its
+// own regions, so wave-level ordering replaces workgroup barriers.
+constexpr int kSfGroupThreads = 64;
+
+template <bool INV>
+__global__ __launch_bounds__(kSfGroupThreads) void k_sfft_lane(SfftPass P, const uint4* g_cantor) {
+    __shared__ uint4 ltab[kSfGroupThreads * kSfTabStride];
+    const uint32_t g = threadIdx.x;
+    uint4* T = ltab + g * kSfTabStride;
+    const uint64_t nchunks = (P.n + (1u << kSfChunkLog) - 1) >> kSfChunkLog;
+    for (uint64_t c = blockIdx.x; c < nchunks; c += gridDim.x) {
+        const uint64_t J0 = c << kSfChunkLog;
+#pragma unroll
+        for (int i = 0; i < kSfGroupPts; ++i) {
+            const uint32_t p = 64 * i + g;
+            const uint64_t j = J0 + p;
+            ltab[(p >> kSfGroupLog) * kSfTabStride + (p & (kSfGroupPts - 1))] =
+                j < P.n ? sfft_load(P, j) : make_uint4(0u, 0u, 0u, 0u);
         }
-        for (uint32_t e = threadIdx.x; e < npts; e += blockDim.x) P.x[J0 | e] = dat[e];
-        __syncthreads();
+        AFFT_WAVE_SYNC();
+        uint4 x[kSfGroupPts];
+#pragma unroll
+        for (int p = 0; p < kSfGroupPts; ++p) x[p] = T[p];
+        AFFT_WAVE_SYNC();
+        sf_group_layers<INV>(P, J0, g, x, T, g_cantor);
+        AFFT_WAVE_SYNC();
+#pragma unroll
+        for (int p = 0; p < kSfGroupPts; ++p) T[p] = x[p];
+        AFFT_WAVE_SYNC();
+#pragma unroll
+        for (int i = 0; i < kSfGroupPts; ++i) {
+            const uint32_t p = 64 * i + g;
+            const uint64_t j = J0 + p;
+            if (j < P.n) P.x[j] = ltab[(p >> kSfGroupLog) * kSfTabStride + (p & (kSfGroupPts - 1))];
+        }
+        AFFT_WAVE_SYNC();
     }
 }
 
@@ -1914,9 +1934,12 @@ PlanParams single_params(const gf2x_ctx* ctx) {
 int launch_sfft(gf2x_ctx* ctx, const std::vector<SfftPass>& passes, hipStream_t st) {
     for (const SfftPass& p : passes) {
         if (p.lo == 0) {
-            const uint64_t chunks = p.n >> p.c;
-            hipLaunchKernelGGL(k_sfft_lane, dim3(grid_for(chunks, 12ull * ctx->ncu)), dim3(kSfLaneThreads), 0, st, p,
-                               (const uint4*)ctx->d_cantor);
+            const uint64_t chunks = (p.n + (1u << kSfChunkLog) - 1) >> kSfChunkLog;
+            const dim3 grid(grid_for(chunks, 18ull * ctx->ncu)), block(kSfGroupThreads);
+            if (p.inverse)
+                hipLaunchKernelGGL(k_sfft_lane<true>, grid, block, 0, st, p, (const uint4*)ctx->d_cantor);
+            else
+                hipLaunchKernelGGL(k_sfft_lane<false>, grid, block, 0, st, p, (const uint4*)ctx->d_cantor);
         } else {
             const uint64_t groups = p.n >> (p.L + p.c);
             hipLaunchKernelGGL(k_sfft_tab, dim3(grid_for(groups, 12ull * ctx->ncu)), dim3(kSfThreads), 0, st, p,

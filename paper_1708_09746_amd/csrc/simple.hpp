@@ -15,8 +15,8 @@
 // deg n < 4: v * w is the sum over the 32 nibbles of w of table entries times
 // x^(4p), accumulated unreduced in 256 bits and reduced once.  A strided FFT
 // pass builds one table per distinct multiplier of its group (shared by all
-// butterflies of that block); the contiguous bottom pass, where blocks hold
-// one or two butterflies, builds the table of the butterfly's operand instead.
+// butterflies of that block); in the contiguous bottom pass each thread holds
+// a group of 8 points and builds the table of each block's multiplier once.
 #pragma once
 
 #include <stdint.h>
@@ -28,14 +28,14 @@
 namespace gf2x {
 
 constexpr int kSfThreads = 256;       // strided-pass workgroup
-constexpr int kSfLaneThreads = 128;   // bottom-pass and pointmul workgroups
+constexpr int kSfLaneThreads = 128;   // pointmul workgroups
 constexpr int kSfTabL = 7;            // layers of one strided pass, at most
 constexpr int kSfTabPtsLog = 10;      // points of one strided-pass workgroup, at most 2^10
 constexpr int kSfTabStride = 17;      // uint4 per table: 16 entries and one pad (spreads LDS banks)
-constexpr int kSfLaneC = 9;           // bottom pass: contiguous chunks of 2^9 points
-constexpr int kSfLaneL = 4;           // bottom pass: layers 0..3 (multipliers shared by at most 8 butterflies)
+constexpr int kSfGroupLog = 3;        // bottom pass: layers 0..2 on groups of 8 points, one group per thread
+constexpr int kSfChunkLog = kSfGroupLog + 6;  // bottom pass: one wave takes 64 groups
 constexpr int kCantorBeta = 128;      // beta_0 .. beta_127 in the device table (the whole Cantor basis)
-constexpr int kCantorTotal = kCantorBeta + (1 << kSfLaneC);  // then phi(u) for u < 2^9
+constexpr int kCantorTotal = kCantorBeta + (1 << kSfGroupLog);  // then phi(u) for u < 2^kSfGroupLog
 
 struct SfftPass {
     uint4* x;               // N points, 16 bytes each, read and written in place
@@ -175,12 +175,6 @@ AFFT_HD uint4 sf_alpha_term(const SfftPass& P, int k, const uint4* beta) {
     return P.alpha >= 0 ? beta[P.alpha - k] : make_uint4(0u, 0u, 0u, 0u);
 }
 
-// The chunk part of a bottom-pass multiplier: s_k(alpha + phi(J0)) for the
-// chunk at J0 (the block part phi((e >> (k + 1)) << 1) is added per butterfly).
-AFFT_HD uint4 sf_lane_lam(const SfftPass& P, uint64_t J0, int k, const uint4* beta) {
-    return xor4(phi_cantor(J0 >> k, beta), sf_alpha_term(P, k, beta));
-}
-
 AFFT_HD uint4 sfft_load(const SfftPass& P, uint64_t j) {
     if (P.words) {
         const uint64_t w = P.words[j & P.wmask];
@@ -232,30 +226,87 @@ AFFT_HD void sf_tab_bfly(const SfftPass& P, int s, uint32_t q, uint4* dat, const
     dat[e1] = w;
 }
 
-// The contiguous bottom pass: layers [0, L) on chunks of 2^c consecutive
-// points (L <= c).  For the chunk at J0 the layer-k multiplier of the block
-// holding local index e is phi(J0 >> k) + phi((e >> (k + 1)) << 1): the first
-// term once per chunk and layer (lam[k]), the second from the phi table.
-// Each butterfly tabulates its own operand in T (multipliers are rarely
-// shared here).
-AFFT_HD void sf_lane_bfly(const SfftPass& P, int s, uint32_t q, uint4* dat, const uint4* lam, const uint4* phit,
-                          uint4* T) {
-    const int k = P.inverse ? s : P.L - 1 - s;
-    const uint32_t e0 = ((q >> k) << (k + 1)) | (q & ((1u << k) - 1));
-    const uint32_t e1 = e0 | (1u << k);
-    const uint4 m = xor4(lam[k], phit[(e0 >> (k + 1)) << 1]);
-    uint4 u = dat[e0], w = dat[e1];
-    if (!P.inverse) {
-        gcm_build_tab(w, T);
-        u = xor4(u, gcm_mul_tab(T, m));
-        w = xor4(w, u);
-    } else {
-        w = xor4(w, u);
-        gcm_build_tab(w, T);
-        u = xor4(u, gcm_mul_tab(T, m));
+// The contiguous bottom pass: layers [0, L) (L <= G = kSfGroupLog) on groups
+// of 2^G consecutive points, one group per thread, held in registers.  A wave
+// takes a chunk of 64 groups at J0 (a multiple of 2^(G+6)); the layer-k
+// multiplier of the block of group g that starts at local point e 2^(k+1) is
+// s_k(alpha + phi(J0 + g 2^G + e 2^(k+1)))
+//     = beta_{A-k} + phi(J0 >> k) + phi(g << (G - k)) + phi(2e)
+// (Sec. 3.3; the index bits of the three phi terms are disjoint).
+//
+// At the step of layer k register p holds point rotl(p, k + 1) of the group
+// (a rotation of G-bit indices), so every layer pairs registers i and i + H
+// (H = 2^(G-1), i < H); between steps the points move to register rotl(p, 1)
+// (forward, layers top-down) or rotr(p, 1) (inverse, bottom-up).  Pair i lies
+// in block e = i mod 2^(G-1-k); visiting the pairs as i = rev(s), the reversal
+// of the G - 1 bits of s < H, takes the blocks one after another, so the
+// table of each block's multiplier is built once and serves its 2^k
+// butterflies.
+constexpr int kSfGroupPts = 1 << kSfGroupLog, kSfGroupHalf = kSfGroupPts / 2;
+
+AFFT_HD constexpr int sf_rev(int s) {
+    int r = 0;
+    for (int b = 0; b < kSfGroupLog - 1; ++b) r |= ((s >> b) & 1) << (kSfGroupLog - 2 - b);
+    return r;
+}
+
+// Keeps a butterfly's results computed where it stands: without it the
+// compiler sinks the arithmetic of all products of a step below the last
+// table build (the loads stay put), and their table entries spill.
+AFFT_HD void sf_pin(uint4& v) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    asm volatile("" : "+v"(v.x), "+v"(v.y), "+v"(v.z), "+v"(v.w));
+#else
+    (void)v;
+#endif
+}
+
+// x[p] -> x[rotl(p, 1)] (forward) or x[rotr(p, 1)] (inverse)
+template <bool INV>
+AFFT_HD void sf_group_rotate(uint4 (&x)[kSfGroupPts]) {
+    uint4 y[kSfGroupPts];
+#pragma unroll
+    for (int p = 0; p < kSfGroupPts; ++p)
+        y[INV ? ((p >> 1) | ((p & 1) << (kSfGroupLog - 1))) : (((p << 1) | (p >> (kSfGroupLog - 1))) & (kSfGroupPts - 1))] =
+            x[p];
+#pragma unroll
+    for (int p = 0; p < kSfGroupPts; ++p) x[p] = y[p];
+}
+
+template <bool INV>
+AFFT_HD void sf_group_layers(const SfftPass& P, uint64_t J0, uint32_t g, uint4 (&x)[kSfGroupPts], uint4* T,
+                             const uint4* beta) {
+    const uint4* phit = beta + kCantorBeta;  // phi(u), u < 2^G
+#pragma unroll
+    for (int st = 0; st < kSfGroupLog; ++st) {
+        const int k = INV ? st : kSfGroupLog - 1 - st;
+        if (INV) sf_group_rotate<true>(x);
+        if (k < P.L) {
+            uint4 mb = xor4(phi_cantor(J0 >> k, beta), sf_alpha_term(P, k, beta));
+#pragma unroll
+            for (int b = 0; b < 6; ++b)
+                if ((g >> b) & 1) mb = xor4(mb, beta[b + kSfGroupLog - k]);
+#pragma unroll
+            for (int s = 0; s < kSfGroupHalf; ++s) {
+                const int i = sf_rev(s);
+                if ((s & ((1 << k) - 1)) == 0)
+                    gcm_build_tab(xor4(mb, phit[(i & ((kSfGroupHalf >> k) - 1)) << 1]), T);
+                uint4 u = x[i], w = x[i + kSfGroupHalf];
+                if (!INV) {
+                    u = xor4(u, gcm_mul_tab(T, w));
+                    w = xor4(w, u);
+                } else {
+                    w = xor4(w, u);
+                    u = xor4(u, gcm_mul_tab(T, w));
+                }
+                sf_pin(u);
+                sf_pin(w);
+                x[i] = u;
+                x[i + kSfGroupHalf] = w;
+            }
+        }
+        if (!INV) sf_group_rotate<false>(x);
     }
-    dat[e0] = u;
-    dat[e1] = w;
 }
 
 // InterleavedCombine, word k: the low half of coefficient k plus the high
@@ -326,13 +377,13 @@ inline bool build_cantor(gcm_u128* beta, int count) {
     return true;
 }
 
-// The device table: beta_0 .. beta_63, then phi(u) for u < 2^kSfLaneC.
+// The device table: beta_0 .. beta_127, then phi(u) for u < 2^kSfGroupLog.
 inline bool build_cantor_table(std::vector<gcm_u128>& out) {
     out.assign(kCantorTotal, 0);
     if (!build_cantor(out.data(), kCantorBeta)) return false;
-    for (uint32_t u = 0; u < (1u << kSfLaneC); ++u) {
+    for (uint32_t u = 0; u < (1u << kSfGroupLog); ++u) {
         gcm_u128 r = 0;
-        for (int t = 0; t < kSfLaneC; ++t)
+        for (int t = 0; t < kSfGroupLog; ++t)
             if ((u >> t) & 1) r ^= out[t];
         out[kCantorBeta + u] = r;
     }
@@ -349,8 +400,8 @@ inline std::vector<SfftPass> sfft_passes(uint4* x, const uint64_t* words, int m_
                                          int alpha = -1) {
     std::vector<SfftPass> v;
     const int M = inverse ? m : m_op;
-    const int C = m < kSfLaneC ? m : kSfLaneC;
-    const int Lb = M < kSfLaneL ? M : kSfLaneL;
+    const int C = m < kSfGroupLog ? m : kSfGroupLog;
+    const int Lb = M < kSfGroupLog ? M : kSfGroupLog;
     v.push_back(SfftPass{x, nullptr, 0, 1ull << m, 0, Lb, C, inverse ? 1 : 0, alpha});
     const int up = M - Lb;
     if (up > 0) {

@@ -282,19 +282,27 @@ bool check_xcd_order(std::mt19937_64& g) {
 std::vector<uint4> CANTOR;
 
 void run_sfft(const std::vector<SfftPass>& passes) {
-    std::vector<uint4> tab(((1 << kSfTabL) - 1) * kSfTabStride), dat(1 << kSfTabPtsLog), T(kSfTabStride),
-        lam(kSfLaneC);
+    std::vector<uint4> tab(((1 << kSfTabL) - 1) * kSfTabStride), dat(1 << kSfTabPtsLog), T(kSfTabStride);
     for (const SfftPass& P : passes) {
         if (P.lo == 0) {
-            const uint32_t npts = 1u << P.c;
-            for (uint64_t g = 0; g < (P.n >> P.c); ++g) {
-                const uint64_t J0 = g << P.c;
-                for (uint32_t e = 0; e < npts; ++e) dat[e] = sfft_load(P, J0 | e);
-                for (int k = 0; k < P.L; ++k) lam[k] = sf_lane_lam(P, J0, k, CANTOR.data());
-                for (int s = 0; s < P.L; ++s)
-                    for (uint32_t q = 0; q < npts / 2; ++q)
-                        sf_lane_bfly(P, s, q, dat.data(), lam.data(), CANTOR.data() + kCantorBeta, T.data());
-                for (uint32_t e = 0; e < npts; ++e) P.x[J0 | e] = dat[e];
+            // chunks of 64 groups of 2^kSfGroupLog points (points past N are zero and not stored)
+            for (uint64_t c = 0; c < ((P.n + (1u << kSfChunkLog) - 1) >> kSfChunkLog); ++c) {
+                const uint64_t J0 = c << kSfChunkLog;
+                for (uint32_t g = 0; g < 64; ++g) {
+                    uint4 x[kSfGroupPts];
+                    for (int p = 0; p < kSfGroupPts; ++p) {
+                        const uint64_t j = J0 + kSfGroupPts * g + p;
+                        x[p] = j < P.n ? sfft_load(P, j) : make_uint4(0u, 0u, 0u, 0u);
+                    }
+                    if (P.inverse)
+                        sf_group_layers<true>(P, J0, g, x, T.data(), CANTOR.data());
+                    else
+                        sf_group_layers<false>(P, J0, g, x, T.data(), CANTOR.data());
+                    for (int p = 0; p < kSfGroupPts; ++p) {
+                        const uint64_t j = J0 + kSfGroupPts * g + p;
+                        if (j < P.n) P.x[j] = x[p];
+                    }
+                }
             }
         } else {
             const uint32_t npts = 1u << (P.L + P.c), ntab = (1u << P.L) - 1;
@@ -548,7 +556,7 @@ int main(int argc, char** argv) {
         PP.word_bits = 64;
     }
     if (what == "all" || what == "simple") {
-        // Alg. 4: bottom pass only (N <= 2^9), one and two strided passes
+        // Alg. 4: bottom pass only (N <= 8), one and several strided passes
         // above it, operands far shorter than N, single words
         bad += !check_simple_tables();
         const uint64_t fixed[][2] = {{1, 1},      {64, 64},     {65, 64},         {1, 700},     {1000, 999},
