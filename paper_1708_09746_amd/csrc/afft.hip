@@ -280,44 +280,44 @@ __global__ __launch_bounds__(kSfThreads) void k_sfft_tab(SfftPass P, const uint4
     }
 }
 
-// The bottom pass: one wave per chunk of 64 groups of 2^kSfGroupLog
-// consecutive points, one group per thread.  A thread's table region
-// (kSfTabStride entries) also carries its group in and out: lane l loads
-// points 64 i + l of the chunk (coalesced) into the regions of their groups'
-// threads, and every thread then reads its own.  Each wave touches only its
-// own regions, so wave-level ordering replaces workgroup barriers.
+// The bottom pass: one wave per chunk of 64 groups of 2^G consecutive
+// points, one group per thread.  A thread's table region (kSfTabStride
+// entries) also carries its group in and out: lane l loads points 64 i + l of
+// the chunk (coalesced) into the regions of their groups' threads, and every
+// thread then reads its own.  Each wave touches only its own regions, so
+// wave-level ordering replaces workgroup barriers.
 constexpr int kSfGroupThreads = 64;
 
-template <bool INV>
+template <int G, bool INV>
 __global__ __launch_bounds__(kSfGroupThreads) void k_sfft_lane(SfftPass P, const uint4* g_cantor) {
+    constexpr int CL = G + 6;  // log2 of the chunk's points
     __shared__ uint4 ltab[kSfGroupThreads * kSfTabStride];
     const uint32_t g = threadIdx.x;
     uint4* T = ltab + g * kSfTabStride;
-    const uint64_t nchunks = (P.n + (1u << kSfChunkLog) - 1) >> kSfChunkLog;
+    const uint64_t nchunks = (P.n + (1u << CL) - 1) >> CL;
     for (uint64_t c = blockIdx.x; c < nchunks; c += gridDim.x) {
-        const uint64_t J0 = c << kSfChunkLog;
+        const uint64_t J0 = c << CL;
 #pragma unroll
-        for (int i = 0; i < kSfGroupPts; ++i) {
+        for (int i = 0; i < (1 << G); ++i) {
             const uint32_t p = 64 * i + g;
             const uint64_t j = J0 + p;
-            ltab[(p >> kSfGroupLog) * kSfTabStride + (p & (kSfGroupPts - 1))] =
-                j < P.n ? sfft_load(P, j) : make_uint4(0u, 0u, 0u, 0u);
+            ltab[(p >> G) * kSfTabStride + (p & ((1 << G) - 1))] = j < P.n ? sfft_load(P, j) : make_uint4(0u, 0u, 0u, 0u);
         }
         AFFT_WAVE_SYNC();
-        uint4 x[kSfGroupPts];
+        uint4 x[1 << G];
 #pragma unroll
-        for (int p = 0; p < kSfGroupPts; ++p) x[p] = T[p];
+        for (int p = 0; p < (1 << G); ++p) x[p] = T[p];
         AFFT_WAVE_SYNC();
-        sf_group_layers<INV>(P, J0, g, x, T, g_cantor);
-        AFFT_WAVE_SYNC();
-#pragma unroll
-        for (int p = 0; p < kSfGroupPts; ++p) T[p] = x[p];
+        sf_group_layers<G, INV>(P, J0, g, x, T, g_cantor);
         AFFT_WAVE_SYNC();
 #pragma unroll
-        for (int i = 0; i < kSfGroupPts; ++i) {
+        for (int p = 0; p < (1 << G); ++p) T[p] = x[p];
+        AFFT_WAVE_SYNC();
+#pragma unroll
+        for (int i = 0; i < (1 << G); ++i) {
             const uint32_t p = 64 * i + g;
             const uint64_t j = J0 + p;
-            if (j < P.n) P.x[j] = ltab[(p >> kSfGroupLog) * kSfTabStride + (p & (kSfGroupPts - 1))];
+            if (j < P.n) P.x[j] = ltab[(p >> G) * kSfTabStride + (p & ((1 << G) - 1))];
         }
         AFFT_WAVE_SYNC();
     }
@@ -1934,12 +1934,19 @@ PlanParams single_params(const gf2x_ctx* ctx) {
 int launch_sfft(gf2x_ctx* ctx, const std::vector<SfftPass>& passes, hipStream_t st) {
     for (const SfftPass& p : passes) {
         if (p.lo == 0) {
-            const uint64_t chunks = (p.n + (1u << kSfChunkLog) - 1) >> kSfChunkLog;
+            if (p.c != 2 && p.c != 3) return fail(ctx, GF2X_EINVAL, "simple-variant bottom pass: group size 2^c with c not 2 or 3");
+            const uint64_t chunks = (p.n + (1ull << (p.c + 6)) - 1) >> (p.c + 6);
             const dim3 grid(grid_for(chunks, 18ull * ctx->ncu)), block(kSfGroupThreads);
-            if (p.inverse)
-                hipLaunchKernelGGL(k_sfft_lane<true>, grid, block, 0, st, p, (const uint4*)ctx->d_cantor);
+            const uint4* cantor = (const uint4*)ctx->d_cantor;
+            if (p.c == 2)
+                if (p.inverse)
+                    hipLaunchKernelGGL((k_sfft_lane<2, true>), grid, block, 0, st, p, cantor);
+                else
+                    hipLaunchKernelGGL((k_sfft_lane<2, false>), grid, block, 0, st, p, cantor);
+            else if (p.inverse)
+                hipLaunchKernelGGL((k_sfft_lane<3, true>), grid, block, 0, st, p, cantor);
             else
-                hipLaunchKernelGGL(k_sfft_lane<false>, grid, block, 0, st, p, (const uint4*)ctx->d_cantor);
+                hipLaunchKernelGGL((k_sfft_lane<3, false>), grid, block, 0, st, p, cantor);
         } else {
             const uint64_t groups = p.n >> (p.L + p.c);
             hipLaunchKernelGGL(k_sfft_tab, dim3(grid_for(groups, 12ull * ctx->ncu)), dim3(kSfThreads), 0, st, p,

@@ -32,10 +32,10 @@ constexpr int kSfLaneThreads = 128;   // pointmul workgroups
 constexpr int kSfTabL = 7;            // layers of one strided pass, at most
 constexpr int kSfTabPtsLog = 10;      // points of one strided-pass workgroup, at most 2^10
 constexpr int kSfTabStride = 17;      // uint4 per table: 16 entries and one pad (spreads LDS banks)
-constexpr int kSfGroupLog = 3;        // bottom pass: layers 0..2 on groups of 8 points, one group per thread
-constexpr int kSfChunkLog = kSfGroupLog + 6;  // bottom pass: one wave takes 64 groups
+constexpr int kSfGroupMaxLog = 3;     // bottom pass: layers 0..G-1 on groups of 2^G points (G = 2 or 3), one per thread
+constexpr int kSfGroupSmallLog = 18;  // G = 2 up to N = 2^18 points when that adds no strided pass
 constexpr int kCantorBeta = 128;      // beta_0 .. beta_127 in the device table (the whole Cantor basis)
-constexpr int kCantorTotal = kCantorBeta + (1 << kSfGroupLog);  // then phi(u) for u < 2^kSfGroupLog
+constexpr int kCantorTotal = kCantorBeta + (1 << kSfGroupMaxLog);  // then phi(u) for u < 2^kSfGroupMaxLog
 
 struct SfftPass {
     uint4* x;               // N points, 16 bytes each, read and written in place
@@ -226,7 +226,7 @@ AFFT_HD void sf_tab_bfly(const SfftPass& P, int s, uint32_t q, uint4* dat, const
     dat[e1] = w;
 }
 
-// The contiguous bottom pass: layers [0, L) (L <= G = kSfGroupLog) on groups
+// The contiguous bottom pass: layers [0, L) (L <= G, G = 2 or 3) on groups
 // of 2^G consecutive points, one group per thread, held in registers.  A wave
 // takes a chunk of 64 groups at J0 (a multiple of 2^(G+6)); the layer-k
 // multiplier of the block of group g that starts at local point e 2^(k+1) is
@@ -242,11 +242,10 @@ AFFT_HD void sf_tab_bfly(const SfftPass& P, int s, uint32_t q, uint4* dat, const
 // of the G - 1 bits of s < H, takes the blocks one after another, so the
 // table of each block's multiplier is built once and serves its 2^k
 // butterflies.
-constexpr int kSfGroupPts = 1 << kSfGroupLog, kSfGroupHalf = kSfGroupPts / 2;
-
+template <int G>
 AFFT_HD constexpr int sf_rev(int s) {
     int r = 0;
-    for (int b = 0; b < kSfGroupLog - 1; ++b) r |= ((s >> b) & 1) << (kSfGroupLog - 2 - b);
+    for (int b = 0; b < G - 1; ++b) r |= ((s >> b) & 1) << (G - 2 - b);
     return r;
 }
 
@@ -262,36 +261,34 @@ AFFT_HD void sf_pin(uint4& v) {
 }
 
 // x[p] -> x[rotl(p, 1)] (forward) or x[rotr(p, 1)] (inverse)
-template <bool INV>
-AFFT_HD void sf_group_rotate(uint4 (&x)[kSfGroupPts]) {
-    uint4 y[kSfGroupPts];
+template <int G, bool INV>
+AFFT_HD void sf_group_rotate(uint4 (&x)[1 << G]) {
+    uint4 y[1 << G];
 #pragma unroll
-    for (int p = 0; p < kSfGroupPts; ++p)
-        y[INV ? ((p >> 1) | ((p & 1) << (kSfGroupLog - 1))) : (((p << 1) | (p >> (kSfGroupLog - 1))) & (kSfGroupPts - 1))] =
-            x[p];
+    for (int p = 0; p < (1 << G); ++p) y[INV ? ((p >> 1) | ((p & 1) << (G - 1))) : (((p << 1) | (p >> (G - 1))) & ((1 << G) - 1))] = x[p];
 #pragma unroll
-    for (int p = 0; p < kSfGroupPts; ++p) x[p] = y[p];
+    for (int p = 0; p < (1 << G); ++p) x[p] = y[p];
 }
 
-template <bool INV>
-AFFT_HD void sf_group_layers(const SfftPass& P, uint64_t J0, uint32_t g, uint4 (&x)[kSfGroupPts], uint4* T,
+template <int G, bool INV>
+AFFT_HD void sf_group_layers(const SfftPass& P, uint64_t J0, uint32_t g, uint4 (&x)[1 << G], uint4* T,
                              const uint4* beta) {
+    constexpr int H = 1 << (G - 1);
     const uint4* phit = beta + kCantorBeta;  // phi(u), u < 2^G
 #pragma unroll
-    for (int st = 0; st < kSfGroupLog; ++st) {
-        const int k = INV ? st : kSfGroupLog - 1 - st;
-        if (INV) sf_group_rotate<true>(x);
+    for (int st = 0; st < G; ++st) {
+        const int k = INV ? st : G - 1 - st;
+        if (INV) sf_group_rotate<G, true>(x);
         if (k < P.L) {
             uint4 mb = xor4(phi_cantor(J0 >> k, beta), sf_alpha_term(P, k, beta));
 #pragma unroll
             for (int b = 0; b < 6; ++b)
-                if ((g >> b) & 1) mb = xor4(mb, beta[b + kSfGroupLog - k]);
+                if ((g >> b) & 1) mb = xor4(mb, beta[b + G - k]);
 #pragma unroll
-            for (int s = 0; s < kSfGroupHalf; ++s) {
-                const int i = sf_rev(s);
-                if ((s & ((1 << k) - 1)) == 0)
-                    gcm_build_tab(xor4(mb, phit[(i & ((kSfGroupHalf >> k) - 1)) << 1]), T);
-                uint4 u = x[i], w = x[i + kSfGroupHalf];
+            for (int s = 0; s < H; ++s) {
+                const int i = sf_rev<G>(s);
+                if ((s & ((1 << k) - 1)) == 0) gcm_build_tab(xor4(mb, phit[(i & ((H >> k) - 1)) << 1]), T);
+                uint4 u = x[i], w = x[i + H];
                 if (!INV) {
                     u = xor4(u, gcm_mul_tab(T, w));
                     w = xor4(w, u);
@@ -302,10 +299,10 @@ AFFT_HD void sf_group_layers(const SfftPass& P, uint64_t J0, uint32_t g, uint4 (
                 sf_pin(u);
                 sf_pin(w);
                 x[i] = u;
-                x[i + kSfGroupHalf] = w;
+                x[i + H] = w;
             }
         }
-        if (!INV) sf_group_rotate<false>(x);
+        if (!INV) sf_group_rotate<G, false>(x);
     }
 }
 
@@ -377,13 +374,13 @@ inline bool build_cantor(gcm_u128* beta, int count) {
     return true;
 }
 
-// The device table: beta_0 .. beta_127, then phi(u) for u < 2^kSfGroupLog.
+// The device table: beta_0 .. beta_127, then phi(u) for u < 2^kSfGroupMaxLog.
 inline bool build_cantor_table(std::vector<gcm_u128>& out) {
     out.assign(kCantorTotal, 0);
     if (!build_cantor(out.data(), kCantorBeta)) return false;
-    for (uint32_t u = 0; u < (1u << kSfGroupLog); ++u) {
+    for (uint32_t u = 0; u < (1u << kSfGroupMaxLog); ++u) {
         gcm_u128 r = 0;
-        for (int t = 0; t < kSfGroupLog; ++t)
+        for (int t = 0; t < kSfGroupMaxLog; ++t)
             if ((u >> t) & 1) r ^= out[t];
         out[kCantorBeta + u] = r;
     }
@@ -393,15 +390,19 @@ inline bool build_cantor_table(std::vector<gcm_u128>& out) {
 // The passes of one transform over N = 2^m points: layers [0, M) with
 // M = m_op forward (the layers above the operand's converted length 2^m_op
 // only copy it: its top half is zero) and M = m inverse.  Bottom pass first
-// (contiguous chunks of 2^min(m, 9) points, layers [0, min(M, 4))), then
-// strided passes of at most 7 layers; the forward transform runs them in the
-// reverse order, its first pass reading the converted words.
+// (groups of 2^G consecutive points, G = 2 or 3 in c, layers
+// [0, min(M, G))), then strided passes of at most 7 layers; the forward
+// transform runs them in the reverse order, its first pass reading the
+// converted words.
 inline std::vector<SfftPass> sfft_passes(uint4* x, const uint64_t* words, int m_op, int m, bool inverse,
                                          int alpha = -1) {
     std::vector<SfftPass> v;
     const int M = inverse ? m : m_op;
-    const int C = m < kSfGroupLog ? m : kSfGroupLog;
-    const int Lb = M < kSfGroupLog ? M : kSfGroupLog;
+    // the bottom pass's group size 2^G (in c): groups of 4 for small
+    // transforms (twice the threads) unless that adds a strided pass
+    const int L2 = M < 2 ? M : 2, L3 = M < 3 ? M : 3;
+    const int C = m <= kSfGroupSmallLog && (M - L2 + kSfTabL - 1) / kSfTabL == (M - L3 + kSfTabL - 1) / kSfTabL ? 2 : 3;
+    const int Lb = C == 2 ? L2 : L3;
     v.push_back(SfftPass{x, nullptr, 0, 1ull << m, 0, Lb, C, inverse ? 1 : 0, alpha});
     const int up = M - Lb;
     if (up > 0) {

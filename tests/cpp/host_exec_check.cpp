@@ -281,29 +281,38 @@ bool check_xcd_order(std::mt19937_64& g) {
 // phase (every thread of a phase before any of the next, as the barriers do)
 std::vector<uint4> CANTOR;
 
+// The bottom pass: chunks of 64 groups of 2^G points, one group per thread
+// (points past N are zero and not stored).
+template <int G>
+void run_sfft_groups(const SfftPass& P, uint4* T) {
+    for (uint64_t c = 0; c < ((P.n + (1ull << (G + 6)) - 1) >> (G + 6)); ++c) {
+        const uint64_t J0 = c << (G + 6);
+        for (uint32_t g = 0; g < 64; ++g) {
+            uint4 x[1 << G];
+            for (int p = 0; p < (1 << G); ++p) {
+                const uint64_t j = J0 + (g << G) + p;
+                x[p] = j < P.n ? sfft_load(P, j) : make_uint4(0u, 0u, 0u, 0u);
+            }
+            if (P.inverse)
+                sf_group_layers<G, true>(P, J0, g, x, T, CANTOR.data());
+            else
+                sf_group_layers<G, false>(P, J0, g, x, T, CANTOR.data());
+            for (int p = 0; p < (1 << G); ++p) {
+                const uint64_t j = J0 + (g << G) + p;
+                if (j < P.n) P.x[j] = x[p];
+            }
+        }
+    }
+}
+
 void run_sfft(const std::vector<SfftPass>& passes) {
     std::vector<uint4> tab(((1 << kSfTabL) - 1) * kSfTabStride), dat(1 << kSfTabPtsLog), T(kSfTabStride);
     for (const SfftPass& P : passes) {
         if (P.lo == 0) {
-            // chunks of 64 groups of 2^kSfGroupLog points (points past N are zero and not stored)
-            for (uint64_t c = 0; c < ((P.n + (1u << kSfChunkLog) - 1) >> kSfChunkLog); ++c) {
-                const uint64_t J0 = c << kSfChunkLog;
-                for (uint32_t g = 0; g < 64; ++g) {
-                    uint4 x[kSfGroupPts];
-                    for (int p = 0; p < kSfGroupPts; ++p) {
-                        const uint64_t j = J0 + kSfGroupPts * g + p;
-                        x[p] = j < P.n ? sfft_load(P, j) : make_uint4(0u, 0u, 0u, 0u);
-                    }
-                    if (P.inverse)
-                        sf_group_layers<true>(P, J0, g, x, T.data(), CANTOR.data());
-                    else
-                        sf_group_layers<false>(P, J0, g, x, T.data(), CANTOR.data());
-                    for (int p = 0; p < kSfGroupPts; ++p) {
-                        const uint64_t j = J0 + kSfGroupPts * g + p;
-                        if (j < P.n) P.x[j] = x[p];
-                    }
-                }
-            }
+            if (P.c == 2)
+                run_sfft_groups<2>(P, T.data());
+            else
+                run_sfft_groups<3>(P, T.data());
         } else {
             const uint32_t npts = 1u << (P.L + P.c), ntab = (1u << P.L) - 1;
             for (uint64_t g = 0; g < sf_tab_groups(P); ++g) {
