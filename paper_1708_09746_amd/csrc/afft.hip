@@ -281,19 +281,23 @@ __global__ __launch_bounds__(kSfThreads) void k_sfft_tab(SfftPass P, const uint4
 }
 
 // The bottom pass: one wave per chunk of 64 groups of 2^G consecutive
-// points, one group per thread.  A thread's table region (kSfTabStride
-// entries) also carries its group in and out: lane l loads points 64 i + l of
-// the chunk (coalesced) into the regions of their groups' threads, and every
-// thread then reads its own.  Each wave touches only its own regions, so
-// wave-level ordering replaces workgroup barriers.
+// points, one group per thread.  The wave's table region (the 64
+// lane-interleaved tables) also carries the groups in and out: lane l loads
+// points 64 i + l of the chunk (coalesced) into slot (2^G + 1) g + p for point
+// p of group g (the pad keeps both the writes and the reads of a group's
+// points apart in the banks), and every thread then reads its own.  Each wave
+// touches only its own region, so wave-level ordering replaces workgroup
+// barriers.
 constexpr int kSfGroupThreads = 64;
 
 template <int G, bool INV>
 __global__ __launch_bounds__(kSfGroupThreads) void k_sfft_lane(SfftPass P, const uint4* g_cantor) {
-    constexpr int CL = G + 6;  // log2 of the chunk's points
-    __shared__ uint4 ltab[kSfGroupThreads * kSfTabStride];
+    constexpr int CL = G + 6;            // log2 of the chunk's points
+    constexpr int GS = (1 << G) + 1;     // staging slots per group
+    __shared__ uint4 ltab[kSfLaneTabWave];
     const uint32_t g = threadIdx.x;
-    uint4* T = ltab + g * kSfTabStride;
+    uint4* T0 = ltab + sf_lane_tab(g);
+    uint4* X = ltab + g * GS;
     const uint64_t nchunks = (P.n + (1u << CL) - 1) >> CL;
     for (uint64_t c = blockIdx.x; c < nchunks; c += gridDim.x) {
         const uint64_t J0 = c << CL;
@@ -301,23 +305,23 @@ __global__ __launch_bounds__(kSfGroupThreads) void k_sfft_lane(SfftPass P, const
         for (int i = 0; i < (1 << G); ++i) {
             const uint32_t p = 64 * i + g;
             const uint64_t j = J0 + p;
-            ltab[(p >> G) * kSfTabStride + (p & ((1 << G) - 1))] = j < P.n ? sfft_load(P, j) : make_uint4(0u, 0u, 0u, 0u);
+            ltab[(p >> G) * GS + (p & ((1 << G) - 1))] = j < P.n ? sfft_load(P, j) : make_uint4(0u, 0u, 0u, 0u);
         }
         AFFT_WAVE_SYNC();
         uint4 x[1 << G];
 #pragma unroll
-        for (int p = 0; p < (1 << G); ++p) x[p] = T[p];
+        for (int p = 0; p < (1 << G); ++p) x[p] = X[p];
         AFFT_WAVE_SYNC();
-        sf_group_layers<G, INV>(P, J0, g, x, T, g_cantor);
+        sf_group_layers<G, INV>(P, J0, g, x, T0, g_cantor);
         AFFT_WAVE_SYNC();
 #pragma unroll
-        for (int p = 0; p < (1 << G); ++p) T[p] = x[p];
+        for (int p = 0; p < (1 << G); ++p) X[p] = x[p];
         AFFT_WAVE_SYNC();
 #pragma unroll
         for (int i = 0; i < (1 << G); ++i) {
             const uint32_t p = 64 * i + g;
             const uint64_t j = J0 + p;
-            if (j < P.n) P.x[j] = ltab[(p >> G) * kSfTabStride + (p & ((1 << G) - 1))];
+            if (j < P.n) P.x[j] = ltab[(p >> G) * GS + (p & ((1 << G) - 1))];
         }
         AFFT_WAVE_SYNC();
     }
@@ -325,12 +329,12 @@ __global__ __launch_bounds__(kSfGroupThreads) void k_sfft_lane(SfftPass P, const
 
 // pointmul of Alg. 4: sc[j] = sa[j] * sb[j] in GF(2^128)
 __global__ __launch_bounds__(kSfLaneThreads) void k_spmul(const uint4* sa, const uint4* sb, uint4* sc, uint64_t n) {
-    __shared__ uint4 ltab[kSfLaneThreads * kSfTabStride];
-    uint4* T = ltab + threadIdx.x * kSfTabStride;
+    __shared__ uint4 ltab[kSfLaneThreads / 64 * kSfLaneTabWave];
+    uint4* T0 = ltab + (threadIdx.x >> 6) * kSfLaneTabWave + sf_lane_tab(threadIdx.x & 63);
     for (uint64_t j = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n; j += (uint64_t)gridDim.x * blockDim.x) {
         const uint4 a = sa[j], b = sb[j];
-        gcm_build_tab(a, T);
-        sc[j] = gcm_mul_tab(T, b);
+        gcm_build_tab<kSfLaneTabStride>(a, T0);
+        sc[j] = gcm_mul_tab_lane(T0, b);
     }
 }
 

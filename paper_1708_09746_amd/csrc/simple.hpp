@@ -60,9 +60,11 @@ AFFT_HD uint4 gcm_mulx(uint4 v) {
     return r;
 }
 
-// T[n] = v * n(x) for the 16 polynomials n of degree < 4 (bit i of n is the
+// T[n S] = v * n(x) for the 16 polynomials n of degree < 4 (bit i of n is the
 // coefficient of x^i), walked in Gray-code order so that each entry is the
-// previous one plus a single v * x^i.
+// previous one plus a single v * x^i.  S = 1: a contiguous table; S =
+// kSfLaneTabStride: a per-thread table in the lane-interleaved layout.
+template <int S = 1>
 AFFT_HD void gcm_build_tab(uint4 v, uint4* T) {
     uint4 b[4];
     b[0] = v;
@@ -75,7 +77,7 @@ AFFT_HD void gcm_build_tab(uint4 v, uint4* T) {
     for (int i = 1; i < 16; ++i) {
         const int flip = __builtin_ctz(i);  // Gray code i ^ (i >> 1) changes this bit
         cur = xor4(cur, b[flip]);
-        T[i ^ (i >> 1)] = cur;
+        T[(i ^ (i >> 1)) * S] = cur;
     }
 }
 
@@ -94,48 +96,57 @@ AFFT_HD uint4 gcm_reduce(const uint32_t (&a)[8]) {
     return r;
 }
 
-// The entry of the LDS table T at byte offset (byte k of v); every byte of v
-// is a multiple of 16.  On the device the address is one VOP2 add that reads
-// byte k of its second operand (SDWA) in place of a shift, a mask and an add.
+// base + (selected part of v) in one VOP2 add that reads a byte or a 16-bit
+// half of its second operand (SDWA): the LDS address of a table entry whose
+// byte offset was placed in that part of v beforehand.
+#if defined(__HIP_DEVICE_COMPILE__)
+typedef const __attribute__((address_space(3))) uint4* gcm_lds_ptr;
+#define GCM_ADD_SEL(SEL, r, base, v)                                                                      \
+    asm("v_add_u32_sdwa %0, %1, %2 dst_sel:DWORD dst_unused:UNUSED_PAD src0_sel:DWORD src1_sel:" SEL \
+        : "=v"(r)                                                                                        \
+        : "v"(base), "v"(v))
+#endif
+
+// The entry of the contiguous LDS table T at byte offset (byte k of v).
 AFFT_HD uint4 gcm_entry(const uint4* T, uint32_t v, int k) {
 #if defined(__HIP_DEVICE_COMPILE__)
-    typedef const __attribute__((address_space(3))) uint4* lds_ptr;
-    const uint32_t base = (uint32_t)(uintptr_t)(lds_ptr)T;
+    const uint32_t base = (uint32_t)(uintptr_t)(gcm_lds_ptr)T;
     uint32_t a;
     switch (k) {
-        case 0:
-            asm("v_add_u32_sdwa %0, %1, %2 dst_sel:DWORD dst_unused:UNUSED_PAD src0_sel:DWORD src1_sel:BYTE_0"
-                : "=v"(a) : "v"(base), "v"(v));
-            break;
-        case 1:
-            asm("v_add_u32_sdwa %0, %1, %2 dst_sel:DWORD dst_unused:UNUSED_PAD src0_sel:DWORD src1_sel:BYTE_1"
-                : "=v"(a) : "v"(base), "v"(v));
-            break;
-        case 2:
-            asm("v_add_u32_sdwa %0, %1, %2 dst_sel:DWORD dst_unused:UNUSED_PAD src0_sel:DWORD src1_sel:BYTE_2"
-                : "=v"(a) : "v"(base), "v"(v));
-            break;
-        default:
-            asm("v_add_u32_sdwa %0, %1, %2 dst_sel:DWORD dst_unused:UNUSED_PAD src0_sel:DWORD src1_sel:BYTE_3"
-                : "=v"(a) : "v"(base), "v"(v));
-            break;
+        case 0: GCM_ADD_SEL("BYTE_0", a, base, v); break;
+        case 1: GCM_ADD_SEL("BYTE_1", a, base, v); break;
+        case 2: GCM_ADD_SEL("BYTE_2", a, base, v); break;
+        default: GCM_ADD_SEL("BYTE_3", a, base, v); break;
     }
-    return *(lds_ptr)(uintptr_t)a;
+    return *(gcm_lds_ptr)(uintptr_t)a;
 #else
     return T[((v >> (8 * k)) & 255u) >> 4];
 #endif
 }
 
-// v * w with T the table of v: sum over nibble positions p = 8q + r of
-// T[nibble] x^(32q) x^(4r), by Horner's rule in x^4 over r.  The four
-// lookups of one r land on words q .. q + 3 of the accumulator; each word
-// takes its (up to four) terms through three-input XORs.  The nibbles of
-// word q are spread once into the bytes of ev[q] (even r, times 16) and
-// od[q] (odd r, times 16): byte offsets of the entries.
-AFFT_HD uint4 gcm_mul_tab(const uint4* T, uint4 w) {
-    const uint32_t ev[4] = {(w.x << 4) & 0xF0F0F0F0u, (w.y << 4) & 0xF0F0F0F0u, (w.z << 4) & 0xF0F0F0F0u,
-                            (w.w << 4) & 0xF0F0F0F0u};
-    const uint32_t od[4] = {w.x & 0xF0F0F0F0u, w.y & 0xF0F0F0F0u, w.z & 0xF0F0F0F0u, w.w & 0xF0F0F0F0u};
+// The entry of the lane-interleaved LDS table at T0 at byte offset (16-bit
+// half h of v).
+AFFT_HD uint4 gcm_entry_lane(const uint4* T0, uint32_t v, int h) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    const uint32_t base = (uint32_t)(uintptr_t)(gcm_lds_ptr)T0;
+    uint32_t a;
+    if (h == 0)
+        GCM_ADD_SEL("WORD_0", a, base, v);
+    else
+        GCM_ADD_SEL("WORD_1", a, base, v);
+    return *(gcm_lds_ptr)(uintptr_t)a;
+#else
+    return T0[((v >> (16 * h)) & 0xFFFFu) >> 4];
+#endif
+}
+
+// v * w from entry(q, r) = T[nibble r of word q of w], T the table of v: sum
+// over nibble positions p = 8q + r of T[nibble] x^(32q) x^(4r), by Horner's
+// rule in x^4 over r.  The four lookups of one r land on words q .. q + 3 of
+// the accumulator; each word takes its (up to four) terms through
+// three-input XORs.
+template <class E>
+AFFT_HD uint4 gcm_horner(const E& entry) {
     uint32_t a[8] = {0, 0, 0, 0, 0, 0, 0, 0};
 #pragma unroll
     for (int r = 7; r >= 0; --r) {
@@ -144,9 +155,7 @@ AFFT_HD uint4 gcm_mul_tab(const uint4* T, uint4 w) {
             for (int i = 7; i > 0; --i) a[i] = (a[i] << 4) | (a[i - 1] >> 28);
             a[0] <<= 4;
         }
-        const uint32_t* s = (r & 1) ? od : ev;
-        const uint4 t0 = gcm_entry(T, s[0], r >> 1), t1 = gcm_entry(T, s[1], r >> 1);
-        const uint4 t2 = gcm_entry(T, s[2], r >> 1), t3 = gcm_entry(T, s[3], r >> 1);
+        const uint4 t0 = entry(0, r), t1 = entry(1, r), t2 = entry(2, r), t3 = entry(3, r);
         a[0] ^= t0.x;
         a[1] = xor3(a[1], t0.y, t1.x);
         a[2] = xor3(a[2], t0.z, t1.y) ^ t2.x;
@@ -156,6 +165,45 @@ AFFT_HD uint4 gcm_mul_tab(const uint4* T, uint4 w) {
         a[6] ^= t3.w;
     }
     return gcm_reduce(a);
+}
+
+// v * w with T the contiguous table of v (16 entries, 16 B apart).  The
+// nibbles of word q are spread once into the bytes of ev[q] (even r) and
+// od[q] (odd r), times 16: the byte offsets of the entries.
+AFFT_HD uint4 gcm_mul_tab(const uint4* T, uint4 w) {
+    const uint32_t ev[4] = {(w.x << 4) & 0xF0F0F0F0u, (w.y << 4) & 0xF0F0F0F0u, (w.z << 4) & 0xF0F0F0F0u,
+                            (w.w << 4) & 0xF0F0F0F0u};
+    const uint32_t od[4] = {w.x & 0xF0F0F0F0u, w.y & 0xF0F0F0F0u, w.z & 0xF0F0F0F0u, w.w & 0xF0F0F0F0u};
+    return gcm_horner([&](int q, int r) __attribute__((always_inline)) {
+        return gcm_entry(T, (r & 1) ? od[q] : ev[q], r >> 1);
+    });
+}
+
+// Per-thread tables in the lane-interleaved layout: the 64 tables of a wave
+// take 16 KiB, and entry n of lane t is uint4 (t >> 4) 256 + 16 n + (t mod 16)
+// of the region.  A b128 read is served 16 lanes at a time, and entry n of any
+// lane t sits in bank group t mod 16 whatever n is, so the random lookups of a
+// product never meet in a bank.  T0 is the lane's entry 0.
+constexpr int kSfLaneTabStride = 16;  // uint4 from one entry of a lane's table to the next
+constexpr int kSfLaneTabWave = 64 * 16;  // uint4 per wave
+AFFT_HD uint32_t sf_lane_tab(uint32_t lane) { return (lane >> 4) * 256 + (lane & 15); }
+
+// v * w with T0 the lane-interleaved table of v.  Nibbles r and r + 4 of word
+// q sit in the low and high halves of P[r mod 4][q], times 256: the byte
+// offsets of the entries.
+AFFT_HD uint4 gcm_mul_tab_lane(const uint4* T0, uint4 w) {
+    const uint32_t W[4] = {w.x, w.y, w.z, w.w};
+    uint32_t P[4][4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        P[0][q] = (W[q] << 8) & 0x0F000F00u;
+        P[1][q] = (W[q] << 4) & 0x0F000F00u;
+        P[2][q] = W[q] & 0x0F000F00u;
+        P[3][q] = (W[q] >> 4) & 0x0F000F00u;
+    }
+    return gcm_horner([&](int q, int r) __attribute__((always_inline)) {
+        return gcm_entry_lane(T0, P[r & 3][q], r >> 2);
+    });
 }
 
 // phi(v) = sum of beta_t over the set bits t of v (v < 2^64)
@@ -240,8 +288,8 @@ AFFT_HD void sf_tab_bfly(const SfftPass& P, int s, uint32_t q, uint4* dat, const
 // (forward, layers top-down) or rotr(p, 1) (inverse, bottom-up).  Pair i lies
 // in block e = i mod 2^(G-1-k); visiting the pairs as i = rev(s), the reversal
 // of the G - 1 bits of s < H, takes the blocks one after another, so the
-// table of each block's multiplier is built once and serves its 2^k
-// butterflies.
+// table of each block's multiplier is built once (lane-interleaved) and
+// serves its 2^k butterflies.
 template <int G>
 AFFT_HD constexpr int sf_rev(int s) {
     int r = 0;
@@ -270,8 +318,9 @@ AFFT_HD void sf_group_rotate(uint4 (&x)[1 << G]) {
     for (int p = 0; p < (1 << G); ++p) x[p] = y[p];
 }
 
+// T0: the thread's lane-interleaved table
 template <int G, bool INV>
-AFFT_HD void sf_group_layers(const SfftPass& P, uint64_t J0, uint32_t g, uint4 (&x)[1 << G], uint4* T,
+AFFT_HD void sf_group_layers(const SfftPass& P, uint64_t J0, uint32_t g, uint4 (&x)[1 << G], uint4* T0,
                              const uint4* beta) {
     constexpr int H = 1 << (G - 1);
     const uint4* phit = beta + kCantorBeta;  // phi(u), u < 2^G
@@ -287,14 +336,15 @@ AFFT_HD void sf_group_layers(const SfftPass& P, uint64_t J0, uint32_t g, uint4 (
 #pragma unroll
             for (int s = 0; s < H; ++s) {
                 const int i = sf_rev<G>(s);
-                if ((s & ((1 << k) - 1)) == 0) gcm_build_tab(xor4(mb, phit[(i & ((H >> k) - 1)) << 1]), T);
+                if ((s & ((1 << k) - 1)) == 0)
+                    gcm_build_tab<kSfLaneTabStride>(xor4(mb, phit[(i & ((H >> k) - 1)) << 1]), T0);
                 uint4 u = x[i], w = x[i + H];
                 if (!INV) {
-                    u = xor4(u, gcm_mul_tab(T, w));
+                    u = xor4(u, gcm_mul_tab_lane(T0, w));
                     w = xor4(w, u);
                 } else {
                     w = xor4(w, u);
-                    u = xor4(u, gcm_mul_tab(T, w));
+                    u = xor4(u, gcm_mul_tab_lane(T0, w));
                 }
                 sf_pin(u);
                 sf_pin(w);

@@ -306,7 +306,7 @@ void run_sfft_groups(const SfftPass& P, uint4* T) {
 }
 
 void run_sfft(const std::vector<SfftPass>& passes) {
-    std::vector<uint4> tab(((1 << kSfTabL) - 1) * kSfTabStride), dat(1 << kSfTabPtsLog), T(kSfTabStride);
+    std::vector<uint4> tab(((1 << kSfTabL) - 1) * kSfTabStride), dat(1 << kSfTabPtsLog), T(16 * kSfLaneTabStride);
     for (const SfftPass& P : passes) {
         if (P.lo == 0) {
             if (P.c == 2)
@@ -335,12 +335,15 @@ bool check_simple_tables() {
     for (int i = 1; i < kCantorBeta; ++i) ok &= (gcm_mul_host(C[i], C[i]) ^ C[i]) == C[i - 1] && !(C[i] & 1);
     // the table product against the shift-and-add product
     std::mt19937_64 g(7);
-    std::vector<uint4> T(16);
+    std::vector<uint4> T(16), TL(16 * kSfLaneTabStride);
     for (int i = 0; i < 2000 && ok; ++i) {
         const gcm_u128 a = ((gcm_u128)g() << 64) | g(), b = ((gcm_u128)g() << 64) | g();
         gcm_build_tab(to_u4(a), T.data());
+        gcm_build_tab<kSfLaneTabStride>(to_u4(a), TL.data());
         const uint4 r = gcm_mul_tab(T.data(), to_u4(b)), want = to_u4(gcm_mul_host(a, b));
+        const uint4 rl = gcm_mul_tab_lane(TL.data(), to_u4(b));
         ok &= r.x == want.x && r.y == want.y && r.z == want.z && r.w == want.w;
+        ok &= rl.x == want.x && rl.y == want.y && rl.z == want.z && rl.w == want.w;
     }
     if (!ok) printf("simple-variant tables or table product wrong\n");
     return ok;
@@ -365,10 +368,10 @@ bool check_simple_product(std::mt19937_64& g, uint64_t na, uint64_t nb) {
     run_ops(ops);
     run_sfft(sfft_passes(sa, wa, s.m_a, s.m, false));
     run_sfft(sfft_passes(sb, wb, s.m_b, s.m, false));
-    std::vector<uint4> T(16);
+    std::vector<uint4> T(16 * kSfLaneTabStride);  // k_spmul's lane-interleaved table
     for (uint64_t j = 0; j < N; ++j) {
-        gcm_build_tab(sa[j], T.data());
-        sb[j] = gcm_mul_tab(T.data(), sb[j]);
+        gcm_build_tab<kSfLaneTabStride>(sa[j], T.data());
+        sb[j] = gcm_mul_tab_lane(T.data(), sb[j]);
     }
     run_sfft(sfft_passes(sb, nullptr, s.m, s.m, true));
     ops.clear();
@@ -437,10 +440,10 @@ bool check_frob_product(std::mt19937_64& g, uint64_t na, uint64_t nb) {
     const uint64_t n = 1ull << s.m;
     frob_forward_host(a.data(), na, wa, s.w_a, sa, s.m);
     frob_forward_host(b.data(), nb, wb, s.w_b, sb, s.m);
-    std::vector<uint4> T(16);
+    std::vector<uint4> T(16 * kSfLaneTabStride);  // k_spmul's lane-interleaved table
     for (uint64_t j = 0; j < n; ++j) {
-        gcm_build_tab(sa[j], T.data());
-        sb[j] = gcm_mul_tab(T.data(), sb[j]);
+        gcm_build_tab<kSfLaneTabStride>(sa[j], T.data());
+        sb[j] = gcm_mul_tab_lane(T.data(), sb[j]);
     }
     run_sfft(sfft_passes(sb, nullptr, s.m, s.m, true, s.m + 64));
     uint64_t* words = (uint64_t*)sa;
