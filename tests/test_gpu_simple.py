@@ -47,9 +47,11 @@ def _spec_ints(spec) -> list:
     return [int(lo) | (int(hi) << 64) for lo, hi in h]
 
 
-# bottom pass only, and one strided pass above it (N = 2^10, 2^11)
-@pytest.mark.parametrize("na,log2n", [(1, 0), (1, 1), (64, 3), (700, 5), (64 * 16, 4), (2000, 9), (3000, 10),
-                                      (64 * 1024, 11)])
+# no layers (one-word operands), the bottom pass only (on groups of 8 for an
+# 8-word operand), one strided pass above it, and two (N = 2^11; groups of 8
+# for the 1024-word operands, whose strided layers fit one pass only then)
+@pytest.mark.parametrize("na,log2n", [(1, 0), (1, 1), (64, 3), (64 * 8, 3), (64 * 8, 6), (700, 5), (64 * 16, 4),
+                                      (2000, 9), (3000, 10), (64 * 1024, 10), (64 * 1024, 11)])
 def test_simple_spectrum_equals_oracle(ctx, na, log2n):
     a = inputs.random_poly(0x5A + na, na)
     say(f"case simple spectrum {na} bits at 2^{log2n} points")
