@@ -262,14 +262,19 @@ __global__ __launch_bounds__(kThreads) void k_psi(PsiOp P, const uint4* g_psi) {
 constexpr int kLookupIters = 2000;
 // ---- the simple variant (Alg. 4): polynomial-basis GF(2^128), Cantor points
 
+// The Cantor basis is staged in LDS once per block: the multipliers of a
+// group's tables are sums of up to m basis elements, taken one after another.
 __global__ __launch_bounds__(kSfThreads) void k_sfft_tab(SfftPass P, const uint4* g_cantor) {
     __shared__ uint4 tab[((1 << kSfTabL) - 1) * kSfTabStride];
     __shared__ uint4 dat[1 << kSfTabPtsLog];
+    __shared__ uint4 beta[kCantorBeta];
     const uint32_t npts = 1u << (P.L + P.c), ntab = (1u << P.L) - 1;
     const uint64_t ngroups = sf_tab_groups(P);
+    for (uint32_t i = threadIdx.x; i < kCantorBeta; i += blockDim.x) beta[i] = g_cantor[i];
+    __syncthreads();
     for (uint64_t g = blockIdx.x; g < ngroups; g += gridDim.x) {
         for (uint32_t e = threadIdx.x; e < npts; e += blockDim.x) dat[e] = sfft_load(P, sf_tab_point(P, g, e));
-        for (uint32_t t = threadIdx.x; t < ntab; t += blockDim.x) sf_tab_table(P, g, t, g_cantor, tab);
+        for (uint32_t t = threadIdx.x; t < ntab; t += blockDim.x) sf_tab_table(P, g, t, beta, tab);
         __syncthreads();
         for (int s = 0; s < P.L; ++s) {
             for (uint32_t q = threadIdx.x; q < npts / 2; q += blockDim.x) sf_tab_bfly(P, s, q, dat, tab);
