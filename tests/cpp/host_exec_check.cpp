@@ -3,6 +3,7 @@
 // transforms, BasisCvt tile and class passes) are executed sequentially on
 // the CPU (thread 0 of 1, the same tile bodies the kernels run) and every
 // product is compared with the oracle.  No GPU is involved.
+#include <algorithm>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -326,6 +327,44 @@ void run_sfft(const std::vector<SfftPass>& passes) {
     }
 }
 
+// The pass plan of every transform size: the bottom pass first (inverse) or
+// last (forward) with groups of 2^c, c = 2 or 3, and layers [0, min(M, c));
+// strided passes of 1..kSfTabL layers covering the rest of [0, M) once, in
+// order, each with 2^c consecutive points, c <= lo and L + c <= kSfTabPtsLog;
+// groups of 4 exactly when N <= 2^kSfGroupSmallLog and they add no strided
+// pass; the forward transform's first pass reads the words.
+bool check_sfft_plan() {
+    auto npass = [](int M, int G) { const int up = M - (M < G ? M : G); return (up + kSfTabL - 1) / kSfTabL; };
+    uint4* x = (uint4*)0x1000;
+    const uint64_t* words = (const uint64_t*)0x2000;
+    for (int m = 0; m <= 32; ++m)
+        for (int m_op = 0; m_op <= m; ++m_op)
+            for (int inv = 0; inv < 2; ++inv) {
+                if (inv && m_op != m) continue;
+                const int M = inv ? m : m_op;
+                std::vector<SfftPass> v = sfft_passes(x, words, m_op, m, inv != 0);
+                if (!inv) std::reverse(v.begin(), v.end());
+                const SfftPass& b = v[0];
+                const int want_c = m <= kSfGroupSmallLog && npass(M, 2) == npass(M, 3) ? 2 : 3;
+                bool ok = b.lo == 0 && b.c == want_c && b.L == (M < want_c ? M : want_c) && (int)v.size() == 1 + npass(M, b.c);
+                int lo = b.L;
+                for (size_t i = 1; i < v.size() && ok; ++i) {
+                    const SfftPass& p = v[i];
+                    ok = p.lo == lo && p.L >= 1 && p.L <= kSfTabL && p.c <= p.lo && p.L + p.c <= kSfTabPtsLog;
+                    lo += p.L;
+                }
+                ok = ok && lo == M;
+                for (const SfftPass& p : v) ok = ok && p.x == x && p.n == (1ull << m) && p.inverse == inv;
+                const SfftPass& first = inv ? v.front() : v.back();
+                ok = ok && (inv ? first.words == nullptr : first.words == words && first.wmask == (1ull << m_op) - 1);
+                if (!ok) {
+                    printf("SIMPLE PLAN WRONG: m %d, m_op %d, inverse %d\n", m, m_op, inv);
+                    return false;
+                }
+            }
+    return true;
+}
+
 bool check_simple_tables() {
     std::vector<gcm_u128> C;
     if (!build_cantor_table(C)) return false;
@@ -568,6 +607,7 @@ int main(int argc, char** argv) {
         PP.word_bits = 64;
     }
     if (what == "all" || what == "simple") {
+        bad += !check_sfft_plan();
         // Alg. 4: bottom pass only (N <= 8), one and several strided passes
         // above it, operands far shorter than N, single words
         bad += !check_simple_tables();
