@@ -276,8 +276,14 @@ __global__ __launch_bounds__(kSfThreads) void k_sfft_tab(SfftPass P, const uint4
         for (uint32_t e = threadIdx.x; e < npts; e += blockDim.x) dat[e] = sfft_load(P, sf_tab_point(P, g, e));
         for (uint32_t t = threadIdx.x; t < ntab; t += blockDim.x) sf_tab_table(P, g, t, beta, tab);
         __syncthreads();
-        for (int s = 0; s < P.L; ++s) {
-            for (uint32_t q = threadIdx.x; q < npts / 2; q += blockDim.x) sf_tab_bfly(P, s, q, dat, tab);
+        for (int s = 0; s < P.L;) {
+            if (sf_tab_quads(P, s)) {  // two layers per LDS round trip
+                for (uint32_t q = threadIdx.x; q < npts / 4; q += blockDim.x) sf_tab_quad(P, s, q, dat, tab);
+                s += 2;
+            } else {
+                for (uint32_t q = threadIdx.x; q < npts / 2; q += blockDim.x) sf_tab_bfly(P, s, q, dat, tab);
+                s += 1;
+            }
             __syncthreads();
         }
         for (uint32_t e = threadIdx.x; e < npts; e += blockDim.x) P.x[sf_tab_point(P, g, e)] = dat[e];

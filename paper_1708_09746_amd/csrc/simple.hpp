@@ -274,6 +274,57 @@ AFFT_HD void sf_tab_bfly(const SfftPass& P, int s, uint32_t q, uint4* dat, const
     dat[e1] = w;
 }
 
+// Steps s and s + 1 on quad q (two layers per LDS round trip): the points
+// whose index bits c + lo and c + hi take all four values, lo < hi the two
+// relative layers.  Layer hi pairs (p0, p2) and (p1, p3) within one block
+// (one table), layer lo pairs (p0, p1) and (p2, p3) in two blocks; forward
+// runs hi then lo, inverse lo then hi, as the single steps do.
+// Steps s, s + 1 run as quads when a workgroup of kSfThreads has a quad for
+// every thread (groups of at least 1024 points); smaller groups keep single
+// steps, which give every thread a butterfly.
+AFFT_HD bool sf_tab_quads(const SfftPass& P, int s) {
+    return P.L - s >= 2 && (1u << (P.L + P.c)) >= 4u * kSfThreads;
+}
+
+AFFT_HD const uint4* sf_tab_of(const SfftPass& P, int r, uint32_t e0, const uint4* tab) {
+    return tab + (((1u << (P.L - 1 - r)) - 1) + (e0 >> (P.c + r + 1))) * kSfTabStride;
+}
+
+AFFT_HD void sf_tab_quad(const SfftPass& P, int s, uint32_t q, uint4* dat, const uint4* tab) {
+    const int lo = P.inverse ? s : P.L - 2 - s, hi = lo + 1;
+    const int sl = P.c + lo, sh = P.c + hi;
+    const uint32_t q1 = ((q >> sl) << (sl + 1)) | (q & ((1u << sl) - 1));
+    const uint32_t p0 = ((q1 >> sh) << (sh + 1)) | (q1 & ((1u << sh) - 1));
+    const uint32_t p1 = p0 | (1u << sl), p2 = p0 | (1u << sh), p3 = p1 | (1u << sh);
+    const uint4* Th = sf_tab_of(P, hi, p0, tab);
+    const uint4* Tl0 = sf_tab_of(P, lo, p0, tab);
+    const uint4* Tl1 = sf_tab_of(P, lo, p2, tab);
+    uint4 x0 = dat[p0], x1 = dat[p1], x2 = dat[p2], x3 = dat[p3];
+    if (!P.inverse) {
+        x0 = xor4(x0, gcm_mul_tab(Th, x2));
+        x2 = xor4(x2, x0);
+        x1 = xor4(x1, gcm_mul_tab(Th, x3));
+        x3 = xor4(x3, x1);
+        x0 = xor4(x0, gcm_mul_tab(Tl0, x1));
+        x1 = xor4(x1, x0);
+        x2 = xor4(x2, gcm_mul_tab(Tl1, x3));
+        x3 = xor4(x3, x2);
+    } else {
+        x1 = xor4(x1, x0);
+        x0 = xor4(x0, gcm_mul_tab(Tl0, x1));
+        x3 = xor4(x3, x2);
+        x2 = xor4(x2, gcm_mul_tab(Tl1, x3));
+        x2 = xor4(x2, x0);
+        x0 = xor4(x0, gcm_mul_tab(Th, x2));
+        x3 = xor4(x3, x1);
+        x1 = xor4(x1, gcm_mul_tab(Th, x3));
+    }
+    dat[p0] = x0;
+    dat[p1] = x1;
+    dat[p2] = x2;
+    dat[p3] = x3;
+}
+
 // The contiguous bottom pass: layers [0, L) (L <= G, G = 2 or 3) on groups
 // of 2^G consecutive points, one group per thread, held in registers.  A wave
 // takes a chunk of 64 groups at J0 (a multiple of 2^(G+6)); the layer-k

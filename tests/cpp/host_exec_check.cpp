@@ -319,8 +319,14 @@ void run_sfft(const std::vector<SfftPass>& passes) {
             for (uint64_t g = 0; g < sf_tab_groups(P); ++g) {
                 for (uint32_t e = 0; e < npts; ++e) dat[e] = sfft_load(P, sf_tab_point(P, g, e));
                 for (uint32_t t = 0; t < ntab; ++t) sf_tab_table(P, g, t, CANTOR.data(), tab.data());
-                for (int s = 0; s < P.L; ++s)
-                    for (uint32_t q = 0; q < npts / 2; ++q) sf_tab_bfly(P, s, q, dat.data(), tab.data());
+                for (int s = 0; s < P.L;)
+                    if (sf_tab_quads(P, s)) {
+                        for (uint32_t q = 0; q < npts / 4; ++q) sf_tab_quad(P, s, q, dat.data(), tab.data());
+                        s += 2;
+                    } else {
+                        for (uint32_t q = 0; q < npts / 2; ++q) sf_tab_bfly(P, s, q, dat.data(), tab.data());
+                        s += 1;
+                    }
                 for (uint32_t e = 0; e < npts; ++e) P.x[sf_tab_point(P, g, e)] = dat[e];
             }
         }
